@@ -1,0 +1,66 @@
+"""Shared test helpers: marshal synthetic workloads into the oracle, brute-force references
+(all-pairs L1 distance), and the relative max-norm error used for parity."""
+import itertools
+
+import numpy as np
+
+import oracle
+from paper_2104_00095_amd import synth
+
+
+def oracle_shape(shape):
+    return oracle.make_shape(shape.kind, shape.centre, shape.semi, shape.rot)
+
+
+def oracle_problem(w, s, r_s=2, r_max=4, normal_layers=2, n_layers=None):
+    return oracle.make_problem(w.grid_n, s.lo, s.ext, oracle_shape(s.shape),
+                               s.n_layers if n_layers is None else n_layers,
+                               r_s=r_s, r_max=r_max, normal_layers=normal_layers)
+
+
+def run_oracle(w, s, **kw):
+    xi_normal = kw.pop("xi_normal", None)
+    nthreads = kw.pop("nthreads", 0)
+    p = oracle_problem(w, s, **kw)
+    return oracle.extrapolate(p, s.xi, xi_normal=xi_normal, nthreads=nthreads)
+
+
+def l1_distance_labels(mask, L, grid_mask_shape=None):
+    """Brute force: label = min L1 distance to an interior cell if <= L, else -1
+    (0 on interior cells).  mask is [n2, n1, n0] bool."""
+    idx = np.argwhere(mask)                       # (k, j, i)
+    out = np.full(mask.shape, -1, dtype=np.int8)
+    if idx.size == 0:
+        return out
+    allc = np.argwhere(np.ones(mask.shape, dtype=bool))
+    d = np.abs(allc[:, None, :] - idx[None, :, :]).sum(axis=2).min(axis=1)
+    lab = np.where(d <= L, d, -1).astype(np.int8)
+    out[tuple(allc.T)] = lab
+    return out
+
+
+def rel_err(a, b, band):
+    """max |a-b| over band cells and components, relative to max |b| there."""
+    if not band.any():
+        return 0.0
+    num = np.max(np.abs(a[:, band] - b[:, band]))
+    den = np.max(np.abs(b[:, band]))
+    return float(num / den)
+
+
+def cube_symmetries():
+    """The 48 signed permutation matrices."""
+    mats = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            m = np.zeros((3, 3), dtype=np.int64)
+            for r in range(3):
+                m[r, perm[r]] = signs[r]
+            mats.append(m)
+    return mats
+
+
+def exact_field(w, s, fn):
+    x, y, z = synth.cell_centres(s.lo, s.ext, w.h, w.origin)
+    X = np.broadcast_arrays(x, y, z)
+    return fn(*X)

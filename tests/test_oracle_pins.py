@@ -1,0 +1,500 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test names the passage it follows.  None of them re-types the oracle's arithmetic:
+they use brute force on tiny inputs (all-pairs L1 distance, dense surface sampling),
+closed forms derived by hand for special configurations, invariants (affine
+reproduction, untouched known cells, cube symmetry, zero weight in front of the
+interface), a library least-squares solve, and the accuracy order.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_00095_amd import synth
+from tests.helpers import (cube_symmetries, exact_field, l1_distance_labels, oracle_problem,
+                           oracle_shape, rel_err, run_oracle)
+
+UNIT_SPHERE = dict(kind=1, centre=(0.0, 0.0, 0.0), semi=(1.0, 1.0, 1.0))
+
+
+def _mask_problem(mask, L, grid_n=None, lo=(0, 0, 0), normal_layers=2, r_s=2, r_max=4,
+                  shape=None):
+    n2, n1, n0 = mask.shape
+    ext = (n0, n1, n2)
+    shape = shape or oracle.make_shape(**UNIT_SPHERE)
+    return oracle.make_problem(grid_n or ext, lo, ext, shape, L, r_s=r_s, r_max=r_max,
+                               normal_layers=normal_layers)
+
+
+def _random_mask(rng, shape):
+    kind = rng.integers(0, 5)
+    m = np.zeros(shape, dtype=bool)
+    K, J, I = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    if kind == 0:      # scattered points
+        m = rng.random(shape) < rng.uniform(0.01, 0.1)
+    elif kind == 1:    # a few balls, some touching walls
+        for _ in range(rng.integers(1, 4)):
+            c = [rng.uniform(-1, s) for s in shape]
+            r = rng.uniform(0.5, 3.5)
+            m |= (K - c[0]) ** 2 + (J - c[1]) ** 2 + (I - c[2]) ** 2 < r * r
+    elif kind == 2:    # one-cell-thin plate
+        ax = rng.integers(0, 3)
+        pos = rng.integers(0, shape[ax])
+        sl = [slice(None)] * 3
+        sl[ax] = pos
+        m[tuple(sl)] = True
+    elif kind == 3:    # disconnected single cells
+        for _ in range(rng.integers(1, 4)):
+            m[tuple(rng.integers(0, s) for s in shape)] = True
+    # kind 4: empty
+    return m
+
+
+# ------------------------------------------------------------------------------------------
+# Layers ("Extrapolation of xi", first paragraph; Fig. 1(c)): capped breadth-first layers
+# through face neighbours equal the L1 distance to the interior set in a box.
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(16))
+def test_labels_equal_bruteforce_l1_distance(seed):
+    rng = np.random.default_rng(1000 + seed)
+    shape = tuple(int(v) for v in rng.integers(3, 13, size=3))
+    mask = _random_mask(rng, shape)
+    L = int(rng.integers(0, 7))
+    xi = synth.tiny_field_from_mask(mask)
+    n_int, lab, trunc = oracle.label(_mask_problem(mask, L), xi)
+    assert n_int == int(mask.sum())
+    assert not trunc                        # box == grid: every face is a wall
+    assert np.array_equal(lab, l1_distance_labels(mask, L))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_box_inside_grid_truncation_and_labels(seed):
+    """A box smaller than the grid: the call is truncated iff the capped distance
+    transform taken over the WHOLE grid reaches a cell outside the box; otherwise the
+    labels equal that transform restricted to the box."""
+    rng = np.random.default_rng(2000 + seed)
+    g = tuple(int(v) for v in rng.integers(8, 15, size=3))      # grid (n2, n1, n0)
+    lo = tuple(int(rng.integers(0, g[a] // 2)) for a in range(3))
+    ext = tuple(int(rng.integers(3, g[a] - lo[a] + 1)) for a in range(3))
+    box = np.zeros(g, dtype=bool)
+    box[lo[0]:lo[0] + ext[0], lo[1]:lo[1] + ext[1], lo[2]:lo[2] + ext[2]] = True
+    full = np.zeros(g, dtype=bool)
+    sub = _random_mask(rng, ext)
+    full[lo[0]:lo[0] + ext[0], lo[1]:lo[1] + ext[1], lo[2]:lo[2] + ext[2]] = sub
+    L = int(rng.integers(1, 5))
+    dt = l1_distance_labels(full, L)
+    expect_trunc = bool(np.any((dt >= 0) & ~box))
+    xi = synth.tiny_field_from_mask(sub)
+    p = _mask_problem(sub, L, grid_n=(g[2], g[1], g[0]), lo=(lo[2], lo[1], lo[0]))
+    n_int, lab, trunc = oracle.label(p, xi)
+    assert trunc == expect_trunc
+    if not trunc:
+        assert np.array_equal(lab, dt[lo[0]:lo[0] + ext[0], lo[1]:lo[1] + ext[1],
+                                      lo[2]:lo[2] + ext[2]])
+
+
+def test_interior_predicate_strict_and_undefined():
+    """phi < 0 strictly marks interior cells; a non-finite xi is never interior."""
+    s = oracle.make_shape(1, (0.0, 0.0, 0.0), (0.5, 0.5, 0.5))
+    assert oracle.is_interior(s, (0.25, 0.0, 0.0))
+    assert not oracle.is_interior(s, (0.5, 0.0, 0.0))      # on the surface: phi = 0
+    assert not oracle.is_interior(s, (np.nan, 0.0, 0.0))
+    assert not oracle.is_interior(s, (0.0, np.inf, 0.0))
+    e = oracle.make_shape(2, (0.0, 0.0, 0.0), (0.5, 0.25, 0.125))
+    assert not oracle.is_interior(e, (0.0, 0.0, 0.125))     # exactly on the surface
+    assert oracle.is_interior(e, (0.0, 0.0, 0.12))
+
+
+# ------------------------------------------------------------------------------------------
+# phi0: exact signed distance ("Blurred interface method": phi0 is a signed distance).
+# ------------------------------------------------------------------------------------------
+def _ellipsoid_surface_samples(semi, n=1500):
+    th = np.linspace(0.0, math.pi, n)
+    ph = np.linspace(0.0, 2.0 * math.pi, 2 * n, endpoint=False)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    return np.stack([semi[0] * np.sin(T) * np.cos(P), semi[1] * np.sin(T) * np.sin(P),
+                     semi[2] * np.cos(T)], axis=-1).reshape(-1, 3)
+
+
+def test_phi0_sphere_and_round_ellipsoid():
+    rng = np.random.default_rng(7)
+    c = np.array([0.3, -0.2, 0.1])
+    s = oracle.make_shape(1, c, (0.4, 0.4, 0.4))
+    rot = synth.random_rotation(rng)
+    e = oracle.make_shape(2, c, (0.4, 0.4, 0.4), rot)
+    for _ in range(200):
+        v = c + rng.normal(size=3) * 0.5
+        d = float(np.linalg.norm(v - c)) - 0.4
+        assert abs(oracle.phi0(s, v) - d) < 1e-15
+        assert abs(oracle.phi0(e, v) - d) < 1e-14
+
+
+def test_phi0_ellipsoid_axes_and_centre():
+    semi = (0.3, 0.2, 0.15)
+    e = oracle.make_shape(2, (0.0, 0.0, 0.0), semi)
+    assert oracle.phi0(e, (0.0, 0.0, 0.0)) == -0.15       # nearest points on the short axis
+    for a in range(3):
+        for s_ in (0.05, 0.5, 1.0):
+            v = [0.0, 0.0, 0.0]
+            v[a] = s_ + semi[a]
+            assert abs(oracle.phi0(e, v) - s_) < 1e-14      # straight out along an axis
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_phi0_ellipsoid_matches_dense_surface_sampling(seed):
+    rng = np.random.default_rng(30 + seed)
+    semi = np.sort(rng.uniform(0.1, 0.4, size=3))[::-1]
+    rot = synth.random_rotation(rng)
+    c = rng.uniform(-0.2, 0.2, size=3)
+    e = oracle.make_shape(2, c, semi, rot)
+    surf = _ellipsoid_surface_samples(semi)
+    pts = [rng.normal(size=3) * 0.3 for _ in range(30)]
+    pts += [np.array([rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05), 0.0])]  # deep, y2=0
+    pts += [np.array([0.0, rng.uniform(-0.1, 0.1), 0.0])]
+    for y in pts:
+        v = c + rot @ y
+        d = abs(oracle.phi0(e, v))
+        ds = float(np.min(np.linalg.norm(surf - y[None, :], axis=1)))
+        # the exact distance never exceeds a sampled one, and sampling is fine enough
+        assert d <= ds + 1e-12
+        assert d >= ds - 2e-5
+        q = float(np.sum((y / semi) ** 2))
+        assert (oracle.phi0(e, v) < 0) == (q < 1)
+
+
+# ------------------------------------------------------------------------------------------
+# Normal (SI weighting scheme): gradient of phi0(xi) from face neighbours.
+# ------------------------------------------------------------------------------------------
+def _normal_probe_field():
+    """9x9x8 box; interior half-space k <= 3 with |xi| = 0.95 (phi = -0.05) for a unit
+    sphere at the origin; band cells undefined except the target e = (4,4,4) with phi =
+    0.05 and its +x neighbour with phi = 1.05."""
+    n0, n1, n2 = 9, 9, 8
+    xi = np.full((3, n2, n1, n0), np.nan)
+    xi[0, :4] = 0.95
+    xi[1, :4] = 0.0
+    xi[2, :4] = 0.0
+    xi[:, 4, 4, 4] = (1.05, 0.0, 0.0)
+    xi[:, 4, 4, 5] = (2.05, 0.0, 0.0)
+    return xi
+
+
+def test_normal_one_sided_differences():
+    """At e: +x neighbour defined, -x undefined -> forward difference; y neighbours
+    undefined -> 0; +z undefined, -z interior -> backward difference."""
+    xi = _normal_probe_field()
+    p = _mask_problem(np.zeros((8, 9, 9), dtype=bool), 1)
+    g = oracle.normal(p, xi, 4, 4, 4)
+    assert abs(g[0] - 1.0) < 1e-14
+    assert g[1] == 0.0
+    assert abs(g[2] - 0.1) < 1e-14
+
+
+def test_normal_central_difference_on_linear_phi():
+    """phi linear in the cell index (a sphere of radius 1 at the origin and xi along +x
+    with |xi| = 2 + 0.25 i) gives the exact slope by central differences."""
+    n0 = n1 = n2 = 5
+    xi = np.zeros((3, n2, n1, n0))
+    for i in range(n0):
+        xi[0, :, :, i] = 2.0 + 0.25 * i
+    p = _mask_problem(np.zeros((n2, n1, n0), dtype=bool), 1)
+    g = oracle.normal(p, xi, 2, 2, 2)
+    assert g[0] == 0.25 and g[1] == 0.0 and g[2] == 0.0
+    g = oracle.normal(p, xi, 0, 2, 2)             # wall: one-sided forward
+    assert g[0] == 0.25
+
+
+# ------------------------------------------------------------------------------------------
+# Weights (SI eq. weight).
+# ------------------------------------------------------------------------------------------
+def _half_space_quadratic(r_s=2):
+    """Interior k <= 3 (9x9x8 box) with xi_x = (i-4)^2, xi_y = xi_z = 0 for a sphere of
+    radius 1000 at the origin; band cells undefined.  Target e = (4, 4, 4) in layer 1."""
+    n0, n1, n2 = 9, 9, 8
+    xi = np.full((3, n2, n1, n0), np.nan)
+    ii = np.arange(n0)
+    xi[0, :4] = ((ii - 4.0) ** 2)[None, None, :]
+    xi[1, :4] = 0.0
+    xi[2, :4] = 0.0
+    shape = oracle.make_shape(1, (0.0, 0.0, 0.0), (1000.0, 1000.0, 1000.0))
+    p = oracle.make_problem((n0, n1, n2), (0, 0, 0), (n0, n1, n2), shape, 1, r_s=r_s,
+                            r_max=4, normal_layers=0)
+    return p, xi
+
+
+def test_kernel_weights_closed_form():
+    """Without the normal factor the weight is 2^-(|di|+|dj|+|dk|) over the Chebyshev box
+    of radius r_s = 2.  Data depend on di only, and the weights factor as
+    2^-|di| 2^-|dj| 2^-|dk|, so the fitted value at the target is the 2^-|di|-weighted mean
+    of di^2 over di in [-2, 2] (equal on both data planes, so the dk slope is 0):
+      (2 (1/2 * 1 + 1/4 * 4)) / (1 + 2/2 + 2/4) = 3 / 2.5 = 1.2.
+    With r_s = 1 the only data plane is dk = -1: the system is degenerate, the radius
+    grows by one and the same value results, recorded as radius 2."""
+    for r_s in (2, 1):
+        p, xi = _half_space_quadratic(r_s)
+        st, out, lab, dec, stats = oracle.extrapolate(p, xi)
+        assert st == 0
+        assert lab[4, 4, 4] == 1 and dec[4, 4, 4] == 2
+        assert abs(out[0, 4, 4, 4] - 1.2) < 1e-14
+        assert abs(out[1, 4, 4, 4]) < 1e-15 and abs(out[2, 4, 4, 4]) < 1e-15
+        assert (stats[17] > 0) == (r_s == 1)
+
+
+def test_normal_factor_zero_in_front_of_interface():
+    """For l <= 2 the weight is max(0, x'.n/|x'| ...): data with x'.n <= 0 get weight 0.
+    At the probe target g = (1, 0, 0.1), so interior data with di >= 1 lie in front and
+    must not influence xi_e, while data with di <= 0 must."""
+    base = _normal_probe_field()
+    rng = np.random.default_rng(5)
+    interior = np.zeros(base.shape[1:], dtype=bool)
+    interior[:4] = True
+    pert = base.copy()
+    pert[:, :4] += 0.001 * rng.standard_normal((3, 4, 9, 9))   # keep |xi| < 1 (interior)
+    p = _mask_problem(np.zeros((8, 9, 9), dtype=bool), 1)
+    st, out0, lab, dec, _ = oracle.extrapolate(p, pert)
+    assert st == 0 and lab[4, 4, 4] == 1 and dec[4, 4, 4] == 2
+    front = pert.copy()
+    front[:, 2:4, :, 5:] += 0.002 * rng.standard_normal((3, 2, 9, 4))
+    st, out1, _, _, _ = oracle.extrapolate(p, front)
+    assert np.array_equal(out0[:, 4, 4, 4], out1[:, 4, 4, 4])
+    behind = pert.copy()
+    behind[:, 2:4, :, 2:5] += 0.002 * rng.standard_normal((3, 2, 9, 3))
+    st, out2, _, _, _ = oracle.extrapolate(p, behind)
+    assert np.max(np.abs(out2[:, 4, 4, 4] - out0[:, 4, 4, 4])) > 1e-6
+
+
+# ------------------------------------------------------------------------------------------
+# Local linear model (main text: WLS local linear model, xi_e = beta x_e).
+# ------------------------------------------------------------------------------------------
+def _perturb_band_outward(w, s, lab, amount):
+    xi = s.xi.copy()
+    band = lab > 0
+    c = s.shape.centre
+    d = xi[:, band] - c[:, None]
+    nrm = np.linalg.norm(d, axis=0)
+    xi[:, band] = xi[:, band] + amount * d / nrm
+    return xi
+
+
+def _affine_case(kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "sphere":
+        w = synth.sphere32(seed=seed, affine=True)
+        A, b = w.affine
+        return w, A, b
+    n = 40
+    h = 1.0 / n
+    c = np.array([0.5, 0.5, 0.5])
+    A = np.eye(3) + 0.1 * rng.standard_normal((3, 3))
+    rot = synth.random_rotation(rng)
+    xi = synth.affine_sine_field((0, 0, 0), (n, n, n), h, (0, 0, 0), c, A, 0.0, None)
+    w = synth.Workload("ell_affine", (n, n, n), h, (0.0, 0.0, 0.0))
+    w.solids.append(synth.Solid((0, 0, 0), (n, n, n),
+                                synth.ellipsoid_shape(c, (0.3, 0.2, 0.15), rot), 6, xi))
+    return w, A, c - A @ c
+
+
+@pytest.mark.parametrize("kind,seed", [("sphere", 1), ("sphere", 11), ("ellipsoid", 2)])
+def test_affine_field_reproduced(kind, seed):
+    """An affine xi is reproduced exactly by any non-degenerate affine WLS fit, whatever
+    the weights.  Band inputs are first pushed outward so that copying them through
+    cannot pass, and stay non-interior so that the labels do not change."""
+    w, A, b = _affine_case(kind, seed)
+    s = w.solids[0]
+    st, _, lab0, _, _ = run_oracle(w, s)
+    assert st == 0
+    s.xi = _perturb_band_outward(w, s, lab0, 0.5 * w.h)
+    st, out, lab, dec, stats = run_oracle(w, s)
+    assert st == 0 and np.array_equal(lab, lab0)
+    exact = exact_field(w, s, lambda x, y, z: np.stack(
+        [b[a] + A[a, 0] * x + A[a, 1] * y + A[a, 2] * z for a in range(3)]))
+    band = lab > 0
+    assert rel_err(s.xi, exact, band) > 1e-3          # inputs really were off
+    assert rel_err(out, exact, band) < 1e-13
+
+
+def test_known_cells_unchanged_bitwise():
+    """Interior (PRM) and unmarked cells are inputs and are never written."""
+    w = synth.sphere32()
+    s = w.solids[0]
+    st, out, lab, dec, stats = run_oracle(w, s)
+    assert st == 0
+    keep = lab <= 0
+    assert np.array_equal(out[:, keep].view(np.uint64), s.xi[:, keep].view(np.uint64))
+    assert np.all(dec[keep] == 0) and np.all(dec[lab > 0] != 0)
+    assert stats[0] == int((lab == 0).sum())
+    for l in range(1, 5):
+        assert stats[l] == int((lab == l).sum())
+
+
+def test_wls_matches_library_lstsq():
+    """Cross-check of the solver only: per-cell numpy lstsq on sqrt(W)[1, delta] with the
+    kernel weights of layers > 2 reproduces the oracle's Householder QR."""
+    w = synth.sphere32(n_layers=5)
+    s = w.solids[0]
+    st, out, lab, dec, stats = run_oracle(w, s)
+    assert st == 0
+    rng = np.random.default_rng(3)
+    n2, n1, n0 = lab.shape
+    cells = np.argwhere(lab >= 3)
+    for k, j, i in cells[rng.choice(len(cells), 60, replace=False)]:
+        le = lab[k, j, i]
+        rows, vals, wts = [], [], []
+        for dk in range(-2, 3):
+            for dj in range(-2, 3):
+                for di in range(-2, 3):
+                    kk, jj, ii = k + dk, j + dj, i + di
+                    if not (0 <= kk < n2 and 0 <= jj < n1 and 0 <= ii < n0):
+                        continue
+                    if 0 <= lab[kk, jj, ii] < le:
+                        rows.append([1.0, di, dj, dk])
+                        vals.append(out[:, kk, jj, ii])
+                        wts.append(2.0 ** -(abs(di) + abs(dj) + abs(dk)))
+        sw = np.sqrt(np.array(wts))[:, None]
+        beta = np.linalg.lstsq(sw * np.array(rows), sw * np.array(vals), rcond=None)[0]
+        assert np.max(np.abs(beta[0] - out[:, k, j, i])) < 1e-13
+
+
+# ------------------------------------------------------------------------------------------
+# Degeneracy (main text: degenerate system -> grow r_s; readings F1/F2 beyond r_max).
+# ------------------------------------------------------------------------------------------
+def test_full_rank_test():
+    assert not oracle.full_rank([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0], [2, 3, 0]])
+    assert oracle.full_rank([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    assert not oracle.full_rank([[0, 0, 0], [1, 1, 1], [2, 2, 2], [-1, -1, -1]])
+    assert not oracle.full_rank([[1, 2, 3]] * 10)
+    rng = np.random.default_rng(11)
+    for _ in range(500):
+        n = int(rng.integers(1, 9))
+        pts = rng.integers(-2, 3, size=(n, 3))
+        if rng.random() < 0.5:                          # force coplanar sets often
+            pts[:, int(rng.integers(0, 3))] = int(rng.integers(-2, 3))
+        X = np.hstack([np.ones((n, 1)), pts])
+        assert oracle.full_rank(pts) == (np.linalg.matrix_rank(X) == 4)
+
+
+def test_plate_falls_back_to_symmetric_mean():
+    """A one-cell-thin plate: the data of the cells next to it are coplanar at every
+    radius, so the cell falls back to the kernel-weighted mean (F2).  With an affine xi on
+    the plate and a symmetric neighbourhood, that mean is the plate value straight
+    below the cell."""
+    n = 15
+    h = 1.0 / n
+    mask = np.zeros((n, n, n), dtype=bool)
+    mask[7] = True                                       # plane k = 7
+    A = np.array([[1.0, 0.2, 0.0], [0.1, 0.9, 0.0], [0.0, 0.0, 1.0]])
+    x = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")            # [j, i]
+    xi = np.full((3, n, n, n), np.nan)
+    for a in range(3):
+        xi[a, 7] = 0.01 * (A[a, 0] * X + A[a, 1] * Y)   # |xi| << 1: interior
+    p = _mask_problem(mask, 2)
+    st, out, lab, dec, stats = oracle.extrapolate(p, xi)
+    assert st == 0
+    for k in (6, 8):
+        assert lab[k, 7, 7] == 1
+        assert dec[k, 7, 7] & 63 == oracle.DEC_F2
+        assert np.max(np.abs(out[:, k, 7, 7] - xi[:, 7, 7, 7])) < 1e-16
+    assert stats[20] > 0
+
+
+def test_single_interior_cell():
+    """A single interior cell: each face neighbour has one datum and copies it (F2)."""
+    mask = np.zeros((9, 9, 9), dtype=bool)
+    mask[4, 4, 4] = True
+    xi = synth.tiny_field_from_mask(mask, inside_value=(0.1, 0.2, 0.3))
+    st, out, lab, dec, stats = oracle.extrapolate(_mask_problem(mask, 3), xi)
+    assert st == 0
+    for (k, j, i) in [(3, 4, 4), (5, 4, 4), (4, 3, 4), (4, 5, 4), (4, 4, 3), (4, 4, 5)]:
+        assert dec[k, j, i] & 63 == oracle.DEC_F2
+        assert np.array_equal(out[:, k, j, i], np.array([0.1, 0.2, 0.3]))
+    assert np.all(np.isfinite(out[:, lab > 0]))
+
+
+# ------------------------------------------------------------------------------------------
+# Invariants of the whole call.
+# ------------------------------------------------------------------------------------------
+def test_cube_symmetry_of_centred_sphere():
+    """xi = x about a sphere centred on the grid centre: labels are invariant under the 48
+    symmetries of the cube, and xi - c transforms with them (to roundoff)."""
+    n = 16
+    h = 1.0 / n
+    c = np.array([0.5, 0.5, 0.5])
+    w = synth.Workload("sym", (n, n, n), h, (0.0, 0.0, 0.0))
+    xi = synth.affine_sine_field((0, 0, 0), (n, n, n), h, (0, 0, 0), c, np.eye(3), 0.0, None)
+    w.solids.append(synth.Solid((0, 0, 0), (n, n, n), synth.sphere_shape(c, 0.3), 4, xi))
+    st, out, lab, dec, stats = run_oracle(w, w.solids[0])
+    assert st == 0
+    idx = np.argwhere(np.ones((n, n, n), dtype=bool))          # (k, j, i)
+    xyz = idx[:, ::-1].astype(np.int64)                       # (i, j, k)
+    ctr = (n - 1) / 2.0
+    band = lab > 0
+    for P in cube_symmetries():
+        moved = np.rint((xyz - ctr) @ P.T + ctr).astype(np.int64)
+        lab_m = lab[moved[:, 2], moved[:, 1], moved[:, 0]]
+        assert np.array_equal(lab_m, lab[idx[:, 0], idx[:, 1], idx[:, 2]])
+        sel = band[idx[:, 0], idx[:, 1], idx[:, 2]]
+        a = out[:, idx[sel, 0], idx[sel, 1], idx[sel, 2]] - c[:, None]
+        b = out[:, moved[sel, 2], moved[sel, 1], moved[sel, 0]] - c[:, None]
+        assert np.max(np.abs(P @ a - b)) < 1e-13
+
+
+def test_second_order_accuracy():
+    """For a smooth (quadratic) xi the affine fits make the band error O(h^2)."""
+    errs = []
+    c = np.array([0.5, 0.5, 0.5])
+    for n in (16, 32, 64):
+        h = 1.0 / n
+
+        def f(x, y, z):
+            return np.stack([x + 0.3 * (x - 0.5) ** 2 + 0.2 * (y - 0.5) * (z - 0.5),
+                             y + 0.25 * (y - 0.5) ** 2, z - 0.2 * (x - 0.5) ** 2])
+        w = synth.Workload("acc", (n, n, n), h, (0.0, 0.0, 0.0))
+        w.solids.append(synth.Solid((0, 0, 0), (n, n, n), synth.sphere_shape(c, 0.3), 3, None))
+        s = w.solids[0]
+        exact = exact_field(w, s, f)
+        s.xi = exact.copy()
+        st, out, lab, dec, stats = run_oracle(w, s)
+        assert st == 0
+        errs.append(float(np.max(np.abs(out[:, lab > 0] - exact[:, lab > 0]))))
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
+def test_statuses():
+    w = synth.sphere32()
+    s = w.solids[0]
+    # truncated: a box that cuts through the band on a non-wall face
+    xi_sub = s.xi[:, 4:28, 4:28, 8:20].copy()
+    p = oracle.make_problem(w.grid_n, (8, 4, 4), (12, 24, 24), oracle_shape(s.shape), 4)
+    st, out, lab, dec, stats = oracle.extrapolate(p, xi_sub)
+    assert st == oracle.E_TRUNCATED
+    assert np.array_equal(out.view(np.uint64), xi_sub.view(np.uint64))
+    # empty: no interior cell
+    far = s.xi + 10.0
+    st, out, lab, dec, stats = run_oracle(w, synth.Solid(s.lo, s.ext, s.shape, 4, far))
+    assert st == oracle.W_EMPTY and np.all(lab == -1)
+    assert np.array_equal(out.view(np.uint64), far.view(np.uint64))
+    # L = 0: labels only
+    st, out, lab, dec, stats = run_oracle(w, s, n_layers=0)
+    assert st == 0 and set(np.unique(lab)) <= {-1, 0}
+    assert np.array_equal(out.view(np.uint64), s.xi.view(np.uint64))
+    # argument errors
+    bad = oracle.make_problem(w.grid_n, (0, 0, 0), (33, 32, 32), oracle_shape(s.shape), 4)
+    assert oracle.extrapolate(bad, np.zeros((3, 32, 32, 33)))[0] == oracle.E_BOX
+    bad = oracle.make_problem(w.grid_n, (0, 0, 0), (32, 32, 32), oracle_shape(s.shape), 17)
+    assert oracle.extrapolate(bad, s.xi)[0] == oracle.E_LAYERS
+    bad = oracle.make_problem(w.grid_n, (0, 0, 0), (32, 32, 32),
+                              oracle.make_shape(2, (0.5,) * 3, (0.1, -0.1, 0.1)), 4)
+    assert oracle.extrapolate(bad, s.xi)[0] == oracle.E_SHAPE
+
+
+def test_suspension_boxes_hold_their_bands():
+    """The generated suspension boxes contain each solid's interior and band (no
+    truncation), and every solid has interior cells."""
+    w = synth.suspension()
+    assert len(w.solids) == 40
+    for s in w.solids:
+        n_int, lab, trunc = oracle.label(oracle_problem(w, s), s.xi)
+        assert not trunc and n_int > 0
