@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the reference-map band extrapolation on one MI355X.
+
+One step = one full call of the hot path (classify, label, normals, L layer fits) over
+one synthetic workload already resident in HBM.  Default workload: the 256^3 cavity
+sphere (L = 4, FP64).  Prints ONE JSON line with throughput (band cells/s), the roofline
+of the dominant kernel (timed live with HIP events on the launch stream), the whole-call
+roofline, the CPU oracle timed on this host's cores, and the extra forms (FP32
+accumulate, batched vs per-solid suspension) under "variants".
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+PRECISIONS = {"fp64": 0, "fp32acc": 1}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def band_and_box(stats, w):
+    nb = sum(sum(s["n_band"][1:17]) for s in stats)
+    return nb, w.box_cells
+
+
+def time_calls(ctx, dw, opt, steps, warmup):
+    """Average ms per call over `steps` back-to-back calls, timed with HIP events on the
+    stream the library launches on, bracketed by device synchronisation."""
+    import torch
+    from paper_2104_00095_amd import rmx
+    arr = dw.array()
+    stream = torch.cuda.current_stream()
+    h = rmx._stream_handle(stream)
+    n = len(dw.solids)
+    for _ in range(warmup):
+        st = ctx.extrapolate_raw(dw.grid, arr, n, opt, h)
+        if st < 0:
+            raise rmx.RmxError(st, "warmup")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.extrapolate_raw(dw.grid, arr, n, opt, h)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def profile_phases(ctx, dw, opt, steps):
+    """Per-kernel average duration (ms) from HIP events around every launch."""
+    import torch
+    from paper_2104_00095_amd import rmx
+    popt = rmx.options(opt.r_s, opt.r_max, opt.normal_layers, opt.precision,
+                       (opt.flags & ~rmx.FLAG_GRAPH) | rmx.FLAG_PROFILE)
+    ctx.profile_read()
+    arr = dw.array()
+    h = rmx._stream_handle(torch.cuda.current_stream())
+    for _ in range(steps):
+        ctx.extrapolate_raw(dw.grid, arr, len(dw.solids), popt, h)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    return {k: (ms / n, n) for k, (ms, n) in prof.items()}
+
+
+def kernel_bytes(phase, w, stats):
+    """Algorithmic HBM bytes of one launch of a phase (see the design notes): classify
+    reads xi once (24 B/cell) and writes the 1-bit mask; label reads the mask and writes
+    int8 labels; a layer fit writes 24 B per band cell of its layer."""
+    cells = w.box_cells
+    if phase == "classify":
+        return 24 * cells + cells / 8
+    if phase == "label":
+        return cells / 8 + cells
+    if phase.startswith("extrap"):
+        l = int(phase[6:])
+        return 24 * sum(s["n_band"][l] for s in stats)
+    return None
+
+
+def cpu_baseline(w, seconds, r_s=2, r_max=4, normal_layers=2):
+    """The oracle as it stands, on this host's cores, on whole calls of the same workload
+    until `seconds` of CPU work have run (at least one call)."""
+    import oracle
+    from tests.helpers import run_oracle
+    cores = len(os.sched_getaffinity(0))
+    calls, band, t0 = 0, 0, time.perf_counter()
+    while True:
+        for s in w.solids:
+            st, xo, lab, dec, stats = run_oracle(w, s, r_s=r_s, r_max=r_max,
+                                                 normal_layers=normal_layers, nthreads=cores)
+            band += int(stats[1:17].sum())
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    del oracle
+    return {"value": band / el, "unit": "band cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"{calls} whole calls of {w.name} ({len(w.solids)} solid(s)), "
+                      f"{el:.1f} s wall, OpenMP threads = {cores}"}
+
+
+def make_workload(name):
+    from paper_2104_00095_amd import synth
+    if name == "cavity256":
+        return synth.cavity256()
+    if name == "ellipsoid128":
+        return synth.ellipsoid128()
+    if name == "suspension":
+        return synth.suspension()
+    if name == "sphere32":
+        return synth.sphere32()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_form(ctx, w, dw, opt, steps, warmup):
+    st, stats = ctx.extrapolate(dw.grid, dw.solids, opt)
+    nb, cells = band_and_box(stats, w)
+    ms, wall = time_calls(ctx, dw, opt, steps, warmup)
+    B = 25 * cells + 24 * nb
+    return {"ms_per_call": ms, "host_ms_per_call": wall, "band_cells": nb,
+            "band_cells_per_s": nb / (ms * 1e-3),
+            "call_hbm_frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}, stats
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cavity256")
+    ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
+    ap.add_argument("--graph", action="store_true", help="replay the launch chain as a hipGraph")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(solids are independent; the sharding design is in DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_00095_amd import fields, rmx
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    log(f"generating {args.workload}")
+    w = make_workload(args.workload)
+    dw = fields.upload(w)
+    ctx = rmx.Context(0)
+    prec = PRECISIONS[args.precision]
+    flags = rmx.FLAG_GRAPH if args.graph else 0
+    opt = rmx.options(precision=prec, flags=flags)
+    log("timing")
+    main_form, stats = run_form(ctx, w, dw, opt, args.steps, args.warmup)
+    nb, cells = band_and_box(stats, w)
+    ms = main_form["ms_per_call"]
+
+    log("profiling kernels")
+    phases = profile_phases(ctx, dw, opt, max(10, min(args.steps, 50)))
+    dom = max((k for k in phases if k != "zero"), key=lambda k: phases[k][0])
+    dom_ms = phases[dom][0]
+    dom_bytes = kernel_bytes(dom, w, stats)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+            "kernel_ms": dom_ms, "algorithmic_bytes": dom_bytes}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    B = 25 * cells + 24 * nb
+
+    variants = {}
+    if not args.no_variants:
+        log("variants")
+        other = 1 - prec
+        o2 = rmx.options(precision=other, flags=flags)
+        f2, _ = run_form(ctx, w, dw, o2, args.steps, args.warmup)
+        variants[[k for k, v in PRECISIONS.items() if v == other][0]] = f2
+        del dw
+        torch.cuda.empty_cache()
+        ws = make_workload("suspension")
+        dws = fields.upload(ws)
+        for name, fl in (("suspension_batched_graph", rmx.FLAG_GRAPH),
+                         ("suspension_batched", 0),
+                         ("suspension_per_solid", rmx.FLAG_PER_SOLID)):
+            f, _ = run_form(ctx, ws, dws, rmx.options(flags=fl), max(20, args.steps // 4), 5)
+            f["solids"] = len(ws.solids)
+            variants[name] = f
+        del dws
+        ws = make_workload("sphere32")
+        dws = fields.upload(ws)
+        for name, fl in (("sphere32_graph", rmx.FLAG_GRAPH), ("sphere32", 0)):
+            f, _ = run_form(ctx, ws, dws, rmx.options(flags=fl), args.steps, args.warmup)
+            variants[name] = f
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    out = {
+        "metric": "band cells extrapolated/s",
+        "value": nb / (ms * 1e-3),
+        "unit": "band cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(w.grid_n), "solids": len(w.solids),
+                   "n_layers": max(s.n_layers for s in w.solids), "band_cells": nb,
+                   "box_cells": cells, "precision": args.precision, "graph": args.graph},
+        "roofline": roof,
+        "call_roofline": {"bound": "hbm", "algorithmic_bytes": B,
+                          "achieved": B / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+        "kernels_ms": {k: v[0] for k, v in phases.items()},
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * rmx.h -- C ABI of the MI355X reference-map extrapolation library (librmx.so).
+ *
+ * The library extends the reference map xi of each solid from its interior cells into a
+ * narrow band of fluid cells, one layer at a time, by the weighted-least-squares (WLS)
+ * local linear fit of Lin, Derr & Rycroft, "Eulerian simulation of complex suspensions
+ * and biolocomotion in three dimensions" (arXiv 2104.00095):
+ *   - layers: main text, section "Extrapolation of xi(x,t)", first paragraph, and
+ *     Fig. 1(c): interior cells (phi < 0) are layer 0; each unmarked face neighbour of a
+ *     layer-(l-1) cell is layer l, until the grid wall or the layer count L;
+ *   - fit: same section, second paragraph: layers in ascending order, cells of a layer
+ *     independent; data are cells of the same object in lower layers within a box of
+ *     radius r_s = 2; an affine model xi(x) ~ beta [1, x] evaluated at the target; a
+ *     degenerate system grows r_s by one;
+ *   - weights: SI section "Weighting scheme for weighted least squares-based
+ *     extrapolation", eq. (weight): 2^-(|di|+|dj|+|dk|), times the non-negative cosine
+ *     between x_e - x_d and the normalised gradient of phi0(xi) for layers <= 2;
+ *   - phi(x) = phi0(xi(x)) with phi0 a signed distance in reference coordinates: main
+ *     text, section "Blurred interface method and monolithic governing equations";
+ *   - objects are extrapolated independently: same section of "Extrapolation of xi",
+ *     third paragraph.
+ * Readings where the paper is silent are fixed below and listed in the repository's
+ * design notes: interior is phi0 < 0 strictly (a square-root-free predicate); the fit is
+ * affine with an intercept, centred on the target; the search box is the Chebyshev cube
+ * |d|_inf <= r; "degenerate" means the positive-weight offsets are coplanar (exact
+ * integer test); r grows to r_max, then the normal factor is dropped (F1), then the
+ * kernel-weighted mean is used (F2); the normal is taken from the field as it is at the
+ * start of the call (or from xi_normal), by central differences of phi0(xi) over face
+ * neighbours, one-sided where a neighbour is undefined or outside the box.
+ *
+ * Memory: every array argument marked DEVICE is a device pointer on the context's GPU,
+ * owned by the caller, and must stay valid until the enqueued work has completed.  The
+ * library owns its workspace.  All functions return an int status (RMX_OK = 0, > 0
+ * warning, < 0 error).  Functions are thread-safe per context only if the caller
+ * serialises calls on one context.
+ */
+#ifndef RMX_H
+#define RMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+#define RMX_OK 0
+#define RMX_W_EMPTY 1          /* solid has no interior cell: labels all -1, xi untouched */
+#define RMX_E_ARG (-1)         /* null pointer, bad count or option out of range           */
+#define RMX_E_BOX (-2)         /* box outside the grid or empty                            */
+#define RMX_E_LAYERS (-3)      /* n_layers outside 0..RMX_MAX_LAYERS                       */
+#define RMX_E_SHAPE (-4)       /* non-positive/non-finite semi-axis, non-orthonormal rot  */
+#define RMX_E_WORKSPACE (-5)   /* fixed workspace too small for the call                   */
+#define RMX_E_HIP (-6)         /* a HIP runtime call failed                                */
+#define RMX_E_TRUNCATED (-7)   /* an interior cell lies within L of a box face that is not
+                                  a grid wall: the band would leave the box.  Labels are
+                                  written, xi is left untouched.                           */
+#define RMX_E_BUDGET (-8)      /* server: request can never fit the HBM budget             */
+#define RMX_E_BUSY (-9)        /* server: submission queue full                            */
+#define RMX_E_NOTFOUND (-10)   /* server: unknown simulation or ticket                     */
+
+#define RMX_MAX_LAYERS 16
+#define RMX_MAX_RADIUS 4
+
+enum { RMX_SPHERE = 1, RMX_ELLIPSOID = 2 };
+enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
+
+/* option flags */
+#define RMX_FLAG_SYNC 1u       /* wait for completion and return the worst device status  */
+#define RMX_FLAG_GRAPH 2u      /* capture the launch chain in a hipGraph and replay it on
+                                  later calls with identical arguments                     */
+#define RMX_FLAG_PER_SOLID 4u  /* plain form: one launch chain per solid, in order        */
+#define RMX_FLAG_PROFILE 8u    /* record HIP events around every kernel of the chain (not
+                                  with RMX_FLAG_GRAPH); read with rmx_profile_read         */
+
+/* Kernel phases reported by rmx_profile_read. */
+#define RMX_PHASE_ZERO 0
+#define RMX_PHASE_CLASSIFY 1
+#define RMX_PHASE_LABEL 2
+#define RMX_PHASE_SCAN 3
+#define RMX_PHASE_NORMAL 4
+#define RMX_PHASE_EXTRAP 5      /* + (layer - 1), layers 1..RMX_MAX_LAYERS               */
+#define RMX_N_PHASES 21
+
+/* Grid: M x N x O cells; cell (i,j,k) has centre origin + (idx + 1/2) h (SI, "Variable
+ * arrangement"; isotropic spacing as in the paper's runs).  The fit is invariant to h
+ * and origin with isotropic spacing, which are validated only. */
+typedef struct {
+    int32_t n[3];
+    double h;
+    double origin[3];
+} rmx_grid;
+
+/* phi0 in reference coordinates.  Body coordinates y = rot^T (xi - centre); rot is
+ * row-major and orthonormal (columns = body axes).  Sphere: radius semi_axes[0].
+ * Ellipsoid: semi-axes along the body axes.  phi0 is the exact signed distance. */
+typedef struct {
+    int32_t kind;
+    double centre[3];
+    double semi_axes[3];
+    double rot[9];
+} rmx_shape;
+
+/* One solid.  Its box D = [lo, lo + ext) must lie in the grid and hold the solid's
+ * interior and band.  xi is SoA [3][ext2][ext1][ext0] FP64 (x fastest); a cell with a
+ * non-finite component is undefined (never interior).  labels is [ext2][ext1][ext0]:
+ * -1 unmarked, 0 interior, 1..L band layer.  decisions (nullable) receives per cell 0
+ * (not band), r (fitted with radius r), 32 (F1), 33 (F2), plus 64 if the cell's layer
+ * uses the normal but the gradient vanished.  xi_normal (nullable) is the field the
+ * normals are taken from (same layout); NULL = xi at the start of the call. */
+typedef struct {
+    int32_t lo[3];
+    int32_t ext[3];
+    rmx_shape phi0;
+    int32_t n_layers;
+    double* xi;               /* DEVICE, in/out                                          */
+    const double* xi_normal;  /* DEVICE, in, nullable                                    */
+    int8_t* labels;           /* DEVICE, out                                             */
+    int8_t* decisions;        /* DEVICE, out, nullable                                   */
+} rmx_solid;
+
+/* r_s: search radius (paper: 2); r_max: growth cap (>= r_s, <= RMX_MAX_RADIUS);
+ * normal_layers: layers that use the normal factor (paper: 2); precision RMX_FP64 or
+ * RMX_FP32_ACCUM (FP32 gathers and moments, FP64 solve and update). */
+typedef struct {
+    int32_t r_s;
+    int32_t r_max;
+    int32_t normal_layers;
+    int32_t precision;
+    uint32_t flags;
+} rmx_options;
+
+typedef struct {
+    int64_t n_interior;
+    int64_t n_band[RMX_MAX_LAYERS + 1];   /* n_band[l], l = 1..L; n_band[0] unused      */
+    int64_t n_r_grown;                    /* cells fitted at r > r_s, or by F1/F2        */
+    int64_t n_no_normal;
+    int64_t n_f1;
+    int64_t n_f2;
+    int32_t status;                       /* RMX_OK, RMX_W_EMPTY or RMX_E_TRUNCATED      */
+    int32_t pad_;
+} rmx_solid_stats;
+
+typedef struct rmx_ctx rmx_ctx;
+typedef struct rmx_server rmx_server;
+
+/* Fill *opt with the paper's settings: r_s = 2, r_max = 4, normal_layers = 2, FP64. */
+int rmx_default_options(rmx_options* opt);
+
+/* Create a context on HIP device `device`.  workspace_bytes = 0: the workspace grows on
+ * demand (a growth frees the old workspace, which waits for the device); > 0: allocated
+ * once, and calls needing more fail with RMX_E_WORKSPACE. */
+int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out);
+int rmx_destroy(rmx_ctx* ctx);
+
+/* Workspace bytes a call with these arguments needs (about 29 bytes per box cell). */
+int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+                       const rmx_options* opt, size_t* bytes);
+
+/* Extrapolate n_solids solids, each independently, enqueued on `hip_stream` (a
+ * hipStream_t; NULL = the default stream).  Arguments are validated on the host first
+ * (nothing is enqueued on error).  All solids go through one batched launch chain unless
+ * RMX_FLAG_PER_SOLID is set.  If `stats` (HOST, n_solids entries) is non-NULL or
+ * RMX_FLAG_SYNC is set, the call waits for the stream, fills `stats` and returns the
+ * first negative per-solid status (else RMX_OK); otherwise it returns at once and the
+ * call does not allocate once the workspace suffices (graph-capturable). */
+int rmx_extrapolate(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
+                    int32_t n_solids, const rmx_options* opt, void* hip_stream,
+                    rmx_solid_stats* stats);
+
+const char* rmx_status_string(int status);
+
+/* Profiling (tracing): wait for every call made with RMX_FLAG_PROFILE since the last
+ * read, then write per phase the summed kernel time in ms (ms[RMX_N_PHASES], HOST) and
+ * the number of launches (launches[RMX_N_PHASES], HOST), and reset the sums. */
+int rmx_profile_read(rmx_ctx* ctx, double* ms, int64_t* launches);
+
+/* ---- serving ------------------------------------------------------------------------
+ * A request loop for many concurrently running simulations (object independence, main
+ * text "Extrapolation of xi", third paragraph, makes every request independent).
+ * register: the server allocates the simulation's resident fields (xi, labels) in HBM
+ *   against the budget; fill them through rmx_server_field.  Returns RMX_E_BUDGET if
+ *   the fields alone exceed the budget.
+ * submit: non-blocking; queues one extrapolation of all solids of the simulation.  A
+ *   scheduler thread admits queued requests while their workspace fits the budget left
+ *   (continuous batching: requests arriving while others run join the next launch round
+ *   as memory frees up), groups them into batched launches over `n_streams` streams.
+ * wait: blocks until the ticket completes; returns its status and latency (seconds from
+ *   submit to completion).  A request that can never fit fails with RMX_E_BUDGET alone.
+ */
+int rmx_server_create(int device, size_t hbm_budget_bytes, int32_t n_streams,
+                      rmx_server** out);
+int rmx_server_register(rmx_server* srv, const rmx_grid* grid, const rmx_solid* templ,
+                        int32_t n_solids, int64_t* sim_id);
+int rmx_server_field(rmx_server* srv, int64_t sim_id, int32_t solid, double** xi,
+                     int8_t** labels);
+int rmx_server_submit(rmx_server* srv, int64_t sim_id, const rmx_options* opt,
+                      int64_t* ticket);
+int rmx_server_wait(rmx_server* srv, int64_t ticket, rmx_solid_stats* stats,
+                    double* latency_s);
+int rmx_server_release(rmx_server* srv, int64_t sim_id);
+/* bytes currently admitted (resident fields + in-flight workspace) and the peak seen */
+int rmx_server_usage(rmx_server* srv, size_t* in_use, size_t* peak);
+int rmx_server_destroy(rmx_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMX_H */

@@ -1,0 +1,612 @@
+// Host core of librmx: argument validation, planning of one batched call, workspace,
+// the launch chain, an optional hipGraph cache, and per-solid statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "rmx.h"
+#include "rmx_core.h"
+#include "rmx_internal.h"
+
+using namespace rmx;
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+bool finite_all(const double* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// Validation and planning (shared with the server).
+// ------------------------------------------------------------------------------------
+int rmx_validate(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+                 const rmx_options* opt) {
+    if (!grid || !solids || n_solids < 1 || !opt) return RMX_E_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (grid->n[a] <= 0) return RMX_E_ARG;
+    if (!(grid->h > 0.0) || !std::isfinite(grid->h) || !finite_all(grid->origin, 3))
+        return RMX_E_ARG;
+    if (opt->r_s < 1 || opt->r_max < opt->r_s || opt->r_max > RMX_MAX_RADIUS) return RMX_E_ARG;
+    if (opt->normal_layers < 0 || opt->normal_layers > RMX_MAX_LAYERS) return RMX_E_ARG;
+    if (opt->precision != RMX_FP64 && opt->precision != RMX_FP32_ACCUM) return RMX_E_ARG;
+    for (int i = 0; i < n_solids; ++i) {
+        const rmx_solid& s = solids[i];
+        for (int a = 0; a < 3; ++a) {
+            if (s.ext[a] <= 0 || s.lo[a] < 0) return RMX_E_BOX;
+            if ((int64_t)s.lo[a] + s.ext[a] > grid->n[a]) return RMX_E_BOX;
+        }
+        const int64_t ncell = (int64_t)s.ext[0] * s.ext[1] * s.ext[2];
+        if (ncell > (int64_t)0x7fffffff - 64) return RMX_E_BOX;
+        if (s.n_layers < 0 || s.n_layers > RMX_MAX_LAYERS) return RMX_E_LAYERS;
+        if (!s.xi || !s.labels) return RMX_E_ARG;
+        const rmx_shape& sh = s.phi0;
+        if (sh.kind != RMX_SPHERE && sh.kind != RMX_ELLIPSOID) return RMX_E_SHAPE;
+        if (!finite_all(sh.centre, 3) || !finite_all(sh.rot, 9)) return RMX_E_SHAPE;
+        const int na = sh.kind == RMX_SPHERE ? 1 : 3;
+        for (int a = 0; a < na; ++a)
+            if (!(sh.semi_axes[a] > 0.0) || !std::isfinite(sh.semi_axes[a])) return RMX_E_SHAPE;
+        if (sh.kind == RMX_ELLIPSOID) {
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) {
+                    double dot = 0.0;
+                    for (int r = 0; r < 3; ++r) dot += sh.rot[r * 3 + p] * sh.rot[r * 3 + q];
+                    if (std::fabs(dot - (p == q ? 1.0 : 0.0)) > 1e-9) return RMX_E_SHAPE;
+                }
+        }
+    }
+    return RMX_OK;
+}
+
+void rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+              const rmx_options* opt, Plan* p) {
+    p->n_solids = n_solids;
+    p->solids.assign(n_solids, DevSolid{});
+    p->tile_solid.clear();
+    p->Lmax = 0;
+    int64_t words = 0, slots = 0, cells = 0;
+    int tiles = 0;
+    for (int i = 0; i < n_solids; ++i) {
+        const rmx_solid& s = solids[i];
+        DevSolid& d = p->solids[i];
+        d.n0 = s.ext[0];
+        d.n1 = s.ext[1];
+        d.n2 = s.ext[2];
+        d.W = (d.n0 + 63) / 64;
+        d.ty = (d.n1 + kTileJ - 1) / kTileJ;
+        d.tz = (d.n2 + kTileK - 1) / kTileK;
+        d.L = s.n_layers;
+        d.kind = s.phi0.kind;
+        for (int a = 0; a < 3; ++a) {
+            d.wall_lo[a] = s.lo[a] == 0;
+            d.wall_hi[a] = s.lo[a] + s.ext[a] == grid->n[a];
+        }
+        d.ncell = (int64_t)d.n0 * d.n1 * d.n2;
+        d.word_base = words;
+        d.tile_base = tiles;
+        d.slot_base = slots;
+        for (int a = 0; a < 3; ++a) d.centre[a] = s.phi0.centre[a];
+        if (s.phi0.kind == RMX_SPHERE) {
+            d.semi[0] = d.semi[1] = d.semi[2] = s.phi0.semi_axes[0];
+            for (int q = 0; q < 9; ++q) d.rot[q] = (q % 4 == 0) ? 1.0 : 0.0;
+        } else {
+            for (int a = 0; a < 3; ++a) d.semi[a] = s.phi0.semi_axes[a];
+            for (int q = 0; q < 9; ++q) d.rot[q] = s.phi0.rot[q];
+        }
+        d.xi = s.xi;
+        d.xi_normal = s.xi_normal ? s.xi_normal : s.xi;
+        d.labels = s.labels;
+        d.decisions = s.decisions;
+        const int nt = d.W * d.ty * d.tz;
+        for (int t = 0; t < nt; ++t) p->tile_solid.push_back(i);
+        words += (int64_t)d.n1 * d.n2 * d.W;
+        tiles += nt;
+        slots += (int64_t)nt * kTileCells;
+        cells += d.ncell;
+        p->Lmax = std::max(p->Lmax, d.L);
+    }
+    p->n_tiles = tiles;
+    p->total_words = words;
+    p->slot_cap = slots;
+    p->total_cells = cells;
+    p->normal_layers = std::min(opt->normal_layers, p->Lmax);
+    // Workspace layout.
+    size_t off = 0;
+    p->off_desc = off;
+    off = align256(off + sizeof(DevSolid) * n_solids);
+    p->off_tile_solid = off;
+    off = align256(off + sizeof(int32_t) * tiles);
+    p->desc_bytes = off;  // descriptors + tile table: one upload
+    p->off_stats = off;
+    off = align256(off + sizeof(unsigned long long) * kStatWords * n_solids);
+    p->off_tile_cnt = off;
+    off = align256(off + sizeof(int32_t) * kLT * (size_t)tiles);
+    p->off_tile_lstart = off;
+    off = align256(off + sizeof(int32_t) * kLT * (size_t)tiles);
+    p->off_tile_off = off;
+    off = align256(off + sizeof(int32_t) * kLT * (size_t)(tiles + 1));
+    p->off_mask = off;
+    off = align256(off + sizeof(unsigned long long) * (size_t)words);
+    p->off_slots = off;
+    off = align256(off + sizeof(int32_t) * (size_t)slots);
+    p->off_normals = off;
+    if (p->normal_layers > 0) off = align256(off + 3 * sizeof(double) * (size_t)slots);
+    p->ws_bytes = off;
+}
+
+void rmx_bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
+    char* base = static_cast<char*>(ws);
+    int64_t word = 0;
+    for (auto& d : p->solids) {
+        d.mask = reinterpret_cast<unsigned long long*>(base + p->off_mask) + word;
+        word += (int64_t)d.n1 * d.n2 * d.W;
+    }
+    b->solids = reinterpret_cast<const DevSolid*>(base + p->off_desc);
+    b->n_solids = p->n_solids;
+    b->n_tiles = p->n_tiles;
+    b->Lmax = p->Lmax;
+    b->normal_layers = p->normal_layers;
+    b->r_s = opt->r_s;
+    b->r_max = opt->r_max;
+    b->total_words = p->total_words;
+    b->slot_cap = p->slot_cap;
+    b->tile_solid = reinterpret_cast<const int32_t*>(base + p->off_tile_solid);
+    b->tile_cnt = reinterpret_cast<int32_t*>(base + p->off_tile_cnt);
+    b->tile_lstart = reinterpret_cast<int32_t*>(base + p->off_tile_lstart);
+    b->tile_off = reinterpret_cast<int32_t*>(base + p->off_tile_off);
+    b->slots = reinterpret_cast<int32_t*>(base + p->off_slots);
+    b->normals = reinterpret_cast<double*>(base + p->off_normals);
+    b->stats = reinterpret_cast<unsigned long long*>(base + p->off_stats);
+}
+
+void rmx_pack_desc(const Plan& p, void* host) {
+    char* h = static_cast<char*>(host);
+    std::memcpy(h + p.off_desc, p.solids.data(), sizeof(DevSolid) * p.n_solids);
+    std::memcpy(h + p.off_tile_solid, p.tile_solid.data(), sizeof(int32_t) * p.n_tiles);
+}
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+hipError_t Profiler::begin(int phase, hipStream_t st, Rec* r) {
+    r->phase = phase;
+    r->a = get();
+    r->b = get();
+    if (!r->a || !r->b) return hipErrorOutOfMemory;
+    return hipEventRecord(r->a, st);
+}
+
+hipError_t Profiler::end(Rec& r, hipStream_t st) {
+    hipError_t e = hipEventRecord(r.b, st);
+    pending.push_back(r);
+    return e;
+}
+
+hipError_t Profiler::drain() {
+    hipError_t err = hipSuccess;
+    for (auto& r : pending) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess) err = e;
+        ms[r.phase] += t;
+        launches[r.phase] += 1;
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    pending.clear();
+    return err;
+}
+
+Profiler::~Profiler() {
+    (void)drain();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+// The kernels of one batched call, in stream order.  Nothing here allocates or
+// synchronises, so the sequence can be captured into a graph.  With a profiler, each
+// launch is bracketed by HIP events on the same stream.
+hipError_t rmx_enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,
+                       Profiler* prof) {
+    hipError_t e;
+    Profiler::Rec rec{};
+#define RMX_TIMED(phase, call)                                              \
+    do {                                                                    \
+        if (prof && (e = prof->begin((phase), st, &rec)) != hipSuccess) return e; \
+        if ((e = (call)) != hipSuccess) return e;                            \
+        if (prof && (e = prof->end(rec, st)) != hipSuccess) return e;        \
+    } while (0)
+    RMX_TIMED(RMX_PHASE_ZERO, launch_zero(b.stats, (int64_t)kStatWords * p.n_solids, st));
+    RMX_TIMED(RMX_PHASE_CLASSIFY, launch_classify(b, st));
+    RMX_TIMED(RMX_PHASE_LABEL, launch_label(b, st));
+    if (p.Lmax == 0) return hipSuccess;
+    RMX_TIMED(RMX_PHASE_SCAN, launch_scan(b, st));
+    // Band cells of one layer: a thin shell; the kernels stride over the true count.
+    const int64_t est = std::max<int64_t>(4096, p.total_cells / 8);
+    if (p.normal_layers > 0)
+        RMX_TIMED(RMX_PHASE_NORMAL, launch_normal(b, est * p.normal_layers, st));
+    for (int l = 1; l <= p.Lmax; ++l)
+        RMX_TIMED(RMX_PHASE_EXTRAP + l - 1, launch_extrap(b, l, precision, est, st));
+#undef RMX_TIMED
+    return hipSuccess;
+}
+
+void rmx_convert_stats(const unsigned long long* dev, int n, rmx_solid_stats* out) {
+    for (int i = 0; i < n; ++i) {
+        const unsigned long long* s = dev + (size_t)i * kStatWords;
+        rmx_solid_stats& o = out[i];
+        std::memset(&o, 0, sizeof(o));
+        o.n_interior = (int64_t)s[ST_INTERIOR];
+        for (int l = 1; l <= RMX_MAX_LAYERS; ++l) o.n_band[l] = (int64_t)s[l];
+        o.n_r_grown = (int64_t)s[ST_GROWN];
+        o.n_no_normal = (int64_t)s[ST_NONORMAL];
+        o.n_f1 = (int64_t)s[ST_F1];
+        o.n_f2 = (int64_t)s[ST_F2];
+        if (s[ST_FLAGS] & FLAG_TRUNCATED)
+            o.status = RMX_E_TRUNCATED;
+        else if (o.n_interior == 0)
+            o.status = RMX_W_EMPTY;
+        else
+            o.status = RMX_OK;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Context.
+// ------------------------------------------------------------------------------------
+namespace {
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* ws_base = nullptr;
+};
+
+struct Staging {
+    void* host = nullptr;
+    size_t size = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+}  // namespace
+
+struct rmx_ctx {
+    int device = 0;
+    bool fixed = false;
+    void* ws = nullptr;
+    size_t ws_size = 0;
+    static constexpr int kRing = 4;
+    Staging stage[kRing];
+    int stage_next = 0;
+    unsigned long long* stats_host = nullptr;
+    size_t stats_host_n = 0;
+    hipStream_t capture_stream = nullptr;
+    std::unordered_map<uint64_t, GraphEntry> graphs;
+    std::vector<rmx_solid_stats> tmp_stats;
+    Profiler prof;
+};
+
+namespace {
+
+void drop_graphs(rmx_ctx* c) {
+    for (auto& kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    c->graphs.clear();
+}
+
+int ensure_ws(rmx_ctx* c, size_t need) {
+    if (need <= c->ws_size) return RMX_OK;
+    if (c->fixed) return RMX_E_WORKSPACE;
+    if (c->ws) {
+        if (hipDeviceSynchronize() != hipSuccess) return RMX_E_HIP;
+        drop_graphs(c);
+        (void)hipFree(c->ws);
+        c->ws = nullptr;
+        c->ws_size = 0;
+    }
+    const size_t sz = need + need / 4;
+    if (hipMalloc(&c->ws, sz) != hipSuccess) {
+        c->ws = nullptr;
+        return RMX_E_HIP;
+    }
+    c->ws_size = sz;
+    return RMX_OK;
+}
+
+// Pinned staging buffer for the descriptor upload; waits if the slot's previous copy is
+// still in flight.
+int get_stage(rmx_ctx* c, size_t bytes, Staging** out) {
+    Staging& s = c->stage[c->stage_next];
+    c->stage_next = (c->stage_next + 1) % rmx_ctx::kRing;
+    if (s.pending) {
+        if (hipEventSynchronize(s.ev) != hipSuccess) return RMX_E_HIP;
+        s.pending = false;
+    }
+    if (s.size < bytes) {
+        if (s.host) (void)hipHostFree(s.host);
+        s.host = nullptr;
+        const size_t sz = std::max<size_t>(bytes, 1 << 16);
+        if (hipHostMalloc(&s.host, sz, hipHostMallocDefault) != hipSuccess) {
+            s.host = nullptr;
+            s.size = 0;
+            return RMX_E_HIP;
+        }
+        s.size = sz;
+    }
+    *out = &s;
+    return RMX_OK;
+}
+
+int ensure_stats_host(rmx_ctx* c, size_t n) {
+    if (c->stats_host_n >= n) return RMX_OK;
+    if (c->stats_host) (void)hipHostFree(c->stats_host);
+    c->stats_host = nullptr;
+    if (hipHostMalloc((void**)&c->stats_host, n * sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess) {
+        c->stats_host_n = 0;
+        return RMX_E_HIP;
+    }
+    c->stats_host_n = n;
+    return RMX_OK;
+}
+
+uint64_t call_key(const rmx_grid* g, const rmx_solid* s, int n, const rmx_options* o) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(g, sizeof(*g), h);
+    h = fnv1a(s, sizeof(*s) * (size_t)n, h);
+    rmx_options oo = *o;
+    oo.flags &= RMX_FLAG_PER_SOLID;
+    h = fnv1a(&oo, sizeof(oo), h);
+    return h;
+}
+
+// One batched call (all of `solids`) enqueued on `st`.
+int run_batch(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int n,
+              const rmx_options* opt, hipStream_t st, bool use_graph, size_t stats_off,
+              bool want_stats) {
+    Plan p;
+    rmx_plan(grid, solids, n, opt, &p);
+    int rc = ensure_ws(c, p.ws_bytes);
+    if (rc != RMX_OK) return rc;
+    Batch b{};
+    rmx_bind(&p, c->ws, opt, &b);
+
+    if (use_graph) {
+        const uint64_t key = call_key(grid, solids, n, opt);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end() || it->second.ws_base != c->ws) {
+            if (it != c->graphs.end()) {
+                (void)hipGraphExecDestroy(it->second.exec);
+                (void)hipGraphDestroy(it->second.graph);
+                c->graphs.erase(it);
+            }
+            // Descriptors live in the workspace; a graph replays with the same workspace,
+            // so they are written once, synchronously, before capture.
+            std::vector<char> host(p.desc_bytes);
+            rmx_pack_desc(p, host.data());
+            if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
+            if (hipMemcpy(c->ws, host.data(), p.desc_bytes, hipMemcpyHostToDevice) != hipSuccess)
+                return RMX_E_HIP;
+            GraphEntry ge;
+            ge.ws_base = c->ws;
+            if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) !=
+                hipSuccess)
+                return RMX_E_HIP;
+            hipError_t e = rmx_enqueue(p, b, opt->precision, c->capture_stream);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
+            if (e != hipSuccess || e2 != hipSuccess || !graph) return RMX_E_HIP;
+            ge.graph = graph;
+            if (hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return RMX_E_HIP;
+            }
+            it = c->graphs.emplace(key, ge).first;
+        }
+        if (hipGraphLaunch(it->second.exec, st) != hipSuccess) return RMX_E_HIP;
+    } else {
+        Staging* sg = nullptr;
+        rc = get_stage(c, p.desc_bytes, &sg);
+        if (rc != RMX_OK) return rc;
+        rmx_pack_desc(p, sg->host);
+        if (hipMemcpyAsync(c->ws, sg->host, p.desc_bytes, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+            return RMX_E_HIP;
+        if (hipEventRecord(sg->ev, st) != hipSuccess) return RMX_E_HIP;
+        sg->pending = true;
+        Profiler* prof = (opt->flags & RMX_FLAG_PROFILE) ? &c->prof : nullptr;
+        if (rmx_enqueue(p, b, opt->precision, st, prof) != hipSuccess) return RMX_E_HIP;
+    }
+    if (want_stats) {
+        if (hipMemcpyAsync(c->stats_host + stats_off, b.stats,
+                           sizeof(unsigned long long) * kStatWords * n, hipMemcpyDeviceToHost,
+                           st) != hipSuccess)
+            return RMX_E_HIP;
+    }
+    return RMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmx_default_options(rmx_options* opt) {
+    if (!opt) return RMX_E_ARG;
+    opt->r_s = 2;
+    opt->r_max = 4;
+    opt->normal_layers = 2;
+    opt->precision = RMX_FP64;
+    opt->flags = 0;
+    return RMX_OK;
+}
+
+int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out) {
+    if (!out) return RMX_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RMX_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return RMX_E_HIP;
+    rmx_ctx* c = new rmx_ctx();
+    c->device = device;
+    for (auto& s : c->stage)
+        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
+            rmx_destroy(c);
+            return RMX_E_HIP;
+        }
+    if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        rmx_destroy(c);
+        return RMX_E_HIP;
+    }
+    if (workspace_bytes > 0) {
+        if (hipMalloc(&c->ws, workspace_bytes) != hipSuccess) {
+            c->ws = nullptr;
+            rmx_destroy(c);
+            return RMX_E_HIP;
+        }
+        c->ws_size = workspace_bytes;
+        c->fixed = true;
+    }
+    *out = c;
+    return RMX_OK;
+}
+
+int rmx_destroy(rmx_ctx* c) {
+    if (!c) return RMX_E_ARG;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    drop_graphs(c);
+    for (auto& s : c->stage) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+    }
+    if (c->stats_host) (void)hipHostFree(c->stats_host);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->ws) (void)hipFree(c->ws);
+    delete c;
+    return RMX_OK;
+}
+
+int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+                       const rmx_options* opt, size_t* bytes) {
+    rmx_options def;
+    rmx_default_options(&def);
+    if (!opt) opt = &def;
+    if (!bytes) return RMX_E_ARG;
+    const int v = rmx_validate(grid, solids, n_solids, opt);
+    if (v != RMX_OK) return v;
+    size_t total = 0;
+    if (opt->flags & RMX_FLAG_PER_SOLID) {
+        for (int i = 0; i < n_solids; ++i) {
+            Plan p;
+            rmx_plan(grid, solids + i, 1, opt, &p);
+            total = std::max(total, p.ws_bytes);
+        }
+    } else {
+        Plan p;
+        rmx_plan(grid, solids, n_solids, opt, &p);
+        total = p.ws_bytes;
+    }
+    *bytes = total;
+    return RMX_OK;
+}
+
+int rmx_extrapolate(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
+                    int32_t n_solids, const rmx_options* opt, void* hip_stream,
+                    rmx_solid_stats* stats) {
+    if (!c) return RMX_E_ARG;
+    rmx_options def;
+    rmx_default_options(&def);
+    if (!opt) opt = &def;
+    int rc = rmx_validate(grid, solids, n_solids, opt);
+    if (rc != RMX_OK) return rc;
+    if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const bool sync = stats || (opt->flags & RMX_FLAG_SYNC);
+    const bool use_graph = (opt->flags & RMX_FLAG_GRAPH) != 0;
+    if (sync) {
+        rc = ensure_stats_host(c, (size_t)kStatWords * n_solids);
+        if (rc != RMX_OK) return rc;
+    }
+    if (opt->flags & RMX_FLAG_PER_SOLID) {
+        for (int i = 0; i < n_solids; ++i) {
+            rc = run_batch(c, grid, solids + i, 1, opt, st, use_graph,
+                           (size_t)kStatWords * i, sync);
+            if (rc != RMX_OK) return rc;
+        }
+    } else {
+        rc = run_batch(c, grid, solids, n_solids, opt, st, use_graph, 0, sync);
+        if (rc != RMX_OK) return rc;
+    }
+    if (!sync) return RMX_OK;
+    if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
+    c->tmp_stats.resize(n_solids);
+    rmx_convert_stats(c->stats_host, n_solids, c->tmp_stats.data());
+    if (stats) std::memcpy(stats, c->tmp_stats.data(), sizeof(rmx_solid_stats) * n_solids);
+    for (int i = 0; i < n_solids; ++i)
+        if (c->tmp_stats[i].status < 0) return c->tmp_stats[i].status;
+    return RMX_OK;
+}
+
+int rmx_profile_read(rmx_ctx* c, double* ms, int64_t* launches) {
+    if (!c) return RMX_E_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
+    const hipError_t e = c->prof.drain();
+    for (int i = 0; i < RMX_N_PHASES; ++i) {
+        if (ms) ms[i] = c->prof.ms[i];
+        if (launches) launches[i] = c->prof.launches[i];
+        c->prof.ms[i] = 0.0;
+        c->prof.launches[i] = 0;
+    }
+    return e == hipSuccess ? RMX_OK : RMX_E_HIP;
+}
+
+const char* rmx_status_string(int s) {
+    switch (s) {
+        case RMX_OK: return "ok";
+        case RMX_W_EMPTY: return "no interior cell";
+        case RMX_E_ARG: return "invalid argument";
+        case RMX_E_BOX: return "box outside the grid";
+        case RMX_E_LAYERS: return "layer count out of range";
+        case RMX_E_SHAPE: return "invalid shape";
+        case RMX_E_WORKSPACE: return "workspace too small";
+        case RMX_E_HIP: return "HIP runtime error";
+        case RMX_E_TRUNCATED: return "band truncated by the box";
+        case RMX_E_BUDGET: return "request exceeds the HBM budget";
+        case RMX_E_BUSY: return "queue full";
+        case RMX_E_NOTFOUND: return "not found";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Internal layout shared by the host core and the HIP kernels of librmx.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmx {
+
+constexpr int kMaxLayers = 16;
+constexpr int kMaxRadius = 4;
+constexpr int kLT = kMaxLayers + 1;          // per-tile layer table stride
+constexpr int kTileJ = 16;                   // rows of a label tile along y
+constexpr int kTileK = 16;                   // rows of a label tile along z
+constexpr int kTileCells = 64 * kTileJ * kTileK;  // one 64-cell mask word along x
+
+// Per-solid device statistics (int64 words).
+constexpr int kStatWords = 24;
+constexpr int ST_INTERIOR = 0;  // 1..16: band cells of layer l
+constexpr int ST_GROWN = 17;
+constexpr int ST_NONORMAL = 18;
+constexpr int ST_F1 = 19;
+constexpr int ST_F2 = 20;
+constexpr int ST_FLAGS = 21;
+constexpr unsigned long long FLAG_TRUNCATED = 1ull;
+
+constexpr int kDecF1 = 32;
+constexpr int kDecF2 = 33;
+constexpr int kDecNoNormal = 64;
+
+// One solid as the kernels see it.
+struct DevSolid {
+    int32_t n0, n1, n2;      // box extents (x fastest)
+    int32_t W;               // 64-cell mask words per row
+    int32_t ty, tz;          // label tiles along y and z
+    int32_t L;               // layers
+    int32_t kind;            // 1 sphere, 2 ellipsoid
+    int32_t wall_lo[3];      // 1 if the low face along the axis is a grid wall
+    int32_t wall_hi[3];
+    int32_t tile_base;       // first global tile index of the solid
+    int32_t pad0;
+    int64_t ncell;
+    int64_t word_base;       // first global mask word
+    int64_t slot_base;       // first slot in the slot buffer
+    double centre[3];
+    double semi[3];
+    double rot[9];
+    double* xi;
+    const double* xi_normal; // field the normals come from (xi if none given)
+    int8_t* labels;
+    int8_t* decisions;       // nullable
+    unsigned long long* mask;  // [n2 * n1][W]
+};
+
+// Device tables of one batched call (all in the workspace).
+struct Batch {
+    const DevSolid* solids;
+    int32_t n_solids;
+    int32_t n_tiles;
+    int32_t Lmax;
+    int32_t normal_layers;
+    int32_t r_s, r_max;
+    int32_t pad0, pad1;
+    int64_t total_words;
+    int64_t slot_cap;        // slot capacity (n_tiles * kTileCells)
+    const int32_t* tile_solid;  // [n_tiles]
+    int32_t* tile_cnt;       // [n_tiles][kLT] cells of layer l in the tile
+    int32_t* tile_lstart;    // [n_tiles][kLT] first slot of layer l within the tile
+    int32_t* tile_off;       // [kLT][n_tiles + 1] exclusive prefix over tiles, per layer
+    int32_t* slots;          // [slot_cap] linear cell index within the solid's box
+    double* normals;         // [3][slot_cap] unnormalised gradient of phi0(xi)
+    unsigned long long* stats;  // [n_solids][kStatWords]
+};
+
+// Launchers (rmx_kernels.hip).
+hipError_t launch_zero(unsigned long long* p, int64_t n, hipStream_t st);
+hipError_t launch_classify(const Batch& b, hipStream_t st);
+hipError_t launch_label(const Batch& b, hipStream_t st);
+hipError_t launch_scan(const Batch& b, hipStream_t st);
+hipError_t launch_normal(const Batch& b, int64_t max_cells, hipStream_t st);
+hipError_t launch_extrap(const Batch& b, int layer, int precision, int64_t max_cells,
+                         hipStream_t st);
+
+}  // namespace rmx

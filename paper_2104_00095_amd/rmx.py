@@ -1,0 +1,301 @@
+"""Thin ctypes binding of librmx.so (include/rmx.h).
+
+Argument marshalling only: every step of the extrapolation runs in the HIP library.
+Device buffers are torch tensors on a ROCm device (PyTorch provides memory and streams).
+The library is loaded from this package directory; if it is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmx.so")
+
+OK, W_EMPTY = 0, 1
+E_ARG, E_BOX, E_LAYERS, E_SHAPE, E_WORKSPACE, E_HIP = -1, -2, -3, -4, -5, -6
+E_TRUNCATED, E_BUDGET, E_BUSY, E_NOTFOUND = -7, -8, -9, -10
+SPHERE, ELLIPSOID = 1, 2
+FP64, FP32_ACCUM = 0, 1
+FLAG_SYNC, FLAG_GRAPH, FLAG_PER_SOLID, FLAG_PROFILE = 1, 2, 4, 8
+N_PHASES = 21
+PHASES = ["zero", "classify", "label", "scan", "normal"] + [f"extrap{l}" for l in range(1, 17)]
+MAX_LAYERS = 16
+DEC_F1, DEC_F2, DEC_NO_NORMAL = 32, 33, 64
+
+EXPORTS = [
+    "rmx_default_options", "rmx_create", "rmx_destroy", "rmx_workspace_size",
+    "rmx_extrapolate", "rmx_status_string", "rmx_server_create", "rmx_server_register",
+    "rmx_server_field", "rmx_server_submit", "rmx_server_wait", "rmx_server_release",
+    "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read",
+]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double),
+                ("origin", ctypes.c_double * 3)]
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("centre", ctypes.c_double * 3),
+                ("semi_axes", ctypes.c_double * 3), ("rot", ctypes.c_double * 9)]
+
+
+class Solid(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("ext", ctypes.c_int32 * 3), ("phi0", Shape),
+                ("n_layers", ctypes.c_int32), ("xi", ctypes.c_void_p),
+                ("xi_normal", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("decisions", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("r_s", ctypes.c_int32), ("r_max", ctypes.c_int32),
+                ("normal_layers", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class SolidStats(ctypes.Structure):
+    _fields_ = [("n_interior", ctypes.c_int64), ("n_band", ctypes.c_int64 * (MAX_LAYERS + 1)),
+                ("n_r_grown", ctypes.c_int64), ("n_no_normal", ctypes.c_int64),
+                ("n_f1", ctypes.c_int64), ("n_f2", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"n_interior": self.n_interior, "n_band": list(self.n_band),
+                "n_r_grown": self.n_r_grown, "n_no_normal": self.n_no_normal,
+                "n_f1": self.n_f1, "n_f2": self.n_f2, "status": self.status}
+
+
+class RmxError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: rmx status {status} ({status_string(status)})")
+
+
+_lib = None
+
+
+def lib():
+    """Load librmx.so; raise loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"librmx.so not found at {LIB_PATH}; build it with "
+                               "`python -m paper_2104_00095_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.rmx_default_options.argtypes = [P(Options)]
+        L.rmx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, P(vp)]
+        L.rmx_destroy.argtypes = [vp]
+        L.rmx_workspace_size.argtypes = [P(Grid), P(Solid), ctypes.c_int32, P(Options),
+                                         P(ctypes.c_size_t)]
+        L.rmx_extrapolate.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, P(Options), vp,
+                                      P(SolidStats)]
+        L.rmx_status_string.argtypes = [ctypes.c_int]
+        L.rmx_status_string.restype = ctypes.c_char_p
+        L.rmx_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32, P(vp)]
+        L.rmx_server_register.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32,
+                                          P(ctypes.c_int64)]
+        L.rmx_server_field.argtypes = [vp, ctypes.c_int64, ctypes.c_int32,
+                                       P(P(ctypes.c_double)), P(P(ctypes.c_int8))]
+        L.rmx_server_submit.argtypes = [vp, ctypes.c_int64, P(Options), P(ctypes.c_int64)]
+        L.rmx_server_wait.argtypes = [vp, ctypes.c_int64, P(SolidStats), P(ctypes.c_double)]
+        L.rmx_server_release.argtypes = [vp, ctypes.c_int64]
+        L.rmx_server_usage.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
+        L.rmx_server_destroy.argtypes = [vp]
+        L.rmx_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+        for name in EXPORTS:
+            if name != "rmx_status_string":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    try:
+        return lib().rmx_status_string(int(st)).decode()
+    except Exception:  # noqa: BLE001 - only used for messages
+        return "?"
+
+
+def options(r_s=2, r_max=4, normal_layers=2, precision=FP64, flags=0) -> Options:
+    o = Options()
+    o.r_s, o.r_max, o.normal_layers, o.precision, o.flags = (
+        int(r_s), int(r_max), int(normal_layers), int(precision), int(flags))
+    return o
+
+
+def grid(n, h, origin=(0.0, 0.0, 0.0)) -> Grid:
+    g = Grid()
+    g.n[:] = [int(v) for v in n]
+    g.h = float(h)
+    g.origin[:] = [float(v) for v in origin]
+    return g
+
+
+def shape(kind, centre, semi, rot=None) -> Shape:
+    s = Shape()
+    s.kind = int(kind)
+    s.centre[:] = [float(v) for v in centre]
+    semi = list(semi) + [0.0] * (3 - len(semi))
+    s.semi_axes[:] = [float(v) for v in semi[:3]]
+    flat = [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
+    if rot is not None:
+        flat = [float(v) for v in (rot.reshape(-1) if hasattr(rot, "reshape") else rot)]
+    s.rot[:] = flat
+    return s
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+def solid(lo, ext, shp: Shape, n_layers, xi, labels, xi_normal=None, decisions=None) -> Solid:
+    """xi: cuda float64 [3, ext2, ext1, ext0]; labels: cuda int8 [ext2, ext1, ext0]."""
+    e = tuple(int(v) for v in ext)
+    assert tuple(xi.shape) == (3, e[2], e[1], e[0]) and xi.is_contiguous(), xi.shape
+    assert tuple(labels.shape) == (e[2], e[1], e[0]) and labels.is_contiguous()
+    s = Solid()
+    s.lo[:] = [int(v) for v in lo]
+    s.ext[:] = list(e)
+    s.phi0 = shp
+    s.n_layers = int(n_layers)
+    s.xi = _ptr(xi)
+    s.xi_normal = _ptr(xi_normal)
+    s.labels = _ptr(labels)
+    s.decisions = _ptr(decisions)
+    # keep the tensors alive with the descriptor
+    s._keep = (xi, labels, xi_normal, decisions)
+    return s
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Context:
+    """An rmx context on one device (workspace, graph cache)."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
+        self.h = ctypes.c_void_p()
+        st = lib().rmx_create(int(device), int(workspace_bytes), ctypes.byref(self.h))
+        if st != OK:
+            raise RmxError(st, "rmx_create")
+
+    def close(self):
+        if self.h:
+            lib().rmx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def workspace_size(self, g: Grid, solids: Sequence[Solid], opt: Optional[Options] = None):
+        arr = (Solid * len(solids))(*solids)
+        n = ctypes.c_size_t(0)
+        st = lib().rmx_workspace_size(ctypes.byref(g), arr, len(solids),
+                                      ctypes.byref(opt) if opt else None, ctypes.byref(n))
+        if st != OK:
+            raise RmxError(st, "rmx_workspace_size")
+        return int(n.value)
+
+    def extrapolate(self, g: Grid, solids: Sequence[Solid], opt: Optional[Options] = None,
+                    stream=None, want_stats: bool = True, check: bool = True):
+        """Run one call; returns (status, [stats dict per solid] or None)."""
+        arr = (Solid * len(solids))(*solids)
+        stats = (SolidStats * len(solids))() if want_stats else None
+        st = lib().rmx_extrapolate(self.h, ctypes.byref(g), arr, len(solids),
+                                   ctypes.byref(opt) if opt else None, _stream_handle(stream),
+                                   stats)
+        if check and st < 0 and st != E_TRUNCATED:
+            raise RmxError(st, "rmx_extrapolate")
+        return st, ([s.as_dict() for s in stats] if want_stats else None)
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} for the profiled calls since the last read."""
+        ms = (ctypes.c_double * N_PHASES)()
+        n = (ctypes.c_int64 * N_PHASES)()
+        st = lib().rmx_profile_read(self.h, ms, n)
+        if st != OK:
+            raise RmxError(st, "rmx_profile_read")
+        return {PHASES[i]: (ms[i], n[i]) for i in range(N_PHASES) if n[i]}
+
+    def extrapolate_raw(self, g: Grid, arr, n: int, opt: Options, stream_handle):
+        """Minimal-overhead call for timing loops: prebuilt Solid array, no stats."""
+        return lib().rmx_extrapolate(self.h, ctypes.byref(g), arr, n, ctypes.byref(opt),
+                                     stream_handle, None)
+
+
+class Server:
+    """Request loop admitting extrapolation jobs by HBM budget (rmx_server_*)."""
+
+    def __init__(self, device: int, hbm_budget_bytes: int, n_streams: int = 4):
+        self.h = ctypes.c_void_p()
+        st = lib().rmx_server_create(int(device), int(hbm_budget_bytes), int(n_streams),
+                                     ctypes.byref(self.h))
+        if st != OK:
+            raise RmxError(st, "rmx_server_create")
+
+    def close(self):
+        if self.h:
+            lib().rmx_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def register(self, g: Grid, templ: Sequence[Solid]) -> int:
+        arr = (Solid * len(templ))(*templ)
+        sid = ctypes.c_int64(-1)
+        st = lib().rmx_server_register(self.h, ctypes.byref(g), arr, len(templ),
+                                       ctypes.byref(sid))
+        if st != OK:
+            raise RmxError(st, "rmx_server_register")
+        return int(sid.value)
+
+    def field(self, sim_id: int, solid_idx: int):
+        xi = ctypes.POINTER(ctypes.c_double)()
+        lab = ctypes.POINTER(ctypes.c_int8)()
+        st = lib().rmx_server_field(self.h, int(sim_id), int(solid_idx), ctypes.byref(xi),
+                                    ctypes.byref(lab))
+        if st != OK:
+            raise RmxError(st, "rmx_server_field")
+        return ctypes.cast(xi, ctypes.c_void_p).value, ctypes.cast(lab, ctypes.c_void_p).value
+
+    def submit(self, sim_id: int, opt: Optional[Options] = None) -> int:
+        t = ctypes.c_int64(-1)
+        st = lib().rmx_server_submit(self.h, int(sim_id), ctypes.byref(opt) if opt else None,
+                                     ctypes.byref(t))
+        if st != OK:
+            raise RmxError(st, "rmx_server_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int, n_solids: int = 0):
+        stats = (SolidStats * max(1, n_solids))() if n_solids else None
+        lat = ctypes.c_double(0.0)
+        st = lib().rmx_server_wait(self.h, int(ticket), stats, ctypes.byref(lat))
+        return st, float(lat.value), ([s.as_dict() for s in stats] if n_solids else None)
+
+    def release(self, sim_id: int):
+        st = lib().rmx_server_release(self.h, int(sim_id))
+        if st != OK:
+            raise RmxError(st, "rmx_server_release")
+
+    def usage(self):
+        a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        lib().rmx_server_usage(self.h, ctypes.byref(a), ctypes.byref(b))
+        return int(a.value), int(b.value)

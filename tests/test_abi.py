@@ -1,0 +1,114 @@
+"""The C-ABI library loads, exports every function include/rmx.h declares, its structs
+match the binding's layout, and host-side validation rejects bad arguments (no GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2104_00095_amd import rmx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rmx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(rmx_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    L = rmx.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(rmx.EXPORTS) == names
+    out = subprocess.check_output(["nm", "-D", "--defined-only", rmx.LIB_PATH]).decode()
+    for n in names:
+        assert re.search(r"\bT " + n + r"\b", out), n
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "rmx.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rmx_grid), sizeof(rmx_shape), sizeof(rmx_solid),
+         sizeof(rmx_options), sizeof(rmx_solid_stats));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(rmx_solid, phi0), offsetof(rmx_solid, xi),
+         offsetof(rmx_solid, decisions), offsetof(rmx_solid_stats, status),
+         offsetof(rmx_shape, rot));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    a = subprocess.check_output([str(exe)]).decode().split()
+    want = [ctypes.sizeof(rmx.Grid), ctypes.sizeof(rmx.Shape), ctypes.sizeof(rmx.Solid),
+            ctypes.sizeof(rmx.Options), ctypes.sizeof(rmx.SolidStats),
+            rmx.Solid.phi0.offset, rmx.Solid.xi.offset, rmx.Solid.decisions.offset,
+            rmx.SolidStats.status.offset, rmx.Shape.rot.offset]
+    assert [int(v) for v in a] == want
+
+
+def _desc(ext=(32, 32, 32), lo=(0, 0, 0), L=4, kind=1, semi=(0.25,), rot=None):
+    s = rmx.Solid()
+    s.lo[:] = list(lo)
+    s.ext[:] = list(ext)
+    s.phi0 = rmx.shape(kind, (0.5, 0.5, 0.5), semi, rot)
+    s.n_layers = L
+    s.xi = 4096        # never dereferenced: workspace sizing is host-only
+    s.labels = 4096
+    return s
+
+
+def _ws(grid, solids, opt=None):
+    arr = (rmx.Solid * len(solids))(*solids)
+    n = ctypes.c_size_t(0)
+    st = rmx.lib().rmx_workspace_size(ctypes.byref(grid), arr, len(solids),
+                                      ctypes.byref(opt) if opt else None, ctypes.byref(n))
+    return st, n.value
+
+
+def test_host_validation():
+    g = rmx.grid((32, 32, 32), 1 / 32)
+    st, n = _ws(g, [_desc()])
+    assert st == rmx.OK and n > 32 ** 3 * 4
+    assert _ws(g, [_desc(ext=(33, 32, 32))])[0] == rmx.E_BOX
+    assert _ws(g, [_desc(lo=(1, 0, 0))])[0] == rmx.E_BOX
+    assert _ws(g, [_desc(ext=(0, 32, 32))])[0] == rmx.E_BOX
+    assert _ws(g, [_desc(L=17)])[0] == rmx.E_LAYERS
+    assert _ws(g, [_desc(L=-1)])[0] == rmx.E_LAYERS
+    assert _ws(g, [_desc(kind=3)])[0] == rmx.E_SHAPE
+    assert _ws(g, [_desc(semi=(-0.1,))])[0] == rmx.E_SHAPE
+    assert _ws(g, [_desc(kind=2, semi=(0.1, 0.2, 0.0))])[0] == rmx.E_SHAPE
+    assert _ws(g, [_desc(kind=2, semi=(0.1, 0.2, 0.3), rot=[1, 0, 0, 0, 1, 0, 0, 0, 2])])[0] \
+        == rmx.E_SHAPE
+    assert _ws(g, [_desc(kind=2, semi=(0.1, 0.2, 0.3), rot=[0, 1, 0, 1, 0, 0, 0, 0, 1])])[0] \
+        == rmx.OK
+    d = _desc()
+    d.labels = None
+    assert _ws(g, [d])[0] == rmx.E_ARG
+    assert _ws(g, [_desc()], rmx.options(r_s=3, r_max=2))[0] == rmx.E_ARG
+    assert _ws(g, [_desc()], rmx.options(r_max=5))[0] == rmx.E_ARG
+    assert _ws(g, [_desc()], rmx.options(precision=2))[0] == rmx.E_ARG
+    assert _ws(rmx.grid((32, 32, 32), 0.0), [_desc()])[0] == rmx.E_ARG
+    # batched workspace covers every solid; the per-solid form needs only the largest
+    two = [_desc(), _desc(ext=(16, 16, 16))]
+    st_b, nb = _ws(g, two)
+    st_p, np_ = _ws(g, two, rmx.options(flags=rmx.FLAG_PER_SOLID))
+    assert st_b == st_p == rmx.OK and nb > np_ >= n
+
+
+def test_null_context_and_status_strings():
+    L = rmx.lib()
+    g = rmx.grid((32, 32, 32), 1 / 32)
+    d = _desc()
+    assert L.rmx_extrapolate(None, ctypes.byref(g), ctypes.byref(d), 1, None, None, None) \
+        == rmx.E_ARG
+    assert rmx.status_string(rmx.E_TRUNCATED) == "band truncated by the box"
+    assert rmx.status_string(0) == "ok"
