@@ -20,6 +20,9 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Sizing without a device: the largest label tile (most slot padding).
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
 uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
     const unsigned char* c = static_cast<const unsigned char*>(p);
     for (size_t i = 0; i < n; ++i) {
@@ -78,14 +81,26 @@ int rmx_validate(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids
     return RMX_OK;
 }
 
-void rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
-              const rmx_options* opt, Plan* p) {
+int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+             const rmx_options* opt, size_t lds_limit, Plan* p) {
     p->n_solids = n_solids;
     p->solids.assign(n_solids, DevSolid{});
     p->tile_solid.clear();
     p->Lmax = 0;
+    int Wmax = 1;
+    for (int i = 0; i < n_solids; ++i) {
+        p->Lmax = std::max(p->Lmax, solids[i].n_layers);
+        Wmax = std::max(Wmax, (solids[i].ext[0] + 63) / 64);
+    }
+    // Label tile width: as many 64-cell words as fit the LDS limit (at most 4).
+    int tw = std::min(4, Wmax);
+    while (tw > 1 && label_lds_bytes(p->Lmax, tw, Wmax) > lds_limit) tw = tw > 2 ? 2 : 1;
+    p->lds_bytes = label_lds_bytes(p->Lmax, tw, Wmax);
+    if (p->lds_bytes > lds_limit) return RMX_E_LAYERS;
+    p->tile_w = tw;
+    p->tile_cells = 64 * tw * kTileJ * kTileK;
     int64_t words = 0, slots = 0, cells = 0;
-    int tiles = 0;
+    int tiles = 0, chunks = 0;
     for (int i = 0; i < n_solids; ++i) {
         const rmx_solid& s = solids[i];
         DevSolid& d = p->solids[i];
@@ -105,6 +120,7 @@ void rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
         d.word_base = words;
         d.tile_base = tiles;
         d.slot_base = slots;
+        d.chunk_base = chunks;
         for (int a = 0; a < 3; ++a) d.centre[a] = s.phi0.centre[a];
         if (s.phi0.kind == RMX_SPHERE) {
             d.semi[0] = d.semi[1] = d.semi[2] = s.phi0.semi_axes[0];
@@ -117,15 +133,20 @@ void rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
         d.xi_normal = s.xi_normal ? s.xi_normal : s.xi;
         d.labels = s.labels;
         d.decisions = s.decisions;
-        const int nt = d.W * d.ty * d.tz;
+        d.ntx = (d.W + tw - 1) / tw;
+        const int nt = d.ntx * d.ty * d.tz;
+        d.n_tiles = nt;
         for (int t = 0; t < nt; ++t) p->tile_solid.push_back(i);
-        words += (int64_t)d.n1 * d.n2 * d.W;
+        const int64_t nw = (int64_t)d.n1 * d.n2 * d.W;
+        chunks += (int)((nw + kChunkWords - 1) / kChunkWords);
+        words += nw;
         tiles += nt;
-        slots += (int64_t)nt * kTileCells;
+        slots += (int64_t)nt * p->tile_cells;
         cells += d.ncell;
-        p->Lmax = std::max(p->Lmax, d.L);
     }
     p->n_tiles = tiles;
+    p->n_chunks = chunks;
+    p->chunk_cap = (int)(slots / kLocateChunk) + 1;
     p->total_words = words;
     p->slot_cap = slots;
     p->total_cells = cells;
@@ -145,6 +166,10 @@ void rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
     off = align256(off + sizeof(int32_t) * kLT * (size_t)tiles);
     p->off_tile_off = off;
     off = align256(off + sizeof(int32_t) * kLT * (size_t)(tiles + 1));
+    p->off_chunk_tile = off;
+    off = align256(off + sizeof(int32_t) * kLT * (size_t)p->chunk_cap);
+    p->off_chunk_flag = off;
+    off = align256(off + sizeof(int32_t) * (size_t)chunks);
     p->off_mask = off;
     off = align256(off + sizeof(unsigned long long) * (size_t)words);
     p->off_slots = off;
@@ -152,6 +177,7 @@ void rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
     p->off_normals = off;
     if (p->normal_layers > 0) off = align256(off + 3 * sizeof(double) * (size_t)slots);
     p->ws_bytes = off;
+    return RMX_OK;
 }
 
 void rmx_bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
@@ -169,7 +195,13 @@ void rmx_bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
     b->r_s = opt->r_s;
     b->r_max = opt->r_max;
     b->total_words = p->total_words;
+    b->n_chunks = p->n_chunks;
+    b->chunk_cap = p->chunk_cap;
     b->slot_cap = p->slot_cap;
+    b->chunk_tile = reinterpret_cast<int32_t*>(base + p->off_chunk_tile);
+    b->chunk_flag = reinterpret_cast<int32_t*>(base + p->off_chunk_flag);
+    b->tile_w = p->tile_w;
+    b->tile_cells = p->tile_cells;
     b->tile_solid = reinterpret_cast<const int32_t*>(base + p->off_tile_solid);
     b->tile_cnt = reinterpret_cast<int32_t*>(base + p->off_tile_cnt);
     b->tile_lstart = reinterpret_cast<int32_t*>(base + p->off_tile_lstart);
@@ -244,11 +276,10 @@ hipError_t rmx_enqueue(const Plan& p, const Batch& b, int precision, hipStream_t
         if ((e = (call)) != hipSuccess) return e;                            \
         if (prof && (e = prof->end(rec, st)) != hipSuccess) return e;        \
     } while (0)
-    RMX_TIMED(RMX_PHASE_ZERO, launch_zero(b.stats, (int64_t)kStatWords * p.n_solids, st));
     RMX_TIMED(RMX_PHASE_CLASSIFY, launch_classify(b, st));
-    RMX_TIMED(RMX_PHASE_LABEL, launch_label(b, st));
-    if (p.Lmax == 0) return hipSuccess;
+    RMX_TIMED(RMX_PHASE_LABEL, launch_label(b, p.lds_bytes, st));
     RMX_TIMED(RMX_PHASE_SCAN, launch_scan(b, st));
+    if (p.Lmax == 0) return hipSuccess;
     // Band cells of one layer: a thin shell; the kernels stride over the true count.
     const int64_t est = std::max<int64_t>(4096, p.total_cells / 8);
     if (p.normal_layers > 0)
@@ -301,6 +332,7 @@ struct Staging {
 
 struct rmx_ctx {
     int device = 0;
+    size_t lds_limit = 65536;
     bool fixed = false;
     void* ws = nullptr;
     size_t ws_size = 0;
@@ -396,8 +428,9 @@ int run_batch(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int n,
               const rmx_options* opt, hipStream_t st, bool use_graph, size_t stats_off,
               bool want_stats) {
     Plan p;
-    rmx_plan(grid, solids, n, opt, &p);
-    int rc = ensure_ws(c, p.ws_bytes);
+    int rc = rmx_plan(grid, solids, n, opt, c->lds_limit, &p);
+    if (rc != RMX_OK) return rc;
+    rc = ensure_ws(c, p.ws_bytes);
     if (rc != RMX_OK) return rc;
     Batch b{};
     rmx_bind(&p, c->ws, opt, &b);
@@ -479,6 +512,11 @@ int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out) {
     if (hipSetDevice(device) != hipSuccess) return RMX_E_HIP;
     rmx_ctx* c = new rmx_ctx();
     c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+            hipSuccess &&
+        lds > 0)
+        c->lds_limit = (size_t)lds;
     for (auto& s : c->stage)
         if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
             rmx_destroy(c);
@@ -529,12 +567,14 @@ int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_
     if (opt->flags & RMX_FLAG_PER_SOLID) {
         for (int i = 0; i < n_solids; ++i) {
             Plan p;
-            rmx_plan(grid, solids + i, 1, opt, &p);
+            const int rc = rmx_plan(grid, solids + i, 1, opt, kMaxLdsBytes, &p);
+            if (rc != RMX_OK) return rc;
             total = std::max(total, p.ws_bytes);
         }
     } else {
         Plan p;
-        rmx_plan(grid, solids, n_solids, opt, &p);
+        const int rc = rmx_plan(grid, solids, n_solids, opt, kMaxLdsBytes, &p);
+        if (rc != RMX_OK) return rc;
         total = p.ws_bytes;
     }
     *bytes = total;

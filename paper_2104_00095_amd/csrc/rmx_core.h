@@ -14,14 +14,20 @@ struct Plan {
     std::vector<DevSolid> solids;
     std::vector<int32_t> tile_solid;
     int n_tiles = 0;
+    int n_chunks = 0;
+    int chunk_cap = 0;
     int Lmax = 0;
     int normal_layers = 0;
+    int tile_w = 1;
+    int tile_cells = 0;
+    size_t lds_bytes = 0;
     int64_t total_words = 0;
     int64_t slot_cap = 0;
     int64_t total_cells = 0;
     // workspace layout (byte offsets); [0, desc_bytes) is uploaded from the host
     size_t off_desc = 0, off_tile_solid = 0, desc_bytes = 0;
     size_t off_stats = 0, off_tile_cnt = 0, off_tile_lstart = 0, off_tile_off = 0;
+    size_t off_chunk_tile = 0, off_chunk_flag = 0;
     size_t off_mask = 0, off_slots = 0, off_normals = 0;
     size_t ws_bytes = 0;
 };
@@ -47,8 +53,8 @@ struct Profiler {
 
 int rmx_validate(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
                  const rmx_options* opt);
-void rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
-              const rmx_options* opt, rmx::Plan* p);
+int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+             const rmx_options* opt, size_t lds_limit, rmx::Plan* p);
 void rmx_bind(rmx::Plan* p, void* ws, const rmx_options* opt, rmx::Batch* b);
 void rmx_pack_desc(const rmx::Plan& p, void* host);
 hipError_t rmx_enqueue(const rmx::Plan& p, const rmx::Batch& b, int precision,

@@ -10,7 +10,8 @@ constexpr int kMaxRadius = 4;
 constexpr int kLT = kMaxLayers + 1;          // per-tile layer table stride
 constexpr int kTileJ = 16;                   // rows of a label tile along y
 constexpr int kTileK = 16;                   // rows of a label tile along z
-constexpr int kTileCells = 64 * kTileJ * kTileK;  // one 64-cell mask word along x
+constexpr int kChunkWords = 64;              // mask words per classification chunk
+constexpr int kLocateChunk = 64;             // band indices per chunk_tile entry
 
 // Per-solid device statistics (int64 words).
 constexpr int kStatWords = 24;
@@ -36,6 +37,9 @@ struct DevSolid {
     int32_t wall_lo[3];      // 1 if the low face along the axis is a grid wall
     int32_t wall_hi[3];
     int32_t tile_base;       // first global tile index of the solid
+    int32_t n_tiles;         // tiles of the solid
+    int32_t ntx;             // tiles along x (tile_w words each)
+    int32_t chunk_base;      // first classification chunk of the solid
     int32_t pad0;
     int64_t ncell;
     int64_t word_base;       // first global mask word
@@ -58,22 +62,27 @@ struct Batch {
     int32_t Lmax;
     int32_t normal_layers;
     int32_t r_s, r_max;
-    int32_t pad0, pad1;
+    int32_t tile_w;          // 64-cell words per label tile along x (1..4)
+    int32_t tile_cells;      // slot capacity of a tile: 64 * tile_w * 16 * 16
     int64_t total_words;
+    int32_t n_chunks;        // classification chunks (kChunkWords mask words each)
+    int32_t chunk_cap;       // entries per layer of chunk_tile
     int64_t slot_cap;        // slot capacity (n_tiles * kTileCells)
     const int32_t* tile_solid;  // [n_tiles]
-    int32_t* tile_cnt;       // [n_tiles][kLT] cells of layer l in the tile
+    int32_t* tile_cnt;       // [n_tiles][kLT] cells of layer l (0: interior) in the tile
     int32_t* tile_lstart;    // [n_tiles][kLT] first slot of layer l within the tile
     int32_t* tile_off;       // [kLT][n_tiles + 1] exclusive prefix over tiles, per layer
+    int32_t* chunk_tile;     // [kLT][chunk_cap] tile holding band index 64c of layer l
+    int32_t* chunk_flag;     // [n_chunks] 1 if the chunk found a truncating interior cell
     int32_t* slots;          // [slot_cap] linear cell index within the solid's box
     double* normals;         // [3][slot_cap] unnormalised gradient of phi0(xi)
     unsigned long long* stats;  // [n_solids][kStatWords]
 };
 
 // Launchers (rmx_kernels.hip).
-hipError_t launch_zero(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_classify(const Batch& b, hipStream_t st);
-hipError_t launch_label(const Batch& b, hipStream_t st);
+size_t label_lds_bytes(int Lmax, int tile_w, int Wmax);
+hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st);
 hipError_t launch_scan(const Batch& b, hipStream_t st);
 hipError_t launch_normal(const Batch& b, int64_t max_cells, hipStream_t st);
 hipError_t launch_extrap(const Batch& b, int layer, int precision, int64_t max_cells,

@@ -188,27 +188,18 @@ __device__ double phi0(const ShapeR& s, double v0, double v1, double v2) {
 // ------------------------------------------------------------------------------------
 // Helpers.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ int find_solid_by_word(const DevSolid* s, int n, int64_t w) {
+__device__ __forceinline__ int find_solid_by_chunk(const DevSolid* s, int n, int c) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s[mid].word_base <= w) lo = mid; else hi = mid - 1;
+        if (s[mid].chunk_base <= c) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-// Last tile t with off[t] <= g: the tile whose layer range holds band index g.
-__device__ __forceinline__ int find_tile(const int32_t* off, int T, int g) {
-    int lo = 0, hi = T - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Exclusive scan of one int per thread over a 256-thread block.
-__device__ __forceinline__ void block_scan256(int v, int& excl, int& total, int* s_wave) {
+// Exclusive scan of one int per thread over a block of NW waves.
+template <int NW>
+__device__ __forceinline__ void block_scan(int v, int& excl, int& total, int* s_wave) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int x = v;
 #pragma unroll
@@ -220,7 +211,7 @@ __device__ __forceinline__ void block_scan256(int v, int& excl, int& total, int*
     __syncthreads();
     int wb = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NW; ++i) {
         const int t = s_wave[i];
         if (i < wid) wb += t;
         tot += t;
@@ -230,194 +221,220 @@ __device__ __forceinline__ void block_scan256(int v, int& excl, int& total, int*
     __syncthreads();
 }
 
-// ------------------------------------------------------------------------------------
-// Zero a stats block (a kernel, not a memset node, so the chain can be graph-captured).
-// ------------------------------------------------------------------------------------
-__global__ void k_zero(unsigned long long* p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0ull;
+// Spread the low 4 bits of x to the low bit of 4 bytes (bit q -> byte q).  The partial
+// products of x * (1 + 2^7 + 2^14 + 2^21) land on distinct bit positions, so no carries.
+__device__ __forceinline__ uint32_t spread4(uint32_t x) {
+    return (x * 0x00204081u) & 0x01010101u;
+}
+
+__device__ __forceinline__ unsigned long long spread8(uint32_t x) {
+    return (unsigned long long)spread4(x & 15u) |
+           ((unsigned long long)spread4((x >> 4) & 15u) << 32);
 }
 
 // ------------------------------------------------------------------------------------
-// Classification: one 64-cell row segment per wave, UNROLL segments in flight.
+// Classification.  A block owns a chunk of kChunkWords consecutive mask words of one
+// solid; each wave streams 16 consecutive 64-cell row segments, 8 at a time (24 loads of
+// 512 contiguous bytes in flight per wave), ballot-packs the interior predicate and
+// writes one mask word per segment.  The chunk records whether an interior cell lies
+// closer than L to a box face that is no grid wall (the band would be truncated).
 // ------------------------------------------------------------------------------------
-constexpr int kClassifyUnroll = 4;
+constexpr int kSeg = 8;
 
 __global__ __launch_bounds__(256) void k_classify(Batch b) {
     const int lane = threadIdx.x & 63;
-    const int wid = uniform_int(blockIdx.x * 4 + (threadIdx.x >> 6));
-    const int nwv = gridDim.x * 4;
-    int acc_s = -1;
-    unsigned long long acc = 0;
-    for (int64_t w0 = wid; w0 < b.total_words; w0 += (int64_t)nwv * kClassifyUnroll) {
-        double v[kClassifyUnroll][3];
-        int sidx[kClassifyUnroll];
-        int64_t lw[kClassifyUnroll];
-        int xs[kClassifyUnroll];
-        bool live[kClassifyUnroll];
+    const int wave = uniform_int(threadIdx.x >> 6);
+    for (int chunk = blockIdx.x; chunk < b.n_chunks; chunk += gridDim.x) {
+        const int s = uniform_int(find_solid_by_chunk(b.solids, b.n_solids, chunk));
+        const DevSolid* dp = b.solids + s;
+        const int n0 = dp->n0, n1 = dp->n1, n2 = dp->n2, W = dp->W, L = dp->L;
+        const int64_t ncell = dp->ncell;
+        const double* __restrict__ xi = dp->xi;
+        unsigned long long* __restrict__ mask = dp->mask;
+        const bool wl0 = dp->wall_lo[0], wh0 = dp->wall_hi[0];
+        const bool wl1 = dp->wall_lo[1], wh1 = dp->wall_hi[1];
+        const bool wl2 = dp->wall_lo[2], wh2 = dp->wall_hi[2];
+        const ShapeR sh = load_shape(dp);
+        const int nwords = n1 * n2 * W;
+        const int first = (chunk - dp->chunk_base) * kChunkWords + wave * (kChunkWords / 4);
+        bool trunc = false;
+#pragma unroll 1
+        for (int it = 0; it < kChunkWords / 4; it += kSeg) {
+            const int w0 = first + it;
+            if (w0 >= nwords) break;
+            int row = w0 / W, wx = w0 - row * W;
+            double v0[kSeg], v1[kSeg], v2[kSeg];
+            int rows[kSeg], xs[kSeg];
 #pragma unroll
-        for (int u = 0; u < kClassifyUnroll; ++u) {
-            const int64_t w = w0 + (int64_t)u * nwv;
-            live[u] = w < b.total_words;
-            v[u][0] = v[u][1] = v[u][2] = __builtin_nan("");
-            sidx[u] = 0;
-            lw[u] = 0;
-            xs[u] = 0;
-            if (live[u]) {
-                const int s = find_solid_by_word(b.solids, b.n_solids, w);
-                const DevSolid* d = &b.solids[s];
-                const int64_t l = w - d->word_base;
-                const int W = d->W;
-                const int64_t row = l / W;
-                const int x = (int)(l - row * W) * 64 + lane;
-                sidx[u] = s;
-                lw[u] = l;
+            for (int u = 0; u < kSeg; ++u) {
+                const int x = wx * 64 + lane;
+                rows[u] = row;
                 xs[u] = x;
-                if (x < d->n0) {
-                    const int64_t c = row * d->n0 + x;
-                    const double* xi = d->xi;
-                    v[u][0] = __builtin_nontemporal_load(xi + c);
-                    v[u][1] = __builtin_nontemporal_load(xi + d->ncell + c);
-                    v[u][2] = __builtin_nontemporal_load(xi + 2 * d->ncell + c);
+                v0[u] = v1[u] = v2[u] = __builtin_nan("");
+                if (w0 + u < nwords && x < n0) {
+                    const int64_t c = (int64_t)row * n0 + x;
+                    v0[u] = __builtin_nontemporal_load(xi + c);
+                    v1[u] = __builtin_nontemporal_load(xi + ncell + c);
+                    v2[u] = __builtin_nontemporal_load(xi + 2 * ncell + c);
+                }
+                if (++wx == W) {
+                    wx = 0;
+                    ++row;
                 }
             }
-        }
 #pragma unroll
-        for (int u = 0; u < kClassifyUnroll; ++u) {
-            if (!live[u]) continue;
-            const int s = sidx[u];
-            const DevSolid* d = &b.solids[s];
-            const ShapeR sh = load_shape(d);
-            const bool in = interior(sh, v[u][0], v[u][1], v[u][2]);
-            const unsigned long long m = __ballot(in);
-            if (lane == 0) d->mask[lw[u]] = m;
-            // Truncation: an interior cell closer than L to a box face that is no wall.
-            bool tr = false;
-            if (in) {
-                const int W = d->W;
-                const int row = (int)(lw[u] / W);
-                const int yy = row % d->n1, zz = row / d->n1, xx = xs[u];
-                const int L = d->L;
-                tr = (!d->wall_lo[0] && xx < L) || (!d->wall_hi[0] && d->n0 - 1 - xx < L) ||
-                     (!d->wall_lo[1] && yy < L) || (!d->wall_hi[1] && d->n1 - 1 - yy < L) ||
-                     (!d->wall_lo[2] && zz < L) || (!d->wall_hi[2] && d->n2 - 1 - zz < L);
-            }
-            const unsigned long long tm = __ballot(tr);
-            if (lane == 0) {
-                if (tm) atomicOr(&b.stats[(int64_t)s * kStatWords + ST_FLAGS], FLAG_TRUNCATED);
-                if (s != acc_s) {
-                    if (acc_s >= 0 && acc)
-                        atomicAdd(&b.stats[(int64_t)acc_s * kStatWords + ST_INTERIOR], acc);
-                    acc_s = s;
-                    acc = 0;
+            for (int u = 0; u < kSeg; ++u) {
+                const bool in = interior(sh, v0[u], v1[u], v2[u]);
+                const unsigned long long m = __ballot(in);
+                if (lane == 0 && w0 + u < nwords) mask[w0 + u] = m;
+                if (m) {
+                    const int yy = rows[u] % n1, zz = rows[u] / n1, xx = xs[u];
+                    trunc |= in && ((!wl0 && xx < L) || (!wh0 && n0 - 1 - xx < L) ||
+                                    (!wl1 && yy < L) || (!wh1 && n1 - 1 - yy < L) ||
+                                    (!wl2 && zz < L) || (!wh2 && n2 - 1 - zz < L));
                 }
-                acc += (unsigned long long)__popcll(m);
             }
         }
+        const int any = __syncthreads_or(trunc);
+        if (threadIdx.x == 0) b.chunk_flag[chunk] = any ? 1 : 0;
     }
-    if (lane == 0 && acc_s >= 0 && acc)
-        atomicAdd(&b.stats[(int64_t)acc_s * kStatWords + ST_INTERIOR], acc);
 }
 
 // ------------------------------------------------------------------------------------
-// Labels.  One workgroup per tile of 16 (y) x 16 (z) rows x one 64-cell word (x); thread
-// (tj, tk) owns one row segment.  The region in LDS carries a halo of L rows in y and z
-// and one word on each side in x (L <= 16 < 64), so after L dilations the tile is exact.
+// Labels.  One workgroup per tile of 16 (y) x 16 (z) rows x tile_w 64-cell words (x);
+// thread (tj, tk) owns one row of the tile.  The region in LDS carries a halo of L rows
+// in y and z and one word on each side in x where the box continues (L <= 16 < 64), so
+// after L dilations through face neighbours (64-bit shifts and ORs) the tile is exact.
+// The first dilation that reaches a cell is its layer.  Per tile it records the
+// interior count and the cells of each layer, and lists the band cells, grouped by
+// layer, in the tile's slot range.
 // ------------------------------------------------------------------------------------
+constexpr int kMaxTileW = 4;
+constexpr int kRowsPerThread = 9;   // ceil((16 + 2 * 16)^2 / 256)
+
 __global__ __launch_bounds__(256) void k_label(Batch b) {
     extern __shared__ unsigned long long lds[];
     __shared__ int s_wave[4];
     const int t = blockIdx.x;
-    const int s = b.tile_solid[t];
+    const int tid = threadIdx.x;
+    const int s = uniform_int(b.tile_solid[t]);
     const DevSolid* d = &b.solids[s];
     const int n0 = d->n0, n1 = d->n1, n2 = d->n2, W = d->W, L = d->L;
+    const int TW = b.tile_w;
     const int lt = t - d->tile_base;
-    const int wx = lt % W;
-    const int tyi = (lt / W) % d->ty;
-    const int tzi = lt / (W * d->ty);
+    const int txi = lt % d->ntx;
+    const int tyi = (lt / d->ntx) % d->ty;
+    const int tzi = lt / (d->ntx * d->ty);
+    const int wx0 = txi * TW, tw = min(TW, W - wx0);
+    const int xr0 = max(0, wx0 - 1), xr1 = min(W, wx0 + tw + 1);
+    const int RW = xr1 - xr0;
     const int j0 = tyi * kTileJ, k0 = tzi * kTileK;
     const int H = L;
     const int RJ = kTileJ + 2 * H, RK = kTileK + 2 * H;
-    const int R3 = 3 * RJ * RK;
+    const int R = RJ * RK;
     unsigned long long* A = lds;
-    unsigned long long* B = lds + R3;
-    const bool truncated = (b.stats[(int64_t)s * kStatWords + ST_FLAGS] & FLAG_TRUNCATED) != 0;
-    const unsigned long long tail =
-        (n0 & 63) ? ((1ull << (n0 & 63)) - 1ull) : ~0ull;
+    unsigned long long* B = lds + (size_t)RW * R;
+    const unsigned long long tail = (n0 & 63) ? ((1ull << (n0 & 63)) - 1ull) : ~0ull;
+    const unsigned long long* __restrict__ mask = d->mask;
 
-    for (int q = threadIdx.x; q < R3; q += 256) {
-        const int w = q % 3, rr = q / 3;
-        const int jj = j0 - H + rr % RJ, kk = k0 - H + rr / RJ;
-        const int gw = wx - 1 + w;
-        unsigned long long v = 0ull;
-        if (jj >= 0 && jj < n1 && kk >= 0 && kk < n2 && gw >= 0 && gw < W)
-            v = d->mask[((int64_t)kk * n1 + jj) * W + gw];
-        A[q] = v;
+    // Region rows owned by this thread, with their position and box membership.
+    int rjs[kRowsPerThread], rks[kRowsPerThread];
+    bool rok[kRowsPerThread];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+        const int rr = tid + 256 * q;
+        const int rj = rr % RJ, rk = rr / RJ;
+        const int jj = j0 - H + rj, kk = k0 - H + rk;
+        rjs[q] = rj;
+        rks[q] = rk;
+        rok[q] = rr < R && jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
+        if (rr < R) {
+            for (int w = 0; w < RW; ++w)
+                A[rr * RW + w] = rok[q] ? mask[((int64_t)kk * n1 + jj) * W + xr0 + w] : 0ull;
+        }
     }
     __syncthreads();
 
-    const int tj = threadIdx.x % kTileJ, tk = threadIdx.x / kTileJ;
+    const int tj = tid % kTileJ, tk = tid / kTileJ;
     const int jrow = j0 + tj, krow = k0 + tk;
     const bool row_ok = jrow < n1 && krow < n2;
-    const int my = ((tk + H) * RJ + (tj + H)) * 3 + 1;
-    unsigned long long prev = A[my];
-    unsigned long long p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;  // bit-planes of the layer
+    const int my = ((tk + H) * RJ + (tj + H)) * RW + (wx0 - xr0);
+    unsigned long long prev[kMaxTileW], p0[kMaxTileW], p1[kMaxTileW], p2[kMaxTileW],
+        p3[kMaxTileW], p4[kMaxTileW];
+    int cnt0 = 0;
+#pragma unroll
+    for (int w = 0; w < kMaxTileW; ++w) {
+        prev[w] = (row_ok && w < tw) ? A[my + w] : 0ull;
+        p0[w] = p1[w] = p2[w] = p3[w] = p4[w] = 0ull;
+        cnt0 += __popcll(prev[w]);
+    }
+    {
+        int excl, total;
+        block_scan<4>(cnt0, excl, total, s_wave);
+        if (tid == 0) b.tile_cnt[t * kLT] = total;
+    }
     int lstart = 0;
-    const int64_t tile_slot = d->slot_base + (int64_t)lt * kTileCells;
-    const int xbase = wx * 64;
-    const int32_t rowbase = (krow * n1 + jrow) * n0 + xbase;
+    const int64_t tile_slot = d->slot_base + (int64_t)lt * b.tile_cells;
+    const int32_t rowbase = (krow * n1 + jrow) * n0 + wx0 * 64;
 
     for (int l = 1; l <= L; ++l) {
-        for (int q = threadIdx.x; q < R3; q += 256) {
-            const int w = q % 3, rr = q / 3;
-            const int rj = rr % RJ, rk = rr / RJ;
-            const unsigned long long c = A[q];
-            const unsigned long long left = (w > 0) ? A[q - 1] : 0ull;
-            const unsigned long long right = (w < 2) ? A[q + 1] : 0ull;
-            unsigned long long v = c | (c << 1) | (c >> 1) | (left >> 63) | (right << 63);
-            if (rj > 0) v |= A[q - 3];
-            if (rj < RJ - 1) v |= A[q + 3];
-            if (rk > 0) v |= A[q - 3 * RJ];
-            if (rk < RK - 1) v |= A[q + 3 * RJ];
-            const int gw = wx - 1 + w;
-            const int jj = j0 - H + rj, kk = k0 - H + rk;
-            unsigned long long vm = (gw == W - 1) ? tail : ~0ull;
-            if (gw < 0 || gw >= W || jj < 0 || jj >= n1 || kk < 0 || kk >= n2) vm = 0ull;
-            B[q] = v & vm;
+#pragma unroll
+        for (int q = 0; q < kRowsPerThread; ++q) {
+            const int rr = tid + 256 * q;
+            if (rr < R) {
+                const int rj = rjs[q], rk = rks[q];
+                for (int w = 0; w < RW; ++w) {
+                    const int idx = rr * RW + w;
+                    const unsigned long long c = A[idx];
+                    const unsigned long long left = (w > 0) ? A[idx - 1] : 0ull;
+                    const unsigned long long right = (w < RW - 1) ? A[idx + 1] : 0ull;
+                    unsigned long long v = c | (c << 1) | (c >> 1) | (left >> 63) | (right << 63);
+                    if (rj > 0) v |= A[idx - RW];
+                    if (rj < RJ - 1) v |= A[idx + RW];
+                    if (rk > 0) v |= A[idx - RW * RJ];
+                    if (rk < RK - 1) v |= A[idx + RW * RJ];
+                    const unsigned long long vm = !rok[q] ? 0ull : (xr0 + w == W - 1 ? tail : ~0ull);
+                    B[idx] = v & vm;
+                }
+            }
         }
         __syncthreads();
         unsigned long long* tmp = A;
         A = B;
         B = tmp;
-        const unsigned long long dl = A[my];
-        const unsigned long long nw = row_ok ? (dl & ~prev) : 0ull;
-        prev = dl;
-        if (l & 1) p0 |= nw;
-        if (l & 2) p1 |= nw;
-        if (l & 4) p2 |= nw;
-        if (l & 8) p3 |= nw;
-        if (l & 16) p4 |= nw;
-        const int cnt = __popcll(nw);
+        unsigned long long nw[kMaxTileW];
+        int cnt = 0;
+#pragma unroll
+        for (int w = 0; w < kMaxTileW; ++w) {
+            const unsigned long long dl = (row_ok && w < tw) ? A[my + w] : 0ull;
+            nw[w] = dl & ~prev[w];
+            prev[w] = dl;
+            if (l & 1) p0[w] |= nw[w];
+            if (l & 2) p1[w] |= nw[w];
+            if (l & 4) p2[w] |= nw[w];
+            if (l & 8) p3[w] |= nw[w];
+            if (l & 16) p4[w] |= nw[w];
+            cnt += __popcll(nw[w]);
+        }
         int excl, total;
-        block_scan256(cnt, excl, total, s_wave);
-        if (cnt && !truncated) {
-            int64_t pos = tile_slot + lstart + excl;
-            unsigned long long m = nw;
+        block_scan<4>(cnt, excl, total, s_wave);
+        int64_t pos = tile_slot + lstart + excl;
+#pragma unroll
+        for (int w = 0; w < kMaxTileW; ++w) {
+            unsigned long long m = nw[w];
             while (m) {
                 const int bit = __ffsll((long long)m) - 1;
                 m &= m - 1ull;
-                b.slots[pos++] = rowbase + bit;
+                b.slots[pos++] = rowbase + w * 64 + bit;
             }
         }
-        if (threadIdx.x == 0) {
-            b.tile_cnt[t * kLT + l] = truncated ? 0 : total;
+        if (tid == 0) {
+            b.tile_cnt[t * kLT + l] = total;
             b.tile_lstart[t * kLT + l] = lstart;
-            if (total) atomicAdd(&b.stats[(int64_t)s * kStatWords + l], (unsigned long long)total);
         }
-        if (!truncated) lstart += total;
+        lstart += total;
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         for (int l = L + 1; l <= b.Lmax; ++l) {
             b.tile_cnt[t * kLT + l] = 0;
             b.tile_lstart[t * kLT + l] = lstart;
@@ -425,84 +442,134 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     }
 
     if (!row_ok) return;
-    const int nx = min(64, n0 - xbase);
-    int8_t* lab = d->labels + ((int64_t)krow * n1 + jrow) * n0 + xbase;
-    int8_t* dec = d->decisions ? d->decisions + ((int64_t)krow * n1 + jrow) * n0 + xbase : nullptr;
-    const bool vec = ((n0 & 7) == 0) && nx == 64 && ((reinterpret_cast<uintptr_t>(lab) & 7) == 0) &&
-                     (!dec || (reinterpret_cast<uintptr_t>(dec) & 7) == 0);
-    if (vec) {
+    int8_t* lab0 = d->labels + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64;
+    int8_t* dec0 = d->decisions ? d->decisions + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64
+                                : nullptr;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-            unsigned long long word = 0ull;
+    for (int w = 0; w < kMaxTileW; ++w) {
+        if (w >= tw) break;
+        int8_t* lab = lab0 + 64 * w;
+        int8_t* dec = dec0 ? dec0 + 64 * w : nullptr;
+        const int nx = min(64, n0 - (wx0 + w) * 64);
+        const bool vec = ((n0 & 7) == 0) && nx == 64 &&
+                         ((reinterpret_cast<uintptr_t>(lab) & 7) == 0) &&
+                         (!dec || (reinterpret_cast<uintptr_t>(dec) & 7) == 0);
+        if (vec) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int i = g * 8 + q;
-                unsigned long long byte;
-                if ((prev >> i) & 1ull) {
-                    byte = ((p0 >> i) & 1ull) | (((p1 >> i) & 1ull) << 1) |
-                           (((p2 >> i) & 1ull) << 2) | (((p3 >> i) & 1ull) << 3) |
-                           (((p4 >> i) & 1ull) << 4);
+            for (int g = 0; g < 8; ++g) {
+                const int sh8 = 8 * g;
+                // label byte = layer bits where marked, 0xFF where unmarked
+                unsigned long long word =
+                    spread8((uint32_t)(p0[w] >> sh8) & 255u) |
+                    (spread8((uint32_t)(p1[w] >> sh8) & 255u) << 1) |
+                    (spread8((uint32_t)(p2[w] >> sh8) & 255u) << 2) |
+                    (spread8((uint32_t)(p3[w] >> sh8) & 255u) << 3) |
+                    (spread8((uint32_t)(p4[w] >> sh8) & 255u) << 4);
+                word |= spread8((uint32_t)(~prev[w] >> sh8) & 255u) * 0xFFull;
+                reinterpret_cast<unsigned long long*>(lab)[g] = word;
+                if (dec) reinterpret_cast<unsigned long long*>(dec)[g] = 0ull;
+            }
+        } else {
+            for (int i = 0; i < nx; ++i) {
+                int v;
+                if ((prev[w] >> i) & 1ull) {
+                    v = (int)(((p0[w] >> i) & 1ull) | (((p1[w] >> i) & 1ull) << 1) |
+                              (((p2[w] >> i) & 1ull) << 2) | (((p3[w] >> i) & 1ull) << 3) |
+                              (((p4[w] >> i) & 1ull) << 4));
                 } else {
-                    byte = 0xFFull;
+                    v = -1;
                 }
-                word |= byte << (8 * q);
+                lab[i] = (int8_t)v;
+                if (dec) dec[i] = 0;
             }
-            reinterpret_cast<unsigned long long*>(lab)[g] = word;
-            if (dec) reinterpret_cast<unsigned long long*>(dec)[g] = 0ull;
-        }
-    } else {
-        for (int i = 0; i < nx; ++i) {
-            int v;
-            if ((prev >> i) & 1ull) {
-                v = (int)(((p0 >> i) & 1ull) | (((p1 >> i) & 1ull) << 1) |
-                          (((p2 >> i) & 1ull) << 2) | (((p3 >> i) & 1ull) << 3) |
-                          (((p4 >> i) & 1ull) << 4));
-            } else {
-                v = -1;
-            }
-            lab[i] = (int8_t)v;
-            if (dec) dec[i] = 0;
         }
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Per-layer exclusive prefix of tile counts (one workgroup of 1024 threads).
+// One workgroup of 1024 threads: per-layer exclusive prefix of the tile counts (all
+// layers at once), the chunk->tile table that lets a band index find its tile with one
+// load, and the per-solid statistics (zeroed here, then the counts as differences of the
+// prefix over the solid's tile range, and the truncation flag from the chunk flags).
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_scan(Batch b) {
-    __shared__ int s_w[16];
+    __shared__ int s_w[kLT][16];
     const int T = b.n_tiles;
+    const int Lm = b.Lmax;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int l = 1; l <= b.Lmax; ++l) {
-        int carry = 0;
-        for (int base = 0; base < T; base += 1024) {
-            const int i = base + threadIdx.x;
-            const int v = i < T ? b.tile_cnt[i * kLT + l] : 0;
-            int x = v;
+    for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 1024) b.stats[i] = 0ull;
+    __syncthreads();
+    int carry[kLT];
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
+    for (int l = 0; l < kLT; ++l) carry[l] = 0;
+    for (int base = 0; base < T; base += 1024) {
+        const int i = base + threadIdx.x;
+        int v[kLT], x[kLT];
+#pragma unroll
+        for (int l = 0; l < kLT; ++l) {
+            v[l] = (i < T && l <= Lm) ? b.tile_cnt[i * kLT + l] : 0;
+            x[l] = v[l];
+        }
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+            for (int l = 0; l < kLT; ++l) {
+                const int y = __shfl_up(x[l], o, 64);
+                if (lane >= o) x[l] += y;
             }
-            if (lane == 63) s_w[wid] = x;
-            __syncthreads();
+        }
+        if (lane == 63) {
+#pragma unroll
+            for (int l = 0; l < kLT; ++l) s_w[l][wid] = x[l];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < kLT; ++l) {
+            if (l > Lm) break;
             int wb = 0, tot = 0;
             for (int q = 0; q < 16; ++q) {
-                const int tq = s_w[q];
+                const int tq = s_w[l][q];
                 if (q < wid) wb += tq;
                 tot += tq;
             }
-            if (i < T) b.tile_off[l * (T + 1) + i] = carry + wb + x - v;
-            carry += tot;
-            __syncthreads();
+            const int off = carry[l] + wb + x[l] - v[l];
+            if (i < T) {
+                b.tile_off[l * (T + 1) + i] = off;
+                if (l > 0) {
+                    int32_t* ct = b.chunk_tile + l * b.chunk_cap;
+                    for (int c = (off + kLocateChunk - 1) / kLocateChunk;
+                         c * kLocateChunk < off + v[l]; ++c)
+                        ct[c] = i;
+                }
+            }
+            carry[l] += tot;
         }
-        if (threadIdx.x == 0) b.tile_off[l * (T + 1) + T] = carry;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int l = 0; l <= Lm; ++l) b.tile_off[l * (T + 1) + T] = carry[l];
+    }
+    // truncation flags (rare): OR of the solid's chunk flags
+    for (int c = threadIdx.x; c < b.n_chunks; c += 1024) {
+        if (b.chunk_flag[c]) {
+            const int s = find_solid_by_chunk(b.solids, b.n_solids, c);
+            atomicOr(&b.stats[(int64_t)s * kStatWords + ST_FLAGS], FLAG_TRUNCATED);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < b.n_solids; i += 1024) {
+        const DevSolid* d = b.solids + i;
+        for (int l = 0; l <= Lm; ++l)
+            b.stats[(int64_t)i * kStatWords + l] =
+                (unsigned long long)(b.tile_off[l * (T + 1) + d->tile_base + d->n_tiles] -
+                                     b.tile_off[l * (T + 1) + d->tile_base]);
     }
 }
 
-// Locate band cell `g` of layer `l`: its global slot, solid and linear cell index.
+// Locate band cell `g` of layer `l`: its tile, global slot, solid and linear cell index.
 struct BandCell {
     int s;
+    bool skip;       // the solid's band was truncated: nothing to fit
     int64_t slot;
     int32_t cell;
 };
@@ -510,29 +577,24 @@ struct BandCell {
 __device__ __forceinline__ BandCell locate(const Batch& b, int l, int g) {
     const int T = b.n_tiles;
     const int32_t* off = b.tile_off + l * (T + 1);
-    const int t = find_tile(off, T, g);
+    int t = b.chunk_tile[l * b.chunk_cap + g / kLocateChunk];
+    while (off[t + 1] <= g) ++t;
     BandCell r;
     r.s = b.tile_solid[t];
     const DevSolid* d = &b.solids[r.s];
-    r.slot = d->slot_base + (int64_t)(t - d->tile_base) * kTileCells +
+    r.skip = (b.stats[(int64_t)r.s * kStatWords + ST_FLAGS] & FLAG_TRUNCATED) != 0;
+    r.slot = d->slot_base + (int64_t)(t - d->tile_base) * b.tile_cells +
              b.tile_lstart[t * kLT + l] + (g - off[t]);
-    r.cell = b.slots[r.slot];
+    r.cell = r.skip ? 0 : b.slots[r.slot];
     return r;
 }
 
 // ------------------------------------------------------------------------------------
-// Normals of the band cells of layers 1..normal_layers (one thread per cell).
+// Normals of the band cells of layers 1..normal_layers (one thread per cell), from the
+// field before any write: central differences of phi0(xi) over the face neighbours,
+// one-sided with the cell itself where a neighbour is undefined or outside the box.
+// The seven cells are loaded unconditionally (clamped into the box) before any use.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ bool phi_at(const DevSolid* d, const ShapeR& sh, const double* f,
-                                       int i, int j, int k, double& out) {
-    if (i < 0 || i >= d->n0 || j < 0 || j >= d->n1 || k < 0 || k >= d->n2) return false;
-    const int64_t c = ((int64_t)k * d->n1 + j) * d->n0 + i;
-    const double v0 = f[c], v1 = f[d->ncell + c], v2 = f[2 * d->ncell + c];
-    if (!finite3(v0, v1, v2)) return false;
-    out = phi0(sh, v0, v1, v2);
-    return true;
-}
-
 __global__ __launch_bounds__(256) void k_normal(Batch b) {
     const int T = b.n_tiles;
     const int NL = min(b.normal_layers, b.Lmax);
@@ -548,25 +610,46 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
             ++l;
         }
         const BandCell bc = locate(b, l, gl);
+        if (bc.skip) continue;
         const DevSolid* d = &b.solids[bc.s];
         const ShapeR sh = load_shape(d);
-        const int n0 = d->n0, n1 = d->n1;
+        const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
+        const int64_t nc = d->ncell;
         const int i = bc.cell % n0, j = (bc.cell / n0) % n1, k = bc.cell / (n0 * n1);
-        const double* f = d->xi_normal;
-        double pe = 0.0;
-        const bool de = phi_at(d, sh, f, i, j, k, pe);
+        const double* __restrict__ f = d->xi_normal;
+        // cells: e, +x, -x, +y, -y, +z, -z
+        bool in[7];
+        int64_t cc[7];
+        in[0] = true;
+        cc[0] = bc.cell;
+        in[1] = i + 1 < n0; cc[1] = in[1] ? bc.cell + 1 : bc.cell;
+        in[2] = i > 0;      cc[2] = in[2] ? bc.cell - 1 : bc.cell;
+        in[3] = j + 1 < n1; cc[3] = in[3] ? bc.cell + n0 : bc.cell;
+        in[4] = j > 0;      cc[4] = in[4] ? bc.cell - n0 : bc.cell;
+        in[5] = k + 1 < n2; cc[5] = in[5] ? bc.cell + (int64_t)n0 * n1 : bc.cell;
+        in[6] = k > 0;      cc[6] = in[6] ? bc.cell - (int64_t)n0 * n1 : bc.cell;
+        double x0[7], x1[7], x2[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            x0[q] = f[cc[q]];
+            x1[q] = f[nc + cc[q]];
+            x2[q] = f[2 * nc + cc[q]];
+        }
+        double ph[7];
+        bool def[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            def[q] = in[q] && finite3(x0[q], x1[q], x2[q]);
+            ph[q] = def[q] ? phi0(sh, x0[q], x1[q], x2[q]) : 0.0;
+        }
         double g[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int ip = i + (a == 0), jp = j + (a == 1), kp = k + (a == 2);
-            const int im = i - (a == 0), jm = j - (a == 1), km = k - (a == 2);
-            double vp = 0.0, vm = 0.0;
-            const bool dp = phi_at(d, sh, f, ip, jp, kp, vp);
-            const bool dm = phi_at(d, sh, f, im, jm, km, vm);
+            const int qp = 1 + 2 * a, qm = 2 + 2 * a;
             double ga;
-            if (dp && dm) ga = 0.5 * (vp - vm);
-            else if (dp && de) ga = vp - pe;
-            else if (dm && de) ga = pe - vm;
+            if (def[qp] && def[qm]) ga = 0.5 * (ph[qp] - ph[qm]);
+            else if (def[qp] && def[0]) ga = ph[qp] - ph[0];
+            else if (def[qm] && def[0]) ga = ph[0] - ph[qm];
             else ga = 0.0;
             g[a] = ga;
         }
@@ -579,13 +662,16 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
 }
 
 // ------------------------------------------------------------------------------------
-// Extrapolation of one layer.  16 lanes per band cell (4 cells per wave).
+// Extrapolation of one layer.  kLanes lanes per band cell (64 / kLanes cells per wave).
 // ------------------------------------------------------------------------------------
+constexpr int kLanes = 8;
+
 template <typename T>
 struct Moments {
     T m[10];   // sum w [1,d][1,d]^T: (0,0) (0,x) (0,y) (0,z) (x,x) (x,y) (x,z) (y,y) (y,z) (z,z)
     T r[12];   // sum w [1,d] v^T: rows 1, dx, dy, dz; columns the 3 components
-    int g[10]; // the same moments over the positive-weight offsets, unweighted, in integers
+    int g[5];  // unweighted integer moments over the positive-weight offsets, two 16-bit
+               // fields per word: (n, sxx) (sx, sxy) (sy, sxz) (sz, syy) (syz, szz)
 };
 
 template <typename T>
@@ -595,29 +681,43 @@ __device__ __forceinline__ void zero(Moments<T>& a) {
 #pragma unroll
     for (int q = 0; q < 12; ++q) a.r[q] = T(0);
 #pragma unroll
-    for (int q = 0; q < 10; ++q) a.g[q] = 0;
+    for (int q = 0; q < 5; ++q) a.g[q] = 0;
 }
 
 template <typename T>
-__device__ __forceinline__ void reduce16(Moments<T>& a) {
+__device__ __forceinline__ void reduce_lanes(Moments<T>& a) {
 #pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) {
+    for (int o = kLanes / 2; o >= 1; o >>= 1) {
 #pragma unroll
-        for (int q = 0; q < 10; ++q) a.m[q] += __shfl_xor(a.m[q], o, 16);
+        for (int q = 0; q < 10; ++q) a.m[q] += __shfl_xor(a.m[q], o, kLanes);
 #pragma unroll
-        for (int q = 0; q < 12; ++q) a.r[q] += __shfl_xor(a.r[q], o, 16);
+        for (int q = 0; q < 12; ++q) a.r[q] += __shfl_xor(a.r[q], o, kLanes);
 #pragma unroll
-        for (int q = 0; q < 10; ++q) a.g[q] += __shfl_xor(a.g[q], o, 16);
+        for (int q = 0; q < 5; ++q) a.g[q] += __shfl_xor(a.g[q], o, kLanes);
     }
 }
 
-// Exact determinant of the integer Gram matrix of [1, d] (Laplace expansion by the 2x2
-// minors of rows 0,1 and 2,3).  |entries| <= 729*16 for r <= 4, so int64 is exact.
-__device__ __forceinline__ long long det_gram(const int* g) {
-    const long long a0 = g[0], a1 = g[1], a2 = g[2], a3 = g[3];       // n sx sy sz
-    const long long b0 = g[1], b1 = g[4], b2 = g[5], b3 = g[6];       // sx sxx sxy sxz
-    const long long c0 = g[2], c1 = g[5], c2 = g[7], c3 = g[8];       // sy sxy syy syz
-    const long long d0 = g[3], d1 = g[6], d2 = g[8], d3 = g[9];       // sz sxz syz szz
+// Two signed 16-bit sums packed as lo + hi * 2^16 (|sums| < 2^15 for r <= 4).
+__device__ __forceinline__ void unpack2(int p, long long& lo, long long& hi) {
+    const int l = (int)(short)(p & 0xffff);
+    lo = l;
+    hi = (long long)((p - l) >> 16);
+}
+
+// Exact determinant of the integer Gram matrix of [1, d] over the positive-weight offsets
+// (Laplace expansion by the 2x2 minors of rows 0,1 and rows 2,3).  For r <= 4 the entries
+// are below 729 * 16 in magnitude, so every product fits in int64.
+__device__ __forceinline__ long long det_gram(const int* gp) {
+    long long n, sxx, sx, sxy, sy, sxz, sz, syy, syz, szz;
+    unpack2(gp[0], n, sxx);
+    unpack2(gp[1], sx, sxy);
+    unpack2(gp[2], sy, sxz);
+    unpack2(gp[3], sz, syy);
+    unpack2(gp[4], syz, szz);
+    const long long a0 = n, a1 = sx, a2 = sy, a3 = sz;
+    const long long b0 = sx, b1 = sxx, b2 = sxy, b3 = sxz;
+    const long long c0 = sy, c1 = sxy, c2 = syy, c3 = syz;
+    const long long d0 = sz, d1 = sxz, d2 = syz, d3 = szz;
     const long long s0 = a0 * b1 - a1 * b0, s1 = a0 * b2 - a2 * b0, s2 = a0 * b3 - a3 * b0;
     const long long s3 = a1 * b2 - a2 * b1, s4 = a1 * b3 - a3 * b1, s5 = a2 * b3 - a3 * b2;
     const long long t5 = c2 * d3 - c3 * d2, t4 = c1 * d3 - c3 * d1, t3 = c1 * d2 - c2 * d1;
@@ -652,87 +752,94 @@ __device__ __forceinline__ void solve_intercept(const double* M, const double* R
     }
 }
 
+// 1 / |d| for |d|^2 = 0..48 (offsets within radius 4).
+__constant__ double c_rlen[49] = {
+    0.0, 1.0, 0.70710678118654752, 0.57735026918962576, 0.5, 0.44721359549995794,
+    0.40824829046386302, 0.37796447300922723, 0.35355339059327376, 0.33333333333333333,
+    0.31622776601683793, 0.30151134457776362, 0.28867513459481288, 0.27735009811261456,
+    0.26726124191242438, 0.25819888974716113, 0.25, 0.24253562503633297,
+    0.23570226039551584, 0.22941573387056177, 0.22360679774997897, 0.21821789023599238,
+    0.21320071635561044, 0.20851441405707477, 0.20412414523193151, 0.2,
+    0.19611613513818404, 0.19245008972987526, 0.18898223650461362, 0.18569533817705186,
+    0.18257418583505538, 0.17960530202677491, 0.17677669529663688, 0.17407765595569785,
+    0.17149858514250883, 0.16903085094570331, 0.16666666666666667, 0.16439898730535729,
+    0.16222142113076254, 0.16012815380508713, 0.15811388300841897, 0.15617376188860607,
+    0.15430334996209191, 0.15249857033260467, 0.15075567228888181, 0.14907119849998598,
+    0.14744195615489714, 0.14586499149789456, 0.14433756729740644};
+
 struct CellCtx {
     int i, j, k, n0, n1, n2, le;
     int64_t ncell;
-    const double* xi;
-    const int8_t* labels;
-    int64_t anchor;               // linear index of the anchor datum
+    const double* __restrict__ xi;
+    const int8_t* __restrict__ labels;
+    int32_t anchor;               // linear index of the anchor datum
     double a0, a1, a2;            // its xi
-    double g0, g1, g2, gn;        // normal (unnormalised) and its length
+    double g0, g1, g2, rgn;       // normal (unnormalised) and 1/|g|
 };
 
-// Weight of datum offset (dx,dy,dz) per eq. (weight); returns false for weight zero.
-// The sign test is the exact expression (dx gx + dy gy) + dz gz < 0 without contraction.
-__device__ __forceinline__ bool weight(const CellCtx& cx, int dx, int dy, int dz,
-                                       bool use_normal, double& w) {
-#pragma clang fp contract(off)
-    const int ad = abs(dx) + abs(dy) + abs(dz);
-    const double base = ldexp(1.0, -ad);
-    if (!use_normal) {
-        w = base;
-        return true;
-    }
-    const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
-    const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
-    if (!(dot < 0.0)) return false;
-    const double dlen = sqrt((fx * fx + fy * fy) + fz * fz);
-    w = (-dot / (dlen * cx.gn)) * base;
-    return true;
-}
-
-constexpr int kChunk = 8;
-
-// Accumulate the moments of the eligible data within Chebyshev radius r, lane q of 16
-// taking offsets q, q+16, ...  Ineligible slots read the anchor (offset 0 after
-// centring) with weight 0, so every load can be issued unconditionally.
-template <typename T>
-__device__ __forceinline__ void gather(const CellCtx& cx, int r, bool use_normal, int l16,
+// Accumulate the moments of the eligible data within Chebyshev radius R.  The (2R+1)^2
+// rows (dy, dz) of the box are dealt to the kLanes lanes of the cell; a lane walks the
+// 2R+1 cells of each of its rows (contiguous in memory).  Eq. (weight):
+// w = 2^-(|dx|+|dy|+|dz|), times the cosine between x_e - x_d = -d h and the normal when
+// use_normal; data with (dx gx + dy gy) + dz gz >= 0 (that exact expression, no
+// contraction) get weight 0.  Ineligible cells read the anchor (0 after centring) with
+// weight 0, so every load is issued unconditionally.
+template <typename T, int R>
+__device__ __forceinline__ void gather(const CellCtx& cx, bool use_normal, int lq,
                                        Moments<T>& acc) {
-    const int D = 2 * r + 1;
-    const int D3 = D * D * D;
-    for (int o0 = l16; o0 < D3; o0 += 16 * kChunk) {
-        int64_t cc[kChunk];
-        int dd[kChunk][3];
-        bool ok[kChunk];
+    constexpr int D = 2 * R + 1;
+    constexpr int ROWS = D * D;
+    constexpr int RPL = (ROWS + kLanes - 1) / kLanes;
+#pragma unroll 1
+    for (int q = 0; q < RPL; ++q) {
+        const int row = lq + kLanes * q;
+        if (row >= ROWS) break;
+        const int dy = row % D - R, dz = row / D - R;
+        const int jj = cx.j + dy, kk = cx.k + dz;
+        const bool rowin = (unsigned)jj < (unsigned)cx.n1 && (unsigned)kk < (unsigned)cx.n2;
+        const int32_t rb = (kk * cx.n1 + jj) * cx.n0;
+        int32_t cc[D];
+        bool ok[D];
+        int lab[D];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const int o = o0 + 16 * u;
-            const int dx = o % D - r, t2 = o / D;
-            const int dy = t2 % D - r, dz = t2 / D - r;
-            const int ii = cx.i + dx, jj = cx.j + dy, kk = cx.k + dz;
-            dd[u][0] = dx;
-            dd[u][1] = dy;
-            dd[u][2] = dz;
-            const bool in = o < D3 && (unsigned)ii < (unsigned)cx.n0 &&
-                            (unsigned)jj < (unsigned)cx.n1 && (unsigned)kk < (unsigned)cx.n2;
-            cc[u] = in ? ((int64_t)kk * cx.n1 + jj) * cx.n0 + ii : cx.anchor;
-            ok[u] = in;
+        for (int u = 0; u < D; ++u) {
+            const int ii = cx.i + u - R;
+            ok[u] = rowin && (unsigned)ii < (unsigned)cx.n0;
+            cc[u] = ok[u] ? rb + ii : cx.anchor;
         }
-        int lab[kChunk];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) lab[u] = cx.labels[cc[u]];
-        double w[kChunk];
+        for (int u = 0; u < D; ++u) lab[u] = cx.labels[cc[u]];
+        const int rowd2 = dy * dy + dz * dz;
+        T w[D];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
+        for (int u = 0; u < D; ++u) {
+            const int dx = u - R;
             bool e = ok[u] && lab[u] >= 0 && lab[u] < cx.le;
-            double ww = 0.0;
-            if (e) e = weight(cx, dd[u][0], dd[u][1], dd[u][2], use_normal, ww);
+            double ww = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
+            if (use_normal) {
+#pragma clang fp contract(off)
+                const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
+                const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
+                e = e && (dot < 0.0);
+                ww = (-dot * c_rlen[dx * dx + rowd2] * cx.rgn) * ww;
+            }
             ok[u] = e;
-            w[u] = e ? ww : 0.0;
+            w[u] = e ? (T)ww : T(0);
             if (!e) cc[u] = cx.anchor;
         }
-        double v[kChunk][3];
+        double v[D][3];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
+        for (int u = 0; u < D; ++u) {
             v[u][0] = cx.xi[cc[u]];
             v[u][1] = cx.xi[cx.ncell + cc[u]];
             v[u][2] = cx.xi[2 * cx.ncell + cc[u]];
         }
+        const T fy = (T)dy, fz = (T)dz;
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const T tw = (T)w[u];
-            const T fx = (T)dd[u][0], fy = (T)dd[u][1], fz = (T)dd[u][2];
+        for (int u = 0; u < D; ++u) {
+            const int dx = u - R;
+            const T tw = w[u];
+            const T fx = (T)dx;
             const T v0 = (T)(v[u][0] - cx.a0), v1 = (T)(v[u][1] - cx.a1),
                     v2 = (T)(v[u][2] - cx.a2);
             const T wx = tw * fx, wy = tw * fy, wz = tw * fz;
@@ -759,33 +866,99 @@ __device__ __forceinline__ void gather(const CellCtx& cx, int r, bool use_normal
             acc.r[10] += wz * v1;
             acc.r[11] += wz * v2;
             if (ok[u]) {
-                const int x = dd[u][0], y = dd[u][1], z = dd[u][2];
-                acc.g[0] += 1;
-                acc.g[1] += x;
-                acc.g[2] += y;
-                acc.g[3] += z;
-                acc.g[4] += x * x;
-                acc.g[5] += x * y;
-                acc.g[6] += x * z;
-                acc.g[7] += y * y;
-                acc.g[8] += y * z;
-                acc.g[9] += z * z;
+                acc.g[0] += 1 + ((dx * dx) << 16);
+                acc.g[1] += dx + ((dx * dy) << 16);
+                acc.g[2] += dy + ((dx * dz) << 16);
+                acc.g[3] += dz + ((dy * dy) << 16);
+                acc.g[4] += (dy * dz) + ((dz * dz) << 16);
             }
         }
     }
 }
 
+// Radii other than r_s = 2 (rare: degenerate systems): the same sums, one cell at a
+// time, rows dealt to the lanes as above.
+template <typename T>
+__device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_normal, int lq,
+                                        Moments<T>& acc) {
+    const int D = 2 * r + 1;
+    for (int row = lq; row < D * D; row += kLanes) {
+        const int dy = row % D - r, dz = row / D - r;
+        const int jj = cx.j + dy, kk = cx.k + dz;
+        if ((unsigned)jj >= (unsigned)cx.n1 || (unsigned)kk >= (unsigned)cx.n2) continue;
+        const int32_t rb = (kk * cx.n1 + jj) * cx.n0;
+        for (int dx = -r; dx <= r; ++dx) {
+            const int ii = cx.i + dx;
+            if ((unsigned)ii >= (unsigned)cx.n0) continue;
+            const int32_t c = rb + ii;
+            const int lab = cx.labels[c];
+            if (lab < 0 || lab >= cx.le) continue;
+            double ww = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
+            if (use_normal) {
+#pragma clang fp contract(off)
+                const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
+                const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
+                if (!(dot < 0.0)) continue;
+                ww = (-dot * c_rlen[dx * dx + dy * dy + dz * dz] * cx.rgn) * ww;
+            }
+            const T tw = (T)ww;
+            const T fx = (T)dx, fy = (T)dy, fz = (T)dz;
+            const T v0 = (T)(cx.xi[c] - cx.a0), v1 = (T)(cx.xi[cx.ncell + c] - cx.a1),
+                    v2 = (T)(cx.xi[2 * cx.ncell + c] - cx.a2);
+            const T wx = tw * fx, wy = tw * fy, wz = tw * fz;
+            acc.m[0] += tw;
+            acc.m[1] += wx;
+            acc.m[2] += wy;
+            acc.m[3] += wz;
+            acc.m[4] += wx * fx;
+            acc.m[5] += wx * fy;
+            acc.m[6] += wx * fz;
+            acc.m[7] += wy * fy;
+            acc.m[8] += wy * fz;
+            acc.m[9] += wz * fz;
+            acc.r[0] += tw * v0;
+            acc.r[1] += tw * v1;
+            acc.r[2] += tw * v2;
+            acc.r[3] += wx * v0;
+            acc.r[4] += wx * v1;
+            acc.r[5] += wx * v2;
+            acc.r[6] += wy * v0;
+            acc.r[7] += wy * v1;
+            acc.r[8] += wy * v2;
+            acc.r[9] += wz * v0;
+            acc.r[10] += wz * v1;
+            acc.r[11] += wz * v2;
+            acc.g[0] += 1 + ((dx * dx) << 16);
+            acc.g[1] += dx + ((dx * dy) << 16);
+            acc.g[2] += dy + ((dx * dz) << 16);
+            acc.g[3] += dz + ((dy * dy) << 16);
+            acc.g[4] += (dy * dz) + ((dz * dz) << 16);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_r(const CellCtx& cx, int r, bool use_normal, int lq,
+                                         Moments<T>& acc) {
+    if (r == 2)
+        gather<T, 2>(cx, use_normal, lq, acc);
+    else
+        gather_any<T>(cx, r, use_normal, lq, acc);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
+    constexpr int kCellsPerWave = 64 / kLanes;
     const int T_ = b.n_tiles;
     const int total = b.tile_off[l * (T_ + 1) + T_];
-    const int lane = threadIdx.x & 63, grp = lane >> 4, l16 = lane & 15;
+    const int lane = threadIdx.x & 63, grp = lane / kLanes, lq = lane % kLanes;
     const int wid = uniform_int(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int nwv = gridDim.x * 4;
-    for (int base = wid * 4; base < total; base += nwv * 4) {
+    for (int base = wid * kCellsPerWave; base < total; base += nwv * kCellsPerWave) {
         const int gidx = base + grp;
         if (gidx >= total) continue;
         const BandCell bc = locate(b, l, gidx);
+        if (bc.skip) continue;
         const DevSolid* d = &b.solids[bc.s];
         CellCtx cx;
         cx.n0 = d->n0;
@@ -800,44 +973,56 @@ __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
         cx.k = bc.cell / (cx.n0 * cx.n1);
         // Anchor: first face neighbour in a lower layer (-x, +x, -y, +y, -z, +z).  One
         // exists: the neighbour the cell was labelled from.
+        int32_t nbc[6];
+        bool nin[6];
+        nin[0] = cx.i > 0;          nbc[0] = nin[0] ? bc.cell - 1 : bc.cell;
+        nin[1] = cx.i + 1 < cx.n0;  nbc[1] = nin[1] ? bc.cell + 1 : bc.cell;
+        nin[2] = cx.j > 0;          nbc[2] = nin[2] ? bc.cell - cx.n0 : bc.cell;
+        nin[3] = cx.j + 1 < cx.n1;  nbc[3] = nin[3] ? bc.cell + cx.n0 : bc.cell;
+        nin[4] = cx.k > 0;          nbc[4] = nin[4] ? bc.cell - cx.n0 * cx.n1 : bc.cell;
+        nin[5] = cx.k + 1 < cx.n2;  nbc[5] = nin[5] ? bc.cell + cx.n0 * cx.n1 : bc.cell;
+        int nlab[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nlab[q] = cx.labels[nbc[q]];
         cx.anchor = bc.cell;
 #pragma unroll
-        for (int q = 5; q >= 0; --q) {
-            const int a = q >> 1, sg = (q & 1) ? 1 : -1;
-            const int ii = cx.i + (a == 0 ? sg : 0), jj = cx.j + (a == 1 ? sg : 0),
-                      kk = cx.k + (a == 2 ? sg : 0);
-            if ((unsigned)ii < (unsigned)cx.n0 && (unsigned)jj < (unsigned)cx.n1 &&
-                (unsigned)kk < (unsigned)cx.n2) {
-                const int64_t c = ((int64_t)kk * cx.n1 + jj) * cx.n0 + ii;
-                const int lb = cx.labels[c];
-                if (lb >= 0 && lb < l) cx.anchor = c;
-            }
-        }
+        for (int q = 5; q >= 0; --q)
+            if (nin[q] && nlab[q] >= 0 && nlab[q] < l) cx.anchor = nbc[q];
         cx.a0 = cx.xi[cx.anchor];
         cx.a1 = cx.xi[cx.ncell + cx.anchor];
         cx.a2 = cx.xi[2 * cx.ncell + cx.anchor];
         bool has_normal = false;
-        cx.g0 = cx.g1 = cx.g2 = cx.gn = 0.0;
+        cx.g0 = cx.g1 = cx.g2 = cx.rgn = 0.0;
         if (l <= b.normal_layers) {
             cx.g0 = b.normals[bc.slot];
             cx.g1 = b.normals[b.slot_cap + bc.slot];
             cx.g2 = b.normals[2 * b.slot_cap + bc.slot];
             has_normal = cx.g0 != 0.0 || cx.g1 != 0.0 || cx.g2 != 0.0;
-            cx.gn = norm3(cx.g0, cx.g1, cx.g2);
+            if (has_normal) cx.rgn = 1.0 / norm3(cx.g0, cx.g1, cx.g2);
         }
         const bool no_normal = (l <= b.normal_layers) && !has_normal;
 
+        // Passes: radii r_s..r_max with eq. (weight), then F1 (normal factor dropped) at
+        // r_max, then F2 (kernel-weighted mean) at r_max.
         int code = -1;
         double res[3] = {0.0, 0.0, 0.0};
-        const int npass = b.r_max - b.r_s + 2;
-        for (int pass = 0; pass < npass; ++pass) {
-            const bool f1 = pass == npass - 1;
-            if (f1 && !has_normal) break;
-            const int r = f1 ? b.r_max : b.r_s + pass;
+        const int nfit = b.r_max - b.r_s + 1;
+        for (int pass = 0; pass <= nfit + 1; ++pass) {
+            const bool f1 = pass == nfit, f2 = pass == nfit + 1;
+            if (f1 && !has_normal) continue;
+            const int r = (f1 || f2) ? b.r_max : b.r_s + pass;
             Moments<T> acc;
             zero(acc);
-            gather<T>(cx, r, has_normal && !f1, l16, acc);
-            reduce16(acc);
+            gather_r<T>(cx, r, has_normal && !f1 && !f2, lq, acc);
+            reduce_lanes(acc);
+            if (f2) {
+                const double sw = (double)acc.m[0];
+                res[0] = (double)acc.r[0] / sw;
+                res[1] = (double)acc.r[1] / sw;
+                res[2] = (double)acc.r[2] / sw;
+                code = kDecF2;
+                break;
+            }
             if (det_gram(acc.g) > 0) {
                 double M[10], Rr[12];
 #pragma unroll
@@ -849,19 +1034,7 @@ __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
                 break;
             }
         }
-        if (code < 0) {
-            // F2: kernel-weighted mean over the eligible data at r_max.
-            Moments<T> acc;
-            zero(acc);
-            gather<T>(cx, b.r_max, false, l16, acc);
-            reduce16(acc);
-            const double sw = (double)acc.m[0];
-            res[0] = (double)acc.r[0] / sw;
-            res[1] = (double)acc.r[1] / sw;
-            res[2] = (double)acc.r[2] / sw;
-            code = kDecF2;
-        }
-        if (l16 == 0) {
+        if (lq == 0) {
             const int64_t c = bc.cell;
             d->xi[c] = cx.a0 + res[0];
             d->xi[cx.ncell + c] = cx.a1 + res[1];
@@ -887,21 +1060,19 @@ static int grid_for(int64_t work, int per_block, int cap) {
     return (int)g;
 }
 
-hipError_t launch_zero(unsigned long long* p, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, p, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_classify(const Batch& b, hipStream_t st) {
-    // 256 CUs x 8 workgroups of 4 waves; each wave keeps 4 segments (4.5 KB) in flight.
-    const int grid = grid_for(b.total_words, 4 * kClassifyUnroll, 2048);
+    const int grid = b.n_chunks < 8192 ? b.n_chunks : 8192;
     hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 
-hipError_t launch_label(const Batch& b, hipStream_t st) {
-    const int RJ = kTileJ + 2 * b.Lmax, RK = kTileK + 2 * b.Lmax;
-    const size_t lds = sizeof(unsigned long long) * 2 * 3 * (size_t)RJ * RK;
+size_t label_lds_bytes(int Lmax, int tile_w, int Wmax) {
+    const int RJ = kTileJ + 2 * Lmax, RK = kTileK + 2 * Lmax;
+    const int RW = tile_w + 2 < Wmax ? tile_w + 2 : Wmax;
+    return sizeof(unsigned long long) * 2 * (size_t)RW * RJ * RK;
+}
+
+hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(k_label, dim3(b.n_tiles), dim3(256), lds, st, b);
     return hipGetLastError();
 }
@@ -918,7 +1089,7 @@ hipError_t launch_normal(const Batch& b, int64_t max_cells, hipStream_t st) {
 
 hipError_t launch_extrap(const Batch& b, int layer, int precision, int64_t max_cells,
                          hipStream_t st) {
-    const int grid = grid_for(max_cells, 16, 4096);
+    const int grid = grid_for(max_cells, 4 * (64 / kLanes), 4096);
     if (precision == 1)
         hipLaunchKernelGGL(k_extrap<float>, dim3(grid), dim3(256), 0, st, b, layer);
     else
