@@ -19,6 +19,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+METRIC = "band cells extrapolated/s & % HBM roofline; p50/p99 latency, batched vs plain"
 PRECISIONS = {"fp64": 0, "fp32acc": 1}
 
 
@@ -73,18 +74,24 @@ def profile_phases(ctx, dw, opt, steps):
     return {k: (ms / n, n) for k, (ms, n) in prof.items()}
 
 
-def kernel_bytes(phase, w, stats):
-    """Algorithmic HBM bytes of one launch of a phase (see the design notes): classify
-    reads xi once (24 B/cell) and writes the 1-bit mask; label reads the mask and writes
-    int8 labels; a layer fit writes 24 B per band cell of its layer."""
+def kernel_bytes(phase, w, stats, normal_layers=2):
+    """Algorithmic HBM bytes of one launch of a phase (the minimum it must move):
+    classify reads xi once (24 B/cell) and writes the 1-bit mask; label reads the mask
+    and writes int8 labels and a 4 B slot per band cell; normals read xi (24 B) and write
+    the normal (24 B) per cell of layers 1..normal_layers; the fit of layer l reads the
+    slot (4 B) and, where a normal is used, the normal (24 B), and writes xi (24 B) and
+    the decision (1 B) per cell of the layer; the scan moves only per-tile counts."""
     cells = w.box_cells
+    band = [sum(s["n_band"][l] for s in stats) for l in range(17)]
     if phase == "classify":
         return 24 * cells + cells / 8
     if phase == "label":
-        return cells / 8 + cells
+        return cells / 8 + cells + 4 * sum(band[1:])
+    if phase == "normal":
+        return 48 * sum(band[1:normal_layers + 1])
     if phase.startswith("extrap"):
         l = int(phase[6:])
-        return 24 * sum(s["n_band"][l] for s in stats)
+        return (29 + (24 if l <= normal_layers else 0)) * band[l]
     return None
 
 
@@ -92,19 +99,21 @@ def cpu_baseline(w, seconds, r_s=2, r_max=4, normal_layers=2):
     """The oracle as it stands, on this host's cores, on whole calls of the same workload
     until `seconds` of CPU work have run (at least one call)."""
     import oracle
-    from tests.helpers import run_oracle
     cores = len(os.sched_getaffinity(0))
+    probs = [oracle.make_problem(w.grid_n, s.lo, s.ext,
+                                 oracle.make_shape(s.shape.kind, s.shape.centre, s.shape.semi,
+                                                   s.shape.rot),
+                                 s.n_layers, r_s=r_s, r_max=r_max, normal_layers=normal_layers)
+             for s in w.solids]
     calls, band, t0 = 0, 0, time.perf_counter()
     while True:
-        for s in w.solids:
-            st, xo, lab, dec, stats = run_oracle(w, s, r_s=r_s, r_max=r_max,
-                                                 normal_layers=normal_layers, nthreads=cores)
+        for p, s in zip(probs, w.solids):
+            st, xo, lab, dec, stats = oracle.extrapolate(p, s.xi, nthreads=cores)
             band += int(stats[1:17].sum())
         calls += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    del oracle
     return {"value": band / el, "unit": "band cells/s", "cores": cores, "kind": "oracle",
             "sample": f"{calls} whole calls of {w.name} ({len(w.solids)} solid(s)), "
                       f"{el:.1f} s wall, OpenMP threads = {cores}"}
@@ -169,8 +178,10 @@ def main():
     ms = main_form["ms_per_call"]
 
     log("profiling kernels")
-    phases = profile_phases(ctx, dw, opt, max(10, min(args.steps, 50)))
-    dom = max((k for k in phases if k != "zero"), key=lambda k: phases[k][0])
+    prof_calls = max(10, min(args.steps, 50))
+    phases = profile_phases(ctx, dw, opt, prof_calls)
+    dom = max((k for k in phases if kernel_bytes(k, w, stats) is not None),
+              key=lambda k: phases[k][0])
     dom_ms = phases[dom][0]
     dom_bytes = kernel_bytes(dom, w, stats)
     roof = {"bound": "hbm", "kernel": dom, "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
@@ -209,7 +220,7 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds)
 
     out = {
-        "metric": "band cells extrapolated/s",
+        "metric": METRIC,
         "value": nb / (ms * 1e-3),
         "unit": "band cells/s",
         "n_gpus": 1,
@@ -228,7 +239,11 @@ def main():
         "call_roofline": {"bound": "hbm", "algorithmic_bytes": B,
                           "achieved": B / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)},
-        "kernels_ms": {k: v[0] for k, v in phases.items()},
+        "kernels": {k: {"ms": v[0], "launches_per_call": v[1] / prof_calls,
+                        "algorithmic_bytes": kernel_bytes(k, w, stats),
+                        "hbm_frac": (kernel_bytes(k, w, stats) / (v[0] * 1e-3) / 1e9
+                                     / HBM_PEAK_GBS) if kernel_bytes(k, w, stats) else None}
+                    for k, v in phases.items()},
         "cpu_baseline": cpu,
         "variants": variants,
     }

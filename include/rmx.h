@@ -59,6 +59,7 @@ extern "C" {
 #define RMX_E_BUDGET (-8)      /* server: request can never fit the HBM budget             */
 #define RMX_E_BUSY (-9)        /* server: submission queue full                            */
 #define RMX_E_NOTFOUND (-10)   /* server: unknown simulation or ticket                     */
+#define RMX_E_DISABLED (-11)   /* the requested launch form is switched off in this build  */
 
 #define RMX_MAX_LAYERS 16
 #define RMX_MAX_RADIUS 4
@@ -73,6 +74,9 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
 #define RMX_FLAG_PER_SOLID 4u  /* plain form: one launch chain per solid, in order        */
 #define RMX_FLAG_PROFILE 8u    /* record HIP events around every kernel of the chain (not
                                   with RMX_FLAG_GRAPH); read with rmx_profile_read         */
+#define RMX_FLAG_PERSISTENT 16u /* all phases of the batch in ONE persistent launch whose
+                                  work items wait on per-slab counters.  Switched off:
+                                  such a call fails with RMX_E_DISABLED.                   */
 
 /* Kernel phases reported by rmx_profile_read. */
 #define RMX_PHASE_ZERO 0
@@ -81,7 +85,8 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
 #define RMX_PHASE_SCAN 3
 #define RMX_PHASE_NORMAL 4
 #define RMX_PHASE_EXTRAP 5      /* + (layer - 1), layers 1..RMX_MAX_LAYERS               */
-#define RMX_N_PHASES 21
+#define RMX_PHASE_FUSED 21      /* the single persistent launch (switched off)           */
+#define RMX_N_PHASES 22
 
 /* Grid: M x N x O cells; cell (i,j,k) has centre origin + (idx + 1/2) h (SI, "Variable
  * arrangement"; isotropic spacing as in the paper's runs).  The fit is invariant to h
@@ -160,8 +165,12 @@ int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_
 
 /* Extrapolate n_solids solids, each independently, enqueued on `hip_stream` (a
  * hipStream_t; NULL = the default stream).  Arguments are validated on the host first
- * (nothing is enqueued on error).  All solids go through one batched launch chain unless
- * RMX_FLAG_PER_SOLID is set.  If `stats` (HOST, n_solids entries) is non-NULL or
+ * (nothing is enqueued on error).  By default the whole batch runs as one chain of
+ * kernels, each covering every solid (classify, label, scan, normals, one fit per layer);
+ * RMX_FLAG_PER_SOLID runs one chain per solid instead (the plain form), and
+ * RMX_FLAG_PERSISTENT is refused with RMX_E_DISABLED.  Calls on one context are ordered
+ * on its workspace: issue them on one stream (or serialise them).
+ * If `stats` (HOST, n_solids entries) is non-NULL or
  * RMX_FLAG_SYNC is set, the call waits for the stream, fills `stats` and returns the
  * first negative per-solid status (else RMX_OK); otherwise it returns at once and the
  * call does not allocate once the workspace suffices (graph-capturable). */

@@ -23,6 +23,19 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // Sizing without a device: the largest label tile (most slot padding).
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
+// The single persistent launch took a GPU memory fault whose cause is not known; until
+// it is, a library build refuses it (RMX_E_DISABLED).  Only the CPU emulation of the
+// kernels, a test harness, defines RMX_ENABLE_PERSISTENT.
+#ifdef RMX_ENABLE_PERSISTENT
+constexpr bool kPersistentEnabled = true;
+#else
+constexpr bool kPersistentEnabled = false;
+#endif
+
+bool persistent_requested(const rmx_options* o) {
+    return (o->flags & RMX_FLAG_PERSISTENT) && !(o->flags & RMX_FLAG_PER_SOLID);
+}
+
 uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
     const unsigned char* c = static_cast<const unsigned char*>(p);
     for (size_t i = 0; i < n; ++i) {
@@ -81,8 +94,98 @@ int rmx_validate(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids
     return RMX_OK;
 }
 
+namespace {
+
+// Dependency-respecting ticket order for the fused launch: per solid, classify the z-slabs
+// middle-out; a slab is labelled once its neighbours are classified; layer l of a slab is
+// fitted once its neighbours are labelled and fitted at layer l-1 (and, when the box has
+// a face inside the grid, once the whole solid is classified, so that a truncated band is
+// known before any write).  Solids are interleaved one classified slab at a time.
+void build_items(Plan* p) {
+    struct S {
+        std::vector<int> order;
+        size_t next = 0;
+        std::vector<char> c, lb;
+        std::vector<std::vector<char>> e;
+        int c_left = 0;
+    };
+    std::vector<S> st(p->n_solids);
+    for (int i = 0; i < p->n_solids; ++i) {
+        const DevSolid& d = p->solids[i];
+        S& x = st[i];
+        const int m = d.n_slabs / 2;
+        x.order.push_back(m);
+        for (int k = 1; (int)x.order.size() < d.n_slabs; ++k) {
+            if (m + k < d.n_slabs) x.order.push_back(m + k);
+            if (m - k >= 0) x.order.push_back(m - k);
+        }
+        x.c.assign(d.n_slabs, 0);
+        x.lb.assign(d.n_slabs, 0);
+        x.e.assign(d.L + 1, std::vector<char>(d.n_slabs, 0));
+        x.c_left = d.n_slabs;
+    }
+    auto chunks = [](const DevSolid& d, int z) {
+        const int z0 = z * kTileK, z1 = std::min(z0 + kTileK, d.n2);
+        const int words = (z1 - z0) * d.n1 * d.W;
+        return (words + kChunkWords - 1) / kChunkWords;
+    };
+    p->items.clear();
+    bool more = true;
+    while (more) {
+        more = false;
+        for (int i = 0; i < p->n_solids; ++i) {
+            const DevSolid& d = p->solids[i];
+            S& x = st[i];
+            if (x.next < x.order.size()) {
+                const int z = x.order[x.next++];
+                const int nch = chunks(d, z);
+                for (int q = 0; q < nch; ++q)
+                    p->items.push_back(FItem{FI_CLASSIFY, 0, (uint16_t)z, (uint16_t)i, (uint16_t)q});
+                x.c[z] = 1;
+                --x.c_left;
+                more = true;
+            }
+            auto all3 = [&](const std::vector<char>& v, int z) {
+                for (int zz = std::max(0, z - 1); zz <= std::min(d.n_slabs - 1, z + 1); ++zz)
+                    if (!v[zz]) return false;
+                return true;
+            };
+            for (int z = 0; z < d.n_slabs; ++z) {
+                if (x.lb[z] || !all3(x.c, z)) continue;
+                for (int q = 0; q < d.ty * d.ntx; ++q)
+                    p->items.push_back(FItem{FI_LABEL, 0, (uint16_t)z, (uint16_t)i, (uint16_t)q});
+                x.lb[z] = 1;
+                more = true;
+            }
+            if (d.has_nonwall && x.c_left > 0) continue;
+            for (int l = 1; l <= d.L; ++l) {
+                for (int z = 0; z < d.n_slabs; ++z) {
+                    if (x.e[l][z] || !all3(x.lb, z) || (l > 1 && !all3(x.e[l - 1], z))) continue;
+                    for (int q = 0; q < d.parts; ++q)
+                        p->items.push_back(
+                            FItem{FI_EXTRAP, (uint8_t)l, (uint16_t)z, (uint16_t)i, (uint16_t)q});
+                    x.e[l][z] = 1;
+                    more = true;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
 int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
-             const rmx_options* opt, size_t lds_limit, Plan* p) {
+             const rmx_options* opt, size_t lds_limit, bool fused, Plan* p) {
+    // Item fields are 16-bit: very large batches or boxes take the chain.
+    if (n_solids > 65535) fused = false;
+    for (int i = 0; i < n_solids && fused; ++i) {
+        const int slabs = (solids[i].ext[2] + kTileK - 1) / kTileK;
+        const int64_t per_slab_words = (int64_t)kTileK * solids[i].ext[1] * ((solids[i].ext[0] + 63) / 64);
+        if (slabs > 65535 || (per_slab_words + kChunkWords - 1) / kChunkWords > 65535 ||
+            (int64_t)((solids[i].ext[1] + kTileJ - 1) / kTileJ) * ((solids[i].ext[0] + 63) / 64) > 65535)
+            fused = false;
+    }
+    p->fused = fused;
     p->n_solids = n_solids;
     p->solids.assign(n_solids, DevSolid{});
     p->tile_solid.clear();
@@ -92,10 +195,12 @@ int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
         p->Lmax = std::max(p->Lmax, solids[i].n_layers);
         Wmax = std::max(Wmax, (solids[i].ext[0] + 63) / 64);
     }
-    // Label tile width: as many 64-cell words as fit the LDS limit (at most 4).
-    int tw = std::min(4, Wmax);
+    // Label tile width: as many 64-cell words as fit the LDS limit (at most 4); the fused
+    // kernel uses one-word tiles (fewer registers, more and smaller items).
+    int tw = fused ? 1 : std::min(4, Wmax);
     while (tw > 1 && label_lds_bytes(p->Lmax, tw, Wmax) > lds_limit) tw = tw > 2 ? 2 : 1;
     p->lds_bytes = label_lds_bytes(p->Lmax, tw, Wmax);
+    if (fused) p->lds_bytes = fused_lds_bytes(p->lds_bytes);
     if (p->lds_bytes > lds_limit) return RMX_E_LAYERS;
     p->tile_w = tw;
     p->tile_cells = 64 * tw * kTileJ * kTileK;
@@ -129,6 +234,13 @@ int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
             for (int a = 0; a < 3; ++a) d.semi[a] = s.phi0.semi_axes[a];
             for (int q = 0; q < 9; ++q) d.rot[q] = s.phi0.rot[q];
         }
+        d.n_slabs = (d.n2 + kTileK - 1) / kTileK;
+        d.nbx = (d.n0 + kBrick - 1) / kBrick;
+        d.nby = (d.n1 + kBrick - 1) / kBrick;
+        d.bcap = d.nbx * d.nby * 2;
+        d.parts = std::max(4, std::min(64, d.bcap / 4));
+        d.has_nonwall = 0;
+        for (int a = 0; a < 3; ++a) d.has_nonwall |= !d.wall_lo[a] || !d.wall_hi[a];
         d.xi = s.xi;
         d.xi_normal = s.xi_normal ? s.xi_normal : s.xi;
         d.labels = s.labels;
@@ -140,6 +252,11 @@ int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
         const int64_t nw = (int64_t)d.n1 * d.n2 * d.W;
         chunks += (int)((nw + kChunkWords - 1) / kChunkWords);
         words += nw;
+        d.total_chunks = 0;
+        for (int z = 0; z < d.n_slabs; ++z) {
+            const int z0 = z * kTileK, z1 = std::min(z0 + kTileK, d.n2);
+            d.total_chunks += ((z1 - z0) * d.n1 * d.W + kChunkWords - 1) / kChunkWords;
+        }
         tiles += nt;
         slots += (int64_t)nt * p->tile_cells;
         cells += d.ncell;
@@ -172,20 +289,42 @@ int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
     off = align256(off + sizeof(int32_t) * (size_t)chunks);
     p->off_mask = off;
     off = align256(off + sizeof(unsigned long long) * (size_t)words);
-    p->off_slots = off;
-    off = align256(off + sizeof(int32_t) * (size_t)slots);
-    p->off_normals = off;
-    if (p->normal_layers > 0) off = align256(off + 3 * sizeof(double) * (size_t)slots);
+    if (!fused) {
+        p->off_slots = off;
+        off = align256(off + sizeof(int32_t) * (size_t)slots);
+        p->off_normals = off;
+        if (p->normal_layers > 0) off = align256(off + 3 * sizeof(double) * (size_t)slots);
+    } else {
+        // per-cell normals of each solid, brick lists, counters
+        p->off_normals = off;
+        if (p->normal_layers > 0) off = align256(off + 3 * sizeof(double) * (size_t)cells);
+        int ctr = kCtrGlobal;
+        int64_t list = 0;
+        for (auto& d : p->solids) {
+            d.ctr = ctr;
+            ctr += kCtrSolid + d.n_slabs * (2 + 2 * d.L);
+            d.list = list;
+            list += (int64_t)d.L * d.n_slabs * d.bcap;
+        }
+        p->ctr_words = ctr;
+        p->off_lists = off;
+        off = align256(off + sizeof(int32_t) * (size_t)std::max<int64_t>(list, 1));
+        build_items(p);
+    }
     p->ws_bytes = off;
     return RMX_OK;
 }
 
 void rmx_bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
     char* base = static_cast<char*>(ws);
-    int64_t word = 0;
+    int64_t word = 0, cell = 0;
     for (auto& d : p->solids) {
         d.mask = reinterpret_cast<unsigned long long*>(base + p->off_mask) + word;
         word += (int64_t)d.n1 * d.n2 * d.W;
+        d.normals = (p->fused && p->normal_layers > 0)
+                        ? reinterpret_cast<double*>(base + p->off_normals) + 3 * cell
+                        : nullptr;
+        cell += d.ncell;
     }
     b->solids = reinterpret_cast<const DevSolid*>(base + p->off_desc);
     b->n_solids = p->n_solids;
@@ -301,7 +440,9 @@ void rmx_convert_stats(const unsigned long long* dev, int n, rmx_solid_stats* ou
         o.n_no_normal = (int64_t)s[ST_NONORMAL];
         o.n_f1 = (int64_t)s[ST_F1];
         o.n_f2 = (int64_t)s[ST_F2];
-        if (s[ST_FLAGS] & FLAG_TRUNCATED)
+        if (s[ST_FLAGS] & FLAG_TIMEOUT)
+            o.status = RMX_E_HIP;
+        else if (s[ST_FLAGS] & FLAG_TRUNCATED)
             o.status = RMX_E_TRUNCATED;
         else if (o.n_interior == 0)
             o.status = RMX_W_EMPTY;
@@ -345,9 +486,70 @@ struct rmx_ctx {
     std::unordered_map<uint64_t, GraphEntry> graphs;
     std::vector<rmx_solid_stats> tmp_stats;
     Profiler prof;
+    // fused launch: item list (cached by content), self-resetting counters, grid sizes
+    FItem* items = nullptr;
+    size_t items_cap = 0;
+    size_t items_n = 0;
+    uint64_t items_key = 0;
+    int* ctr = nullptr;
+    size_t ctr_cap = 0;
+    std::unordered_map<uint64_t, int> fused_blocks;
 };
 
 namespace {
+
+void drop_graphs(rmx_ctx* c);
+
+// Upload the item list unless the cached one is identical.
+int ensure_items(rmx_ctx* c, const Plan& p, hipStream_t st) {
+    const size_t n = p.items.size();
+    const uint64_t key = fnv1a(p.items.data(), n * sizeof(FItem), 1469598103934665603ull ^ n);
+    if (c->items && c->items_n == n && c->items_key == key) return RMX_OK;
+    if (n > c->items_cap) {
+        if (c->items) {
+            if (hipDeviceSynchronize() != hipSuccess) return RMX_E_HIP;
+            drop_graphs(c);
+            (void)hipFree(c->items);
+            c->items = nullptr;
+        }
+        const size_t cap = n + n / 2 + 64;
+        if (hipMalloc(&c->items, cap * sizeof(FItem)) != hipSuccess) {
+            c->items = nullptr;
+            c->items_cap = 0;
+            return RMX_E_HIP;
+        }
+        c->items_cap = cap;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
+    if (hipMemcpy(c->items, p.items.data(), n * sizeof(FItem), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return RMX_E_HIP;
+    c->items_n = n;
+    c->items_key = key;
+    return RMX_OK;
+}
+
+// Counters start at zero and the kernel's last block resets them, so a grown buffer is
+// cleared once, here, outside any graph.
+int ensure_ctr(rmx_ctx* c, size_t words) {
+    if (words <= c->ctr_cap) return RMX_OK;
+    if (c->ctr) {
+        if (hipDeviceSynchronize() != hipSuccess) return RMX_E_HIP;
+        drop_graphs(c);
+        (void)hipFree(c->ctr);
+        c->ctr = nullptr;
+    }
+    const size_t cap = words + words / 2 + 256;
+    if (hipMalloc(&c->ctr, cap * sizeof(int)) != hipSuccess) {
+        c->ctr = nullptr;
+        c->ctr_cap = 0;
+        return RMX_E_HIP;
+    }
+    if (hipMemset(c->ctr, 0, cap * sizeof(int)) != hipSuccess) return RMX_E_HIP;
+    if (hipDeviceSynchronize() != hipSuccess) return RMX_E_HIP;
+    c->ctr_cap = cap;
+    return RMX_OK;
+}
 
 void drop_graphs(rmx_ctx* c) {
     for (auto& kv : c->graphs) {
@@ -427,13 +629,45 @@ uint64_t call_key(const rmx_grid* g, const rmx_solid* s, int n, const rmx_option
 int run_batch(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int n,
               const rmx_options* opt, hipStream_t st, bool use_graph, size_t stats_off,
               bool want_stats) {
+    const bool fused = persistent_requested(opt);
     Plan p;
-    int rc = rmx_plan(grid, solids, n, opt, c->lds_limit, &p);
+    int rc = rmx_plan(grid, solids, n, opt, c->lds_limit, fused, &p);
     if (rc != RMX_OK) return rc;
     rc = ensure_ws(c, p.ws_bytes);
     if (rc != RMX_OK) return rc;
     Batch b{};
     rmx_bind(&p, c->ws, opt, &b);
+    Fused f{};
+    int blocks = 0;
+    if (fused) {
+        if ((rc = ensure_ctr(c, (size_t)p.ctr_words)) != RMX_OK) return rc;
+        if ((rc = ensure_items(c, p, st)) != RMX_OK) return rc;
+        f.items = c->items;
+        f.n_items = (int32_t)p.items.size();
+        f.ctr_words = p.ctr_words;
+        f.ctr = c->ctr;
+        f.lists = reinterpret_cast<int32_t*>(static_cast<char*>(c->ws) + p.off_lists);
+        f.lds_work = (int32_t)(p.lds_bytes - kFusedSmallBytes);
+        const uint64_t gkey = ((uint64_t)opt->precision << 40) ^ (uint64_t)p.lds_bytes;
+        auto it = c->fused_blocks.find(gkey);
+        if (it == c->fused_blocks.end()) {
+            int nb = 0;
+            if (fused_grid(opt->precision, p.lds_bytes, c->device, &nb) != hipSuccess)
+                return RMX_E_HIP;
+            it = c->fused_blocks.emplace(gkey, nb).first;
+        }
+        blocks = std::max(1, std::min(it->second, f.n_items));
+    }
+    auto enqueue = [&](hipStream_t s, Profiler* prof) -> hipError_t {
+        if (!fused) return rmx_enqueue(p, b, opt->precision, s, prof);
+        Profiler::Rec rec{};
+        hipError_t e;
+        if (prof && (e = prof->begin(RMX_PHASE_FUSED, s, &rec)) != hipSuccess) return e;
+        if ((e = launch_fused(b, f, opt->precision, p.lds_bytes, blocks, s)) != hipSuccess)
+            return e;
+        if (prof && (e = prof->end(rec, s)) != hipSuccess) return e;
+        return hipSuccess;
+    };
 
     if (use_graph) {
         const uint64_t key = call_key(grid, solids, n, opt);
@@ -456,7 +690,7 @@ int run_batch(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int n,
             if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) !=
                 hipSuccess)
                 return RMX_E_HIP;
-            hipError_t e = rmx_enqueue(p, b, opt->precision, c->capture_stream);
+            hipError_t e = enqueue(c->capture_stream, nullptr);
             hipGraph_t graph = nullptr;
             hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
             if (e != hipSuccess || e2 != hipSuccess || !graph) return RMX_E_HIP;
@@ -479,7 +713,7 @@ int run_batch(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int n,
         if (hipEventRecord(sg->ev, st) != hipSuccess) return RMX_E_HIP;
         sg->pending = true;
         Profiler* prof = (opt->flags & RMX_FLAG_PROFILE) ? &c->prof : nullptr;
-        if (rmx_enqueue(p, b, opt->precision, st, prof) != hipSuccess) return RMX_E_HIP;
+        if (enqueue(st, prof) != hipSuccess) return RMX_E_HIP;
     }
     if (want_stats) {
         if (hipMemcpyAsync(c->stats_host + stats_off, b.stats,
@@ -550,6 +784,8 @@ int rmx_destroy(rmx_ctx* c) {
     }
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->items) (void)hipFree(c->items);
+    if (c->ctr) (void)hipFree(c->ctr);
     if (c->ws) (void)hipFree(c->ws);
     delete c;
     return RMX_OK;
@@ -567,13 +803,14 @@ int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_
     if (opt->flags & RMX_FLAG_PER_SOLID) {
         for (int i = 0; i < n_solids; ++i) {
             Plan p;
-            const int rc = rmx_plan(grid, solids + i, 1, opt, kMaxLdsBytes, &p);
+            const int rc = rmx_plan(grid, solids + i, 1, opt, kMaxLdsBytes, false, &p);
             if (rc != RMX_OK) return rc;
             total = std::max(total, p.ws_bytes);
         }
     } else {
         Plan p;
-        const int rc = rmx_plan(grid, solids, n_solids, opt, kMaxLdsBytes, &p);
+        const int rc = rmx_plan(grid, solids, n_solids, opt, kMaxLdsBytes,
+                                persistent_requested(opt), &p);
         if (rc != RMX_OK) return rc;
         total = p.ws_bytes;
     }
@@ -590,6 +827,7 @@ int rmx_extrapolate(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     if (!opt) opt = &def;
     int rc = rmx_validate(grid, solids, n_solids, opt);
     if (rc != RMX_OK) return rc;
+    if (persistent_requested(opt) && !kPersistentEnabled) return RMX_E_DISABLED;
     if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const bool sync = stats || (opt->flags & RMX_FLAG_SYNC);
@@ -645,6 +883,7 @@ const char* rmx_status_string(int s) {
         case RMX_E_BUDGET: return "request exceeds the HBM budget";
         case RMX_E_BUSY: return "queue full";
         case RMX_E_NOTFOUND: return "not found";
+        case RMX_E_DISABLED: return "launch form switched off in this build";
         default: return "unknown status";
     }
 }

@@ -30,6 +30,11 @@ struct Plan {
     size_t off_chunk_tile = 0, off_chunk_flag = 0;
     size_t off_mask = 0, off_slots = 0, off_normals = 0;
     size_t ws_bytes = 0;
+    // fused persistent form
+    bool fused = false;
+    std::vector<FItem> items;
+    int ctr_words = 0;
+    size_t off_lists = 0;
 };
 
 // Records HIP events around each launch of the chain when attached to rmx_enqueue.
@@ -54,7 +59,7 @@ struct Profiler {
 int rmx_validate(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
                  const rmx_options* opt);
 int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
-             const rmx_options* opt, size_t lds_limit, rmx::Plan* p);
+             const rmx_options* opt, size_t lds_limit, bool fused, rmx::Plan* p);
 void rmx_bind(rmx::Plan* p, void* ws, const rmx_options* opt, rmx::Batch* b);
 void rmx_pack_desc(const rmx::Plan& p, void* host);
 hipError_t rmx_enqueue(const rmx::Plan& p, const rmx::Batch& b, int precision,

@@ -1,0 +1,604 @@
+// Device helpers shared by the per-solid launch chain and the fused persistent kernel.
+// Method: Lin, Derr & Rycroft (arXiv 2104.00095), section "Extrapolation of xi(x,t)" and
+// SI "Weighting scheme for weighted least squares-based extrapolation", eq. (weight).
+#pragma once
+#include "rmx_internal.h"
+
+namespace rmx {
+namespace dev {
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------------------------
+// phi0 and the interior predicate.  Evaluated without contraction, in the fixed order the
+// interface documents, so that the interior decision and the normal's sign test are
+// bit-identical to any other implementation of the same expressions.
+// ------------------------------------------------------------------------------------
+struct ShapeR {
+    int kind;
+    double c0, c1, c2;
+    double e0, e1, e2;
+    double r00, r01, r02, r10, r11, r12, r20, r21, r22;  // rot[b][a]
+};
+
+__device__ __forceinline__ ShapeR load_shape(const DevSolid* d) {
+    ShapeR s;
+    s.kind = d->kind;
+    s.c0 = d->centre[0]; s.c1 = d->centre[1]; s.c2 = d->centre[2];
+    s.e0 = d->semi[0]; s.e1 = d->semi[1]; s.e2 = d->semi[2];
+    s.r00 = d->rot[0]; s.r01 = d->rot[1]; s.r02 = d->rot[2];
+    s.r10 = d->rot[3]; s.r11 = d->rot[4]; s.r12 = d->rot[5];
+    s.r20 = d->rot[6]; s.r21 = d->rot[7]; s.r22 = d->rot[8];
+    return s;
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) {
+#pragma clang fp contract(off)
+    return sqrt((a * a + b * b) + c * c);
+}
+
+__device__ __forceinline__ bool finite3(double a, double b, double c) {
+    return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
+}
+
+__device__ __forceinline__ void body(const ShapeR& s, double v0, double v1, double v2,
+                                     double& y0, double& y1, double& y2) {
+#pragma clang fp contract(off)
+    const double d0 = v0 - s.c0, d1 = v1 - s.c1, d2 = v2 - s.c2;
+    y0 = (s.r00 * d0 + s.r10 * d1) + s.r20 * d2;
+    y1 = (s.r01 * d0 + s.r11 * d1) + s.r21 * d2;
+    y2 = (s.r02 * d0 + s.r12 * d1) + s.r22 * d2;
+}
+
+// phi0(xi) < 0: |xi - c|^2 < R^2 (sphere) or the quadratic form < 1 (ellipsoid).
+__device__ __forceinline__ bool interior(const ShapeR& s, double v0, double v1, double v2) {
+#pragma clang fp contract(off)
+    if (!finite3(v0, v1, v2)) return false;
+    if (s.kind == 1) {
+        const double dx = v0 - s.c0, dy = v1 - s.c1, dz = v2 - s.c2;
+        return ((dx * dx + dy * dy) + dz * dz) < s.e0 * s.e0;
+    }
+    double y0, y1, y2;
+    body(s, v0, v1, v2, y0, y1, y2);
+    const double q0 = y0 / s.e0, q1 = y1 / s.e1, q2 = y2 / s.e2;
+    return ((q0 * q0 + q1 * q1) + q2 * q2) < 1.0;
+}
+
+__device__ __forceinline__ double pick3(int i, double a, double b, double c) {
+    return i == 0 ? a : (i == 1 ? b : c);
+}
+
+// Distance from body point y to the ellipsoid with semi-axes e: Lagrange multiplier of
+// the closest point measured from the pole of the shortest axis among the non-zero
+// coordinates, bisected until the midpoint equals an end of the bracket; the off-plane
+// candidate first when every shortest-axis coordinate is exactly zero.
+__device__ inline double ellipsoid_distance(double e0, double e1, double e2, double y0, double y1,
+                                     double y2) {
+#pragma clang fp contract(off)
+    const double u0 = fabs(y0), u1 = fabs(y1), u2 = fabs(y2);
+    const double q0 = e0 * e0, q1 = e1 * e1, q2 = e2 * e2;
+    int amin = 0;
+    if (e1 < pick3(amin, e0, e1, e2)) amin = 1;
+    if (e2 < pick3(amin, e0, e1, e2)) amin = 2;
+    int m = -1;
+    if (u0 > 0.0) m = 0;
+    if (u1 > 0.0 && (m < 0 || e1 < pick3(m, e0, e1, e2))) m = 1;
+    if (u2 > 0.0 && (m < 0 || e2 < pick3(m, e0, e1, e2))) m = 2;
+    const double emin = pick3(amin, e0, e1, e2);
+    if (m < 0) return emin;
+    const double em = pick3(m, e0, e1, e2);
+    const double qmin = pick3(amin, q0, q1, q2);
+    if (em > emin) {
+        double S = 0.0, D = 0.0;
+        if (u0 > 0.0) {
+            const double x = (q0 * u0) / (q0 - qmin);
+            const double t = x / e0;
+            S = S + t * t;
+            D = D + (x - u0) * (x - u0);
+        }
+        if (u1 > 0.0) {
+            const double x = (q1 * u1) / (q1 - qmin);
+            const double t = x / e1;
+            S = S + t * t;
+            D = D + (x - u1) * (x - u1);
+        }
+        if (u2 > 0.0) {
+            const double x = (q2 * u2) / (q2 - qmin);
+            const double t = x / e2;
+            S = S + t * t;
+            D = D + (x - u2) * (x - u2);
+        }
+        if (S < 1.0) return sqrt(D + qmin * (1.0 - S));
+    }
+    const double qm = pick3(m, q0, q1, q2);
+    const double d0 = q0 - qm, d1 = q1 - qm, d2 = q2 - qm;
+    double sq = 0.0;
+    if (u0 > 0.0) { const double p = e0 * u0; sq = sq + p * p; }
+    if (u1 > 0.0) { const double p = e1 * u1; sq = sq + p * p; }
+    if (u2 > 0.0) { const double p = e2 * u2; sq = sq + p * p; }
+    double s0 = em * pick3(m, u0, u1, u2);
+    double s1 = sqrt(sq);
+    for (int it = 0; it < 4096; ++it) {
+        const double sm = 0.5 * (s0 + s1);
+        if (sm <= s0 || sm >= s1) break;
+        double f = 0.0;
+        if (u0 > 0.0) { const double t = (e0 * u0) / (sm + d0); f = f + t * t; }
+        if (u1 > 0.0) { const double t = (e1 * u1) / (sm + d1); f = f + t * t; }
+        if (u2 > 0.0) { const double t = (e2 * u2) / (sm + d2); f = f + t * t; }
+        f = f - 1.0;
+        if (f > 0.0) {
+            s0 = sm;
+        } else if (f < 0.0) {
+            s1 = sm;
+        } else {
+            s0 = sm;
+            s1 = sm;
+            break;
+        }
+    }
+    const double s = 0.5 * (s0 + s1);
+    double D = 0.0;
+    {
+        const double x = (u0 > 0.0) ? (q0 * u0) / (s + d0) : 0.0;
+        D = D + (x - u0) * (x - u0);
+    }
+    {
+        const double x = (u1 > 0.0) ? (q1 * u1) / (s + d1) : 0.0;
+        D = D + (x - u1) * (x - u1);
+    }
+    {
+        const double x = (u2 > 0.0) ? (q2 * u2) / (s + d2) : 0.0;
+        D = D + (x - u2) * (x - u2);
+    }
+    return sqrt(D);
+}
+
+// Signed distance phi0(v), negative inside; the sign is the interior predicate's.
+__device__ inline double phi0(const ShapeR& s, double v0, double v1, double v2) {
+#pragma clang fp contract(off)
+    double dist;
+    if (s.kind == 1) {
+        const double dx = v0 - s.c0, dy = v1 - s.c1, dz = v2 - s.c2;
+        dist = fabs(sqrt((dx * dx + dy * dy) + dz * dz) - s.e0);
+    } else {
+        double y0, y1, y2;
+        body(s, v0, v1, v2, y0, y1, y2);
+        dist = ellipsoid_distance(s.e0, s.e1, s.e2, y0, y1, y2);
+    }
+    return interior(s, v0, v1, v2) ? -dist : dist;
+}
+
+// ------------------------------------------------------------------------------------
+// Helpers.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int find_solid_by_chunk(const DevSolid* s, int n, int c) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s[mid].chunk_base <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Exclusive scan of one int per thread over a block of NW waves.
+template <int NW>
+__device__ __forceinline__ void block_scan(int v, int& excl, int& total, int* s_wave) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    int wb = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int t = s_wave[i];
+        if (i < wid) wb += t;
+        tot += t;
+    }
+    excl = wb + x - v;
+    total = tot;
+    __syncthreads();
+}
+
+// Spread the low 4 bits of x to the low bit of 4 bytes (bit q -> byte q).  The partial
+// products of x * (1 + 2^7 + 2^14 + 2^21) land on distinct bit positions, so no carries.
+__device__ __forceinline__ uint32_t spread4(uint32_t x) {
+    return (x * 0x00204081u) & 0x01010101u;
+}
+
+__device__ __forceinline__ unsigned long long spread8(uint32_t x) {
+    return (unsigned long long)spread4(x & 15u) |
+           ((unsigned long long)spread4((x >> 4) & 15u) << 32);
+}
+
+// ------------------------------------------------------------------------------------
+// Extrapolation of one layer.  kLanes lanes per band cell (64 / kLanes cells per wave).
+// ------------------------------------------------------------------------------------
+constexpr int kLanes = 8;
+
+template <typename T>
+struct Moments {
+    T m[10];   // sum w [1,d][1,d]^T: (0,0) (0,x) (0,y) (0,z) (x,x) (x,y) (x,z) (y,y) (y,z) (z,z)
+    T r[12];   // sum w [1,d] v^T: rows 1, dx, dy, dz; columns the 3 components
+    int g[5];  // unweighted integer moments over the positive-weight offsets, two 16-bit
+               // fields per word: (n, sxx) (sx, sxy) (sy, sxz) (sz, syy) (syz, szz)
+};
+
+template <typename T>
+__device__ __forceinline__ void zero(Moments<T>& a) {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) a.m[q] = T(0);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) a.r[q] = T(0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a.g[q] = 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void reduce_lanes(Moments<T>& a) {
+#pragma unroll
+    for (int o = kLanes / 2; o >= 1; o >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) a.m[q] += __shfl_xor(a.m[q], o, kLanes);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) a.r[q] += __shfl_xor(a.r[q], o, kLanes);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a.g[q] += __shfl_xor(a.g[q], o, kLanes);
+    }
+}
+
+// Two signed 16-bit sums packed as lo + hi * 2^16 (|sums| < 2^15 for r <= 4).
+__device__ __forceinline__ void unpack2(int p, long long& lo, long long& hi) {
+    const int l = (int)(short)(p & 0xffff);
+    lo = l;
+    hi = (long long)((p - l) >> 16);
+}
+
+// Exact determinant of the integer Gram matrix of [1, d] over the positive-weight offsets
+// (Laplace expansion by the 2x2 minors of rows 0,1 and rows 2,3).  For r <= 4 the entries
+// are below 729 * 16 in magnitude, so every product fits in int64.
+__device__ __forceinline__ long long det_gram(const int* gp) {
+    long long n, sxx, sx, sxy, sy, sxz, sz, syy, syz, szz;
+    unpack2(gp[0], n, sxx);
+    unpack2(gp[1], sx, sxy);
+    unpack2(gp[2], sy, sxz);
+    unpack2(gp[3], sz, syy);
+    unpack2(gp[4], syz, szz);
+    const long long a0 = n, a1 = sx, a2 = sy, a3 = sz;
+    const long long b0 = sx, b1 = sxx, b2 = sxy, b3 = sxz;
+    const long long c0 = sy, c1 = sxy, c2 = syy, c3 = syz;
+    const long long d0 = sz, d1 = sxz, d2 = syz, d3 = szz;
+    const long long s0 = a0 * b1 - a1 * b0, s1 = a0 * b2 - a2 * b0, s2 = a0 * b3 - a3 * b0;
+    const long long s3 = a1 * b2 - a2 * b1, s4 = a1 * b3 - a3 * b1, s5 = a2 * b3 - a3 * b2;
+    const long long t5 = c2 * d3 - c3 * d2, t4 = c1 * d3 - c3 * d1, t3 = c1 * d2 - c2 * d1;
+    const long long t2 = c0 * d3 - c3 * d0, t1 = c0 * d2 - c2 * d0, t0 = c0 * d1 - c1 * d0;
+    return s0 * t5 - s1 * t4 + s2 * t3 + s3 * t2 - s4 * t1 + s5 * t0;
+}
+
+// Intercept of the WLS fit from the normal equations, Cholesky in FP64.
+__device__ __forceinline__ void solve_intercept(const double* M, const double* Rr,
+                                                double out[3]) {
+    const double l00 = sqrt(M[0]);
+    const double i00 = 1.0 / l00;
+    const double l10 = M[1] * i00, l20 = M[2] * i00, l30 = M[3] * i00;
+    const double l11 = sqrt(M[4] - l10 * l10);
+    const double i11 = 1.0 / l11;
+    const double l21 = (M[5] - l20 * l10) * i11, l31 = (M[6] - l30 * l10) * i11;
+    const double l22 = sqrt(M[7] - l20 * l20 - l21 * l21);
+    const double i22 = 1.0 / l22;
+    const double l32 = (M[8] - l30 * l20 - l31 * l21) * i22;
+    const double l33 = sqrt(M[9] - l30 * l30 - l31 * l31 - l32 * l32);
+    const double i33 = 1.0 / l33;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double y0 = Rr[c] * i00;
+        const double y1 = (Rr[3 + c] - l10 * y0) * i11;
+        const double y2 = (Rr[6 + c] - l20 * y0 - l21 * y1) * i22;
+        const double y3 = (Rr[9 + c] - l30 * y0 - l31 * y1 - l32 * y2) * i33;
+        const double b3 = y3 * i33;
+        const double b2 = (y2 - l32 * b3) * i22;
+        const double b1 = (y1 - l21 * b2 - l31 * b3) * i11;
+        out[c] = (y0 - l10 * b1 - l20 * b2 - l30 * b3) * i00;
+    }
+}
+
+// 1 / |d| for |d|^2 = 0..48 (offsets within radius 4).
+static __constant__ double c_rlen[49] = {
+    0.0, 1.0, 0.70710678118654752, 0.57735026918962576, 0.5, 0.44721359549995794,
+    0.40824829046386302, 0.37796447300922723, 0.35355339059327376, 0.33333333333333333,
+    0.31622776601683793, 0.30151134457776362, 0.28867513459481288, 0.27735009811261456,
+    0.26726124191242438, 0.25819888974716113, 0.25, 0.24253562503633297,
+    0.23570226039551584, 0.22941573387056177, 0.22360679774997897, 0.21821789023599238,
+    0.21320071635561044, 0.20851441405707477, 0.20412414523193151, 0.2,
+    0.19611613513818404, 0.19245008972987526, 0.18898223650461362, 0.18569533817705186,
+    0.18257418583505538, 0.17960530202677491, 0.17677669529663688, 0.17407765595569785,
+    0.17149858514250883, 0.16903085094570331, 0.16666666666666667, 0.16439898730535729,
+    0.16222142113076254, 0.16012815380508713, 0.15811388300841897, 0.15617376188860607,
+    0.15430334996209191, 0.15249857033260467, 0.15075567228888181, 0.14907119849998598,
+    0.14744195615489714, 0.14586499149789456, 0.14433756729740644};
+
+struct CellCtx {
+    int i, j, k, n0, n1, n2, le;
+    int64_t ncell;
+    const double* __restrict__ xi;
+    const int8_t* __restrict__ labels;
+    int32_t anchor;               // linear index of the anchor datum
+    double a0, a1, a2;            // its xi
+    double g0, g1, g2, rgn;       // normal (unnormalised) and 1/|g|
+};
+
+// Accumulate the moments of the eligible data within Chebyshev radius R.  The (2R+1)^2
+// rows (dy, dz) of the box are dealt to the kLanes lanes of the cell; a lane walks the
+// 2R+1 cells of each of its rows (contiguous in memory).  Eq. (weight):
+// w = 2^-(|dx|+|dy|+|dz|), times the cosine between x_e - x_d = -d h and the normal when
+// use_normal; data with (dx gx + dy gy) + dz gz >= 0 (that exact expression, no
+// contraction) get weight 0.  Ineligible cells read the anchor (0 after centring) with
+// weight 0, so every load is issued unconditionally.
+template <typename T, int R>
+__device__ __forceinline__ void gather(const CellCtx& cx, bool use_normal, int lq,
+                                       Moments<T>& acc) {
+    constexpr int D = 2 * R + 1;
+    constexpr int ROWS = D * D;
+    constexpr int RPL = (ROWS + kLanes - 1) / kLanes;
+#pragma unroll 1
+    for (int q = 0; q < RPL; ++q) {
+        const int row = lq + kLanes * q;
+        if (row >= ROWS) break;
+        const int dy = row % D - R, dz = row / D - R;
+        const int jj = cx.j + dy, kk = cx.k + dz;
+        const bool rowin = (unsigned)jj < (unsigned)cx.n1 && (unsigned)kk < (unsigned)cx.n2;
+        const int32_t rb = (kk * cx.n1 + jj) * cx.n0;
+        int32_t cc[D];
+        bool ok[D];
+        int lab[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int ii = cx.i + u - R;
+            ok[u] = rowin && (unsigned)ii < (unsigned)cx.n0;
+            cc[u] = ok[u] ? rb + ii : cx.anchor;
+        }
+#pragma unroll
+        for (int u = 0; u < D; ++u) lab[u] = cx.labels[cc[u]];
+        const int rowd2 = dy * dy + dz * dz;
+        T w[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int dx = u - R;
+            bool e = ok[u] && lab[u] >= 0 && lab[u] < cx.le;
+            double ww = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
+            if (use_normal) {
+#pragma clang fp contract(off)
+                const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
+                const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
+                e = e && (dot < 0.0);
+                ww = (-dot * c_rlen[dx * dx + rowd2] * cx.rgn) * ww;
+            }
+            ok[u] = e;
+            w[u] = e ? (T)ww : T(0);
+            if (!e) cc[u] = cx.anchor;
+        }
+        double v[D][3];
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            v[u][0] = cx.xi[cc[u]];
+            v[u][1] = cx.xi[cx.ncell + cc[u]];
+            v[u][2] = cx.xi[2 * cx.ncell + cc[u]];
+        }
+        const T fy = (T)dy, fz = (T)dz;
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int dx = u - R;
+            const T tw = w[u];
+            const T fx = (T)dx;
+            const T v0 = (T)(v[u][0] - cx.a0), v1 = (T)(v[u][1] - cx.a1),
+                    v2 = (T)(v[u][2] - cx.a2);
+            const T wx = tw * fx, wy = tw * fy, wz = tw * fz;
+            acc.m[0] += tw;
+            acc.m[1] += wx;
+            acc.m[2] += wy;
+            acc.m[3] += wz;
+            acc.m[4] += wx * fx;
+            acc.m[5] += wx * fy;
+            acc.m[6] += wx * fz;
+            acc.m[7] += wy * fy;
+            acc.m[8] += wy * fz;
+            acc.m[9] += wz * fz;
+            acc.r[0] += tw * v0;
+            acc.r[1] += tw * v1;
+            acc.r[2] += tw * v2;
+            acc.r[3] += wx * v0;
+            acc.r[4] += wx * v1;
+            acc.r[5] += wx * v2;
+            acc.r[6] += wy * v0;
+            acc.r[7] += wy * v1;
+            acc.r[8] += wy * v2;
+            acc.r[9] += wz * v0;
+            acc.r[10] += wz * v1;
+            acc.r[11] += wz * v2;
+            if (ok[u]) {
+                acc.g[0] += 1 + ((dx * dx) << 16);
+                acc.g[1] += dx + ((dx * dy) << 16);
+                acc.g[2] += dy + ((dx * dz) << 16);
+                acc.g[3] += dz + ((dy * dy) << 16);
+                acc.g[4] += (dy * dz) + ((dz * dz) << 16);
+            }
+        }
+    }
+}
+
+// Radii other than r_s = 2 (rare: degenerate systems): the same sums, one cell at a
+// time, rows dealt to the lanes as above.
+template <typename T>
+__device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_normal, int lq,
+                                        Moments<T>& acc) {
+    const int D = 2 * r + 1;
+    for (int row = lq; row < D * D; row += kLanes) {
+        const int dy = row % D - r, dz = row / D - r;
+        const int jj = cx.j + dy, kk = cx.k + dz;
+        if ((unsigned)jj >= (unsigned)cx.n1 || (unsigned)kk >= (unsigned)cx.n2) continue;
+        const int32_t rb = (kk * cx.n1 + jj) * cx.n0;
+        for (int dx = -r; dx <= r; ++dx) {
+            const int ii = cx.i + dx;
+            if ((unsigned)ii >= (unsigned)cx.n0) continue;
+            const int32_t c = rb + ii;
+            const int lab = cx.labels[c];
+            if (lab < 0 || lab >= cx.le) continue;
+            double ww = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
+            if (use_normal) {
+#pragma clang fp contract(off)
+                const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
+                const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
+                if (!(dot < 0.0)) continue;
+                ww = (-dot * c_rlen[dx * dx + dy * dy + dz * dz] * cx.rgn) * ww;
+            }
+            const T tw = (T)ww;
+            const T fx = (T)dx, fy = (T)dy, fz = (T)dz;
+            const T v0 = (T)(cx.xi[c] - cx.a0), v1 = (T)(cx.xi[cx.ncell + c] - cx.a1),
+                    v2 = (T)(cx.xi[2 * cx.ncell + c] - cx.a2);
+            const T wx = tw * fx, wy = tw * fy, wz = tw * fz;
+            acc.m[0] += tw;
+            acc.m[1] += wx;
+            acc.m[2] += wy;
+            acc.m[3] += wz;
+            acc.m[4] += wx * fx;
+            acc.m[5] += wx * fy;
+            acc.m[6] += wx * fz;
+            acc.m[7] += wy * fy;
+            acc.m[8] += wy * fz;
+            acc.m[9] += wz * fz;
+            acc.r[0] += tw * v0;
+            acc.r[1] += tw * v1;
+            acc.r[2] += tw * v2;
+            acc.r[3] += wx * v0;
+            acc.r[4] += wx * v1;
+            acc.r[5] += wx * v2;
+            acc.r[6] += wy * v0;
+            acc.r[7] += wy * v1;
+            acc.r[8] += wy * v2;
+            acc.r[9] += wz * v0;
+            acc.r[10] += wz * v1;
+            acc.r[11] += wz * v2;
+            acc.g[0] += 1 + ((dx * dx) << 16);
+            acc.g[1] += dx + ((dx * dy) << 16);
+            acc.g[2] += dy + ((dx * dz) << 16);
+            acc.g[3] += dz + ((dy * dy) << 16);
+            acc.g[4] += (dy * dz) + ((dz * dz) << 16);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_r(const CellCtx& cx, int r, bool use_normal, int lq,
+                                         Moments<T>& acc) {
+    if (r == 2)
+        gather<T, 2>(cx, use_normal, lq, acc);
+    else
+        gather_any<T>(cx, r, use_normal, lq, acc);
+}
+
+// Unnormalised gradient of phi0(xi) at box cell (i, j, k) of `f` (SI, weighting scheme):
+// central differences over the face neighbours where both are defined and inside the
+// box, else one-sided with the cell itself (forward first), else 0.  The seven cells are
+// loaded unconditionally (clamped into the box) before any use.
+__device__ __forceinline__ void normal_at(const ShapeR& sh, const double* __restrict__ f,
+                                          int64_t nc, int n0, int n1, int n2, int32_t cell,
+                                          int i, int j, int k, double g[3]) {
+    bool in[7];
+    int64_t cc[7];
+    in[0] = true;
+    cc[0] = cell;
+    in[1] = i + 1 < n0; cc[1] = in[1] ? cell + 1 : cell;
+    in[2] = i > 0;      cc[2] = in[2] ? cell - 1 : cell;
+    in[3] = j + 1 < n1; cc[3] = in[3] ? cell + n0 : cell;
+    in[4] = j > 0;      cc[4] = in[4] ? cell - n0 : cell;
+    in[5] = k + 1 < n2; cc[5] = in[5] ? cell + (int64_t)n0 * n1 : cell;
+    in[6] = k > 0;      cc[6] = in[6] ? cell - (int64_t)n0 * n1 : cell;
+    double x0[7], x1[7], x2[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        x0[q] = f[cc[q]];
+        x1[q] = f[nc + cc[q]];
+        x2[q] = f[2 * nc + cc[q]];
+    }
+    double ph[7];
+    bool def[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        def[q] = in[q] && finite3(x0[q], x1[q], x2[q]);
+        ph[q] = def[q] ? phi0(sh, x0[q], x1[q], x2[q]) : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int qp = 1 + 2 * a, qm = 2 + 2 * a;
+        double ga;
+        if (def[qp] && def[qm]) ga = 0.5 * (ph[qp] - ph[qm]);
+        else if (def[qp] && def[0]) ga = ph[qp] - ph[0];
+        else if (def[qm] && def[0]) ga = ph[0] - ph[qm];
+        else ga = 0.0;
+        g[a] = ga;
+    }
+}
+
+// Weighted moments from one (weight, offset, centred value) datum.
+template <typename T>
+__device__ __forceinline__ void add_datum(Moments<T>& acc, T tw, int dx, int dy, int dz,
+                                          T v0, T v1, T v2, bool counted) {
+    const T fx = (T)dx, fy = (T)dy, fz = (T)dz;
+    const T wx = tw * fx, wy = tw * fy, wz = tw * fz;
+    acc.m[0] += tw;
+    acc.m[1] += wx;
+    acc.m[2] += wy;
+    acc.m[3] += wz;
+    acc.m[4] += wx * fx;
+    acc.m[5] += wx * fy;
+    acc.m[6] += wx * fz;
+    acc.m[7] += wy * fy;
+    acc.m[8] += wy * fz;
+    acc.m[9] += wz * fz;
+    acc.r[0] += tw * v0;
+    acc.r[1] += tw * v1;
+    acc.r[2] += tw * v2;
+    acc.r[3] += wx * v0;
+    acc.r[4] += wx * v1;
+    acc.r[5] += wx * v2;
+    acc.r[6] += wy * v0;
+    acc.r[7] += wy * v1;
+    acc.r[8] += wy * v2;
+    acc.r[9] += wz * v0;
+    acc.r[10] += wz * v1;
+    acc.r[11] += wz * v2;
+    if (counted) {
+        acc.g[0] += 1 + ((dx * dx) << 16);
+        acc.g[1] += dx + ((dx * dy) << 16);
+        acc.g[2] += dy + ((dx * dz) << 16);
+        acc.g[3] += dz + ((dy * dy) << 16);
+        acc.g[4] += (dy * dz) + ((dz * dz) << 16);
+    }
+}
+
+// Weight of offset (dx, dy, dz) per eq. (weight); false if it is zero (ineligible or in
+// front of the interface).  The sign test is the exact expression
+// (dx gx + dy gy) + dz gz < 0, without contraction.
+__device__ __forceinline__ bool weight_of(int dx, int dy, int dz, bool use_normal, double g0,
+                                          double g1, double g2, double rgn, double& w) {
+    double ww = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
+    if (use_normal) {
+#pragma clang fp contract(off)
+        const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
+        const double dot = (fx * g0 + fy * g1) + fz * g2;
+        if (!(dot < 0.0)) {
+            w = 0.0;
+            return false;
+        }
+        ww = (-dot * c_rlen[dx * dx + dy * dy + dz * dz] * rgn) * ww;
+    }
+    w = ww;
+    return true;
+}
+
+}  // namespace dev
+}  // namespace rmx

@@ -40,7 +40,16 @@ struct DevSolid {
     int32_t n_tiles;         // tiles of the solid
     int32_t ntx;             // tiles along x (tile_w words each)
     int32_t chunk_base;      // first classification chunk of the solid
+    // fused path: z-slabs of kTileK planes, 8^3 bricks, counters and brick lists
+    int32_t n_slabs;
+    int32_t nbx, nby;        // bricks along x, y
+    int32_t bcap;            // brick capacity of one slab: nbx * nby * 2
+    int32_t parts;           // extrapolation items per (slab, layer)
+    int32_t has_nonwall;     // some box face is not a grid wall (truncation possible)
+    int32_t total_chunks;    // classification items of the solid
+    int32_t ctr;             // first counter of the solid
     int32_t pad0;
+    int64_t list;            // first brick-list entry of the solid
     int64_t ncell;
     int64_t word_base;       // first global mask word
     int64_t slot_base;       // first slot in the slot buffer
@@ -49,6 +58,7 @@ struct DevSolid {
     double rot[9];
     double* xi;
     const double* xi_normal; // field the normals come from (xi if none given)
+    double* normals;         // fused path: [3][ncell] normals of the band cells, or null
     int8_t* labels;
     int8_t* decisions;       // nullable
     unsigned long long* mask;  // [n2 * n1][W]
@@ -79,7 +89,43 @@ struct Batch {
     unsigned long long* stats;  // [n_solids][kStatWords]
 };
 
-// Launchers (rmx_kernels.hip).
+// Fused persistent path: one launch, work items taken by ticket in an order where every
+// dependency precedes its dependents.
+enum : uint8_t { FI_CLASSIFY = 0, FI_LABEL = 1, FI_EXTRAP = 2 };
+struct FItem {
+    uint8_t type;
+    uint8_t layer;
+    uint16_t slab;
+    uint16_t solid;
+    uint16_t idx;            // chunk / tile within the slab, or extrapolation part
+};
+constexpr int kBrick = 8;                    // brick edge (cells)
+constexpr int kBrickHalo = 2;                // r_s of the paper
+constexpr int kBrickSpan = kBrick + 2 * kBrickHalo;   // 12
+constexpr int kBrickCells = kBrickSpan * kBrickSpan * kBrickSpan;  // 1728
+constexpr size_t kBrickLds = kBrickCells * 25 + 512 * 2;   // xi + labels + cell list
+// counters: [0] ticket, [1] finished blocks, [2] error; per solid from its `ctr`:
+// +0 classified chunks, +1 truncated, +2 radius grown, +3 no normal, +4 F1, +5 F2, then
+// per slab: classified chunks, labelled tiles; per (layer, slab): finished extrapolation
+// items, bricks listed.
+constexpr int kCtrGlobal = 4;
+constexpr int kCtrSolid = 6;
+constexpr unsigned long long FLAG_TIMEOUT = 2ull;
+
+struct Fused {
+    const FItem* items;
+    int32_t n_items;
+    int32_t ctr_words;       // counters used by this call (reset at the end)
+    int* ctr;
+    int32_t* lists;
+    int32_t lds_work;        // bytes of the item work area at the start of the dynamic LDS
+    int32_t pad0;
+};
+// block state after the work area: scan slots, ticket, last flag; brick flags
+constexpr int kFusedSmallInts = 8;
+constexpr size_t kFusedSmallBytes = kFusedSmallInts * sizeof(int) + kMaxLayers * 32;
+
+// Launchers (rmx_kernels.hip, rmx_fused.hip).
 hipError_t launch_classify(const Batch& b, hipStream_t st);
 size_t label_lds_bytes(int Lmax, int tile_w, int Wmax);
 hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st);
@@ -87,5 +133,9 @@ hipError_t launch_scan(const Batch& b, hipStream_t st);
 hipError_t launch_normal(const Batch& b, int64_t max_cells, hipStream_t st);
 hipError_t launch_extrap(const Batch& b, int layer, int precision, int64_t max_cells,
                          hipStream_t st);
+size_t fused_lds_bytes(size_t label_lds);
+hipError_t fused_grid(int precision, size_t lds, int device, int* blocks);
+hipError_t launch_fused(const Batch& b, const Fused& f, int precision, size_t lds, int blocks,
+                        hipStream_t st);
 
 }  // namespace rmx

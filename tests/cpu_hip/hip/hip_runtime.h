@@ -1,0 +1,183 @@
+// CPU emulation of the small HIP subset librmx uses, so that the library (host core AND
+// kernels) can be compiled for the host and run under AddressSanitizer on tiny inputs.
+// Test infrastructure only.  A block's threads are host threads; __syncthreads and the
+// cross-lane operations are barriers over the block, the 64-lane wave or the shuffle
+// group.  Blocks of a launch run one after another, so a kernel's __shared__ variables can
+// be statics; device memory is host memory.  Kernels whose blocks wait on each other work
+// when the launch has a single block (the host shim reports one CU, one block per CU).
+#pragma once
+#include <algorithm>
+#include <atomic>
+#include <barrier>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __noinline__
+#define __constant__
+#define __shared__ static
+#define __launch_bounds__(...)
+#define __align__(n) alignas(n)
+#define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(rmx_emu::dyn_lds());
+
+struct dim3 {
+    unsigned x = 1, y = 1, z = 1;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+
+using std::max;
+using std::min;
+
+namespace rmx_emu {
+struct Block;
+extern thread_local dim3 threadIdx_, blockIdx_;
+extern dim3 blockDim_, gridDim_;
+extern thread_local Block* block_;
+unsigned char* dyn_lds();
+void sync_block();
+// exchange of one 64-bit value among `width` consecutive lanes of the caller's group
+uint64_t* group_exchange(uint64_t v, int width);
+void group_done(int width);
+}  // namespace rmx_emu
+
+#define threadIdx rmx_emu::threadIdx_
+#define blockIdx rmx_emu::blockIdx_
+#define blockDim rmx_emu::blockDim_
+#define gridDim rmx_emu::gridDim_
+
+inline void __syncthreads() { rmx_emu::sync_block(); }
+inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+int __syncthreads_or(int p);
+
+template <typename T>
+inline uint64_t rmx_emu_bits(T v) {
+    uint64_t u = 0;
+    std::memcpy(&u, &v, sizeof(T));
+    return u;
+}
+template <typename T>
+inline T rmx_emu_from(uint64_t u) {
+    T v;
+    std::memcpy(&v, &u, sizeof(T));
+    return v;
+}
+
+inline unsigned long long __ballot(int pred) {
+    uint64_t* s = rmx_emu::group_exchange(pred ? 1 : 0, 64);
+    unsigned long long m = 0;
+    for (int i = 0; i < 64; ++i)
+        if (s[i]) m |= 1ull << i;
+    rmx_emu::group_done(64);
+    return m;
+}
+template <typename T>
+inline T __shfl_xor(T v, int o, int width = 64) {
+    const int lane = threadIdx.x % width;
+    uint64_t* s = rmx_emu::group_exchange(rmx_emu_bits(v), width);
+    const T r = rmx_emu_from<T>(s[lane ^ o]);
+    rmx_emu::group_done(width);
+    return r;
+}
+template <typename T>
+inline T __shfl_up(T v, int o, int width = 64) {
+    const int lane = threadIdx.x % width;
+    uint64_t* s = rmx_emu::group_exchange(rmx_emu_bits(v), width);
+    const T r = lane >= o ? rmx_emu_from<T>(s[lane - o]) : v;
+    rmx_emu::group_done(width);
+    return r;
+}
+inline int __builtin_amdgcn_readfirstlane(int v) {
+    uint64_t* s = rmx_emu::group_exchange((uint64_t)(uint32_t)v, 64);
+    const int r = (int)(uint32_t)s[0];
+    rmx_emu::group_done(64);
+    return r;
+}
+inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+inline int __ffsll(long long x) { return __builtin_ffsll(x); }
+
+template <typename T>
+inline T atomicAdd(T* p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+template <typename T>
+inline T atomicOr(T* p, T v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+#define __HIP_MEMORY_SCOPE_AGENT 0
+#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
+
+// ---- host API ------------------------------------------------------------------------
+typedef enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 } hipError_t;
+typedef struct rmx_emu_stream* hipStream_t;
+typedef struct rmx_emu_event* hipEvent_t;
+typedef struct rmx_emu_graph* hipGraph_t;
+typedef struct rmx_emu_graph* hipGraphExec_t;
+typedef struct rmx_emu_graph_node* hipGraphNode_t;
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
+enum hipDeviceAttribute_t { hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            hipDeviceAttributeMultiprocessorCount };
+enum hipStreamCaptureMode { hipStreamCaptureModeThreadLocal };
+#define hipHostMallocDefault 0
+#define hipEventDisableTiming 0
+#define hipStreamNonBlocking 0
+
+hipError_t hipGetDeviceCount(int* n);
+hipError_t hipSetDevice(int d);
+hipError_t hipDeviceSynchronize();
+hipError_t hipGetLastError();
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int d);
+hipError_t hipMalloc(void** p, size_t n);
+template <typename T>
+inline hipError_t hipMalloc(T** p, size_t n) { return hipMalloc(reinterpret_cast<void**>(p), n); }
+hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t n, unsigned flags);
+template <typename T>
+inline hipError_t hipHostMalloc(T** p, size_t n, unsigned flags) {
+    return hipHostMalloc(reinterpret_cast<void**>(p), n, flags);
+}
+hipError_t hipHostFree(void* p);
+hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind k);
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st);
+hipError_t hipMemset(void* d, int v, size_t n);
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned f);
+hipError_t hipStreamDestroy(hipStream_t s);
+hipError_t hipStreamSynchronize(hipStream_t s);
+hipError_t hipEventCreate(hipEvent_t* e);
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned f);
+hipError_t hipEventDestroy(hipEvent_t e);
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
+hipError_t hipEventSynchronize(hipEvent_t e);
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode m);
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g);
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t* n, char* l,
+                               size_t ln);
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
+hipError_t hipGraphExecDestroy(hipGraphExec_t e);
+hipError_t hipGraphDestroy(hipGraph_t g);
+namespace rmx_emu { int concurrent_blocks(); }
+template <typename K>
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, K, int, size_t) {
+    *n = rmx_emu::concurrent_blocks();
+    return hipSuccess;
+}
+
+namespace rmx_emu {
+// `concurrent`: run all blocks of the launch at once (kernels whose blocks wait on each
+// other and keep no block state in static __shared__ variables).
+void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, bool concurrent,
+            std::function<void()> body);
+int concurrent_blocks();
+}
+#define hipLaunchKernelGGL(K, G, B, L, S, ...)                                          \
+    rmx_emu::launch((G), (B), (L), (S), std::string(#K).find("k_fused") == 0,          \
+                    [=]() { K(__VA_ARGS__); })

@@ -1,0 +1,112 @@
+// Runs one rmx_extrapolate call of the CPU-emulated library on a case written by
+// tests/cpu_hip/emu.py and writes the outputs next to it.  Test infrastructure only.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "hip/hip_runtime.h"
+#include "rmx.h"
+
+static std::vector<char> slurp(const char* path) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) { std::perror(path); std::exit(2); }
+    std::fseek(f, 0, SEEK_END);
+    const long n = std::ftell(f);
+    std::fseek(f, 0, SEEK_SET);
+    std::vector<char> b(n);
+    if (n && std::fread(b.data(), 1, n, f) != (size_t)n) std::exit(2);
+    std::fclose(f);
+    return b;
+}
+
+int main(int argc, char** argv) {
+    if (argc != 2) return 2;
+    const std::string dir = argv[1];
+    FILE* h = std::fopen((dir + "/case.txt").c_str(), "r");
+    if (!h) return 2;
+    rmx_grid g{};
+    rmx_options o{};
+    int ns = 0, reps = 1;
+    if (std::fscanf(h, "%d %d %d %d %lf %lf %lf %lf", &ns, &g.n[0], &g.n[1], &g.n[2], &g.h,
+                    &g.origin[0], &g.origin[1], &g.origin[2]) != 8) return 2;
+    unsigned flags = 0;
+    if (std::fscanf(h, "%d %d %d %d %u %d", &o.r_s, &o.r_max, &o.normal_layers, &o.precision,
+                    &flags, &reps) != 6) return 2;
+    o.flags = flags;
+    std::vector<rmx_solid> sol(ns);
+    std::vector<size_t> ncell(ns);
+    for (int i = 0; i < ns; ++i) {
+        rmx_solid& s = sol[i];
+        int has_normal = 0;
+        if (std::fscanf(h, "%d %d %d %d %d %d %d %d", &s.lo[0], &s.lo[1], &s.lo[2], &s.ext[0],
+                        &s.ext[1], &s.ext[2], &s.n_layers, &s.phi0.kind) != 8) return 2;
+        for (double* p : {&s.phi0.centre[0], &s.phi0.centre[1], &s.phi0.centre[2],
+                          &s.phi0.semi_axes[0], &s.phi0.semi_axes[1], &s.phi0.semi_axes[2]})
+            if (std::fscanf(h, "%lf", p) != 1) return 2;
+        for (int q = 0; q < 9; ++q)
+            if (std::fscanf(h, "%lf", &s.phi0.rot[q]) != 1) return 2;
+        if (std::fscanf(h, "%d", &has_normal) != 1) return 2;
+        ncell[i] = (size_t)s.ext[0] * s.ext[1] * s.ext[2];
+        auto xi = slurp((dir + "/xi" + std::to_string(i) + ".bin").c_str());
+        double* dxi = nullptr;
+        hipMalloc(&dxi, xi.size());
+        std::memcpy(dxi, xi.data(), xi.size());
+        s.xi = dxi;
+        if (has_normal) {
+            auto xn = slurp((dir + "/xn" + std::to_string(i) + ".bin").c_str());
+            double* dxn = nullptr;
+            hipMalloc(&dxn, xn.size());
+            std::memcpy(dxn, xn.data(), xn.size());
+            s.xi_normal = dxn;
+        }
+        int8_t* lab = nullptr;
+        int8_t* dec = nullptr;
+        hipMalloc(&lab, ncell[i]);
+        hipMalloc(&dec, ncell[i]);
+        s.labels = lab;
+        s.decisions = dec;
+    }
+    std::fclose(h);
+    rmx_ctx* ctx = nullptr;
+    int st = rmx_create(0, 0, &ctx);
+    if (st) return 3;
+    std::vector<rmx_solid_stats> stats(ns);
+    // Optional warm-up calls with other flags on fresh copies of the fields (the same
+    // context), as a test process does before the measured call.
+    FILE* pre = std::fopen((dir + "/pre_flags.txt").c_str(), "r");
+    if (pre) {
+        unsigned pf = 0;
+        while (std::fscanf(pre, "%u", &pf) == 1) {
+            std::vector<rmx_solid> tmp = sol;
+            for (int i = 0; i < ns; ++i) {
+                double* x = nullptr;
+                hipMalloc(&x, ncell[i] * 3 * sizeof(double));
+                std::memcpy(x, sol[i].xi, ncell[i] * 3 * sizeof(double));
+                tmp[i].xi = x;
+            }
+            rmx_options po = o;
+            po.flags = pf;
+            rmx_extrapolate(ctx, &g, tmp.data(), ns, &po, nullptr, stats.data());
+            for (int i = 0; i < ns; ++i) hipFree(tmp[i].xi);
+        }
+        std::fclose(pre);
+    }
+    for (int r = 0; r < reps; ++r) st = rmx_extrapolate(ctx, &g, sol.data(), ns, &o, nullptr,
+                                                         stats.data());
+    FILE* out = std::fopen((dir + "/status.txt").c_str(), "w");
+    std::fprintf(out, "%d\n", st);
+    std::fclose(out);
+    for (int i = 0; i < ns; ++i) {
+        auto put = [&](const char* name, const void* p, size_t n) {
+            FILE* f = std::fopen((dir + "/" + name + std::to_string(i) + ".bin").c_str(), "wb");
+            std::fwrite(p, 1, n, f);
+            std::fclose(f);
+        };
+        put("out", sol[i].xi, ncell[i] * 3 * sizeof(double));
+        put("lab", sol[i].labels, ncell[i]);
+        put("dec", sol[i].decisions, ncell[i]);
+        put("st", &stats[i], sizeof(rmx_solid_stats));
+    }
+    rmx_destroy(ctx);
+    return 0;
+}

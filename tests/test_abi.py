@@ -97,11 +97,12 @@ def test_host_validation():
     assert _ws(g, [_desc()], rmx.options(r_max=5))[0] == rmx.E_ARG
     assert _ws(g, [_desc()], rmx.options(precision=2))[0] == rmx.E_ARG
     assert _ws(rmx.grid((32, 32, 32), 0.0), [_desc()])[0] == rmx.E_ARG
-    # batched workspace covers every solid; the per-solid form needs only the largest
+    # the batched chain's workspace covers every solid; the per-solid form needs only the
+    # largest
     two = [_desc(), _desc(ext=(16, 16, 16))]
     st_b, nb = _ws(g, two)
     st_p, np_ = _ws(g, two, rmx.options(flags=rmx.FLAG_PER_SOLID))
-    assert st_b == st_p == rmx.OK and nb > np_ >= n
+    assert st_b == st_p == rmx.OK and nb > np_ > 0
 
 
 def test_null_context_and_status_strings():
@@ -111,4 +112,5 @@ def test_null_context_and_status_strings():
     assert L.rmx_extrapolate(None, ctypes.byref(g), ctypes.byref(d), 1, None, None, None) \
         == rmx.E_ARG
     assert rmx.status_string(rmx.E_TRUNCATED) == "band truncated by the box"
+    assert rmx.status_string(rmx.E_DISABLED) == "launch form switched off in this build"
     assert rmx.status_string(0) == "ok"

@@ -14,6 +14,22 @@ from tests.helpers import oracle_problem, rel_err, run_oracle
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-12, 1: 1e-5}
+# Launch forms: the batched multi-kernel chain (default) and the single persistent launch.
+# The persistent launch is switched off in the library (RMX_E_DISABLED) after a GPU memory
+# fault whose cause is not known; its cases stay skipped until that cause is found.  Its
+# kernel logic runs, bit for bit against the oracle, in the CPU emulation tests.
+MODES = {"chain": 0, "fused": 16}
+FUSED_SKIP = ("persistent launch switched off: GPU memory fault of unknown cause "
+              "(kernel logic covered by the CPU emulation tests)")
+
+
+def mode_param(mode):
+    if mode == "fused":
+        return pytest.param(mode, marks=pytest.mark.skip(reason=FUSED_SKIP))
+    return mode
+
+
+MODE_PARAMS = [mode_param(m) for m in sorted(MODES)]
 
 
 @pytest.fixture(scope="module")
@@ -73,43 +89,48 @@ def compare(w, gpu, precision, r_s=2, r_max=4, normal_layers=2, xi_normal=None, 
     return worst
 
 
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_sphere32(ctx, precision):
+def test_sphere32(ctx, precision, mode):
     w = synth.sphere32()
-    st, gpu = run_gpu(ctx, w, precision)
+    st, gpu = run_gpu(ctx, w, precision, flags=MODES[mode])
     assert st == 0
     print("sphere32 rel err", compare(w, gpu, precision, tag="sphere32"))
 
 
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_ellipsoid_ragged(ctx, precision):
+def test_ellipsoid_ragged(ctx, precision, mode):
     """40^3: ragged tiles along every axis (40 = 64 - 24 along x, 2.5 tiles in y, z)."""
     w = synth.ellipsoid128(n=40, n_layers=5)
-    st, gpu = run_gpu(ctx, w, precision)
+    st, gpu = run_gpu(ctx, w, precision, flags=MODES[mode])
     assert st == 0
     compare(w, gpu, precision, tag="ell40")
 
 
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_ellipsoid128_full(ctx, precision):
+def test_ellipsoid128_full(ctx, precision, mode):
     w = synth.ellipsoid128()
-    st, gpu = run_gpu(ctx, w, precision)
+    st, gpu = run_gpu(ctx, w, precision, flags=MODES[mode])
     assert st == 0
     print("ellipsoid128 rel err", compare(w, gpu, precision, tag="ell128"))
 
 
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_suspension_batched_full(ctx, precision):
+def test_suspension_batched_full(ctx, precision, mode):
     w = synth.suspension()
-    st, gpu = run_gpu(ctx, w, precision)
+    st, gpu = run_gpu(ctx, w, precision, flags=MODES[mode])
     assert st == 0
     print("suspension rel err", compare(w, gpu, precision, tag="susp"))
 
 
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_cavity256_full(ctx, precision):
+def test_cavity256_full(ctx, precision, mode):
     w = synth.cavity256()
-    st, gpu = run_gpu(ctx, w, precision, decisions=True)
+    st, gpu = run_gpu(ctx, w, precision, decisions=True, flags=MODES[mode])
     assert st == 0
     print("cavity256 rel err", compare(w, gpu, precision, tag="cav256"))
 
@@ -144,8 +165,9 @@ def _mask_workload(masks, L, grid_n=None, inside=(0.0, 0.0, 0.0)):
     return w
 
 
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("seed", range(6))
-def test_random_masks_batched(ctx, seed):
+def test_random_masks_batched(ctx, seed, mode):
     """Many tiny solids of random shapes and layer counts in one batched call."""
     from tests.test_oracle_pins import _random_mask
     rng = np.random.default_rng(500 + seed)
@@ -161,11 +183,12 @@ def test_random_masks_batched(ctx, seed):
             xi[:, ext] = 2.0 + rng.random((3, int(ext.sum())))
         w.solids.append(synth.Solid((0, 0, 0), (shp[2], shp[1], shp[0]),
                                     synth.sphere_shape((0.0, 0.0, 0.0), 1.0), L, xi))
-    st, gpu = run_gpu(ctx, w, 0)
+    st, gpu = run_gpu(ctx, w, 0, flags=MODES[mode])
     compare(w, gpu, 0, tag=f"masks{seed}")
 
 
-def test_degenerate_paths(ctx):
+@pytest.mark.parametrize("mode", MODE_PARAMS)
+def test_degenerate_paths(ctx, mode):
     """Single interior cell and one-cell-thin plate: radius growth, F1/F2 fallbacks."""
     m1 = np.zeros((9, 9, 9), dtype=bool)
     m1[4, 4, 4] = True
@@ -173,15 +196,16 @@ def test_degenerate_paths(ctx):
     m2[7] = True
     w = _mask_workload([m1, m2], 3, grid_n=(15, 15, 15), inside=(0.1, 0.2, 0.3))
     w.solids[0].lo = (0, 0, 0)
-    st, gpu = run_gpu(ctx, w, 0)
+    st, gpu = run_gpu(ctx, w, 0, flags=MODES[mode])
     compare(w, gpu, 0, tag="degenerate")
     assert gpu[0][3]["n_f2"] > 0 and gpu[1][3]["n_f2"] > 0
 
 
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("r_s,normal_layers", [(1, 2), (2, 0), (3, 4)])
-def test_option_variants(ctx, r_s, normal_layers):
+def test_option_variants(ctx, r_s, normal_layers, mode):
     w = synth.sphere32(seed=7)
-    st, gpu = run_gpu(ctx, w, 0, r_s=r_s, normal_layers=normal_layers)
+    st, gpu = run_gpu(ctx, w, 0, r_s=r_s, normal_layers=normal_layers, flags=MODES[mode])
     compare(w, gpu, 0, r_s=r_s, normal_layers=normal_layers, tag=f"opt{r_s}{normal_layers}")
 
 
@@ -193,7 +217,8 @@ def test_xi_normal_field(ctx):
     compare(w, gpu, 0, xi_normal=[prev], tag="xi_normal")
 
 
-def test_statuses(ctx):
+@pytest.mark.parametrize("mode", MODE_PARAMS)
+def test_statuses(ctx, mode):
     from paper_2104_00095_amd import rmx
     w = synth.sphere32()
     s = w.solids[0]
@@ -203,36 +228,51 @@ def test_statuses(ctx):
     sub.solids.append(synth.Solid(s.lo, s.ext, s.shape, 4, s.xi + 10.0))      # empty
     sub.solids.append(synth.Solid(s.lo, s.ext, s.shape, 0, s.xi.copy()))      # L = 0
     sub.solids.append(synth.Solid(s.lo, s.ext, s.shape, 4, s.xi.copy()))      # normal
-    st, gpu = run_gpu(ctx, sub, 0)
+    st, gpu = run_gpu(ctx, sub, 0, flags=MODES[mode])
     assert st == rmx.E_TRUNCATED
     assert [g[3]["status"] for g in gpu] == [rmx.E_TRUNCATED, rmx.W_EMPTY, 0, 0]
     compare(sub, gpu, 0, tag="statuses")
 
 
-def test_batch_equals_alone_and_per_solid(ctx):
-    """Object independence: each solid's result in the batched launch is bitwise the
-    result of its solo call and of the per-solid launch chain."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_alone_and_per_solid(ctx, precision):
+    """Object independence: each solid's result in the batched call is bitwise the result
+    of its solo call and of the per-solid form (the per-cell arithmetic does not depend on
+    the batch or the form)."""
     from paper_2104_00095_amd import rmx
     w = synth.suspension(n_solids=12, grid_n=(64, 64, 128), h=1.0 / 64)
-    st, batched = run_gpu(ctx, w, 0)
-    st2, per = run_gpu(ctx, w, 0, flags=rmx.FLAG_PER_SOLID)
+    st, batched = run_gpu(ctx, w, precision)
+    st2, per = run_gpu(ctx, w, precision, flags=rmx.FLAG_PER_SOLID)
+    assert st == st2 == 0
     for i, s in enumerate(w.solids):
         one = synth.Workload("one", w.grid_n, w.h, w.origin)
         one.solids.append(s)
-        _, alone = run_gpu(ctx, one, 0)
+        _, alone = run_gpu(ctx, one, precision)
         assert np.array_equal(batched[i][0].view(np.uint64), alone[0][0].view(np.uint64))
         assert np.array_equal(batched[i][0].view(np.uint64), per[i][0].view(np.uint64))
         assert np.array_equal(batched[i][1], alone[0][1])
+        assert np.array_equal(batched[i][2], per[i][2])
 
 
-def test_graph_replay_matches_eager(ctx):
+def test_persistent_launch_refused(ctx):
+    """The switched-off persistent form is refused on the host, before any launch."""
+    from paper_2104_00095_amd import fields, rmx
+    w = synth.sphere32()
+    dw = fields.upload(w)
+    st, _ = ctx.extrapolate(dw.grid, dw.solids, rmx.options(flags=rmx.FLAG_PERSISTENT),
+                            check=False)
+    assert st == rmx.E_DISABLED
+
+
+@pytest.mark.parametrize("mode", MODE_PARAMS)
+def test_graph_replay_matches_eager(ctx, mode):
     import torch
     from paper_2104_00095_amd import fields, rmx
     w = synth.suspension(n_solids=8, grid_n=(64, 64, 128), h=1.0 / 64)
     dw = fields.upload(w)
-    ctx.extrapolate(dw.grid, dw.solids, rmx.options())
+    ctx.extrapolate(dw.grid, dw.solids, rmx.options(flags=MODES[mode]))
     eager = [x.clone() for x in dw.xi]
-    opt = rmx.options(flags=rmx.FLAG_GRAPH)
+    opt = rmx.options(flags=rmx.FLAG_GRAPH | MODES[mode])
     for rep in range(4):
         dw.reset()
         torch.cuda.synchronize()
