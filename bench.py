@@ -74,24 +74,25 @@ def profile_phases(ctx, dw, opt, steps):
     return {k: (ms / n, n) for k, (ms, n) in prof.items()}
 
 
-def kernel_bytes(phase, w, stats, normal_layers=2):
-    """Algorithmic HBM bytes of one launch of a phase (the minimum it must move):
-    classify reads xi once (24 B/cell) and writes the 1-bit mask; label reads the mask
-    and writes int8 labels and a 4 B slot per band cell; normals read xi (24 B) and write
-    the normal (24 B) per cell of layers 1..normal_layers; the fit of layer l reads the
-    slot (4 B) and, where a normal is used, the normal (24 B), and writes xi (24 B) and
-    the decision (1 B) per cell of the layer; the scan moves only per-tile counts."""
+def kernel_bytes(phase, w, stats, normal_layers=2, decisions=False):
+    """Algorithmic HBM bytes of one launch of a kernel (the minimum it must move):
+    classify reads xi once (24 B/cell) and writes the 1-bit mask; label reads the mask and
+    writes int8 labels (and decisions); normal reads xi (24 B) and writes the normal
+    (24 B) of each cell of layers 1..normal_layers; the fit of layer l writes xi (24 B)
+    and the decision (1 B) of each cell of the layer and reads its normal (24 B) where one
+    is used (the staged neighbourhoods are re-reads of data the chain wrote just before)."""
     cells = w.box_cells
     band = [sum(s["n_band"][l] for s in stats) for l in range(17)]
+    dec = 1 if decisions else 0
     if phase == "classify":
         return 24 * cells + cells / 8
     if phase == "label":
-        return cells / 8 + cells + 4 * sum(band[1:])
+        return cells / 8 + (1 + dec) * cells
     if phase == "normal":
         return 48 * sum(band[1:normal_layers + 1])
     if phase.startswith("extrap"):
         l = int(phase[6:])
-        return (29 + (24 if l <= normal_layers else 0)) * band[l]
+        return (24 + dec + (24 if l <= normal_layers else 0)) * band[l]
     return None
 
 

@@ -79,14 +79,11 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
                                   such a call fails with RMX_E_DISABLED.                   */
 
 /* Kernel phases reported by rmx_profile_read. */
-#define RMX_PHASE_ZERO 0
-#define RMX_PHASE_CLASSIFY 1
-#define RMX_PHASE_LABEL 2
-#define RMX_PHASE_SCAN 3
-#define RMX_PHASE_NORMAL 4
-#define RMX_PHASE_EXTRAP 5      /* + (layer - 1), layers 1..RMX_MAX_LAYERS               */
-#define RMX_PHASE_FUSED 21      /* the single persistent launch (switched off)           */
-#define RMX_N_PHASES 22
+#define RMX_PHASE_CLASSIFY 0
+#define RMX_PHASE_LABEL 1
+#define RMX_PHASE_NORMAL 2      /* per-solid counts and the normals of layers <= nl      */
+#define RMX_PHASE_EXTRAP 3      /* + (layer - 1), layers 1..RMX_MAX_LAYERS               */
+#define RMX_N_PHASES 19
 
 /* Grid: M x N x O cells; cell (i,j,k) has centre origin + (idx + 1/2) h (SI, "Variable
  * arrangement"; isotropic spacing as in the paper's runs).  The fit is invariant to h

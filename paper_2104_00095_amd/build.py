@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librmx.so")
-SOURCES = ["rmx_kernels.hip", "rmx_fused.hip", "rmx_core.cpp", "rmx_server.cpp"]
+SOURCES = ["rmx_kernels.hip", "rmx_plan.cpp", "rmx_core.cpp", "rmx_server.cpp"]
 # No packed-FP32 instructions; device code for gfx950 only.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,7 +1,9 @@
-// Host-side planning of one batched call; shared by the context API and the server.
+// Host-side planning and launch sequencing of librmx (shared by the context API and the
+// serving loop).
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
 #include <vector>
 
 #include "rmx.h"
@@ -9,33 +11,41 @@
 
 namespace rmx {
 
+// Launch shapes a call may vary without changing any result: the label tile width and
+// the number of blocks striding over a layer's brick list.
+struct Tuning {
+    int tile_w = 0;          // 1, 2 or 4 (0: the widest that fits the LDS)
+    int extrap_blocks = 0;   // 0: three per compute unit
+};
+
 struct Plan {
     int n_solids = 0;
     std::vector<DevSolid> solids;
     std::vector<int32_t> tile_solid;
     int n_tiles = 0;
     int n_chunks = 0;
-    int chunk_cap = 0;
     int Lmax = 0;
     int normal_layers = 0;
     int tile_w = 1;
-    int tile_cells = 0;
+    int extrap_blocks = 1;
     size_t lds_bytes = 0;
     int64_t total_words = 0;
-    int64_t slot_cap = 0;
     int64_t total_cells = 0;
+    int64_t blist_cap = 0;
     // workspace layout (byte offsets); [0, desc_bytes) is uploaded from the host
     size_t off_desc = 0, off_tile_solid = 0, desc_bytes = 0;
-    size_t off_stats = 0, off_tile_cnt = 0, off_tile_lstart = 0, off_tile_off = 0;
-    size_t off_chunk_tile = 0, off_chunk_flag = 0;
-    size_t off_mask = 0, off_slots = 0, off_normals = 0;
+    size_t off_stats = 0, off_tile_cnt = 0, off_bcount = 0, off_mask = 0, off_normals = 0;
+    size_t off_blist = 0;
     size_t ws_bytes = 0;
-    // fused persistent form
-    bool fused = false;
-    std::vector<FItem> items;
-    int ctr_words = 0;
-    size_t off_lists = 0;
+    // red zones between regions (CPU emulation build only): (offset, bytes)
+    std::vector<std::pair<size_t, size_t>> gaps;
 };
+
+#ifdef RMX_EMU_REDZONES
+// CPU emulation: make the whole workspace addressable, then poison the red zones.
+void rmx_emu_poison_gaps(void* ws, size_t ws_bytes,
+                         const std::vector<std::pair<size_t, size_t>>& gaps);
+#endif
 
 // Records HIP events around each launch of the chain when attached to rmx_enqueue.
 struct Profiler {
@@ -54,14 +64,18 @@ struct Profiler {
     ~Profiler();
 };
 
-}  // namespace rmx
+// Validation of one solid against its grid, and of the options.
+int validate_options(const rmx_options* opt);
+int validate_solid(const rmx_grid* grid, const rmx_solid* s);
 
-int rmx_validate(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
-                 const rmx_options* opt);
-int rmx_plan(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
-             const rmx_options* opt, size_t lds_limit, bool fused, rmx::Plan* p);
-void rmx_bind(rmx::Plan* p, void* ws, const rmx_options* opt, rmx::Batch* b);
-void rmx_pack_desc(const rmx::Plan& p, void* host);
-hipError_t rmx_enqueue(const rmx::Plan& p, const rmx::Batch& b, int precision,
-                       hipStream_t st, rmx::Profiler* prof = nullptr);
-void rmx_convert_stats(const unsigned long long* dev, int n, rmx_solid_stats* out);
+// Plan a batch: solid i lives on grid grids[i].  `cu` = compute units of the device.
+int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,
+         const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p);
+void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b);
+void pack_desc(const Plan& p, void* host);
+hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,
+                   Profiler* prof = nullptr);
+void convert_stats(const unsigned long long* dev, int n, rmx_solid_stats* out);
+uint64_t fnv1a(const void* p, size_t n, uint64_t h);
+
+}  // namespace rmx

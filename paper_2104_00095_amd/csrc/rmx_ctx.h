@@ -1,0 +1,67 @@
+// The context object behind rmx_ctx* (host state of one device's calls).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <unordered_map>
+#include <vector>
+
+#include "rmx.h"
+#include "rmx_core.h"
+
+namespace rmx {
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* ws_base = nullptr;
+};
+
+struct Staging {
+    void* host = nullptr;
+    size_t size = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+}  // namespace rmx
+
+struct rmx_ctx {
+    int device = 0;
+    size_t lds_limit = 65536;
+    int cus = 256;
+    bool fixed = false;
+    bool exact_ws = false;   // grow the workspace to exactly what a call needs (server)
+    void* ws = nullptr;
+    size_t ws_size = 0;
+    static constexpr int kRing = 4;
+    rmx::Staging stage[kRing];
+    int stage_next = 0;
+    // what the workspace's descriptor region holds now
+    bool desc_valid = false;
+    void* desc_ws = nullptr;
+    uint64_t desc_hash = 0;
+    size_t desc_len = 0;
+    std::vector<char> desc_host;
+    unsigned long long* stats_host = nullptr;   // pinned, kStatWords per solid
+    size_t stats_host_n = 0;
+    hipStream_t capture_stream = nullptr;
+    std::unordered_map<uint64_t, rmx::GraphEntry> graphs;
+    std::unordered_map<uint64_t, rmx::Tuning> tuned;   // launch shapes per tune_key
+    std::vector<rmx_solid_stats> tmp_stats;
+    std::vector<const rmx_grid*> grid_ptrs;
+    rmx::Profiler prof;
+};
+
+namespace rmx {
+
+// Pinned host statistics of at least n words.
+int ctx_stats_host(rmx_ctx* c, size_t n);
+// Shape class of a planned call (the key of the tuned launch shapes).
+uint64_t tune_key(const Plan& p);
+// Enqueue one batched call on `st` (descriptor upload, kernels, optional statistics
+// read-back into stats_host + stats_off).  `force` overrides the tuned launch shapes.
+int run_batch(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
+              const rmx_options* opt, hipStream_t st, bool use_graph, size_t stats_off,
+              bool want_stats, const Tuning* force);
+
+}  // namespace rmx

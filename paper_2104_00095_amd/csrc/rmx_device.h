@@ -1,4 +1,4 @@
-// Device helpers shared by the per-solid launch chain and the fused persistent kernel.
+// Device helpers of the launch chain (classification, labels, per-layer brick fits).
 // Method: Lin, Derr & Rycroft (arXiv 2104.00095), section "Extrapolation of xi(x,t)" and
 // SI "Weighting scheme for weighted least squares-based extrapolation", eq. (weight).
 #pragma once
@@ -331,107 +331,11 @@ struct CellCtx {
     double g0, g1, g2, rgn;       // normal (unnormalised) and 1/|g|
 };
 
-// Accumulate the moments of the eligible data within Chebyshev radius R.  The (2R+1)^2
-// rows (dy, dz) of the box are dealt to the kLanes lanes of the cell; a lane walks the
-// 2R+1 cells of each of its rows (contiguous in memory).  Eq. (weight):
-// w = 2^-(|dx|+|dy|+|dz|), times the cosine between x_e - x_d = -d h and the normal when
-// use_normal; data with (dx gx + dy gy) + dz gz >= 0 (that exact expression, no
-// contraction) get weight 0.  Ineligible cells read the anchor (0 after centring) with
-// weight 0, so every load is issued unconditionally.
-template <typename T, int R>
-__device__ __forceinline__ void gather(const CellCtx& cx, bool use_normal, int lq,
-                                       Moments<T>& acc) {
-    constexpr int D = 2 * R + 1;
-    constexpr int ROWS = D * D;
-    constexpr int RPL = (ROWS + kLanes - 1) / kLanes;
-#pragma unroll 1
-    for (int q = 0; q < RPL; ++q) {
-        const int row = lq + kLanes * q;
-        if (row >= ROWS) break;
-        const int dy = row % D - R, dz = row / D - R;
-        const int jj = cx.j + dy, kk = cx.k + dz;
-        const bool rowin = (unsigned)jj < (unsigned)cx.n1 && (unsigned)kk < (unsigned)cx.n2;
-        const int32_t rb = (kk * cx.n1 + jj) * cx.n0;
-        int32_t cc[D];
-        bool ok[D];
-        int lab[D];
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int ii = cx.i + u - R;
-            ok[u] = rowin && (unsigned)ii < (unsigned)cx.n0;
-            cc[u] = ok[u] ? rb + ii : cx.anchor;
-        }
-#pragma unroll
-        for (int u = 0; u < D; ++u) lab[u] = cx.labels[cc[u]];
-        const int rowd2 = dy * dy + dz * dz;
-        T w[D];
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int dx = u - R;
-            bool e = ok[u] && lab[u] >= 0 && lab[u] < cx.le;
-            double ww = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
-            if (use_normal) {
-#pragma clang fp contract(off)
-                const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
-                const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
-                e = e && (dot < 0.0);
-                ww = (-dot * c_rlen[dx * dx + rowd2] * cx.rgn) * ww;
-            }
-            ok[u] = e;
-            w[u] = e ? (T)ww : T(0);
-            if (!e) cc[u] = cx.anchor;
-        }
-        double v[D][3];
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            v[u][0] = cx.xi[cc[u]];
-            v[u][1] = cx.xi[cx.ncell + cc[u]];
-            v[u][2] = cx.xi[2 * cx.ncell + cc[u]];
-        }
-        const T fy = (T)dy, fz = (T)dz;
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int dx = u - R;
-            const T tw = w[u];
-            const T fx = (T)dx;
-            const T v0 = (T)(v[u][0] - cx.a0), v1 = (T)(v[u][1] - cx.a1),
-                    v2 = (T)(v[u][2] - cx.a2);
-            const T wx = tw * fx, wy = tw * fy, wz = tw * fz;
-            acc.m[0] += tw;
-            acc.m[1] += wx;
-            acc.m[2] += wy;
-            acc.m[3] += wz;
-            acc.m[4] += wx * fx;
-            acc.m[5] += wx * fy;
-            acc.m[6] += wx * fz;
-            acc.m[7] += wy * fy;
-            acc.m[8] += wy * fz;
-            acc.m[9] += wz * fz;
-            acc.r[0] += tw * v0;
-            acc.r[1] += tw * v1;
-            acc.r[2] += tw * v2;
-            acc.r[3] += wx * v0;
-            acc.r[4] += wx * v1;
-            acc.r[5] += wx * v2;
-            acc.r[6] += wy * v0;
-            acc.r[7] += wy * v1;
-            acc.r[8] += wy * v2;
-            acc.r[9] += wz * v0;
-            acc.r[10] += wz * v1;
-            acc.r[11] += wz * v2;
-            if (ok[u]) {
-                acc.g[0] += 1 + ((dx * dx) << 16);
-                acc.g[1] += dx + ((dx * dy) << 16);
-                acc.g[2] += dy + ((dx * dz) << 16);
-                acc.g[3] += dz + ((dy * dy) << 16);
-                acc.g[4] += (dy * dz) + ((dz * dz) << 16);
-            }
-        }
-    }
-}
-
-// Radii other than r_s = 2 (rare: degenerate systems): the same sums, one cell at a
-// time, rows dealt to the lanes as above.
+// Accumulate, from global memory, the moments of the eligible data within Chebyshev
+// radius r (used for radii beyond the staged halo).  The (2r+1)^2 rows (dy, dz) of the box
+// are dealt to the kLanes lanes of the cell.  Eq. (weight): w = 2^-(|dx|+|dy|+|dz|), times
+// the cosine between x_e - x_d = -d h and the normal when use_normal; data with
+// (dx gx + dy gy) + dz gz >= 0 (that exact expression, no contraction) get weight 0.
 template <typename T>
 __device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_normal, int lq,
                                         Moments<T>& acc) {
@@ -489,15 +393,6 @@ __device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_no
             acc.g[4] += (dy * dz) + ((dz * dz) << 16);
         }
     }
-}
-
-template <typename T>
-__device__ __forceinline__ void gather_r(const CellCtx& cx, int r, bool use_normal, int lq,
-                                         Moments<T>& acc) {
-    if (r == 2)
-        gather<T, 2>(cx, use_normal, lq, acc);
-    else
-        gather_any<T>(cx, r, use_normal, lq, acc);
 }
 
 // Unnormalised gradient of phi0(xi) at box cell (i, j, k) of `f` (SI, weighting scheme):

@@ -1,284 +1,427 @@
-// HIP kernels (gfx950) of the layer-wise WLS reference-map extrapolation.
-//
-// Method: Lin, Derr & Rycroft (arXiv 2104.00095), section "Extrapolation of xi(x,t)" and
-// SI "Weighting scheme for weighted least squares-based extrapolation", eq. (weight).
-//
-// Launch chain of one call (all solids of a batch at once):
-//   k_classify  streams xi once (24 B/cell), one wave per 64-cell row segment; the
-//               interior predicate is ballot-packed into a 1-bit-per-cell mask.
-//   k_label     per 16x16-row x 64-cell tile: the mask (+ halo of L rows and one word)
-//               goes to LDS and is dilated L times through face neighbours with 64-bit
-//               shifts and ORs; the first dilation that reaches a cell is its layer.
-//               Writes int8 labels and the tile's band cells, grouped by layer, into the
-//               tile's slot range.
-//   k_scan      exclusive prefix of the per-tile layer counts (one workgroup).
-//   k_normal    gradient of phi0(xi) for band cells of layers <= normal_layers, from the
-//               field as it is before any write.
-//   k_extrap    one launch per layer, ascending; 16 lanes per band cell gather the
-//               (2r+1)^3 box, build the 4x4 normal-equation moments, reduce them over the
-//               16 lanes with cross-lane shuffles, decide degeneracy by an exact integer
-//               determinant, solve by Cholesky in FP64 and write xi_e in place.
-// The work is gather- and bandwidth-bound, with 4x4 systems per cell: no MFMA.
+// HIP kernels of the reference-map band extrapolation (Lin, Derr & Rycroft, arXiv
+// 2104.00095, section "Extrapolation of xi(x,t)"; SI "Weighting scheme for weighted least
+// squares-based extrapolation", eq. (weight)).  One call is a chain of L + 2 launches,
+// each covering every solid of the batch:
+//   k_classify  streams xi once (coalesced, nontemporal) and packs the interior predicate
+//               phi0(xi) < 0 into a 1-bit mask (wave ballots); zeroes the call's counters.
+//   k_label     per 16 x 16-row tile: L bit-parallel dilations in LDS give the layers
+//               (first dilation reaching a cell = its layer), written as int8 labels; the
+//               tile counts its interior and band cells, detects a band truncated by a box
+//               face, and lists the 8^3 bricks holding cells of each layer.
+//   k_normal    sums the tile counts per solid; per listed brick of layers
+//               1..normal_layers, evaluates phi0(xi) once per needed cell (LDS) and forms
+//               the normals of the brick's cells of that layer by central differences, from
+//               the field before any write.
+//   k_extrap    one launch per layer, ascending: a block stages a listed brick with a
+//               halo of r_s (xi and labels, 12^3 cells) in LDS; 8 lanes per cell of the
+//               layer gather the (2r+1)^3 box from LDS, accumulate the 4x4 normal-equation
+//               moments, reduce them with cross-lane shuffles, decide degeneracy by an
+//               exact integer determinant, solve by Cholesky in FP64 and write xi_e.
+// The work is bandwidth- and latency-bound, with 4x4 systems per cell: no MFMA.
 #include "rmx_device.h"
-#include "rmx_fused_common.h"
 
 namespace rmx {
 namespace {
 using namespace dev;
 
 // ------------------------------------------------------------------------------------
-// Classification: a block owns a chunk of kChunkWords mask words of one solid.
+// Classification of mask words [wb, we) of solid d by the 4 waves of the block: each wave
+// streams 16 consecutive 64-cell row segments, 8 at a time (24 loads of 512 contiguous
+// bytes in flight), ballot-packs the interior predicate and writes one mask word per
+// segment.  Cells past the row end (x >= n0) are never interior.
 // ------------------------------------------------------------------------------------
+constexpr int kSeg = 8;
+
+__device__ __forceinline__ void classify_words(const DevSolid* dp, int wb, int we) {
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int n0 = dp->n0, W = dp->W;
+    const int64_t ncell = dp->ncell;
+    const double* __restrict__ xi = dp->xi;
+    unsigned long long* __restrict__ mask = dp->mask;
+    const ShapeR sh = load_shape(dp);
+    const int first = wb + wave * (kChunkWords / 4);
+#pragma unroll 1
+    for (int it = 0; it < kChunkWords / 4; it += kSeg) {
+        const int w0 = first + it;
+        if (w0 >= we) break;
+        int row = w0 / W, wx = w0 - row * W;
+        double v0[kSeg], v1[kSeg], v2[kSeg];
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) {
+            const int x = wx * 64 + lane;
+            v0[u] = v1[u] = v2[u] = __builtin_nan("");
+            if (w0 + u < we && x < n0) {
+                const int64_t c = (int64_t)row * n0 + x;
+                v0[u] = __builtin_nontemporal_load(xi + c);
+                v1[u] = __builtin_nontemporal_load(xi + ncell + c);
+                v2[u] = __builtin_nontemporal_load(xi + 2 * ncell + c);
+            }
+            if (++wx == W) {
+                wx = 0;
+                ++row;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSeg; ++u) {
+            const unsigned long long m = __ballot(interior(sh, v0[u], v1[u], v2[u]));
+            if (lane == 0 && w0 + u < we) mask[w0 + u] = m;
+        }
+    }
+}
+
+// A block owns a chunk of kChunkWords mask words of one solid.  Block 0 also zeroes the
+// call's statistics and brick counters, which nothing else touches before the labels.
 __global__ __launch_bounds__(256) void k_classify(Batch b) {
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 256) b.stats[i] = 0ull;
+        for (int i = threadIdx.x; i < kMaxLayers * kBuckets; i += 256) b.bcount[i] = 0;
+    }
     for (int chunk = blockIdx.x; chunk < b.n_chunks; chunk += gridDim.x) {
         const int s = uniform_int(find_solid_by_chunk(b.solids, b.n_solids, chunk));
         const DevSolid* dp = b.solids + s;
         const int nwords = dp->n1 * dp->n2 * dp->W;
         const int first = (chunk - dp->chunk_base) * kChunkWords;
-        const bool trunc = classify_words(dp, first, min(first + kChunkWords, nwords));
-        const int any = __syncthreads_or(trunc);
-        if (threadIdx.x == 0) b.chunk_flag[chunk] = any ? 1 : 0;
+        classify_words(dp, first, min(first + kChunkWords, nwords));
     }
 }
 
 // ------------------------------------------------------------------------------------
-// Labels: one workgroup per tile.
+// Labels of one tile of 16 (y) x 16 (z) rows x tile_w 64-cell words (x); thread (tj, tk)
+// owns one row of the tile.  The region in LDS carries a halo of L rows in y and z and
+// one word on each side in x where the box continues (L <= 16 < 64), so after L dilations
+// through face neighbours (64-bit shifts and ORs) the tile is exact.
 // ------------------------------------------------------------------------------------
+constexpr int kRowsPerThread = 9;   // ceil((16 + 2 * 16)^2 / 256)
+
+template <int MAXTW>
 __global__ __launch_bounds__(256) void k_label(Batch b) {
+    constexpr int FPL = 4 * 8 * MAXTW;   // brick flags per layer: 2 (y) x 2 (z) x 8 per word
     HIP_DYNAMIC_SHARED(double, lds_d)
-    unsigned char* lds = reinterpret_cast<unsigned char*>(lds_d);
-    __shared__ int s_wave[4];
+    unsigned long long* lds = reinterpret_cast<unsigned long long*>(lds_d);
+    __shared__ int s_wave[5];
+    __shared__ unsigned char s_bflag[kMaxLayers * FPL];
+
     const int t = blockIdx.x;
     const int s = uniform_int(b.tile_solid[t]);
-    label_tile<false, kMaxTileW>(b, nullptr, t, s, b.solids + s, lds, s_wave, nullptr);
-}
+    const DevSolid* d = b.solids + s;
+    unsigned long long* st = b.stats + (int64_t)s * kStatWords;
+    const int tid = threadIdx.x;
+    const int n0 = d->n0, n1 = d->n1, n2 = d->n2, W = d->W, L = d->L;
+    const int lt = t - d->tile_base;
+    const int txi = lt % d->ntx;
+    const int tyi = (lt / d->ntx) % d->ty;
+    const int tzi = lt / (d->ntx * d->ty);
+    const int wx0 = txi * MAXTW, tw = min(MAXTW, W - wx0);
+    const int xr0 = max(0, wx0 - 1), xr1 = min(W, wx0 + tw + 1);
+    const int RW = xr1 - xr0;
+    const int j0 = tyi * kTileJ, k0 = tzi * kTileK;
+    const int RJ = kTileJ + 2 * L, RK = kTileK + 2 * L;
+    const int R = RJ * RK;
+    unsigned long long* A = lds;
+    unsigned long long* B = lds + (size_t)RW * R;
+    const unsigned long long tail = (n0 & 63) ? ((1ull << (n0 & 63)) - 1ull) : ~0ull;
+    const unsigned long long* __restrict__ mask = d->mask;
 
-// ------------------------------------------------------------------------------------
-// One workgroup of 1024 threads: per-layer exclusive prefix of the tile counts (all
-// layers at once), the chunk->tile table that lets a band index find its tile with one
-// load, and the per-solid statistics (zeroed here, then the counts as differences of the
-// prefix over the solid's tile range, and the truncation flag from the chunk flags).
-// ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_scan(Batch b) {
-    __shared__ int s_w[kLT][16];
-    const int T = b.n_tiles;
-    const int Lm = b.Lmax;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 1024) b.stats[i] = 0ull;
+    for (int q = tid; q < L * FPL; q += 256) s_bflag[q] = 0;
+    // Region rows owned by this thread, packed: rj | rk << 8 | in-box << 16 (RJ, RK <= 48).
+    int rinfo[kRowsPerThread];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+        const int rr = tid + 256 * q;
+        const int rj = rr % RJ, rk = rr / RJ;
+        const int jj = j0 - L + rj, kk = k0 - L + rk;
+        const bool ok = rr < R && jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
+        rinfo[q] = rj | (rk << 8) | (ok ? 1 << 16 : 0);
+        if (rr < R) {
+            for (int w = 0; w < RW; ++w)
+                A[rr * RW + w] = ok ? mask[((int64_t)kk * n1 + jj) * W + xr0 + w] : 0ull;
+        }
+    }
     __syncthreads();
-    int carry[kLT];
+
+    const int tj = tid % kTileJ, tk = tid / kTileJ;
+    const int jrow = j0 + tj, krow = k0 + tk;
+    const bool row_ok = jrow < n1 && krow < n2;
+    const int my = ((tk + L) * RJ + (tj + L)) * RW + (wx0 - xr0);
+    unsigned long long prev[MAXTW], p0[MAXTW], p1[MAXTW], p2[MAXTW], p3[MAXTW], p4[MAXTW];
+    int cnt0 = 0;
+    bool trunc = false;
 #pragma unroll
-    for (int l = 0; l < kLT; ++l) carry[l] = 0;
-    for (int base = 0; base < T; base += 1024) {
-        const int i = base + threadIdx.x;
-        int v[kLT], x[kLT];
-#pragma unroll
-        for (int l = 0; l < kLT; ++l) {
-            v[l] = (i < T && l <= Lm) ? b.tile_cnt[i * kLT + l] : 0;
-            x[l] = v[l];
-        }
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-            for (int l = 0; l < kLT; ++l) {
-                const int y = __shfl_up(x[l], o, 64);
-                if (lane >= o) x[l] += y;
+    for (int w = 0; w < MAXTW; ++w) {
+        prev[w] = (row_ok && w < tw) ? A[my + w] : 0ull;
+        p0[w] = p1[w] = p2[w] = p3[w] = p4[w] = 0ull;
+        cnt0 += __popcll(prev[w]);
+        // An interior cell closer than L to a box face that is no grid wall: the band
+        // would leave the box (reported; the solid's band is then not fitted).
+        if (prev[w]) {
+            const int x0 = (wx0 + w) * 64;
+            if (!d->wall_lo[0] && x0 < L) {
+                const int nb = min(64, L - x0);
+                trunc |= (prev[w] & (nb == 64 ? ~0ull : ((1ull << nb) - 1ull))) != 0ull;
             }
-        }
-        if (lane == 63) {
-#pragma unroll
-            for (int l = 0; l < kLT; ++l) s_w[l][wid] = x[l];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int l = 0; l < kLT; ++l) {
-            if (l > Lm) break;
-            int wb = 0, tot = 0;
-            for (int q = 0; q < 16; ++q) {
-                const int tq = s_w[l][q];
-                if (q < wid) wb += tq;
-                tot += tq;
+            if (!d->wall_hi[0] && x0 + 63 >= n0 - L) {
+                const int f = max(0, n0 - L - x0);
+                trunc |= (prev[w] & (~0ull << f)) != 0ull;
             }
-            const int off = carry[l] + wb + x[l] - v[l];
-            if (i < T) {
-                b.tile_off[l * (T + 1) + i] = off;
-                if (l > 0) {
-                    int32_t* ct = b.chunk_tile + l * b.chunk_cap;
-                    for (int c = (off + kLocateChunk - 1) / kLocateChunk;
-                         c * kLocateChunk < off + v[l]; ++c)
-                        ct[c] = i;
+            trunc |= (!d->wall_lo[1] && jrow < L) || (!d->wall_hi[1] && jrow >= n1 - L) ||
+                     (!d->wall_lo[2] && krow < L) || (!d->wall_hi[2] && krow >= n2 - L);
+        }
+    }
+    {
+        int excl, total;
+        block_scan<4>(cnt0, excl, total, s_wave);
+        if (tid == 0) b.tile_cnt[(int64_t)t * kLT] = total;
+    }
+    if (__syncthreads_or(trunc) && tid == 0) atomicOr(st + ST_FLAGS, FLAG_TRUNCATED);
+
+    const int by2 = (tk >> 3) * 2 + (tj >> 3);   // which of the tile's 2 x 2 brick rows
+    for (int l = 1; l <= L; ++l) {
+#pragma unroll
+        for (int q = 0; q < kRowsPerThread; ++q) {
+            const int rr = tid + 256 * q;
+            if (rr < R) {
+                const int rj = rinfo[q] & 255, rk = (rinfo[q] >> 8) & 255;
+                const bool rok = (rinfo[q] >> 16) & 1;
+                for (int w = 0; w < RW; ++w) {
+                    const int idx = rr * RW + w;
+                    const unsigned long long c = A[idx];
+                    const unsigned long long left = (w > 0) ? A[idx - 1] : 0ull;
+                    const unsigned long long right = (w < RW - 1) ? A[idx + 1] : 0ull;
+                    unsigned long long v = c | (c << 1) | (c >> 1) | (left >> 63) | (right << 63);
+                    if (rj > 0) v |= A[idx - RW];
+                    if (rj < RJ - 1) v |= A[idx + RW];
+                    if (rk > 0) v |= A[idx - RW * RJ];
+                    if (rk < RK - 1) v |= A[idx + RW * RJ];
+                    const unsigned long long vm =
+                        !rok ? 0ull : (xr0 + w == W - 1 ? tail : ~0ull);
+                    B[idx] = v & vm;
                 }
             }
-            carry[l] += tot;
         }
         __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        for (int l = 0; l <= Lm; ++l) b.tile_off[l * (T + 1) + T] = carry[l];
-    }
-    // truncation flags (rare): OR of the solid's chunk flags
-    for (int c = threadIdx.x; c < b.n_chunks; c += 1024) {
-        if (b.chunk_flag[c]) {
-            const int s = find_solid_by_chunk(b.solids, b.n_solids, c);
-            atomicOr(&b.stats[(int64_t)s * kStatWords + ST_FLAGS], FLAG_TRUNCATED);
+        unsigned long long* tmp = A;
+        A = B;
+        B = tmp;
+        int cnt = 0;
+#pragma unroll
+        for (int w = 0; w < MAXTW; ++w) {
+            const unsigned long long dl = (row_ok && w < tw) ? A[my + w] : 0ull;
+            const unsigned long long nw = dl & ~prev[w];
+            prev[w] = dl;
+            if (l & 1) p0[w] |= nw;
+            if (l & 2) p1[w] |= nw;
+            if (l & 4) p2[w] |= nw;
+            if (l & 8) p3[w] |= nw;
+            if (l & 16) p4[w] |= nw;
+            cnt += __popcll(nw);
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+                if ((nw >> (8 * g)) & 255ull) s_bflag[(l - 1) * FPL + by2 * 8 * MAXTW + w * 8 + g] = 1;
         }
+        int excl, total;
+        block_scan<4>(cnt, excl, total, s_wave);
+        if (tid == 0) b.tile_cnt[(int64_t)t * kLT + l] = total;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < b.n_solids; i += 1024) {
-        const DevSolid* d = b.solids + i;
-        for (int l = 0; l <= Lm; ++l)
-            b.stats[(int64_t)i * kStatWords + l] =
-                (unsigned long long)(b.tile_off[l * (T + 1) + d->tile_base + d->n_tiles] -
-                                     b.tile_off[l * (T + 1) + d->tile_base]);
+
+    // Bricks holding cells of each layer, appended to the layer's list in this tile's
+    // bucket with one atomic addition per layer.  A brick lies in exactly one tile, so a
+    // tile lists at most FPL bricks per layer and its bucket never overflows.
+    {
+        const int bk = t % kBuckets;
+        const int64_t base0 = bucket_base(bk, b.n_tiles, b.tile_w);
+        const int64_t cap = bucket_base(bk + 1, b.n_tiles, b.tile_w) - base0;
+        for (int l = 1; l <= L; ++l) {
+            const int f = tid < FPL ? s_bflag[(l - 1) * FPL + tid] : 0;
+            int excl, total;
+            block_scan<4>(f, excl, total, s_wave);
+            if (total == 0) continue;   // uniform
+            if (tid == 0) s_wave[4] = atomicAdd(b.bcount + (l - 1) * kBuckets + bk, total);
+            __syncthreads();
+            const int pos = s_wave[4] + excl;
+            if (f) {
+                const int r = tid, yz = r / (8 * MAXTW), xb = r % (8 * MAXTW);
+                const int bx = wx0 * 8 + xb, by = 2 * tyi + (yz & 1), bz = 2 * tzi + (yz >> 1);
+                if (pos < cap)
+                    b.blist[(int64_t)(l - 1) * b.blist_cap + base0 + pos] =
+                        ((unsigned long long)s << 32) |
+                        (unsigned long long)(bx | (by << 10) | (bz << 20));
+                else
+                    atomicOr(st + ST_FLAGS, FLAG_OVERFLOW);
+            }
+            __syncthreads();
+        }
+    }
+
+    if (row_ok) {
+        int8_t* lab0 = d->labels + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64;
+        int8_t* dec0 = d->decisions ? d->decisions + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64
+                                    : nullptr;
+#pragma unroll
+        for (int w = 0; w < MAXTW; ++w) {
+            if (w >= tw) break;
+            int8_t* lab = lab0 + 64 * w;
+            int8_t* dec = dec0 ? dec0 + 64 * w : nullptr;
+            const int nx = min(64, n0 - (wx0 + w) * 64);
+            const bool vec = ((n0 & 7) == 0) && nx == 64 &&
+                             ((reinterpret_cast<uintptr_t>(lab) & 7) == 0) &&
+                             (!dec || (reinterpret_cast<uintptr_t>(dec) & 7) == 0);
+            if (vec) {
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
+                    const int sh8 = 8 * g;
+                    // label byte = layer bits where marked, 0xFF where unmarked
+                    unsigned long long word =
+                        spread8((uint32_t)(p0[w] >> sh8) & 255u) |
+                        (spread8((uint32_t)(p1[w] >> sh8) & 255u) << 1) |
+                        (spread8((uint32_t)(p2[w] >> sh8) & 255u) << 2) |
+                        (spread8((uint32_t)(p3[w] >> sh8) & 255u) << 3) |
+                        (spread8((uint32_t)(p4[w] >> sh8) & 255u) << 4);
+                    word |= spread8((uint32_t)(~prev[w] >> sh8) & 255u) * 0xFFull;
+                    reinterpret_cast<unsigned long long*>(lab)[g] = word;
+                    if (dec) reinterpret_cast<unsigned long long*>(dec)[g] = 0ull;
+                }
+            } else {
+                for (int i = 0; i < nx; ++i) {
+                    int v;
+                    if ((prev[w] >> i) & 1ull) {
+                        v = (int)(((p0[w] >> i) & 1ull) | (((p1[w] >> i) & 1ull) << 1) |
+                                  (((p2[w] >> i) & 1ull) << 2) | (((p3[w] >> i) & 1ull) << 3) |
+                                  (((p4[w] >> i) & 1ull) << 4));
+                    } else {
+                        v = -1;
+                    }
+                    lab[i] = (int8_t)v;
+                    if (dec) dec[i] = 0;
+                }
+            }
+        }
     }
 }
 
-// Locate band cell `g` of layer `l`: its tile, global slot, solid and linear cell index.
-struct BandCell {
-    int s;
-    bool skip;       // the solid's band was truncated: nothing to fit
-    int64_t slot;
-    int32_t cell;
-};
-
-__device__ __forceinline__ BandCell locate(const Batch& b, int l, int g) {
-    const int T = b.n_tiles;
-    const int32_t* off = b.tile_off + l * (T + 1);
-    int t = b.chunk_tile[l * b.chunk_cap + g / kLocateChunk];
-    while (off[t + 1] <= g) ++t;
-    BandCell r;
-    r.s = b.tile_solid[t];
-    const DevSolid* d = &b.solids[r.s];
-    r.skip = (b.stats[(int64_t)r.s * kStatWords + ST_FLAGS] & FLAG_TRUNCATED) != 0;
-    r.slot = d->slot_base + (int64_t)(t - d->tile_base) * b.tile_cells +
-             b.tile_lstart[t * kLT + l] + (g - off[t]);
-    r.cell = r.skip ? 0 : b.slots[r.slot];
-    return r;
-}
-
 // ------------------------------------------------------------------------------------
-// Normals of the band cells of layers 1..normal_layers (one thread per cell), from the
-// field before any write: central differences of phi0(xi) over the face neighbours,
-// one-sided with the cell itself where a neighbour is undefined or outside the box.
-// The seven cells are loaded unconditionally (clamped into the box) before any use.
+// Extrapolation of the layer-l cells of one brick, staged in LDS.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_normal(Batch b) {
-    const int T = b.n_tiles;
-    const int NL = min(b.normal_layers, b.Lmax);
-    int total = 0;
-    for (int l = 1; l <= NL; ++l) total += b.tile_off[l * (T + 1) + T];
-    for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < total;
-         gi += gridDim.x * blockDim.x) {
-        int l = 1, gl = gi;
-        for (;;) {
-            const int nl = b.tile_off[l * (T + 1) + T];
-            if (gl < nl) break;
-            gl -= nl;
-            ++l;
-        }
-        const BandCell bc = locate(b, l, gl);
-        if (bc.skip) continue;
-        const DevSolid* d = &b.solids[bc.s];
-        const ShapeR sh = load_shape(d);
-        const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
-        const int64_t nc = d->ncell;
-        const int i = bc.cell % n0, j = (bc.cell / n0) % n1, k = bc.cell / (n0 * n1);
-        const double* __restrict__ f = d->xi_normal;
-        // cells: e, +x, -x, +y, -y, +z, -z
-        bool in[7];
-        int64_t cc[7];
-        in[0] = true;
-        cc[0] = bc.cell;
-        in[1] = i + 1 < n0; cc[1] = in[1] ? bc.cell + 1 : bc.cell;
-        in[2] = i > 0;      cc[2] = in[2] ? bc.cell - 1 : bc.cell;
-        in[3] = j + 1 < n1; cc[3] = in[3] ? bc.cell + n0 : bc.cell;
-        in[4] = j > 0;      cc[4] = in[4] ? bc.cell - n0 : bc.cell;
-        in[5] = k + 1 < n2; cc[5] = in[5] ? bc.cell + (int64_t)n0 * n1 : bc.cell;
-        in[6] = k > 0;      cc[6] = in[6] ? bc.cell - (int64_t)n0 * n1 : bc.cell;
-        double x0[7], x1[7], x2[7];
+template <typename T>
+__device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
+                                           const int8_t* __restrict__ sl, int idx, int le,
+                                           bool use_normal, double g0, double g1, double g2,
+                                           double rgn, double a0, double a1, double a2,
+                                           int lq, Moments<T>& acc) {
+    constexpr int S = kBrickSpan, S2 = kBrickSpan * kBrickSpan;
+#pragma unroll 1
+    for (int row = lq; row < 25; row += kLanes) {
+        const int dy = row % 5 - 2, dz = row / 5 - 2;
+        const int rb = idx + dz * S2 + dy * S;
 #pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            x0[q] = f[cc[q]];
-            x1[q] = f[nc + cc[q]];
-            x2[q] = f[2 * nc + cc[q]];
+        for (int dx = -2; dx <= 2; ++dx) {
+            const int q = rb + dx;
+            const int lab = sl[q];
+            double w = 0.0;
+            bool e = lab >= 0 && lab < le;
+            if (e) e = weight_of(dx, dy, dz, use_normal, g0, g1, g2, rgn, w);
+            if (!e) continue;
+            add_datum<T>(acc, (T)w, dx, dy, dz, (T)(sx[q] - a0), (T)(sx[kBrickCells + q] - a1),
+                         (T)(sx[2 * kBrickCells + q] - a2), true);
         }
-        double ph[7];
-        bool def[7];
-#pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            def[q] = in[q] && finite3(x0[q], x1[q], x2[q]);
-            ph[q] = def[q] ? phi0(sh, x0[q], x1[q], x2[q]) : 0.0;
-        }
-        double g[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int qp = 1 + 2 * a, qm = 2 + 2 * a;
-            double ga;
-            if (def[qp] && def[qm]) ga = 0.5 * (ph[qp] - ph[qm]);
-            else if (def[qp] && def[0]) ga = ph[qp] - ph[0];
-            else if (def[qm] && def[0]) ga = ph[0] - ph[qm];
-            else ga = 0.0;
-            g[a] = ga;
-        }
-        b.normals[bc.slot] = g[0];
-        b.normals[b.slot_cap + bc.slot] = g[1];
-        b.normals[2 * b.slot_cap + bc.slot] = g[2];
-        if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0)
-            atomicAdd(&b.stats[(int64_t)bc.s * kStatWords + ST_NONORMAL], 1ull);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
-    constexpr int kCellsPerWave = 64 / kLanes;
-    const int T_ = b.n_tiles;
-    const int total = b.tile_off[l * (T_ + 1) + T_];
-    const int lane = threadIdx.x & 63, grp = lane / kLanes, lq = lane % kLanes;
-    const int wid = uniform_int(blockIdx.x * 4 + (threadIdx.x >> 6));
-    const int nwv = gridDim.x * 4;
-    for (int base = wid * kCellsPerWave; base < total; base += nwv * kCellsPerWave) {
-        const int gidx = base + grp;
-        if (gidx >= total) continue;
-        const BandCell bc = locate(b, l, gidx);
-        if (bc.skip) continue;
-        const DevSolid* d = &b.solids[bc.s];
+__device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
+                                             unsigned long long* st, int l, int bx, int by,
+                                             int bz, unsigned char* lds, int* s_wave) {
+    double* sx = reinterpret_cast<double*>(lds);
+    int8_t* sl = reinterpret_cast<int8_t*>(lds + kBrickCells * 24);
+    uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * 25);
+    const int tid = threadIdx.x;
+    const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
+    const int64_t nc = d->ncell;
+    const double* __restrict__ xi = d->xi;
+    const int8_t* __restrict__ labels = d->labels;
+    const int ox = kBrick * bx - kBrickHalo, oy = kBrick * by - kBrickHalo,
+              oz = kBrick * bz - kBrickHalo;
+    // Stage xi and labels of the 12^3 cells (outside the box: label -1).
+#pragma unroll
+    for (int h = 0; h < (kBrickCells + 255) / 256; ++h) {
+        const int q = tid + 256 * h;
+        if (q < kBrickCells) {
+            const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
+                      z = q / (kBrickSpan * kBrickSpan);
+            const int gx = ox + x, gy = oy + y, gz = oz + z;
+            const bool in = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+                            (unsigned)gz < (unsigned)n2;
+            const int32_t c = in ? (gz * n1 + gy) * n0 + gx : 0;
+            const int lab = labels[c];
+            const double v0 = xi[c], v1 = xi[nc + c], v2 = xi[2 * nc + c];
+            sl[q] = in ? (int8_t)lab : (int8_t)-1;
+            sx[q] = in ? v0 : 0.0;
+            sx[kBrickCells + q] = in ? v1 : 0.0;
+            sx[2 * kBrickCells + q] = in ? v2 : 0.0;
+        }
+    }
+    __syncthreads();
+    // the layer-l cells of the brick interior, compacted
+    int mine[2], cnt = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 256 * h;
+        const int x = kBrickHalo + q % kBrick, y = kBrickHalo + (q / kBrick) % kBrick,
+                  z = kBrickHalo + q / (kBrick * kBrick);
+        const int idx = (z * kBrickSpan + y) * kBrickSpan + x;
+        mine[h] = sl[idx] == l ? idx : -1;
+        cnt += mine[h] >= 0;
+    }
+    int excl, total;
+    block_scan<4>(cnt, excl, total, s_wave);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (mine[h] >= 0) cells[excl++] = (uint16_t)mine[h];
+    __syncthreads();
+
+    const int grp = tid / kLanes, lq = tid % kLanes;
+    for (int ci = grp; ci < total; ci += 256 / kLanes) {
+        const int idx = cells[ci];
+        const int x = idx % kBrickSpan, y = (idx / kBrickSpan) % kBrickSpan,
+                  z = idx / (kBrickSpan * kBrickSpan);
         CellCtx cx;
-        cx.n0 = d->n0;
-        cx.n1 = d->n1;
-        cx.n2 = d->n2;
-        cx.ncell = d->ncell;
-        cx.xi = d->xi;
-        cx.labels = d->labels;
+        cx.i = ox + x;
+        cx.j = oy + y;
+        cx.k = oz + z;
+        cx.n0 = n0;
+        cx.n1 = n1;
+        cx.n2 = n2;
         cx.le = l;
-        cx.i = bc.cell % cx.n0;
-        cx.j = (bc.cell / cx.n0) % cx.n1;
-        cx.k = bc.cell / (cx.n0 * cx.n1);
-        // Anchor: first face neighbour in a lower layer (-x, +x, -y, +y, -z, +z).  One
-        // exists: the neighbour the cell was labelled from.
-        int32_t nbc[6];
-        bool nin[6];
-        nin[0] = cx.i > 0;          nbc[0] = nin[0] ? bc.cell - 1 : bc.cell;
-        nin[1] = cx.i + 1 < cx.n0;  nbc[1] = nin[1] ? bc.cell + 1 : bc.cell;
-        nin[2] = cx.j > 0;          nbc[2] = nin[2] ? bc.cell - cx.n0 : bc.cell;
-        nin[3] = cx.j + 1 < cx.n1;  nbc[3] = nin[3] ? bc.cell + cx.n0 : bc.cell;
-        nin[4] = cx.k > 0;          nbc[4] = nin[4] ? bc.cell - cx.n0 * cx.n1 : bc.cell;
-        nin[5] = cx.k + 1 < cx.n2;  nbc[5] = nin[5] ? bc.cell + cx.n0 * cx.n1 : bc.cell;
-        int nlab[6];
+        cx.ncell = nc;
+        cx.xi = xi;
+        cx.labels = labels;
+        const int32_t cell = (cx.k * n1 + cx.j) * n0 + cx.i;
+        // Anchor (centring datum): the first face neighbour in a lower layer in the order
+        // -x, +x, -y, +y, -z, +z.  One exists: the neighbour the cell was labelled from.
+        const int nb[6] = {idx - 1, idx + 1, idx - kBrickSpan, idx + kBrickSpan,
+                           idx - kBrickSpan * kBrickSpan, idx + kBrickSpan * kBrickSpan};
+        const int32_t nbg[6] = {cell - 1, cell + 1, cell - n0, cell + n0, cell - n0 * n1,
+                                cell + n0 * n1};
+        int aidx = idx;
+        cx.anchor = cell;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) nlab[q] = cx.labels[nbc[q]];
-        cx.anchor = bc.cell;
-#pragma unroll
-        for (int q = 5; q >= 0; --q)
-            if (nin[q] && nlab[q] >= 0 && nlab[q] < l) cx.anchor = nbc[q];
-        cx.a0 = cx.xi[cx.anchor];
-        cx.a1 = cx.xi[cx.ncell + cx.anchor];
-        cx.a2 = cx.xi[2 * cx.ncell + cx.anchor];
+        for (int q = 5; q >= 0; --q) {
+            const int lb = sl[nb[q]];
+            if (lb >= 0 && lb < l) {
+                aidx = nb[q];
+                cx.anchor = nbg[q];
+            }
+        }
+        cx.a0 = sx[aidx];
+        cx.a1 = sx[kBrickCells + aidx];
+        cx.a2 = sx[2 * kBrickCells + aidx];
         bool has_normal = false;
         cx.g0 = cx.g1 = cx.g2 = cx.rgn = 0.0;
         if (l <= b.normal_layers) {
-            cx.g0 = b.normals[bc.slot];
-            cx.g1 = b.normals[b.slot_cap + bc.slot];
-            cx.g2 = b.normals[2 * b.slot_cap + bc.slot];
+            cx.g0 = d->normals[cell];
+            cx.g1 = d->normals[nc + cell];
+            cx.g2 = d->normals[2 * nc + cell];
             has_normal = cx.g0 != 0.0 || cx.g1 != 0.0 || cx.g2 != 0.0;
             if (has_normal) cx.rgn = 1.0 / norm3(cx.g0, cx.g1, cx.g2);
         }
@@ -293,9 +436,14 @@ __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
             const bool f1 = pass == nfit, f2 = pass == nfit + 1;
             if (f1 && !has_normal) continue;
             const int r = (f1 || f2) ? b.r_max : b.r_s + pass;
+            const bool un = has_normal && !f1 && !f2;
             Moments<T> acc;
             zero(acc);
-            gather_r<T>(cx, r, has_normal && !f1 && !f2, lq, acc);
+            if (r == kBrickHalo)
+                gather_lds<T>(sx, sl, idx, l, un, cx.g0, cx.g1, cx.g2, cx.rgn, cx.a0, cx.a1,
+                              cx.a2, lq, acc);
+            else
+                gather_any<T>(cx, r, un, lq, acc);
             reduce_lanes(acc);
             if (f2) {
                 const double sw = (double)acc.m[0];
@@ -317,16 +465,230 @@ __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
             }
         }
         if (lq == 0) {
-            const int64_t c = bc.cell;
-            d->xi[c] = cx.a0 + res[0];
-            d->xi[cx.ncell + c] = cx.a1 + res[1];
-            d->xi[2 * cx.ncell + c] = cx.a2 + res[2];
-            if (d->decisions) d->decisions[c] = (int8_t)(code + (no_normal ? kDecNoNormal : 0));
-            unsigned long long* st = b.stats + (int64_t)bc.s * kStatWords;
+            d->xi[cell] = cx.a0 + res[0];
+            d->xi[nc + cell] = cx.a1 + res[1];
+            d->xi[2 * nc + cell] = cx.a2 + res[2];
+            if (d->decisions) d->decisions[cell] = (int8_t)(code + (no_normal ? kDecNoNormal : 0));
             if (code == kDecF1) atomicAdd(st + ST_F1, 1ull);
             if (code == kDecF2) atomicAdd(st + ST_F2, 1ull);
             if (code == kDecF1 || code == kDecF2 || code > b.r_s) atomicAdd(st + ST_GROWN, 1ull);
         }
+    }
+    __syncthreads();   // the LDS is reused by the next brick
+}
+
+// ------------------------------------------------------------------------------------
+// Brick lists: the bucket counts of layers l0..l0+nl-1 are turned into one prefix in LDS
+// (s_pref[0..nl*kBuckets]); entry e of the concatenation is then found by bisection.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int list_prefix(const Batch& b, int l0, int nl, int* s_pref,
+                                           int* s_wave) {
+    const int n = nl * kBuckets;   // <= 1024: four counts per thread
+    int v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = threadIdx.x * 4 + q;
+        v[q] = i < n ? b.bcount[(l0 - 1) * kBuckets + i] : 0;
+        // entries past a bucket's capacity were never written (the overflow is reported)
+        if (i < n) {
+            const int bk = i % kBuckets;
+            const int64_t cap = bucket_base(bk + 1, b.n_tiles, b.tile_w) -
+                                bucket_base(bk, b.n_tiles, b.tile_w);
+            v[q] = (int)min((int64_t)v[q], cap);
+        }
+        sum += v[q];
+    }
+    int excl, total;
+    block_scan<4>(sum, excl, total, s_wave);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = threadIdx.x * 4 + q;
+        if (i < n) s_pref[i] = excl;
+        excl += v[q];
+    }
+    if (threadIdx.x == 0) s_pref[n] = total;
+    __syncthreads();
+    return total;
+}
+
+// Entry e of the listed bricks: which layer (l0 + ...) and where in the list it sits.
+__device__ __forceinline__ unsigned long long list_entry(const Batch& b, int l0, int nl,
+                                                         const int* s_pref, int e, int* layer) {
+    int lo = 0, hi = nl * kBuckets - 1;   // last i with s_pref[i] <= e
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pref[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int l = l0 + lo / kBuckets, bk = lo % kBuckets;
+    *layer = l;
+    return b.blist[(int64_t)(l - 1) * b.blist_cap + bucket_base(bk, b.n_tiles, b.tile_w) +
+                   (e - s_pref[lo])];
+}
+
+// ------------------------------------------------------------------------------------
+// Per-solid statistics from the tile counts, then the normals of the listed bricks of
+// layers 1..normal_layers.
+// ------------------------------------------------------------------------------------
+constexpr int kNSpan = kBrick + 2;                        // brick with a halo of 1
+constexpr int kNCells = kNSpan * kNSpan * kNSpan;         // 1000
+
+__device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long long* st, int l,
+                                             int bx, int by, int bz, double* s_phi,
+                                             unsigned char* s_flag, int8_t* s_lab,
+                                             uint16_t* s_list, int* s_wave) {
+    const int tid = threadIdx.x;
+    const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
+    const int64_t nc = d->ncell;
+    const int ox = kBrick * bx - 1, oy = kBrick * by - 1, oz = kBrick * bz - 1;
+    for (int q = tid; q < kNCells; q += 256) s_flag[q] = 0;
+    for (int q = tid; q < kBrick * kBrick * kBrick; q += 256) {
+        const int x = q % kBrick, y = (q / kBrick) % kBrick, z = q / (kBrick * kBrick);
+        const int gx = ox + 1 + x, gy = oy + 1 + y, gz = oz + 1 + z;
+        const bool in = gx < n0 && gy < n1 && gz < n2;
+        s_lab[q] = in ? d->labels[((int64_t)gz * n1 + gy) * n0 + gx] : (int8_t)-1;
+    }
+    __syncthreads();
+    // a cell of layer l needs phi0 at itself and at its six face neighbours
+    for (int q = tid; q < kBrick * kBrick * kBrick; q += 256) {
+        if (s_lab[q] != l) continue;
+        const int x = q % kBrick, y = (q / kBrick) % kBrick, z = q / (kBrick * kBrick);
+        const int r = ((z + 1) * kNSpan + (y + 1)) * kNSpan + (x + 1);
+        s_flag[r] = 1;
+        s_flag[r - 1] = 1;
+        s_flag[r + 1] = 1;
+        s_flag[r - kNSpan] = 1;
+        s_flag[r + kNSpan] = 1;
+        s_flag[r - kNSpan * kNSpan] = 1;
+        s_flag[r + kNSpan * kNSpan] = 1;
+    }
+    __syncthreads();
+    // compact the needed cells (four region cells per thread)
+    int cnt = 0;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const int q = tid * 4 + h;
+        cnt += (q < kNCells && s_flag[q]) ? 1 : 0;
+    }
+    int excl, total;
+    block_scan<4>(cnt, excl, total, s_wave);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const int q = tid * 4 + h;
+        if (q < kNCells && s_flag[q]) s_list[excl++] = (uint16_t)q;
+    }
+    __syncthreads();
+    // phi0 of each needed cell once (defined: inside the box with a finite xi)
+    const ShapeR sh = load_shape(d);
+    const double* __restrict__ f = d->xi_normal;
+    for (int i = tid; i < total; i += 256) {
+        const int r = s_list[i];
+        const int x = r % kNSpan, y = (r / kNSpan) % kNSpan, z = r / (kNSpan * kNSpan);
+        const int gx = ox + x, gy = oy + y, gz = oz + z;
+        const bool in = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+                        (unsigned)gz < (unsigned)n2;
+        const int64_t c = in ? ((int64_t)gz * n1 + gy) * n0 + gx : 0;
+        const double x0 = f[c], x1 = f[nc + c], x2 = f[2 * nc + c];
+        const bool def = in && finite3(x0, x1, x2);
+        s_phi[r] = def ? phi0(sh, x0, x1, x2) : 0.0;
+        s_flag[r] = def ? 3 : 1;
+    }
+    __syncthreads();
+    // central differences where both neighbours are defined, else one-sided with the cell
+    // itself (forward first), else 0
+    int nzero = 0;
+    for (int q = tid; q < kBrick * kBrick * kBrick; q += 256) {
+        if (s_lab[q] != l) continue;
+        const int x = q % kBrick, y = (q / kBrick) % kBrick, z = q / (kBrick * kBrick);
+        const int r = ((z + 1) * kNSpan + (y + 1)) * kNSpan + (x + 1);
+        const int step[3] = {1, kNSpan, kNSpan * kNSpan};
+        const bool d0 = s_flag[r] == 3;
+        double g[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int rp = r + step[a], rm = r - step[a];
+            const bool dp = s_flag[rp] == 3, dm = s_flag[rm] == 3;
+            double ga;
+            if (dp && dm) ga = 0.5 * (s_phi[rp] - s_phi[rm]);
+            else if (dp && d0) ga = s_phi[rp] - s_phi[r];
+            else if (dm && d0) ga = s_phi[r] - s_phi[rm];
+            else ga = 0.0;
+            g[a] = ga;
+        }
+        const int64_t cell = ((int64_t)(oz + 1 + z) * n1 + (oy + 1 + y)) * n0 + (ox + 1 + x);
+        d->normals[cell] = g[0];
+        d->normals[nc + cell] = g[1];
+        d->normals[2 * nc + cell] = g[2];
+        nzero += (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0);
+    }
+    int zx, ztot;
+    block_scan<4>(nzero, zx, ztot, s_wave);
+    if (tid == 0 && ztot) atomicAdd(st + ST_NONORMAL, (unsigned long long)ztot);
+}
+
+__global__ __launch_bounds__(256) void k_normal(Batch b) {
+    __shared__ int s_wave[4];
+    __shared__ int s_pref[kMaxLayers * kBuckets + 1];
+    __shared__ unsigned long long s_acc[kLT];
+    __shared__ double s_phi[kNCells];
+    __shared__ unsigned char s_flag[kNCells];
+    __shared__ int8_t s_lab[kBrick * kBrick * kBrick];
+    __shared__ uint16_t s_list[kNCells];
+    const int tid = threadIdx.x;
+    // per-solid interior and band counts: the sums of the solid's tile counts
+    for (int s = blockIdx.x; s < b.n_solids; s += gridDim.x) {
+        const DevSolid* d = b.solids + s;
+        if (tid < kLT) s_acc[tid] = 0ull;
+        __syncthreads();
+        unsigned long long acc[kLT];
+#pragma unroll
+        for (int l = 0; l < kLT; ++l) acc[l] = 0ull;
+        for (int t = d->tile_base + tid; t < d->tile_base + d->n_tiles; t += 256)
+#pragma unroll
+            for (int l = 0; l < kLT; ++l)
+                if (l <= d->L) acc[l] += (unsigned)b.tile_cnt[(int64_t)t * kLT + l];
+#pragma unroll
+        for (int l = 0; l < kLT; ++l)
+            if (acc[l]) atomicAdd(&s_acc[l], acc[l]);
+        __syncthreads();
+        if (tid < kLT) b.stats[(int64_t)s * kStatWords + tid] = s_acc[tid];
+        __syncthreads();
+    }
+    const int nl = b.normal_layers;
+    if (nl <= 0) return;
+    const int total = list_prefix(b, 1, nl, s_pref, s_wave);
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        int l = 0;
+        const unsigned long long pk = list_entry(b, 1, nl, s_pref, e, &l);
+        const int s = uniform_int((int)(pk >> 32));
+        const int bx = uniform_int((int)(pk & 1023ull));
+        const int by = uniform_int((int)((pk >> 10) & 1023ull));
+        const int bz = uniform_int((int)((pk >> 20) & 1023ull));
+        l = uniform_int(l);
+        unsigned long long* st = b.stats + (int64_t)s * kStatWords;
+        if (st[ST_FLAGS] & FLAG_TRUNCATED) continue;   // uniform: no fit follows
+        normal_brick(b.solids + s, st, l, bx, by, bz, s_phi, s_flag, s_lab, s_list, s_wave);
+        __syncthreads();   // the LDS is reused by the next brick
+    }
+}
+
+// One launch per layer: blocks stride over the layer's brick list.
+template <typename T>
+__global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
+    HIP_DYNAMIC_SHARED(double, lds_d)
+    unsigned char* lds = reinterpret_cast<unsigned char*>(lds_d);
+    __shared__ int s_wave[4];
+    __shared__ int s_pref[kBuckets + 1];
+    const int count = list_prefix(b, l, 1, s_pref, s_wave);
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        int ll = 0;
+        const unsigned long long pk = list_entry(b, l, 1, s_pref, e, &ll);
+        const int s = uniform_int((int)(pk >> 32));
+        const int bx = uniform_int((int)(pk & 1023ull));
+        const int by = uniform_int((int)((pk >> 10) & 1023ull));
+        const int bz = uniform_int((int)((pk >> 20) & 1023ull));
+        unsigned long long* st = b.stats + (int64_t)s * kStatWords;
+        if (st[ST_FLAGS] & FLAG_TRUNCATED) continue;   // uniform: whole block skips
+        extrap_brick<T>(b, b.solids + s, st, l, bx, by, bz, lds, s_wave);
     }
 }
 
@@ -335,13 +697,6 @@ __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
 // ------------------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------------------
-static int grid_for(int64_t work, int per_block, int cap) {
-    int64_t g = (work + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (int)g;
-}
-
 hipError_t launch_classify(const Batch& b, hipStream_t st) {
     const int grid = b.n_chunks < 8192 ? b.n_chunks : 8192;
     hipLaunchKernelGGL(k_classify, dim3(grid), dim3(256), 0, st, b);
@@ -355,27 +710,28 @@ size_t label_lds_bytes(int Lmax, int tile_w, int Wmax) {
 }
 
 hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(k_label, dim3(b.n_tiles), dim3(256), lds, st, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_scan(const Batch& b, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_normal(const Batch& b, int64_t max_cells, hipStream_t st) {
-    hipLaunchKernelGGL(k_normal, dim3(grid_for(max_cells, 256, 4096)), dim3(256), 0, st, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_extrap(const Batch& b, int layer, int precision, int64_t max_cells,
-                         hipStream_t st) {
-    const int grid = grid_for(max_cells, 4 * (64 / kLanes), 4096);
-    if (precision == 1)
-        hipLaunchKernelGGL(k_extrap<float>, dim3(grid), dim3(256), 0, st, b, layer);
+    if (b.tile_w == 1)
+        hipLaunchKernelGGL(k_label<1>, dim3(b.n_tiles), dim3(256), lds, st, b);
+    else if (b.tile_w == 2)
+        hipLaunchKernelGGL(k_label<2>, dim3(b.n_tiles), dim3(256), lds, st, b);
+    else if (b.tile_w == 4)
+        hipLaunchKernelGGL(k_label<4>, dim3(b.n_tiles), dim3(256), lds, st, b);
     else
-        hipLaunchKernelGGL(k_extrap<double>, dim3(grid), dim3(256), 0, st, b, layer);
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_normal, dim3(blocks), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_extrap(const Batch& b, int layer, int precision, int blocks,
+                         hipStream_t st) {
+    if (precision == 1)
+        hipLaunchKernelGGL(k_extrap<float>, dim3(blocks), dim3(256), kBrickLds, st, b, layer);
+    else
+        hipLaunchKernelGGL(k_extrap<double>, dim3(blocks), dim3(256), kBrickLds, st, b, layer);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ CSRC = os.path.join(ROOT, "paper_2104_00095_amd", "csrc")
 EXE = os.path.join(HERE, "run_case_emu")
 CLANG = "/opt/rocm/lib/llvm/bin/clang++"
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("rmx_kernels.hip", "rmx_fused.hip", "rmx_core.cpp", "rmx_server.cpp")] + \
+           ("rmx_kernels.hip", "rmx_plan.cpp", "rmx_core.cpp", "rmx_server.cpp")] + \
           [os.path.join(HERE, "hip_emu.cpp"), os.path.join(HERE, "run_case.cpp")]
 
 
@@ -24,7 +24,7 @@ def build(sanitize=True):
         return EXE
     flags = ["-std=c++20", "-g", "-O1", "-fno-omit-frame-pointer", "-Wno-unknown-attributes",
              "-Wno-unused-command-line-argument", "-I", HERE, "-I", os.path.join(ROOT, "include"),
-             "-I", CSRC, "-DRMX_ENABLE_PERSISTENT"]
+             "-I", CSRC, "-DRMX_EMU_REDZONES"]
     if sanitize:
         flags += ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
     cmd = [CLANG] + flags + ["-x", "c++"] + srcs + ["-o", EXE + ".tmp", "-lpthread"]
@@ -34,7 +34,7 @@ def build(sanitize=True):
 
 
 def run(w, tmpdir, r_s=2, r_max=4, normal_layers=2, precision=0, flags=0, reps=1,
-        xi_normal=None, timeout=600, blocks=1, pre_flags=()):
+        xi_normal=None, timeout=600, pre_flags=()):
     """Write workload `w` to tmpdir, run the emulated library, return
     (status, [(xi_out, labels, decisions, stats_raw)])."""
     os.makedirs(tmpdir, exist_ok=True)
@@ -62,7 +62,7 @@ def run(w, tmpdir, r_s=2, r_max=4, normal_layers=2, precision=0, flags=0, reps=1
     elif os.path.exists(pre):
         os.remove(pre)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-               UBSAN_OPTIONS="print_stacktrace=1", RMX_EMU_BLOCKS=str(blocks))
+               UBSAN_OPTIONS="print_stacktrace=1")
     subprocess.run([build(), tmpdir], check=True, timeout=timeout, env=env)
     st = int(open(os.path.join(tmpdir, "status.txt")).read())
     outs = []

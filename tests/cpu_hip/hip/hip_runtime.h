@@ -156,6 +156,7 @@ hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned f);
 hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventSynchronize(hipEvent_t e);
+hipError_t hipEventQuery(hipEvent_t e);
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode m);
 hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g);
@@ -164,20 +165,10 @@ hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t* 
 hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
 hipError_t hipGraphExecDestroy(hipGraphExec_t e);
 hipError_t hipGraphDestroy(hipGraph_t g);
-namespace rmx_emu { int concurrent_blocks(); }
-template <typename K>
-inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, K, int, size_t) {
-    *n = rmx_emu::concurrent_blocks();
-    return hipSuccess;
-}
-
 namespace rmx_emu {
-// `concurrent`: run all blocks of the launch at once (kernels whose blocks wait on each
-// other and keep no block state in static __shared__ variables).
-void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, bool concurrent,
-            std::function<void()> body);
-int concurrent_blocks();
+// Blocks run one after another (static __shared__ variables are one copy); the threads
+// of a block run concurrently.
+void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, std::function<void()> body);
 }
-#define hipLaunchKernelGGL(K, G, B, L, S, ...)                                          \
-    rmx_emu::launch((G), (B), (L), (S), std::string(#K).find("k_fused") == 0,          \
-                    [=]() { K(__VA_ARGS__); })
+#define hipLaunchKernelGGL(K, G, B, L, S, ...) \
+    rmx_emu::launch((G), (B), (L), (S), [=]() { K(__VA_ARGS__); })

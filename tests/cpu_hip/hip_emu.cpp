@@ -10,10 +10,6 @@ thread_local dim3 threadIdx_, blockIdx_;
 dim3 blockDim_, gridDim_;
 thread_local Block* block_ = nullptr;
 
-int concurrent_blocks() {
-    const char* e = std::getenv("RMX_EMU_BLOCKS");
-    return e ? std::max(1, std::atoi(e)) : 1;
-}
 
 struct Block {
     int n = 0;
@@ -43,7 +39,6 @@ namespace {
 struct Capture {
     dim3 grid, block;
     size_t lds;
-    bool concurrent;
     std::function<void()> body;
 };
 hipStream_t g_capturing = nullptr;
@@ -84,43 +79,32 @@ static void init_block(Block& blk, int n, size_t lds) {
     fill_garbage(blk.lds.data(), lds);
 }
 
-static void run(dim3 grid, dim3 block, size_t lds, bool concurrent,
-                const std::function<void()>& body) {
+static void run(dim3 grid, dim3 block, size_t lds, const std::function<void()>& body) {
     gridDim_ = grid;
     blockDim_ = block;
-    const int nb = concurrent ? (int)grid.x : 1;
-    std::vector<Block> blks(nb);
-    for (auto& b : blks) init_block(b, (int)block.x, lds);
+    Block blk;
+    init_block(blk, (int)block.x, lds);
     std::vector<std::thread> th;
-    for (int q = 0; q < nb; ++q) {
-        for (int t = 0; t < (int)block.x; ++t) {
-            th.emplace_back([&, q, t]() {
-                Block& blk = blks[q];
-                block_ = &blk;
-                threadIdx_ = dim3(t);
-                if (concurrent) {
-                    blockIdx_ = dim3(q);
-                    body();
-                    return;
-                }
-                for (unsigned b = 0; b < grid.x; ++b) {
-                    blockIdx_ = dim3(b);
-                    body();
-                    blk.all->arrive_and_wait();
-                }
-            });
-        }
+    for (int t = 0; t < (int)block.x; ++t) {
+        th.emplace_back([&, t]() {
+            block_ = &blk;
+            threadIdx_ = dim3(t);
+            for (unsigned b = 0; b < grid.x; ++b) {
+                blockIdx_ = dim3(b);
+                body();
+                blk.all->arrive_and_wait();
+            }
+        });
     }
     for (auto& x : th) x.join();
 }
 
-void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, bool concurrent,
-            std::function<void()> body) {
+void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, std::function<void()> body) {
     if (st && st == g_capturing) {
-        g_captured.push_back(Capture{grid, block, lds, concurrent, body});
+        g_captured.push_back(Capture{grid, block, lds, body});
         return;
     }
-    run(grid, block, lds, concurrent, body);
+    run(grid, block, lds, body);
 }
 
 struct Graph {
@@ -140,7 +124,7 @@ hipError_t end_capture(hipStream_t, hipGraph_t* g) {
     return hipSuccess;
 }
 void replay(hipGraph_t g) {
-    for (auto& c : reinterpret_cast<Graph*>(g)->nodes) run(c.grid, c.block, c.lds, c.concurrent, c.body);
+    for (auto& c : reinterpret_cast<Graph*>(g)->nodes) run(c.grid, c.block, c.lds, c.body);
 }
 void destroy(hipGraph_t g) { delete reinterpret_cast<Graph*>(g); }
 
@@ -197,6 +181,7 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
     return hipSuccess;
 }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventQuery(hipEvent_t) { return hipSuccess; }   // emulated work is synchronous
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
     *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count();
     return hipSuccess;
@@ -212,3 +197,17 @@ hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*,
 hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) { rmx_emu::replay(e); return hipSuccess; }
 hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 hipError_t hipGraphDestroy(hipGraph_t g) { rmx_emu::destroy(g); return hipSuccess; }
+
+// Red zones between workspace regions (the emulation build of the host core records
+// them): the whole workspace is made addressable, then each zone is poisoned.
+#include <sanitizer/asan_interface.h>
+#include <utility>
+namespace rmx {
+void rmx_emu_poison_gaps(void* ws, size_t ws_bytes,
+                         const std::vector<std::pair<size_t, size_t>>& gaps) {
+    char* base = static_cast<char*>(ws);
+    ASAN_UNPOISON_MEMORY_REGION(base, ws_bytes);
+    for (const auto& g : gaps)
+        if (g.first + g.second <= ws_bytes) ASAN_POISON_MEMORY_REGION(base + g.first, g.second);
+}
+}  // namespace rmx

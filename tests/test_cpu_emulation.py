@@ -1,9 +1,10 @@
 """The library's HIP kernels, host core included, built for the CPU over a host emulation
 of the HIP subset they use (tests/cpu_hip) and run under AddressSanitizer and
 UndefinedBehaviorSanitizer on tiny workloads.  Labels and decisions must equal the
-oracle's and xi must meet the GPU tolerance.  Thread blocks are host threads; the
-persistent launch runs several blocks concurrently, so its per-slab waits are exercised
-in earnest.  Test infrastructure only: the product library never contains this build.
+oracle's and xi must meet the GPU tolerance.  The threads of a block are host threads
+(blocks run in turn), and the workspace regions are separated by poisoned red zones, so an
+access past any region is reported.  Test infrastructure only: the product library never
+contains this build.
 """
 import os
 
@@ -17,7 +18,7 @@ emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
 
 TOL = {0: 1e-12, 1: 1e-5}
-CHAIN, PER_SOLID, PERSISTENT = 0, 4, 16
+BATCHED, PER_SOLID, GRAPH, PERSISTENT = 0, 4, 2, 16
 
 
 def _cases():
@@ -44,28 +45,34 @@ def _check(w, outs, precision, **kw):
         assert np.array_equal(xo[:, keep].view(np.uint64), s.xi[:, keep].view(np.uint64))
 
 
-@pytest.mark.parametrize("flags,blocks", [(CHAIN, 1), (PER_SOLID, 1), (PERSISTENT, 1),
-                                          (PERSISTENT, 5)])
-@pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("case", ["sphere16", "ellipsoid24", "suspension3"])
-def test_emulated_kernels_match_oracle(built, tmp_path, case, precision, flags, blocks):
-    if precision == 1 and case != "suspension3":
-        pytest.skip("FP32 accumulation: one multi-solid case suffices")
+@pytest.mark.parametrize("case,precision,flags", [
+    ("sphere16", 0, BATCHED),
+    ("ellipsoid24", 0, BATCHED),
+    ("suspension3", 0, BATCHED),
+    ("suspension3", 0, PER_SOLID),
+    ("suspension3", 1, GRAPH),
+])
+def test_emulated_kernels_match_oracle(built, tmp_path, case, precision, flags):
     w = _cases()[case]
-    st, outs = emu.run(w, str(tmp_path), precision=precision, flags=flags, blocks=blocks)
+    st, outs = emu.run(w, str(tmp_path), precision=precision, flags=flags)
     assert st == 0
     _check(w, outs, precision)
 
 
-def test_emulated_persistent_after_chain_calls(built, tmp_path):
-    """Persistent launches interleaved with chain calls on one context (shared workspace;
-    each call on a fresh copy of the field): the counters must come back to zero after
-    every persistent launch for the last one to be right."""
-    w = _cases()["sphere16"]
-    st, outs = emu.run(w, str(tmp_path), flags=PERSISTENT, blocks=4,
-                       pre_flags=(CHAIN, PERSISTENT, CHAIN, PERSISTENT))
+def test_emulated_repeated_calls(built, tmp_path):
+    """Calls of different forms on one context (shared workspace, descriptors cached
+    between identical calls), each on a fresh copy of the field, before the checked call."""
+    w = _cases()["suspension3"]
+    st, outs = emu.run(w, str(tmp_path), flags=BATCHED,
+                       pre_flags=(BATCHED, GRAPH, BATCHED))
     assert st == 0
     _check(w, outs, 0)
+
+
+def test_emulated_persistent_refused(built, tmp_path):
+    w = _cases()["sphere16"]
+    st, _ = emu.run(w, str(tmp_path), flags=PERSISTENT)
+    assert st == -11
 
 
 def test_emulated_statuses(built, tmp_path):
@@ -78,8 +85,8 @@ def test_emulated_statuses(built, tmp_path):
     w.solids.append(synth.Solid(s.lo, s.ext, s.shape, 3, s.xi + 10.0))
     w.solids.append(synth.Solid(s.lo, s.ext, s.shape, 0, s.xi.copy()))
     w.solids.append(synth.Solid(s.lo, s.ext, s.shape, 3, s.xi.copy()))
-    for flags, blocks in ((CHAIN, 1), (PERSISTENT, 3)):
-        st, outs = emu.run(w, str(tmp_path), flags=flags, blocks=blocks)
+    for flags in (BATCHED, PER_SOLID):
+        st, outs = emu.run(w, str(tmp_path), flags=flags)
         assert st == -7
         _check(w, outs, 0)
 

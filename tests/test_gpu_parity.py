@@ -14,22 +14,10 @@ from tests.helpers import oracle_problem, rel_err, run_oracle
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-12, 1: 1e-5}
-# Launch forms: the batched multi-kernel chain (default) and the single persistent launch.
-# The persistent launch is switched off in the library (RMX_E_DISABLED) after a GPU memory
-# fault whose cause is not known; its cases stay skipped until that cause is found.  Its
-# kernel logic runs, bit for bit against the oracle, in the CPU emulation tests.
-MODES = {"chain": 0, "fused": 16}
-FUSED_SKIP = ("persistent launch switched off: GPU memory fault of unknown cause "
-              "(kernel logic covered by the CPU emulation tests)")
-
-
-def mode_param(mode):
-    if mode == "fused":
-        return pytest.param(mode, marks=pytest.mark.skip(reason=FUSED_SKIP))
-    return mode
-
-
-MODE_PARAMS = [mode_param(m) for m in sorted(MODES)]
+# Launch forms: every solid of the call in one chain of launches (default), and one chain
+# per solid (the plain form).
+MODES = {"batched": 0, "per_solid": 4}
+MODE_PARAMS = sorted(MODES)
 
 
 @pytest.fixture(scope="module")
