@@ -74,9 +74,33 @@ def profile_phases(ctx, dw, opt, steps):
     return {k: (ms / n, n) for k, (ms, n) in prof.items()}
 
 
-def kernel_bytes(phase, w, stats, normal_layers=2, decisions=False):
+def classify_bytes(w):
+    """Bytes the classification must read under its exact early-out rule: xi_x of every
+    cell, xi_y where dx^2 < T, xi_z where dx^2 + dy^2 < T (T = R^2 for a sphere,
+    e_max^2 (1 + 1e-6) for an ellipsoid; the same operation order as the kernel), plus
+    the 1-bit mask written."""
+    import numpy as np
+    total = 0.0
+    for s in w.solids:
+        c = s.shape.centre
+        T = float(s.shape.semi[0]) ** 2 if s.shape.kind == 1 else \
+            float(np.max(s.shape.semi)) ** 2 * (1.0 + 1e-6)
+        with np.errstate(invalid="ignore"):
+            dx = s.xi[0] - c[0]
+            p = dx * dx
+            ny = p < T
+            dy = s.xi[1] - c[1]
+            p2 = p + dy * dy
+            nz = ny & (p2 < T)
+        cells = s.xi[0].size
+        total += 8.0 * cells + 8.0 * float(ny.sum()) + 8.0 * float(nz.sum()) + cells / 8.0
+    return total
+
+
+def kernel_bytes(phase, w, stats, normal_layers=2, decisions=False, cls_bytes=None):
     """Algorithmic HBM bytes of one launch of a kernel (the minimum it must move):
-    classify reads xi once (24 B/cell) and writes the 1-bit mask; label reads the mask and
+    classify reads xi under its early-out rule (see classify_bytes; at most 24 B/cell)
+    and writes the 1-bit mask; label reads the mask and
     writes int8 labels (and decisions); normal reads xi (24 B) and writes the normal
     (24 B) of each cell of layers 1..normal_layers; the fit of layer l writes xi (24 B)
     and the decision (1 B) of each cell of the layer and reads its normal (24 B) where one
@@ -85,7 +109,7 @@ def kernel_bytes(phase, w, stats, normal_layers=2, decisions=False):
     band = [sum(s["n_band"][l] for s in stats) for l in range(17)]
     dec = 1 if decisions else 0
     if phase == "classify":
-        return 24 * cells + cells / 8
+        return cls_bytes if cls_bytes is not None else 24 * cells + cells / 8
     if phase == "label":
         return cells / 8 + (1 + dec) * cells
     if phase == "normal":
@@ -118,6 +142,27 @@ def cpu_baseline(w, seconds, r_s=2, r_max=4, normal_layers=2):
     return {"value": band / el, "unit": "band cells/s", "cores": cores, "kind": "oracle",
             "sample": f"{calls} whole calls of {w.name} ({len(w.solids)} solid(s)), "
                       f"{el:.1f} s wall, OpenMP threads = {cores}"}
+
+
+def copy_calibration(n_bytes=1 << 30, reps=5):
+    """A plain device-to-device copy of n_bytes (read n_bytes, write n_bytes), `reps`
+    times: under a counter profiler, its FETCH_SIZE and WRITE_SIZE per dispatch against
+    n_bytes give the scale of those counters."""
+    import torch
+    src = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": n_bytes, "copy_bytes_written": n_bytes,
+                      "ms": ms, "GB_per_s": 2 * n_bytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def make_workload(name):
@@ -154,6 +199,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (the reference for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters) and print its rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -165,6 +213,9 @@ def main():
     from paper_2104_00095_amd import fields, rmx
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     log(f"generating {args.workload}")
     w = make_workload(args.workload)
@@ -181,10 +232,12 @@ def main():
     log("profiling kernels")
     prof_calls = max(10, min(args.steps, 50))
     phases = profile_phases(ctx, dw, opt, prof_calls)
-    dom = max((k for k in phases if kernel_bytes(k, w, stats) is not None),
+    cb = classify_bytes(w)
+    kb = {k: kernel_bytes(k, w, stats, cls_bytes=cb) for k in phases}
+    dom = max((k for k in phases if kb[k] is not None),
               key=lambda k: phases[k][0])
     dom_ms = phases[dom][0]
-    dom_bytes = kernel_bytes(dom, w, stats)
+    dom_bytes = kb[dom]
     roof = {"bound": "hbm", "kernel": dom, "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
             "kernel_ms": dom_ms, "algorithmic_bytes": dom_bytes}
@@ -241,9 +294,9 @@ def main():
                           "achieved": B / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)},
         "kernels": {k: {"ms": v[0], "launches_per_call": v[1] / prof_calls,
-                        "algorithmic_bytes": kernel_bytes(k, w, stats),
-                        "hbm_frac": (kernel_bytes(k, w, stats) / (v[0] * 1e-3) / 1e9
-                                     / HBM_PEAK_GBS) if kernel_bytes(k, w, stats) else None}
+                        "algorithmic_bytes": kb[k],
+                        "hbm_frac": (kb[k] / (v[0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                        if kb[k] else None}
                     for k, v in phases.items()},
         "cpu_baseline": cpu,
         "variants": variants,

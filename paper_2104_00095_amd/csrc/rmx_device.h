@@ -466,13 +466,12 @@ __device__ __forceinline__ void add_datum(Moments<T>& acc, T tw, int dx, int dy,
     acc.r[9] += wz * v0;
     acc.r[10] += wz * v1;
     acc.r[11] += wz * v2;
-    if (counted) {
-        acc.g[0] += 1 + ((dx * dx) << 16);
-        acc.g[1] += dx + ((dx * dy) << 16);
-        acc.g[2] += dy + ((dx * dz) << 16);
-        acc.g[3] += dz + ((dy * dy) << 16);
-        acc.g[4] += (dy * dz) + ((dz * dz) << 16);
-    }
+    const int ce = counted ? 1 : 0;
+    acc.g[0] += ce * (1 + ((dx * dx) << 16));
+    acc.g[1] += ce * (dx + ((dx * dy) << 16));
+    acc.g[2] += ce * (dy + ((dx * dz) << 16));
+    acc.g[3] += ce * (dz + ((dy * dy) << 16));
+    acc.g[4] += ce * ((dy * dz) + ((dz * dz) << 16));
 }
 
 // Weight of offset (dx, dy, dz) per eq. (weight); false if it is zero (ineligible or in

@@ -26,29 +26,86 @@ using namespace dev;
 
 // ------------------------------------------------------------------------------------
 // Classification of mask words [wb, we) of solid d by the 4 waves of the block: each wave
-// streams 16 consecutive 64-cell row segments, 8 at a time (24 loads of 512 contiguous
-// bytes in flight), ballot-packs the interior predicate and writes one mask word per
-// segment.  Cells past the row end (x >= n0) are never interior.
+// streams its 16 consecutive 64-cell row segments, ballot-packs the interior predicate
+// and writes one mask word per segment.  Cells past the row end (x >= n0) are never
+// interior.
+//
+// Sphere: the components are read in turn, each only where the decision is still open,
+// which leaves it unchanged: the test is ((dx*dx + dy*dy) + dz*dz) < R*R, and in
+// round-to-nearest a sum of non-negative terms is never below any of its partial sums,
+// so dx*dx >= R*R, or dx*dx + dy*dy >= R*R, already means "not interior" (a non-finite
+// component fails its test as well, as in the full predicate).  The running sum is all a
+// lane keeps, so a wave issues each component's 16 loads at once.  Ellipsoid: the body
+// coordinates need all three components, read together.
 // ------------------------------------------------------------------------------------
-constexpr int kSeg = 8;
+constexpr int kWaveWords = kChunkWords / 4;   // 16 segments per wave
+constexpr int kSegE = 4;                       // ellipsoid: segments per batch
 
-__device__ __forceinline__ void classify_words(const DevSolid* dp, int wb, int we) {
+__device__ __forceinline__ void classify_sphere(const DevSolid* dp, const ShapeR& sh, int wb,
+                                                int we) {
+#pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int n0 = dp->n0, W = dp->W;
     const int64_t ncell = dp->ncell;
     const double* __restrict__ xi = dp->xi;
     unsigned long long* __restrict__ mask = dp->mask;
-    const ShapeR sh = load_shape(dp);
-    const int first = wb + wave * (kChunkWords / 4);
+    const double T = sh.e0 * sh.e0;
+    const int w0 = wb + wave * kWaveWords;
+    if (w0 >= we) return;
+    int row = w0 / W, wx = w0 - row * W;
+    int32_t c[kWaveWords];
+    double p[kWaveWords];
+#pragma unroll
+    for (int u = 0; u < kWaveWords; ++u) {
+        const int x = wx * 64 + lane;
+        c[u] = (w0 + u < we && x < n0) ? row * n0 + x : -1;
+        p[u] = __builtin_nan("");
+        if (c[u] >= 0) p[u] = __builtin_nontemporal_load(xi + c[u]);
+        if (++wx == W) {
+            wx = 0;
+            ++row;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kWaveWords; ++u) {
+        const double dx = p[u] - sh.c0;
+        p[u] = dx * dx;
+    }
+#pragma unroll
+    for (int u = 0; u < kWaveWords; ++u) {
+        double v = __builtin_nan("");
+        if (p[u] < T) v = __builtin_nontemporal_load(xi + ncell + c[u]);
+        const double dy = v - sh.c1;
+        p[u] = p[u] + dy * dy;
+    }
+#pragma unroll
+    for (int u = 0; u < kWaveWords; ++u) {
+        double v = __builtin_nan("");
+        if (p[u] < T) v = __builtin_nontemporal_load(xi + 2 * ncell + c[u]);
+        const double dz = v - sh.c2;
+        const unsigned long long m = __ballot((p[u] + dz * dz) < T);
+        if (lane == 0 && w0 + u < we) mask[w0 + u] = m;
+    }
+}
+
+__device__ __forceinline__ void classify_ellipsoid(const DevSolid* dp, const ShapeR& sh,
+                                                   int wb, int we) {
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int n0 = dp->n0, W = dp->W;
+    const int64_t ncell = dp->ncell;
+    const double* __restrict__ xi = dp->xi;
+    unsigned long long* __restrict__ mask = dp->mask;
+    const int first = wb + wave * kWaveWords;
 #pragma unroll 1
-    for (int it = 0; it < kChunkWords / 4; it += kSeg) {
+    for (int it = 0; it < kWaveWords; it += kSegE) {
         const int w0 = first + it;
         if (w0 >= we) break;
         int row = w0 / W, wx = w0 - row * W;
-        double v0[kSeg], v1[kSeg], v2[kSeg];
+        double v0[kSegE], v1[kSegE], v2[kSegE];
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) {
+        for (int u = 0; u < kSegE; ++u) {
             const int x = wx * 64 + lane;
             v0[u] = v1[u] = v2[u] = __builtin_nan("");
             if (w0 + u < we && x < n0) {
@@ -63,11 +120,19 @@ __device__ __forceinline__ void classify_words(const DevSolid* dp, int wb, int w
             }
         }
 #pragma unroll
-        for (int u = 0; u < kSeg; ++u) {
+        for (int u = 0; u < kSegE; ++u) {
             const unsigned long long m = __ballot(interior(sh, v0[u], v1[u], v2[u]));
             if (lane == 0 && w0 + u < we) mask[w0 + u] = m;
         }
     }
+}
+
+__device__ __forceinline__ void classify_words(const DevSolid* dp, int wb, int we) {
+    const ShapeR sh = load_shape(dp);
+    if (sh.kind == 1)
+        classify_sphere(dp, sh, wb, we);
+    else
+        classify_ellipsoid(dp, sh, wb, we);
 }
 
 // A block owns a chunk of kChunkWords mask words of one solid.  Block 0 also zeroes the
@@ -303,9 +368,17 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
 // ------------------------------------------------------------------------------------
 // Extrapolation of the layer-l cells of one brick, staged in LDS.
 // ------------------------------------------------------------------------------------
+// Moments of the eligible data of radius r_s = 2 around staged cell idx.  A lane takes
+// whole rows (dy, dz); within a row the five data (dx = -2..2) are first summed into row
+// moments (sum w, sum w dx, sum w dx^2, sum w v, sum w dx v), which then update the
+// 4 x 4 normal matrix and the right-hand sides once per row.  Branch-free: a datum outside
+// the eligible set (or behind the interface) enters with weight 0 and a zero value
+// (selects, so a non-finite value of an ineligible cell cannot leak in).  The integer
+// moments of the eligible offsets (for the exact rank test) are summed the same way.
 template <typename T>
 __device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
-                                           const int8_t* __restrict__ sl, int idx, int le,
+                                           const int8_t* __restrict__ sl,
+                                           const double* __restrict__ s_rlen, int idx, int le,
                                            bool use_normal, double g0, double g1, double g2,
                                            double rgn, double a0, double a1, double a2,
                                            int lq, Moments<T>& acc) {
@@ -314,24 +387,85 @@ __device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
     for (int row = lq; row < 25; row += kLanes) {
         const int dy = row % 5 - 2, dz = row / 5 - 2;
         const int rb = idx + dz * S2 + dy * S;
+        int lab[5];
+        double v0[5], v1[5], v2[5];
 #pragma unroll
-        for (int dx = -2; dx <= 2; ++dx) {
-            const int q = rb + dx;
-            const int lab = sl[q];
-            double w = 0.0;
-            bool e = lab >= 0 && lab < le;
-            if (e) e = weight_of(dx, dy, dz, use_normal, g0, g1, g2, rgn, w);
-            if (!e) continue;
-            add_datum<T>(acc, (T)w, dx, dy, dz, (T)(sx[q] - a0), (T)(sx[kBrickCells + q] - a1),
-                         (T)(sx[2 * kBrickCells + q] - a2), true);
+        for (int u = 0; u < 5; ++u) {
+            const int q = rb + u - 2;
+            lab[u] = sl[q];
+            v0[u] = sx[q];
+            v1[u] = sx[kBrickCells + q];
+            v2[u] = sx[2 * kBrickCells + q];
         }
+        const int rowd2 = dy * dy + dz * dz;
+        const double rowbase = ldexp(1.0, -(abs(dy) + abs(dz)));   // 2^-(|dy|+|dz|), exact
+        T s0 = T(0), s1 = T(0), s2 = T(0);
+        T t0[3] = {T(0), T(0), T(0)}, t1[3] = {T(0), T(0), T(0)};
+        int n = 0, nx = 0, nxx = 0;
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+            const int dx = u - 2;
+            bool e = lab[u] >= 0 && lab[u] < le;
+            double ww = rowbase * (dx == 0 ? 1.0 : (dx == 1 || dx == -1 ? 0.5 : 0.25));
+            if (use_normal) {
+#pragma clang fp contract(off)
+                const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
+                const double dot = (fx * g0 + fy * g1) + fz * g2;
+                e = e && (dot < 0.0);
+                ww = (-dot * s_rlen[dx * dx + rowd2] * rgn) * ww;
+            }
+            const T w = e ? (T)ww : T(0);
+            const T p0 = w * (e ? (T)(v0[u] - a0) : T(0));
+            const T p1 = w * (e ? (T)(v1[u] - a1) : T(0));
+            const T p2 = w * (e ? (T)(v2[u] - a2) : T(0));
+            s0 += w;
+            t0[0] += p0;
+            t0[1] += p1;
+            t0[2] += p2;
+            if (dx != 0) {   // resolved at compile time (the loop is unrolled)
+                const T fx = (T)dx;
+                s1 += fx * w;
+                s2 += (fx * fx) * w;
+                t1[0] += fx * p0;
+                t1[1] += fx * p1;
+                t1[2] += fx * p2;
+            }
+            const int ei = e ? 1 : 0;
+            n += ei;
+            nx += ei * dx;
+            nxx += ei * dx * dx;
+        }
+        const T fy = (T)dy, fz = (T)dz;
+        acc.m[0] += s0;
+        acc.m[1] += s1;
+        acc.m[2] += fy * s0;
+        acc.m[3] += fz * s0;
+        acc.m[4] += s2;
+        acc.m[5] += fy * s1;
+        acc.m[6] += fz * s1;
+        acc.m[7] += (fy * fy) * s0;
+        acc.m[8] += (fy * fz) * s0;
+        acc.m[9] += (fz * fz) * s0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc.r[c] += t0[c];
+            acc.r[3 + c] += t1[c];
+            acc.r[6 + c] += fy * t0[c];
+            acc.r[9 + c] += fz * t0[c];
+        }
+        acc.g[0] += n + (nxx << 16);
+        acc.g[1] += nx + ((dy * nx) << 16);
+        acc.g[2] += dy * n + ((dz * nx) << 16);
+        acc.g[3] += dz * n + ((dy * dy * n) << 16);
+        acc.g[4] += dy * dz * n + ((dz * dz * n) << 16);
     }
 }
 
 template <typename T>
 __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
                                              unsigned long long* st, int l, int bx, int by,
-                                             int bz, unsigned char* lds, int* s_wave) {
+                                             int bz, unsigned char* lds, int* s_wave,
+                                             const double* s_rlen) {
     double* sx = reinterpret_cast<double*>(lds);
     int8_t* sl = reinterpret_cast<int8_t*>(lds + kBrickCells * 24);
     uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * 25);
@@ -342,23 +476,38 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
     const int8_t* __restrict__ labels = d->labels;
     const int ox = kBrick * bx - kBrickHalo, oy = kBrick * by - kBrickHalo,
               oz = kBrick * bz - kBrickHalo;
-    // Stage xi and labels of the 12^3 cells (outside the box: label -1).
+    // Stage the labels of the 12^3 cells (outside the box: -1), then xi of the cells that
+    // can carry data for layer l (0 <= label < l); the others are staged as 0 and never
+    // enter a sum (their weight is selected to 0).
+    constexpr int kH = (kBrickCells + 255) / 256;
+    int32_t cc[kH];
+    int lb[kH];
 #pragma unroll
-    for (int h = 0; h < (kBrickCells + 255) / 256; ++h) {
+    for (int h = 0; h < kH; ++h) {
         const int q = tid + 256 * h;
+        const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
+                  z = q / (kBrickSpan * kBrickSpan);
+        const int gx = ox + x, gy = oy + y, gz = oz + z;
+        const bool in = q < kBrickCells && (unsigned)gx < (unsigned)n0 &&
+                        (unsigned)gy < (unsigned)n1 && (unsigned)gz < (unsigned)n2;
+        cc[h] = in ? (gz * n1 + gy) * n0 + gx : -1;
+        lb[h] = in ? (int)labels[cc[h]] : -1;
+        if (q < kBrickCells) sl[q] = (int8_t)lb[h];
+    }
+#pragma unroll
+    for (int h = 0; h < kH; ++h) {
+        const int q = tid + 256 * h;
+        const bool use = lb[h] >= 0 && lb[h] < l;   // only cells inside the box: cc >= 0
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        if (use) {
+            v0 = xi[cc[h]];
+            v1 = xi[nc + cc[h]];
+            v2 = xi[2 * nc + cc[h]];
+        }
         if (q < kBrickCells) {
-            const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
-                      z = q / (kBrickSpan * kBrickSpan);
-            const int gx = ox + x, gy = oy + y, gz = oz + z;
-            const bool in = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
-                            (unsigned)gz < (unsigned)n2;
-            const int32_t c = in ? (gz * n1 + gy) * n0 + gx : 0;
-            const int lab = labels[c];
-            const double v0 = xi[c], v1 = xi[nc + c], v2 = xi[2 * nc + c];
-            sl[q] = in ? (int8_t)lab : (int8_t)-1;
-            sx[q] = in ? v0 : 0.0;
-            sx[kBrickCells + q] = in ? v1 : 0.0;
-            sx[2 * kBrickCells + q] = in ? v2 : 0.0;
+            sx[q] = v0;
+            sx[kBrickCells + q] = v1;
+            sx[2 * kBrickCells + q] = v2;
         }
     }
     __syncthreads();
@@ -397,6 +546,13 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
         cx.xi = xi;
         cx.labels = labels;
         const int32_t cell = (cx.k * n1 + cx.j) * n0 + cx.i;
+        const bool nrm = l <= b.normal_layers;
+        double gn0 = 0.0, gn1 = 0.0, gn2 = 0.0;
+        if (nrm) {   // issued first: the only global loads of the cell
+            gn0 = d->normals[cell];
+            gn1 = d->normals[nc + cell];
+            gn2 = d->normals[2 * nc + cell];
+        }
         // Anchor (centring datum): the first face neighbour in a lower layer in the order
         // -x, +x, -y, +y, -z, +z.  One exists: the neighbour the cell was labelled from.
         const int nb[6] = {idx - 1, idx + 1, idx - kBrickSpan, idx + kBrickSpan,
@@ -416,16 +572,13 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
         cx.a0 = sx[aidx];
         cx.a1 = sx[kBrickCells + aidx];
         cx.a2 = sx[2 * kBrickCells + aidx];
-        bool has_normal = false;
-        cx.g0 = cx.g1 = cx.g2 = cx.rgn = 0.0;
-        if (l <= b.normal_layers) {
-            cx.g0 = d->normals[cell];
-            cx.g1 = d->normals[nc + cell];
-            cx.g2 = d->normals[2 * nc + cell];
-            has_normal = cx.g0 != 0.0 || cx.g1 != 0.0 || cx.g2 != 0.0;
-            if (has_normal) cx.rgn = 1.0 / norm3(cx.g0, cx.g1, cx.g2);
-        }
-        const bool no_normal = (l <= b.normal_layers) && !has_normal;
+        cx.g0 = gn0;
+        cx.g1 = gn1;
+        cx.g2 = gn2;
+        cx.rgn = 0.0;
+        const bool has_normal = nrm && (gn0 != 0.0 || gn1 != 0.0 || gn2 != 0.0);
+        if (has_normal) cx.rgn = 1.0 / norm3(gn0, gn1, gn2);
+        const bool no_normal = nrm && !has_normal;
 
         // Passes: radii r_s..r_max with eq. (weight), then F1 (normal factor dropped) at
         // r_max, then F2 (kernel-weighted mean) at r_max.
@@ -440,8 +593,8 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
             Moments<T> acc;
             zero(acc);
             if (r == kBrickHalo)
-                gather_lds<T>(sx, sl, idx, l, un, cx.g0, cx.g1, cx.g2, cx.rgn, cx.a0, cx.a1,
-                              cx.a2, lq, acc);
+                gather_lds<T>(sx, sl, s_rlen, idx, l, un, cx.g0, cx.g1, cx.g2, cx.rgn, cx.a0,
+                              cx.a1, cx.a2, lq, acc);
             else
                 gather_any<T>(cx, r, un, lq, acc);
             reduce_lanes(acc);
@@ -478,8 +631,9 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
 }
 
 // ------------------------------------------------------------------------------------
-// Brick lists: the bucket counts of layers l0..l0+nl-1 are turned into one prefix in LDS
-// (s_pref[0..nl*kBuckets]); entry e of the concatenation is then found by bisection.
+// Brick lists: the bucket counts of layers l0..l0+nl-1 form one prefix in LDS
+// (s_pref[0..nl*kBuckets]); entry e of the concatenation is found by bisection.  Blocks
+// stride over the entries.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int list_prefix(const Batch& b, int l0, int nl, int* s_pref,
                                            int* s_wave) {
@@ -488,13 +642,13 @@ __device__ __forceinline__ int list_prefix(const Batch& b, int l0, int nl, int* 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = threadIdx.x * 4 + q;
-        v[q] = i < n ? b.bcount[(l0 - 1) * kBuckets + i] : 0;
-        // entries past a bucket's capacity were never written (the overflow is reported)
+        v[q] = 0;
         if (i < n) {
             const int bk = i % kBuckets;
             const int64_t cap = bucket_base(bk + 1, b.n_tiles, b.tile_w) -
                                 bucket_base(bk, b.n_tiles, b.tile_w);
-            v[q] = (int)min((int64_t)v[q], cap);
+            // entries past a bucket's capacity were never written (reported as overflow)
+            v[q] = (int)min((int64_t)b.bcount[(l0 - 1) * kBuckets + i], cap);
         }
         sum += v[q];
     }
@@ -511,7 +665,7 @@ __device__ __forceinline__ int list_prefix(const Batch& b, int l0, int nl, int* 
     return total;
 }
 
-// Entry e of the listed bricks: which layer (l0 + ...) and where in the list it sits.
+// Entry e of the concatenated lists: its layer and list entry.
 __device__ __forceinline__ unsigned long long list_entry(const Batch& b, int l0, int nl,
                                                          const int* s_pref, int e, int* layer) {
     int lo = 0, hi = nl * kBuckets - 1;   // last i with s_pref[i] <= e
@@ -519,9 +673,9 @@ __device__ __forceinline__ unsigned long long list_entry(const Batch& b, int l0,
         const int mid = (lo + hi + 1) >> 1;
         if (s_pref[mid] <= e) lo = mid; else hi = mid - 1;
     }
-    const int l = l0 + lo / kBuckets, bk = lo % kBuckets;
-    *layer = l;
-    return b.blist[(int64_t)(l - 1) * b.blist_cap + bucket_base(bk, b.n_tiles, b.tile_w) +
+    const int li = lo / kBuckets, bk = lo % kBuckets;
+    *layer = l0 + li;
+    return b.blist[(int64_t)(l0 - 1 + li) * b.blist_cap + bucket_base(bk, b.n_tiles, b.tile_w) +
                    (e - s_pref[lo])];
 }
 
@@ -678,6 +832,8 @@ __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
     unsigned char* lds = reinterpret_cast<unsigned char*>(lds_d);
     __shared__ int s_wave[4];
     __shared__ int s_pref[kBuckets + 1];
+    __shared__ double s_rlen[13];   // 1/|d| for |d|^2 = 0..12 (radius 2)
+    if (threadIdx.x < 13) s_rlen[threadIdx.x] = c_rlen[threadIdx.x];
     const int count = list_prefix(b, l, 1, s_pref, s_wave);
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
         int ll = 0;
@@ -688,7 +844,7 @@ __global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
         const int bz = uniform_int((int)((pk >> 20) & 1023ull));
         unsigned long long* st = b.stats + (int64_t)s * kStatWords;
         if (st[ST_FLAGS] & FLAG_TRUNCATED) continue;   // uniform: whole block skips
-        extrap_brick<T>(b, b.solids + s, st, l, bx, by, bz, lds, s_wave);
+        extrap_brick<T>(b, b.solids + s, st, l, bx, by, bz, lds, s_wave, s_rlen);
     }
 }
 

@@ -162,8 +162,9 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     // A tile lists at most 32 bricks per 64-cell word and layer (2 x 2 x 8).
     p->blist_cap = (int64_t)tiles * 32 * tw;
     p->normal_layers = std::min(opt->normal_layers, p->Lmax);
+    // Blocks striding over the brick lists.
     const int eb = tune.extrap_blocks > 0 ? tune.extrap_blocks : 3 * std::max(cu, 1);
-    p->extrap_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(eb, p->blist_cap));
+    p->extrap_blocks = std::max(eb, 1);
 
     // Workspace layout.
     size_t off = 0;

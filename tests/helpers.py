@@ -64,3 +64,33 @@ def exact_field(w, s, fn):
     x, y, z = synth.cell_centres(s.lo, s.ext, w.h, w.origin)
     X = np.broadcast_arrays(x, y, z)
     return fn(*X)
+
+
+def edge_workloads(seed=11, n=16, n_layers=3):
+    """Classification edge cases: a sphere and a rotated ellipsoid on an n^3 grid with
+    xi = x, plus cells exactly on |xi - c|^2 = R^2 or on an axis, and NaN / +-inf in single
+    components (some deep inside the solid)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    x, y, z = synth.cell_centres((0, 0, 0), (n, n, n), h, (0.0, 0.0, 0.0))
+    out = []
+    for kind in (synth.SPHERE, synth.ELLIPSOID):
+        c = np.array([0.5, 0.5, 0.5])
+        if kind == synth.SPHERE:
+            shape = synth.sphere_shape(c, 0.25)
+        else:
+            shape = synth.ellipsoid_shape(c, [0.3, 0.2, 0.25], synth.random_rotation(rng))
+        xi = np.empty((3, n, n, n))
+        xi[0], xi[1], xi[2] = np.broadcast_arrays(x, y, z)
+        m = n // 2
+        xi[:, m, m, 2] = [c[0] + 0.25, c[1], c[2]]
+        xi[:, m, 2, m] = [c[0], c[1] - 0.25, c[2]]
+        xi[:, 2, m, m] = [c[0], c[1], c[2] + 0.25]
+        for _ in range(60):
+            k, j, i = rng.integers(0, n, size=3)
+            a = int(rng.integers(0, 3))
+            xi[a, k, j, i] = [np.nan, np.inf, -np.inf][int(rng.integers(0, 3))]
+        w = synth.Workload("edge", (n, n, n), h, (0.0, 0.0, 0.0))
+        w.solids.append(synth.Solid((0, 0, 0), (n, n, n), shape, n_layers, xi))
+        out.append(w)
+    return out

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
-from tests.helpers import rel_err, run_oracle
+from tests.helpers import edge_workloads, rel_err, run_oracle
 
 emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
@@ -90,3 +90,11 @@ def test_emulated_statuses(built, tmp_path):
         assert st == -7
         _check(w, outs, 0)
 
+
+
+def test_emulated_nonfinite_and_boundary(built, tmp_path):
+    """Classification edge cases against the oracle: NaN and infinite components, cells
+    exactly on |xi - c|^2 = R^2 or on an axis; a sphere and a rotated ellipsoid."""
+    for w in edge_workloads():
+        st, outs = emu.run(w, str(tmp_path))
+        _check(w, outs, 0)

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2104_00095_amd import synth
-from tests.helpers import oracle_problem, rel_err, run_oracle
+from tests.helpers import edge_workloads, oracle_problem, rel_err, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -240,6 +240,15 @@ def test_batch_equals_alone_and_per_solid(ctx, precision):
         assert np.array_equal(batched[i][0].view(np.uint64), per[i][0].view(np.uint64))
         assert np.array_equal(batched[i][1], alone[0][1])
         assert np.array_equal(batched[i][2], per[i][2])
+
+
+@pytest.mark.parametrize("mode", MODE_PARAMS)
+def test_nonfinite_and_boundary(ctx, mode):
+    """Classification edge cases (NaN / inf components, cells exactly on the sphere or on
+    an axis) for a sphere and a rotated ellipsoid."""
+    for w in edge_workloads():
+        st, gpu = run_gpu(ctx, w, 0, flags=MODES[mode])
+        compare(w, gpu, 0, tag="edge")
 
 
 def test_persistent_launch_refused(ctx):
