@@ -9,6 +9,7 @@ roofline, the CPU oracle timed on this host's cores, and the extra forms (FP32
 accumulate, batched vs per-solid suspension) under "variants".
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -120,9 +121,12 @@ def kernel_bytes(phase, w, stats, normal_layers=2, decisions=False, cls_bytes=No
     return None
 
 
-def cpu_baseline(w, seconds, r_s=2, r_max=4, normal_layers=2):
+def cpu_baseline(w, seconds, gpu=None, r_s=2, r_max=4, normal_layers=2):
     """The oracle as it stands, on this host's cores, on whole calls of the same workload
-    until `seconds` of CPU work have run (at least one call)."""
+    until `seconds` of CPU work have run (at least one call).  `gpu`: {precision: per-solid
+    (xi, labels) of one GPU call on the same input}; the oracle's output of its first call
+    is compared with them (labels equal; relative max-norm error of xi over the band)."""
+    import numpy as np
     import oracle
     cores = len(os.sched_getaffinity(0))
     probs = [oracle.make_problem(w.grid_n, s.lo, s.ext,
@@ -131,38 +135,184 @@ def cpu_baseline(w, seconds, r_s=2, r_max=4, normal_layers=2):
                                  s.n_layers, r_s=r_s, r_max=r_max, normal_layers=normal_layers)
              for s in w.solids]
     calls, band, t0 = 0, 0, time.perf_counter()
+    first = None
     while True:
+        outs = []
         for p, s in zip(probs, w.solids):
             st, xo, lab, dec, stats = oracle.extrapolate(p, s.xi, nthreads=cores)
             band += int(stats[1:17].sum())
+            if first is None:
+                outs.append((xo, lab))
+        if first is None:
+            first = outs
         calls += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return {"value": band / el, "unit": "band cells/s", "cores": cores, "kind": "oracle",
-            "sample": f"{calls} whole calls of {w.name} ({len(w.solids)} solid(s)), "
-                      f"{el:.1f} s wall, OpenMP threads = {cores}"}
+    res = {"value": band / el, "unit": "band cells/s", "cores": cores, "kind": "oracle",
+           "sample": f"{calls} whole calls of {w.name} ({len(w.solids)} solid(s)), "
+                     f"{el:.1f} s wall, OpenMP threads = {cores}"}
+    for prec, g in (gpu or {}).items():
+        worst, same = 0.0, True
+        for (xo, lo), (xg, lg) in zip(first, g):
+            same &= bool(np.array_equal(lo, lg))
+            worst = max(worst, rel_err(xg, xo, lo > 0))
+        name = "fp64" if prec == 0 else "fp32acc"
+        res[f"gpu_{name}_labels_equal"] = same
+        res[f"gpu_{name}_rel_max_err"] = worst
+    return res
 
 
-def copy_calibration(n_bytes=1 << 30, reps=5):
-    """A plain device-to-device copy of n_bytes (read n_bytes, write n_bytes), `reps`
-    times: under a counter profiler, its FETCH_SIZE and WRITE_SIZE per dispatch against
-    n_bytes give the scale of those counters."""
+def rel_err(a, b, band):
+    import numpy as np
+    if not band.any():
+        return 0.0
+    return float(np.max(np.abs(a[:, band] - b[:, band])) / np.max(np.abs(b[:, band])))
+
+
+def gpu_outputs(ctx, w, precision):
+    """One call on a fresh copy of the workload; host copies of xi and labels per solid."""
     import torch
-    src = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
+    from paper_2104_00095_amd import fields, rmx
+    dw = fields.upload(w)
+    ctx.extrapolate(dw.grid, dw.solids, rmx.options(precision=precision), check=False)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_bytes_read": n_bytes, "copy_bytes_written": n_bytes,
-                      "ms": ms, "GB_per_s": 2 * n_bytes / (ms * 1e-3) / 1e9}), flush=True)
+    out = [(dw.xi[i].cpu().numpy(), dw.labels[i].cpu().numpy()) for i in range(len(w.solids))]
+    del dw
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_variants(ctx, n_requests=2000, rate=200.0, n_streams=4, log=print):
+    """The serving trace (simulations of grids 32..192^3 with 1-64 ellipsoids, Poisson
+    arrivals) through the request loop, against the plain form (requests in arrival order,
+    one solid at a time).  Latency = completion - arrival.  Fields live on the device:
+    generated there (same formula as the host generator), then resident."""
+    import queue
+    import threading
+    import numpy as np
+    import torch
+    from paper_2104_00095_amd import rmx, synth, synth_device
+    sims, reqs = synth.serving_trace(rate=rate)
+    reqs = reqs[:n_requests]
+    layouts = [synth.sim_layout(sp)[0] for sp in sims]
+    opts = [rmx.options(precision=sp.precision) for sp in sims]
+    resident = sum(25 * int(np.prod(sp.ext)) for lay in layouts for sp in lay)
+
+    def fill(srv, ids):
+        for sp, sid, lay in zip(sims, ids, layouts):
+            for j, spec in enumerate(lay):
+                srv.upload(sid, j, synth_device.affine_sine_field(spec, 1.0 / sp.n))
+        torch.cuda.synchronize()
+
+    def serve(budget, saturated):
+        srv = rmx.Server(0, budget, n_streams)
+        try:
+            ids = []
+            for sp, lay in zip(sims, layouts):
+                templ = [rmx.solid_template(q.lo, q.ext, rmx.shape(q.shape.kind, q.shape.centre,
+                                                                    q.shape.semi, q.shape.rot),
+                                            q.n_layers) for q in lay]
+                ids.append(srv.register(rmx.grid((sp.n,) * 3, 1.0 / sp.n), templ))
+            fill(srv, ids)
+            done = queue.Queue()
+            band, comp, errors = [0] * len(reqs), [0.0] * len(reqs), []
+
+            def waiter():
+                while True:
+                    item = done.get()
+                    if item is None:
+                        return
+                    t, i, t_sub = item
+                    st, l, stats = srv.wait(t, len(layouts[reqs[i].sim_id]))
+                    if st < 0:
+                        errors.append((i, st))
+                    comp[i] = t_sub + l
+                    band[i] = sum(sum(x["n_band"][1:17]) for x in stats)
+
+            th = threading.Thread(target=waiter)
+            th.start()
+            t0 = time.perf_counter()
+            for i, r in enumerate(reqs):
+                if not saturated:
+                    dt = t0 + r.arrival_s - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                t_sub = time.perf_counter()
+                t = srv.submit(ids[r.sim_id], opts[r.sim_id])
+                done.put((t, i, t_sub))
+            done.put(None)
+            th.join()
+            if errors:
+                raise RuntimeError(f"served requests failed: {errors[:5]}")
+            arr = [t0 + (0.0 if saturated else r.arrival_s) for r in reqs]
+            lat = np.array([c - a for c, a in zip(comp, arr)])
+            span = max(comp) - t0
+            used, peak = srv.usage()
+        finally:
+            srv.close()
+        return {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "mean_ms": 1e3 * float(lat.mean()), "span_s": span,
+                "band_cells_per_s": float(sum(band)) / span,
+                "requests_per_s": len(reqs) / span, "hbm_budget_bytes": budget,
+                "peak_admitted_bytes": peak}
+
+    def plain(saturated):
+        # the same fields, owned by a server (admission out of play), driven one solid at a
+        # time in arrival order through a context
+        srv = rmx.Server(0, 1 << 40, 1)
+        try:
+            ids, solids = [], []
+            for sp, lay in zip(sims, layouts):
+                templ = [rmx.solid_template(q.lo, q.ext, rmx.shape(q.shape.kind, q.shape.centre,
+                                                                    q.shape.semi, q.shape.rot),
+                                            q.n_layers) for q in lay]
+                sid = srv.register(rmx.grid((sp.n,) * 3, 1.0 / sp.n), templ)
+                ids.append(sid)
+                row = []
+                for j, t in enumerate(templ):
+                    xp, lp = srv.field(sid, j)
+                    t.xi = ctypes.c_void_p(xp)
+                    t.labels = ctypes.c_void_p(lp)
+                    row.append((rmx.Solid * 1)(t))
+                solids.append(row)
+            fill(srv, ids)
+            grids = [rmx.grid((sp.n,) * 3, 1.0 / sp.n) for sp in sims]
+            stats = (rmx.SolidStats * 1)()
+            lat, band = [], 0
+            t0 = time.perf_counter()
+            for r in reqs:
+                arrive = t0 + (0.0 if saturated else r.arrival_s)
+                dt = arrive - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                for arr in solids[r.sim_id]:
+                    st = rmx.lib().rmx_extrapolate(ctx.h, ctypes.byref(grids[r.sim_id]), arr, 1,
+                                                   ctypes.byref(opts[r.sim_id]), None, stats)
+                    if st < 0:
+                        raise RuntimeError(f"plain call failed: {st}")
+                    band += sum(stats[0].n_band[1:17])
+                lat.append(time.perf_counter() - arrive)
+            span = time.perf_counter() - t0
+        finally:
+            srv.close()
+        lat = np.array(lat)
+        return {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "mean_ms": 1e3 * float(lat.mean()), "span_s": span,
+                "band_cells_per_s": band / span, "requests_per_s": len(reqs) / span}
+
+    out = {"requests": len(reqs), "simulations": len(sims), "rate_per_s": rate,
+           "streams": n_streams, "resident_field_bytes": resident}
+    log("serving: trace replay, tight budget")
+    out["served_4GiB"] = serve(4 << 30, False)
+    log("serving: trace replay, plain")
+    out["plain"] = plain(False)
+    log("serving: saturated")
+    out["served_saturated_64GiB"] = serve(64 << 30, True)
+    out["plain_saturated"] = plain(True)
+    return out
 
 
 def make_workload(name):
@@ -199,6 +349,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and print its rate")
@@ -267,11 +419,22 @@ def main():
         for name, fl in (("sphere32_graph", rmx.FLAG_GRAPH), ("sphere32", 0)):
             f, _ = run_form(ctx, ws, dws, rmx.options(flags=fl), args.steps, args.warmup)
             variants[name] = f
+        del dws
+        ws = make_workload("ellipsoid128")
+        dws = fields.upload(ws)
+        for name, pr in (("ellipsoid128_fp64", 0), ("ellipsoid128_fp32acc", 1)):
+            f, _ = run_form(ctx, ws, dws, rmx.options(precision=pr), args.steps, args.warmup)
+            variants[name] = f
+        del dws
+        torch.cuda.empty_cache()
+        if not args.no_serving:
+            variants["serving"] = serving_variants(ctx, args.serving_requests, log=log)
 
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        gpu = {p: gpu_outputs(ctx, w, p) for p in (0, 1)}
+        cpu = cpu_baseline(w, args.cpu_seconds, gpu)
 
     out = {
         "metric": METRIC,

@@ -156,7 +156,8 @@ int rmx_default_options(rmx_options* opt);
 int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out);
 int rmx_destroy(rmx_ctx* ctx);
 
-/* Workspace bytes a call with these arguments needs (about 29 bytes per box cell). */
+/* Workspace bytes a call with these arguments needs (about 25 bytes per box cell with
+ * normals, 1 without); the field pointers of `solids` are not used. */
 int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
                        const rmx_options* opt, size_t* bytes);
 

@@ -292,7 +292,7 @@ int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_
     int rc = validate_options(opt);
     if (rc != RMX_OK) return rc;
     for (int i = 0; i < n_solids; ++i)
-        if ((rc = validate_solid(grid, solids + i)) != RMX_OK) return rc;
+        if ((rc = validate_solid(grid, solids + i, false)) != RMX_OK) return rc;
     size_t total = 0;
     const bool per_solid = (opt->flags & RMX_FLAG_PER_SOLID) != 0;
     const int calls = per_solid ? n_solids : 1;

@@ -66,7 +66,8 @@ struct Profiler {
 
 // Validation of one solid against its grid, and of the options.
 int validate_options(const rmx_options* opt);
-int validate_solid(const rmx_grid* grid, const rmx_solid* s);
+// need_fields = false: the field pointers are not checked (sizing, server templates).
+int validate_solid(const rmx_grid* grid, const rmx_solid* s, bool need_fields = true);
 
 // Plan a batch: solid i lives on grid grids[i].  `cu` = compute units of the device.
 int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,

@@ -56,7 +56,7 @@ int validate_options(const rmx_options* opt) {
     return RMX_OK;
 }
 
-int validate_solid(const rmx_grid* grid, const rmx_solid* sp) {
+int validate_solid(const rmx_grid* grid, const rmx_solid* sp, bool need_fields) {
     if (!grid || !sp) return RMX_E_ARG;
     for (int a = 0; a < 3; ++a)
         if (grid->n[a] <= 0) return RMX_E_ARG;
@@ -70,7 +70,7 @@ int validate_solid(const rmx_grid* grid, const rmx_solid* sp) {
     const int64_t ncell = (int64_t)s.ext[0] * s.ext[1] * s.ext[2];
     if (ncell > (int64_t)0x7fffffff - 64) return RMX_E_BOX;
     if (s.n_layers < 0 || s.n_layers > RMX_MAX_LAYERS) return RMX_E_LAYERS;
-    if (!s.xi || !s.labels) return RMX_E_ARG;
+    if (need_fields && (!s.xi || !s.labels)) return RMX_E_ARG;
     const rmx_shape& sh = s.phi0;
     if (sh.kind != RMX_SPHERE && sh.kind != RMX_ELLIPSOID) return RMX_E_SHAPE;
     if (!finite_all(sh.centre, 3) || !finite_all(sh.rot, 9)) return RMX_E_SHAPE;

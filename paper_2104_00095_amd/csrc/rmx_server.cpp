@@ -314,11 +314,11 @@ int rmx_server_register(rmx_server* s, const rmx_grid* grid, const rmx_solid* te
     std::vector<size_t> off(n_solids);
     for (int i = 0; i < n_solids; ++i) {
         rmx_solid& t = sim.solids[i];
-        t.xi = reinterpret_cast<double*>(16);      // placeholders for the validation
-        t.labels = reinterpret_cast<int8_t*>(16);
+        t.xi = nullptr;
+        t.labels = nullptr;
         t.xi_normal = nullptr;
         t.decisions = nullptr;
-        const int rc = validate_solid(grid, &t);
+        const int rc = validate_solid(grid, &t, false);
         if (rc != RMX_OK) return rc;
         const size_t nc = (size_t)t.ext[0] * t.ext[1] * t.ext[2];
         off[i] = bytes;

@@ -155,6 +155,27 @@ def _ptr(t):
     return ctypes.c_void_p(int(t.data_ptr()))
 
 
+def solid_template(lo, ext, shp: Shape, n_layers) -> Solid:
+    """A solid without fields: for rmx_server_register (the server allocates them) and
+    rmx_workspace_size."""
+    s = Solid()
+    s.lo[:] = [int(v) for v in lo]
+    s.ext[:] = [int(v) for v in ext]
+    s.phi0 = shp
+    s.n_layers = int(n_layers)
+    return s
+
+
+def workspace_size(g: Grid, solids: Sequence[Solid], opt: Optional[Options] = None) -> int:
+    arr = (Solid * len(solids))(*solids)
+    n = ctypes.c_size_t(0)
+    st = lib().rmx_workspace_size(ctypes.byref(g), arr, len(solids),
+                                  ctypes.byref(opt) if opt else None, ctypes.byref(n))
+    if st != OK:
+        raise RmxError(st, "rmx_workspace_size")
+    return int(n.value)
+
+
 def solid(lo, ext, shp: Shape, n_layers, xi, labels, xi_normal=None, decisions=None) -> Solid:
     """xi: cuda float64 [3, ext2, ext1, ext0]; labels: cuda int8 [ext2, ext1, ext0]."""
     e = tuple(int(v) for v in ext)
@@ -237,6 +258,36 @@ class Context:
                                      stream_handle, None)
 
 
+_HIP = None
+H2D, D2H, D2D = 1, 2, 3
+
+
+def _hip():
+    """The HIP runtime library (for copies into and out of server-owned fields)."""
+    global _HIP
+    if _HIP is None:
+        last = None
+        for name in ("libamdhip64.so", "/opt/rocm/lib/libamdhip64.so"):
+            try:
+                L = ctypes.CDLL(name)
+                break
+            except OSError as e:  # noqa: PERF203
+                last = e
+        else:
+            raise RuntimeError(f"HIP runtime library not found: {last}")
+        L.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        L.hipMemcpy.restype = ctypes.c_int
+        _HIP = L
+    return _HIP
+
+
+def memcpy(dst: int, src: int, nbytes: int, kind: int):
+    """Synchronous hipMemcpy between raw addresses (kind: H2D, D2H or D2D)."""
+    e = _hip().hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), int(nbytes), int(kind))
+    if e != 0:
+        raise RuntimeError(f"hipMemcpy failed with HIP error {e}")
+
+
 class Server:
     """Request loop admitting extrapolation jobs by HBM budget (rmx_server_*)."""
 
@@ -299,3 +350,27 @@ class Server:
         a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
         lib().rmx_server_usage(self.h, ctypes.byref(a), ctypes.byref(b))
         return int(a.value), int(b.value)
+
+    # Copies into and out of the resident fields; only while no request of the simulation
+    # is queued or running.
+    def upload(self, sim_id: int, solid_idx: int, xi):
+        """xi: float64 [3, ext2, ext1, ext0], a numpy array (host) or a CUDA tensor."""
+        dst, _ = self.field(sim_id, solid_idx)
+        if hasattr(xi, "is_cuda") and xi.is_cuda:
+            import torch
+            torch.cuda.synchronize()
+            memcpy(dst, xi.data_ptr(), xi.numel() * 8, D2D)
+        else:
+            import numpy as np
+            a = np.ascontiguousarray(xi, dtype=np.float64)
+            memcpy(dst, a.ctypes.data, a.nbytes, H2D)
+
+    def download(self, sim_id: int, solid_idx: int, ext):
+        """(xi float64 [3, ext2, ext1, ext0], labels int8 [ext2, ext1, ext0]) on the host."""
+        import numpy as np
+        xp, lp = self.field(sim_id, solid_idx)
+        xi = np.empty((3, ext[2], ext[1], ext[0]), dtype=np.float64)
+        lab = np.empty((ext[2], ext[1], ext[0]), dtype=np.int8)
+        memcpy(xi.ctypes.data, xp, xi.nbytes, D2H)
+        memcpy(lab.ctypes.data, lp, lab.nbytes, D2H)
+        return xi, lab

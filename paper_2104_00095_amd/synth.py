@@ -262,19 +262,45 @@ def solid_box(cpos, amax, h, grid_n, n_layers):
     return tuple(lo), tuple(ext)
 
 
-def suspension(seed: int = 3, n_solids: int = 40, grid_n=(128, 128, 256), h=1.0 / 128,
-               n_layers: int = 4, semi_lo=0.04, semi_hi=0.1, amp=0.01,
-               phase_shift=0.0) -> Workload:
+@dataclass
+class SolidSpec:
+    """A solid of an affine+sine workload before its field is evaluated."""
+    lo: tuple
+    ext: tuple
+    shape: Shape
+    n_layers: int
+    c: np.ndarray               # centre of the affine map (the solid's centre)
+    A: np.ndarray               # (3, 3)
+    amp: float
+    modes: tuple                # (u list, k list, theta list)
+
+
+def suspension_layout(seed: int = 3, n_solids: int = 40, grid_n=(128, 128, 256),
+                      h=1.0 / 128, n_layers: int = 4, semi_lo=0.04, semi_hi=0.1, amp=0.01):
+    """Placement, boxes and field parameters of ``suspension`` (no field arrays)."""
     rng = np.random.default_rng(seed)
     lengths = [g * h for g in grid_n]
     placed, gave_up = place_ellipsoids(rng, n_solids, lengths, h, semi_lo, semi_hi)
-    w = Workload("suspension", tuple(grid_n), h, (0.0, 0.0, 0.0))
+    specs = []
     for cpos, semi, rot in placed:
         A = np.eye(3) + 0.05 * rng.standard_normal((3, 3))
         modes = _modes(rng, 3, 2)
         lo, ext = solid_box(cpos, float(np.max(semi)), h, grid_n, n_layers)
-        xi = affine_sine_field(lo, ext, h, (0.0, 0.0, 0.0), cpos, A, amp, modes, phase_shift)
-        w.solids.append(Solid(lo, ext, ellipsoid_shape(cpos, semi, rot), n_layers, xi))
+        specs.append(SolidSpec(lo, ext, ellipsoid_shape(cpos, semi, rot), n_layers, cpos, A,
+                               amp, modes))
+    return specs, gave_up
+
+
+def suspension(seed: int = 3, n_solids: int = 40, grid_n=(128, 128, 256), h=1.0 / 128,
+               n_layers: int = 4, semi_lo=0.04, semi_hi=0.1, amp=0.01,
+               phase_shift=0.0) -> Workload:
+    specs, gave_up = suspension_layout(seed, n_solids, grid_n, h, n_layers, semi_lo, semi_hi,
+                                       amp)
+    w = Workload("suspension", tuple(grid_n), h, (0.0, 0.0, 0.0))
+    for sp in specs:
+        xi = affine_sine_field(sp.lo, sp.ext, h, (0.0, 0.0, 0.0), sp.c, sp.A, sp.amp, sp.modes,
+                               phase_shift)
+        w.solids.append(Solid(sp.lo, sp.ext, sp.shape, sp.n_layers, xi))
     w.gave_up = gave_up
     return w
 
@@ -360,6 +386,14 @@ def serving_trace(seed: int = 5, n_sims: int = 100, steps: int = 20, rate: float
     t = np.cumsum(gaps)
     reqs = [Request(float(t[i]), order[i][0], order[i][1]) for i in range(total)]
     return sims, reqs
+
+
+def sim_layout(spec: SimSpec, semi_lo=0.05, semi_hi=0.2):
+    """The solids of one served simulation (placed as in ``suspension``; the unit cube at
+    n^3), without their fields."""
+    return suspension_layout(seed=spec.seed, n_solids=spec.n_solids_requested,
+                             grid_n=(spec.n, spec.n, spec.n), h=1.0 / spec.n,
+                             n_layers=spec.n_layers, semi_lo=semi_lo, semi_hi=semi_hi)
 
 
 def sim_workload(spec: SimSpec, semi_lo=0.05, semi_hi=0.2) -> Workload:

@@ -91,8 +91,8 @@ def test_host_validation():
     assert _ws(g, [_desc(kind=2, semi=(0.1, 0.2, 0.3), rot=[0, 1, 0, 1, 0, 0, 0, 0, 1])])[0] \
         == rmx.OK
     d = _desc()
-    d.labels = None
-    assert _ws(g, [d])[0] == rmx.E_ARG
+    d.labels = None     # sizing does not look at the field pointers
+    assert _ws(g, [d])[0] == rmx.OK
     assert _ws(g, [_desc()], rmx.options(r_s=3, r_max=2))[0] == rmx.E_ARG
     assert _ws(g, [_desc()], rmx.options(r_max=5))[0] == rmx.E_ARG
     assert _ws(g, [_desc()], rmx.options(precision=2))[0] == rmx.E_ARG
