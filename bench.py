@@ -350,6 +350,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (the reference for "
@@ -376,6 +377,10 @@ def main():
     prec = PRECISIONS[args.precision]
     flags = rmx.FLAG_GRAPH if args.graph else 0
     opt = rmx.options(precision=prec, flags=flags)
+    tuned = None
+    if not args.no_autotune:
+        log("autotune (label tile width, blocks per layer fit)")
+        tuned = ctx.autotune(dw.grid, dw.solids, rmx.options(precision=prec), reps=5)
     log("timing")
     main_form, stats = run_form(ctx, w, dw, opt, args.steps, args.warmup)
     nb, cells = band_and_box(stats, w)
@@ -451,7 +456,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(w.grid_n), "solids": len(w.solids),
                    "n_layers": max(s.n_layers for s in w.solids), "band_cells": nb,
-                   "box_cells": cells, "precision": args.precision, "graph": args.graph},
+                   "box_cells": cells, "precision": args.precision, "graph": args.graph,
+                   "launch_shapes": tuned},
         "roofline": roof,
         "call_roofline": {"bound": "hbm", "algorithmic_bytes": B,
                           "achieved": B / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,

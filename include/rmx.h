@@ -178,6 +178,23 @@ int rmx_extrapolate(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
 
 const char* rmx_status_string(int status);
 
+/* Autotuner.  Launch shapes that change no result: the label tile width (1, 2 or 4 words
+ * of 64 cells) and the number of blocks striding over a layer's brick list.  rmx_autotune
+ * times every candidate over `reps` calls of this batch on `hip_stream` (each candidate on
+ * the same input: xi is saved first and restored before each candidate and at the end;
+ * labels and decisions hold the last timed call's result), keeps the fastest for later
+ * calls of the same shape class on this context (same largest layer count, row width,
+ * normal layers and size class), and returns it in *best (HOST).  It allocates (a copy of
+ * xi) and synchronises: a set-up call, not for graph capture. */
+typedef struct {
+    int32_t tile_w;
+    int32_t extrap_blocks;
+    double ms;                /* average time of one call with this shape */
+} rmx_tuning;
+int rmx_autotune(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
+                 int32_t n_solids, const rmx_options* opt, void* hip_stream, int32_t reps,
+                 rmx_tuning* best);
+
 /* Profiling (tracing): wait for every call made with RMX_FLAG_PROFILE since the last
  * read, then write per phase the summed kernel time in ms (ms[RMX_N_PHASES], HOST) and
  * the number of launches (launches[RMX_N_PHASES], HOST), and reset the sums. */

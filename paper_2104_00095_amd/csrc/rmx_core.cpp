@@ -353,6 +353,102 @@ int rmx_extrapolate(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     return RMX_OK;
 }
 
+int rmx_autotune(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+                 const rmx_options* opt, void* hip_stream, int32_t reps, rmx_tuning* best) {
+    if (!c || !grid || !solids || n_solids < 1 || !best || reps < 1) return RMX_E_ARG;
+    rmx_options def;
+    rmx_default_options(&def);
+    if (!opt) opt = &def;
+    int rc = validate_options(opt);
+    if (rc != RMX_OK) return rc;
+    for (int i = 0; i < n_solids; ++i)
+        if ((rc = validate_solid(grid, solids + i)) != RMX_OK) return rc;
+    if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    rmx_options o = *opt;
+    o.flags &= ~(uint32_t)(RMX_FLAG_GRAPH | RMX_FLAG_PROFILE | RMX_FLAG_SYNC | RMX_FLAG_PER_SOLID);
+    c->grid_ptrs.assign(n_solids, grid);
+    Plan probe;
+    rc = plan(c->grid_ptrs.data(), solids, n_solids, &o, c->lds_limit, c->cus, Tuning{}, &probe);
+    if (rc != RMX_OK) return rc;
+    int Wmax = 1;
+    for (const auto& d : probe.solids) Wmax = std::max(Wmax, d.W);
+    // save xi
+    std::vector<size_t> bytes(n_solids), off(n_solids);
+    size_t total = 0;
+    for (int i = 0; i < n_solids; ++i) {
+        bytes[i] = 24 * (size_t)solids[i].ext[0] * solids[i].ext[1] * solids[i].ext[2];
+        off[i] = total;
+        total += bytes[i];
+    }
+    char* save = nullptr;
+    if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
+    if (hipMalloc(&save, total) != hipSuccess) return RMX_E_HIP;
+    auto copy = [&](bool restore) -> hipError_t {
+        for (int i = 0; i < n_solids; ++i) {
+            void* a = save + off[i];
+            void* x = solids[i].xi;
+            const hipError_t e = restore ? hipMemcpyAsync(x, a, bytes[i], hipMemcpyDeviceToDevice, st)
+                                         : hipMemcpyAsync(a, x, bytes[i], hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = RMX_OK;
+    if (copy(false) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        rc = RMX_E_HIP;
+    Tuning win{};
+    double win_ms = 1e300;
+    const int tws[3] = {1, 2, 4};
+    const int per_cu[4] = {2, 3, 4, 6};
+    for (int a = 0; a < 3 && rc == RMX_OK; ++a) {
+        if (tws[a] > 1 && tws[a] > Wmax + 1) continue;           // wider than every row
+        if (label_lds_bytes(probe.Lmax, tws[a], Wmax) > c->lds_limit) continue;
+        for (int q = 0; q < 4 && rc == RMX_OK; ++q) {
+            Tuning t{tws[a], per_cu[q] * c->cus};
+            if (copy(true) != hipSuccess) { rc = RMX_E_HIP; break; }
+            // one untimed call (workspace growth, descriptor upload), then `reps` timed
+            if ((rc = run_batch(c, c->grid_ptrs.data(), solids, n_solids, &o, st, false, 0, false,
+                                &t)) != RMX_OK)
+                break;
+            if (copy(true) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+                rc = RMX_E_HIP;
+                break;
+            }
+            for (int r = 0; r < reps && rc == RMX_OK; ++r)
+                rc = run_batch(c, c->grid_ptrs.data(), solids, n_solids, &o, st, false, 0, false,
+                               &t);
+            if (rc != RMX_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = RMX_E_HIP;
+                break;
+            }
+            // (the restore copy before each timed run is outside the events)
+            const double per = ms / reps;
+            if (per < win_ms) {
+                win_ms = per;
+                win = t;
+            }
+        }
+    }
+    if (rc == RMX_OK && copy(true) != hipSuccess) rc = RMX_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess && rc == RMX_OK) rc = RMX_E_HIP;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    if (rc != RMX_OK) return rc;
+    if (!(win.tile_w > 0)) return RMX_E_ARG;
+    c->tuned[tune_key(probe)] = win;
+    best->tile_w = win.tile_w;
+    best->extrap_blocks = win.extrap_blocks;
+    best->ms = win_ms;
+    return RMX_OK;
+}
+
 int rmx_profile_read(rmx_ctx* c, double* ms, int64_t* launches) {
     if (!c) return RMX_E_ARG;
     if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;

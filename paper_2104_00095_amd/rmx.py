@@ -29,7 +29,7 @@ EXPORTS = [
     "rmx_default_options", "rmx_create", "rmx_destroy", "rmx_workspace_size",
     "rmx_extrapolate", "rmx_status_string", "rmx_server_create", "rmx_server_register",
     "rmx_server_field", "rmx_server_submit", "rmx_server_wait", "rmx_server_release",
-    "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read",
+    "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read", "rmx_autotune",
 ]
 
 
@@ -54,6 +54,11 @@ class Options(ctypes.Structure):
     _fields_ = [("r_s", ctypes.c_int32), ("r_max", ctypes.c_int32),
                 ("normal_layers", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("extrap_blocks", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class SolidStats(ctypes.Structure):
@@ -107,6 +112,8 @@ def lib():
         L.rmx_server_usage.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
         L.rmx_server_destroy.argtypes = [vp]
         L.rmx_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+        L.rmx_autotune.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, P(Options), vp,
+                                   ctypes.c_int32, P(Tuning)]
         for name in EXPORTS:
             if name != "rmx_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -251,6 +258,19 @@ class Context:
         if st != OK:
             raise RmxError(st, "rmx_profile_read")
         return {PHASES[i]: (ms[i], n[i]) for i in range(N_PHASES) if n[i]}
+
+    def autotune(self, g: Grid, solids: Sequence[Solid], opt: Optional[Options] = None,
+                 reps: int = 5, stream=None):
+        """Time the launch-shape candidates on this batch and keep the fastest for its
+        shape class; returns {"tile_w", "extrap_blocks", "ms"}."""
+        arr = (Solid * len(solids))(*solids)
+        best = Tuning()
+        st = lib().rmx_autotune(self.h, ctypes.byref(g), arr, len(solids),
+                                ctypes.byref(opt) if opt else None, _stream_handle(stream),
+                                int(reps), ctypes.byref(best))
+        if st != OK:
+            raise RmxError(st, "rmx_autotune")
+        return {"tile_w": best.tile_w, "extrap_blocks": best.extrap_blocks, "ms": best.ms}
 
     def extrapolate_raw(self, g: Grid, arr, n: int, opt: Options, stream_handle):
         """Minimal-overhead call for timing loops: prebuilt Solid array, no stats."""

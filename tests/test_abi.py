@@ -42,6 +42,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", offsetof(rmx_solid, phi0), offsetof(rmx_solid, xi),
          offsetof(rmx_solid, decisions), offsetof(rmx_solid_stats, status),
          offsetof(rmx_shape, rot));
+  printf("%zu %zu\\n", sizeof(rmx_tuning), offsetof(rmx_tuning, ms));
   return 0;
 }
 """)
@@ -51,7 +52,8 @@ int main(void) {
     want = [ctypes.sizeof(rmx.Grid), ctypes.sizeof(rmx.Shape), ctypes.sizeof(rmx.Solid),
             ctypes.sizeof(rmx.Options), ctypes.sizeof(rmx.SolidStats),
             rmx.Solid.phi0.offset, rmx.Solid.xi.offset, rmx.Solid.decisions.offset,
-            rmx.SolidStats.status.offset, rmx.Shape.rot.offset]
+            rmx.SolidStats.status.offset, rmx.Shape.rot.offset,
+            ctypes.sizeof(rmx.Tuning), rmx.Tuning.ms.offset]
     assert [int(v) for v in a] == want
 
 

@@ -4,9 +4,12 @@ UndefinedBehaviorSanitizer on tiny workloads.  Labels and decisions must equal t
 oracle's and xi must meet the GPU tolerance.  The threads of a block are host threads
 (blocks run in turn), and the workspace regions are separated by poisoned red zones, so an
 access past any region is reported.  Test infrastructure only: the product library never
-contains this build.
+contains this build.  The emulated runs are separate processes; they run four at a time,
+once per module, and each test checks its own.
 """
 import os
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -19,64 +22,11 @@ pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host c
 
 TOL = {0: 1e-12, 1: 1e-5}
 BATCHED, PER_SOLID, GRAPH, PERSISTENT = 0, 4, 2, 16
+AUTOTUNE = 1024   # (run_case: run the autotuner on the fields first)
 
 
-def _cases():
-    return {
-        "sphere16": synth.sphere32(n=16, n_layers=3),
-        "ellipsoid24": synth.ellipsoid128(n=24, n_layers=3),
-        "suspension3": synth.suspension(n_solids=3, grid_n=(24, 24, 40), h=1 / 24),
-    }
-
-
-@pytest.fixture(scope="module")
-def built():
-    return emu.build()
-
-
-def _check(w, outs, precision, **kw):
-    for (xo, lab, dec, _), s in zip(outs, w.solids):
-        st, xr, lr, dr, _ = run_oracle(w, s, **kw)
-        assert np.array_equal(lab, lr)
-        if st == 0:
-            assert np.array_equal(dec, dr)
-            assert rel_err(xo, xr, lr > 0) <= TOL[precision]
-        keep = lr <= 0 if st == 0 else np.ones(lr.shape, bool)
-        assert np.array_equal(xo[:, keep].view(np.uint64), s.xi[:, keep].view(np.uint64))
-
-
-@pytest.mark.parametrize("case,precision,flags", [
-    ("sphere16", 0, BATCHED),
-    ("ellipsoid24", 0, BATCHED),
-    ("suspension3", 0, BATCHED),
-    ("suspension3", 0, PER_SOLID),
-    ("suspension3", 1, GRAPH),
-])
-def test_emulated_kernels_match_oracle(built, tmp_path, case, precision, flags):
-    w = _cases()[case]
-    st, outs = emu.run(w, str(tmp_path), precision=precision, flags=flags)
-    assert st == 0
-    _check(w, outs, precision)
-
-
-def test_emulated_repeated_calls(built, tmp_path):
-    """Calls of different forms on one context (shared workspace, descriptors cached
-    between identical calls), each on a fresh copy of the field, before the checked call."""
-    w = _cases()["suspension3"]
-    st, outs = emu.run(w, str(tmp_path), flags=BATCHED,
-                       pre_flags=(BATCHED, GRAPH, BATCHED))
-    assert st == 0
-    _check(w, outs, 0)
-
-
-def test_emulated_persistent_refused(built, tmp_path):
-    w = _cases()["sphere16"]
-    st, _ = emu.run(w, str(tmp_path), flags=PERSISTENT)
-    assert st == -11
-
-
-def test_emulated_statuses(built, tmp_path):
-    """Truncated band, no interior cell and L = 0 in one batch, both launch forms."""
+def _truncation_batch():
+    """Truncated band, no interior cell, L = 0 and an ordinary solid in one batch."""
     w0 = synth.sphere32(n=24, n_layers=3)
     s = w0.solids[0]
     w = synth.Workload("statuses", w0.grid_n, w0.h, w0.origin)
@@ -85,16 +35,98 @@ def test_emulated_statuses(built, tmp_path):
     w.solids.append(synth.Solid(s.lo, s.ext, s.shape, 3, s.xi + 10.0))
     w.solids.append(synth.Solid(s.lo, s.ext, s.shape, 0, s.xi.copy()))
     w.solids.append(synth.Solid(s.lo, s.ext, s.shape, 3, s.xi.copy()))
-    for flags in (BATCHED, PER_SOLID):
-        st, outs = emu.run(w, str(tmp_path), flags=flags)
-        assert st == -7
-        _check(w, outs, 0)
+    return w
 
 
+def _runs():
+    sphere = synth.sphere32(n=16, n_layers=3)
+    ell = synth.ellipsoid128(n=24, n_layers=3)
+    susp = synth.suspension(n_solids=3, grid_n=(24, 24, 40), h=1 / 24)
+    edges = edge_workloads()
+    trunc = _truncation_batch()
+    # name: (workload, precision, flags, calls made first on the same context)
+    return {
+        "sphere16": (sphere, 0, BATCHED, ()),
+        "ellipsoid24": (ell, 0, BATCHED, ()),
+        "suspension3": (susp, 0, BATCHED, ()),
+        "suspension3_per_solid": (susp, 0, PER_SOLID, ()),
+        "suspension3_fp32_graph": (susp, 1, GRAPH, ()),
+        "repeated_calls": (susp, 0, BATCHED, (BATCHED, GRAPH, BATCHED)),
+        "autotune_then_call": (sphere, 0, BATCHED, (AUTOTUNE,)),
+        "persistent_refused": (sphere, 0, PERSISTENT, ()),
+        "statuses_batched": (trunc, 0, BATCHED, ()),
+        "statuses_per_solid": (trunc, 0, PER_SOLID, ()),
+        "edge_sphere": (edges[0], 0, BATCHED, ()),
+        "edge_ellipsoid": (edges[1], 0, BATCHED, ()),
+    }
 
-def test_emulated_nonfinite_and_boundary(built, tmp_path):
+
+@pytest.fixture(scope="module")
+def emulated():
+    emu.build()
+    root = tempfile.mkdtemp(prefix="rmx_emu_")
+
+    def one(item):
+        name, (w, prec, flags, pre) = item
+        st, outs = emu.run(w, os.path.join(root, name), precision=prec, flags=flags,
+                           pre_flags=pre)
+        return name, (w, prec, st, outs)
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        return dict(ex.map(one, _runs().items()))
+
+
+def _check(w, outs, precision):
+    for (xo, lab, dec, _), s in zip(outs, w.solids):
+        st, xr, lr, dr, _ = run_oracle(w, s)
+        assert np.array_equal(lab, lr)
+        if st == 0:
+            assert np.array_equal(dec, dr)
+            assert rel_err(xo, xr, lr > 0) <= TOL[precision]
+        keep = lr <= 0 if st == 0 else np.ones(lr.shape, bool)
+        assert np.array_equal(xo[:, keep].view(np.uint64), s.xi[:, keep].view(np.uint64))
+
+
+@pytest.mark.parametrize("name", ["sphere16", "ellipsoid24", "suspension3",
+                                  "suspension3_per_solid", "suspension3_fp32_graph"])
+def test_emulated_kernels_match_oracle(emulated, name):
+    w, prec, st, outs = emulated[name]
+    assert st == 0
+    _check(w, outs, prec)
+
+
+def test_emulated_repeated_calls(emulated):
+    """Calls of different forms on one context (shared workspace, descriptors cached
+    between identical calls), each on a fresh copy of the field, before the checked call."""
+    w, prec, st, outs = emulated["repeated_calls"]
+    assert st == 0
+    _check(w, outs, prec)
+
+
+def test_emulated_autotune_then_call(emulated):
+    """The autotuner (every candidate launch shape, xi saved and restored) followed by the
+    checked call with the tuned shapes: the result must still be the oracle's."""
+    w, prec, st, outs = emulated["autotune_then_call"]
+    assert st == 0
+    _check(w, outs, prec)
+
+
+def test_emulated_persistent_refused(emulated):
+    w, prec, st, outs = emulated["persistent_refused"]
+    assert st == -11
+
+
+@pytest.mark.parametrize("name", ["statuses_batched", "statuses_per_solid"])
+def test_emulated_statuses(emulated, name):
+    """Truncated band, no interior cell and L = 0 in one batch."""
+    w, prec, st, outs = emulated[name]
+    assert st == -7
+    _check(w, outs, prec)
+
+
+@pytest.mark.parametrize("name", ["edge_sphere", "edge_ellipsoid"])
+def test_emulated_nonfinite_and_boundary(emulated, name):
     """Classification edge cases against the oracle: NaN and infinite components, cells
     exactly on |xi - c|^2 = R^2 or on an axis; a sphere and a rotated ellipsoid."""
-    for w in edge_workloads():
-        st, outs = emu.run(w, str(tmp_path))
-        _check(w, outs, 0)
+    w, prec, st, outs = emulated[name]
+    _check(w, outs, prec)

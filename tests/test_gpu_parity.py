@@ -295,3 +295,29 @@ def test_deterministic_repeats(ctx):
             outs.append(dw.xi[0].cpu().numpy().copy())
         assert np.array_equal(outs[-1].view(np.uint64), outs[-2].view(np.uint64))
         assert np.array_equal(outs[-1].view(np.uint64), outs[-3].view(np.uint64))
+
+
+def test_autotune_keeps_inputs_and_results(ctx):
+    """The autotuner restores xi, and a call with the tuned launch shapes gives, bit for
+    bit, the result of a context that was never tuned."""
+    import torch
+    from paper_2104_00095_amd import fields, rmx
+    w = synth.suspension(n_solids=6, grid_n=(64, 64, 128), h=1.0 / 64)
+    dw = fields.upload(w)
+    before = [x.clone() for x in dw.xi]
+    best = ctx.autotune(dw.grid, dw.solids, rmx.options(), reps=2)
+    torch.cuda.synchronize()
+    assert best["tile_w"] in (1, 2, 4) and best["extrap_blocks"] > 0 and best["ms"] > 0
+    for a, b in zip(dw.xi, before):
+        assert torch.equal(a, b)
+    st, tuned = run_gpu(ctx, w, 0)
+    fresh = rmx.Context(0)
+    try:
+        st2, plain = run_gpu(fresh, w, 0)
+    finally:
+        fresh.close()
+    assert st == st2 == 0
+    for (xa, la, da, _), (xb, lb, db, _) in zip(tuned, plain):
+        assert np.array_equal(xa.view(np.uint64), xb.view(np.uint64))
+        assert np.array_equal(la, lb) and np.array_equal(da, db)
+    print("autotune", best)
