@@ -98,6 +98,41 @@ def classify_bytes(w):
     return total
 
 
+KERNEL_SOURCES = ("paper_2104_00095_amd/csrc/rmx_kernels.hip",
+                  "paper_2104_00095_amd/csrc/rmx_device.h",
+                  "paper_2104_00095_amd/csrc/rmx_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE counters, each scaled
+    by the same counter on a plain device copy of known size) from the committed summary
+    profiles/<kernel>_<workload>_counters.md, if it was taken on the current kernel
+    sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def kernel_bytes(phase, w, stats, normal_layers=2, decisions=False, cls_bytes=None):
     """Algorithmic HBM bytes of one launch of a kernel (the minimum it must move):
     classify reads xi under its early-out rule (see classify_bytes; at most 24 B/cell)
@@ -161,6 +196,27 @@ def cpu_baseline(w, seconds, gpu=None, r_s=2, r_max=4, normal_layers=2):
         res[f"gpu_{name}_labels_equal"] = same
         res[f"gpu_{name}_rel_max_err"] = worst
     return res
+
+
+def copy_calibration(n_bytes=1 << 30, reps=5):
+    """A plain device-to-device copy of n_bytes (read n_bytes, write n_bytes), `reps`
+    times: under a counter profiler, its FETCH_SIZE and WRITE_SIZE per dispatch against
+    n_bytes give the scale of those counters."""
+    import torch
+    src = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": n_bytes, "copy_bytes_written": n_bytes,
+                      "ms": ms, "GB_per_s": 2 * n_bytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def rel_err(a, b, band):
@@ -396,7 +452,8 @@ def main():
     dom_ms = phases[dom][0]
     dom_bytes = kb[dom]
     roof = {"bound": "hbm", "kernel": dom, "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "traffic": committed_traffic(dom, args.workload),
             "kernel_ms": dom_ms, "algorithmic_bytes": dom_bytes}
     roof["frac"] = roof["achieved"] / roof["peak"]
     B = 25 * cells + 24 * nb
