@@ -216,9 +216,8 @@ __device__ __forceinline__ unsigned long long spread8(uint32_t x) {
 }
 
 // ------------------------------------------------------------------------------------
-// Extrapolation of one layer.  kLanes lanes per band cell (64 / kLanes cells per wave).
+// Extrapolation of one layer.  A group of NL = 4, 8 or 16 aligned lanes per band cell.
 // ------------------------------------------------------------------------------------
-constexpr int kLanes = 8;
 
 template <typename T>
 struct Moments {
@@ -238,17 +237,42 @@ __device__ __forceinline__ void zero(Moments<T>& a) {
     for (int q = 0; q < 5; ++q) a.g[q] = 0;
 }
 
-template <typename T>
+// Sums over aligned groups of NL lanes (4, 8 or 16) by DPP moves within a row: swap
+// neighbours, swap pairs, then mirror the half-row (8) and the row (16).  Every lane of a
+// group ends with the same, commutatively formed, sum.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_v(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_v(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+
+template <int NL, int CTRL, typename T>
+__device__ __forceinline__ void reduce_step(Moments<T>& a) {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) a.m[q] += dpp_v<CTRL>(a.m[q]);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) a.r[q] += dpp_v<CTRL>(a.r[q]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a.g[q] += dpp_i<CTRL>(a.g[q]);
+}
+
+template <int NL, typename T>
 __device__ __forceinline__ void reduce_lanes(Moments<T>& a) {
-#pragma unroll
-    for (int o = kLanes / 2; o >= 1; o >>= 1) {
-#pragma unroll
-        for (int q = 0; q < 10; ++q) a.m[q] += __shfl_xor(a.m[q], o, kLanes);
-#pragma unroll
-        for (int q = 0; q < 12; ++q) a.r[q] += __shfl_xor(a.r[q], o, kLanes);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) a.g[q] += __shfl_xor(a.g[q], o, kLanes);
-    }
+    static_assert(NL == 4 || NL == 8 || NL == 16, "lane group");
+    reduce_step<NL, 0xB1>(a);                   // quad_perm [1,0,3,2]
+    reduce_step<NL, 0x4E>(a);                   // quad_perm [2,3,0,1]
+    if (NL >= 8) reduce_step<NL, 0x141>(a);     // row_half_mirror
+    if (NL >= 16) reduce_step<NL, 0x140>(a);    // row_mirror
 }
 
 // Two signed 16-bit sums packed as lo + hi * 2^16 (|sums| < 2^15 for r <= 4).
@@ -333,14 +357,14 @@ struct CellCtx {
 
 // Accumulate, from global memory, the moments of the eligible data within Chebyshev
 // radius r (used for radii beyond the staged halo).  The (2r+1)^2 rows (dy, dz) of the box
-// are dealt to the kLanes lanes of the cell.  Eq. (weight): w = 2^-(|dx|+|dy|+|dz|), times
+// are dealt to the NL lanes of the cell.  Eq. (weight): w = 2^-(|dx|+|dy|+|dz|), times
 // the cosine between x_e - x_d = -d h and the normal when use_normal; data with
 // (dx gx + dy gy) + dz gz >= 0 (that exact expression, no contraction) get weight 0.
-template <typename T>
+template <int NL, typename T>
 __device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_normal, int lq,
                                         Moments<T>& acc) {
     const int D = 2 * r + 1;
-    for (int row = lq; row < D * D; row += kLanes) {
+    for (int row = lq; row < D * D; row += NL) {
         const int dy = row % D - r, dz = row / D - r;
         const int jj = cx.j + dy, kk = cx.k + dz;
         if ((unsigned)jj >= (unsigned)cx.n1 || (unsigned)kk >= (unsigned)cx.n2) continue;

@@ -1,6 +1,6 @@
 // HIP kernels of the reference-map band extrapolation (Lin, Derr & Rycroft, arXiv
 // 2104.00095, section "Extrapolation of xi(x,t)"; SI "Weighting scheme for weighted least
-// squares-based extrapolation", eq. (weight)).  One call is a chain of L + 2 launches,
+// squares-based extrapolation", eq. (weight)).  One call is a chain of L + 3 launches,
 // each covering every solid of the batch:
 //   k_classify  streams xi once (coalesced, nontemporal) and packs the interior predicate
 //               phi0(xi) < 0 into a 1-bit mask (wave ballots); zeroes the call's counters.
@@ -13,10 +13,11 @@
 //               the normals of the brick's cells of that layer by central differences, from
 //               the field before any write.
 //   k_extrap    one launch per layer, ascending: a block stages a listed brick with a
-//               halo of r_s (xi and labels, 12^3 cells) in LDS; 8 lanes per cell of the
-//               layer gather the (2r+1)^3 box from LDS, accumulate the 4x4 normal-equation
-//               moments, reduce them with cross-lane shuffles, decide degeneracy by an
-//               exact integer determinant, solve by Cholesky in FP64 and write xi_e.
+//               halo of r_s (xi and labels, 12^3 cells) in LDS; a group of 4, 8 or 16
+//               lanes per cell of the layer (as many as keep the brick's cells in one pass)
+//               gathers the (2r+1)^3 box from LDS, accumulates the 4x4 normal-equation
+//               moments, reduces them by DPP moves, decides degeneracy by an exact
+//               integer determinant, solves by Cholesky in FP64 and writes xi_e.
 // The work is bandwidth- and latency-bound, with 4x4 systems per cell: no MFMA.
 #include "rmx_device.h"
 
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
 // the eligible set (or behind the interface) enters with weight 0 and a zero value
 // (selects, so a non-finite value of an ineligible cell cannot leak in).  The integer
 // moments of the eligible offsets (for the exact rank test) are summed the same way.
-template <typename T>
+template <int NL, typename T>
 __device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
                                            const int8_t* __restrict__ sl,
                                            const double* __restrict__ s_rlen, int idx, int le,
@@ -384,7 +385,7 @@ __device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
                                            int lq, Moments<T>& acc) {
     constexpr int S = kBrickSpan, S2 = kBrickSpan * kBrickSpan;
 #pragma unroll 1
-    for (int row = lq; row < 25; row += kLanes) {
+    for (int row = lq; row < 25; row += NL) {
         const int dy = row % 5 - 2, dz = row / 5 - 2;
         const int rb = idx + dz * S2 + dy * S;
         int lab[5];
@@ -461,76 +462,20 @@ __device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
-                                             unsigned long long* st, int l, int bx, int by,
-                                             int bz, unsigned char* lds, int* s_wave,
-                                             const double* s_rlen) {
-    double* sx = reinterpret_cast<double*>(lds);
-    int8_t* sl = reinterpret_cast<int8_t*>(lds + kBrickCells * 24);
-    uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * 25);
-    const int tid = threadIdx.x;
+// The fits of the compacted layer-l cells of a staged brick, NL lanes per cell.
+template <int NL, typename T>
+__device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
+                                          unsigned long long* st, int l, int ox, int oy, int oz,
+                                          int total, unsigned char* lds, const double* s_rlen) {
+    const double* sx = reinterpret_cast<const double*>(lds);
+    const int8_t* sl = reinterpret_cast<const int8_t*>(lds + kBrickCells * 24);
+    const uint16_t* cells = reinterpret_cast<const uint16_t*>(lds + kBrickCells * 25);
     const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
     const int64_t nc = d->ncell;
     const double* __restrict__ xi = d->xi;
     const int8_t* __restrict__ labels = d->labels;
-    const int ox = kBrick * bx - kBrickHalo, oy = kBrick * by - kBrickHalo,
-              oz = kBrick * bz - kBrickHalo;
-    // Stage the labels of the 12^3 cells (outside the box: -1), then xi of the cells that
-    // can carry data for layer l (0 <= label < l); the others are staged as 0 and never
-    // enter a sum (their weight is selected to 0).
-    constexpr int kH = (kBrickCells + 255) / 256;
-    int32_t cc[kH];
-    int lb[kH];
-#pragma unroll
-    for (int h = 0; h < kH; ++h) {
-        const int q = tid + 256 * h;
-        const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
-                  z = q / (kBrickSpan * kBrickSpan);
-        const int gx = ox + x, gy = oy + y, gz = oz + z;
-        const bool in = q < kBrickCells && (unsigned)gx < (unsigned)n0 &&
-                        (unsigned)gy < (unsigned)n1 && (unsigned)gz < (unsigned)n2;
-        cc[h] = in ? (gz * n1 + gy) * n0 + gx : -1;
-        lb[h] = in ? (int)labels[cc[h]] : -1;
-        if (q < kBrickCells) sl[q] = (int8_t)lb[h];
-    }
-#pragma unroll
-    for (int h = 0; h < kH; ++h) {
-        const int q = tid + 256 * h;
-        const bool use = lb[h] >= 0 && lb[h] < l;   // only cells inside the box: cc >= 0
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        if (use) {
-            v0 = xi[cc[h]];
-            v1 = xi[nc + cc[h]];
-            v2 = xi[2 * nc + cc[h]];
-        }
-        if (q < kBrickCells) {
-            sx[q] = v0;
-            sx[kBrickCells + q] = v1;
-            sx[2 * kBrickCells + q] = v2;
-        }
-    }
-    __syncthreads();
-    // the layer-l cells of the brick interior, compacted
-    int mine[2], cnt = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int q = tid + 256 * h;
-        const int x = kBrickHalo + q % kBrick, y = kBrickHalo + (q / kBrick) % kBrick,
-                  z = kBrickHalo + q / (kBrick * kBrick);
-        const int idx = (z * kBrickSpan + y) * kBrickSpan + x;
-        mine[h] = sl[idx] == l ? idx : -1;
-        cnt += mine[h] >= 0;
-    }
-    int excl, total;
-    block_scan<4>(cnt, excl, total, s_wave);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-        if (mine[h] >= 0) cells[excl++] = (uint16_t)mine[h];
-    __syncthreads();
-
-    const int grp = tid / kLanes, lq = tid % kLanes;
-    for (int ci = grp; ci < total; ci += 256 / kLanes) {
+    const int grp = threadIdx.x / NL, lq = threadIdx.x % NL;
+    for (int ci = grp; ci < total; ci += 256 / NL) {
         const int idx = cells[ci];
         const int x = idx % kBrickSpan, y = (idx / kBrickSpan) % kBrickSpan,
                   z = idx / (kBrickSpan * kBrickSpan);
@@ -593,11 +538,11 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
             Moments<T> acc;
             zero(acc);
             if (r == kBrickHalo)
-                gather_lds<T>(sx, sl, s_rlen, idx, l, un, cx.g0, cx.g1, cx.g2, cx.rgn, cx.a0,
+                gather_lds<NL, T>(sx, sl, s_rlen, idx, l, un, cx.g0, cx.g1, cx.g2, cx.rgn, cx.a0,
                               cx.a1, cx.a2, lq, acc);
             else
-                gather_any<T>(cx, r, un, lq, acc);
-            reduce_lanes(acc);
+                gather_any<NL, T>(cx, r, un, lq, acc);
+            reduce_lanes<NL>(acc);
             if (f2) {
                 const double sw = (double)acc.m[0];
                 res[0] = (double)acc.r[0] / sw;
@@ -627,6 +572,83 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
             if (code == kDecF1 || code == kDecF2 || code > b.r_s) atomicAdd(st + ST_GROWN, 1ull);
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
+                                             unsigned long long* st, int l, int bx, int by,
+                                             int bz, unsigned char* lds, int* s_wave,
+                                             const double* s_rlen) {
+    double* sx = reinterpret_cast<double*>(lds);
+    int8_t* sl = reinterpret_cast<int8_t*>(lds + kBrickCells * 24);
+    uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * 25);
+    const int tid = threadIdx.x;
+    const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
+    const int64_t nc = d->ncell;
+    const double* __restrict__ xi = d->xi;
+    const int8_t* __restrict__ labels = d->labels;
+    const int ox = kBrick * bx - kBrickHalo, oy = kBrick * by - kBrickHalo,
+              oz = kBrick * bz - kBrickHalo;
+    // Stage the labels of the 12^3 cells (outside the box: -1), then xi of the cells that
+    // can carry data for layer l (0 <= label < l); the others are staged as 0 and never
+    // enter a sum (their weight is selected to 0).
+    constexpr int kH = (kBrickCells + 255) / 256;
+#pragma unroll
+    for (int h = 0; h < kH; ++h) {
+        const int q = tid + 256 * h;
+        const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
+                  z = q / (kBrickSpan * kBrickSpan);
+        const int gx = ox + x, gy = oy + y, gz = oz + z;
+        const bool in = q < kBrickCells && (unsigned)gx < (unsigned)n0 &&
+                        (unsigned)gy < (unsigned)n1 && (unsigned)gz < (unsigned)n2;
+        const int lbv = in ? (int)labels[(gz * n1 + gy) * n0 + gx] : -1;
+        if (q < kBrickCells) sl[q] = (int8_t)lbv;
+    }
+#pragma unroll 1
+    for (int h = 0; h < kH; ++h) {
+        const int q = tid + 256 * h;
+        if (q >= kBrickCells) break;
+        const int lbv = sl[q];   // written by this thread above
+        const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
+                  z = q / (kBrickSpan * kBrickSpan);
+        const int c = ((oz + z) * n1 + (oy + y)) * n0 + (ox + x);
+        const bool use = lbv >= 0 && lbv < l;   // only cells inside the box
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        if (use) {
+            v0 = xi[c];
+            v1 = xi[nc + c];
+            v2 = xi[2 * nc + c];
+        }
+        sx[q] = v0;
+        sx[kBrickCells + q] = v1;
+        sx[2 * kBrickCells + q] = v2;
+    }
+    __syncthreads();
+    // the layer-l cells of the brick interior, compacted
+    int mine[2], cnt = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 256 * h;
+        const int x = kBrickHalo + q % kBrick, y = kBrickHalo + (q / kBrick) % kBrick,
+                  z = kBrickHalo + q / (kBrick * kBrick);
+        const int idx = (z * kBrickSpan + y) * kBrickSpan + x;
+        mine[h] = sl[idx] == l ? idx : -1;
+        cnt += mine[h] >= 0;
+    }
+    int excl, total;
+    block_scan<4>(cnt, excl, total, s_wave);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (mine[h] >= 0) cells[excl++] = (uint16_t)mine[h];
+    __syncthreads();
+
+    // lanes per cell: as many as keep every cell of the brick in one pass of the block
+    if (total <= 256 / 16)
+        fit_cells<16, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen);
+    else if (total <= 256 / 8)
+        fit_cells<8, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen);
+    else
+        fit_cells<4, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen);
     __syncthreads();   // the LDS is reused by the next brick
 }
 
@@ -827,7 +849,7 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
 
 // One launch per layer: blocks stride over the layer's brick list.
 template <typename T>
-__global__ __launch_bounds__(256) void k_extrap(Batch b, int l) {
+__global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
     HIP_DYNAMIC_SHARED(double, lds_d)
     unsigned char* lds = reinterpret_cast<unsigned char*>(lds_d);
     __shared__ int s_wave[4];

@@ -98,6 +98,25 @@ inline T __shfl_up(T v, int o, int width = 64) {
     rmx_emu::group_done(width);
     return r;
 }
+inline long long __double_as_longlong(double v) { return rmx_emu_from<long long>(rmx_emu_bits(v)); }
+inline double __longlong_as_double(long long v) { return rmx_emu_from<double>(rmx_emu_bits(v)); }
+inline int __float_as_int(float v) { return rmx_emu_from<int>(rmx_emu_bits(v)); }
+inline float __int_as_float(int v) { return rmx_emu_from<float>(rmx_emu_bits(v)); }
+// DPP moves used by the library, within the aligned group that holds every source lane:
+// quad_perm (0x00-0xff, groups of 4), row_half_mirror (0x141, 8), row_mirror (0x140, 16).
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int, int, bool) {
+    const int w = ctrl <= 0xff ? 4 : (ctrl == 0x141 ? 8 : (ctrl == 0x140 ? 16 : 0));
+    if (w == 0) std::abort();
+    const int lane = threadIdx.x % w;
+    int from = 0;
+    if (w == 4) from = (ctrl >> (2 * lane)) & 3;
+    else from = w - 1 - lane;
+    uint64_t* s = rmx_emu::group_exchange((uint64_t)(uint32_t)src, w);
+    const int r = (int)(uint32_t)s[from];
+    rmx_emu::group_done(w);
+    (void)old;
+    return r;
+}
 inline int __builtin_amdgcn_readfirstlane(int v) {
     uint64_t* s = rmx_emu::group_exchange((uint64_t)(uint32_t)v, 64);
     const int r = (int)(uint32_t)s[0];
