@@ -204,6 +204,32 @@ __device__ __forceinline__ void block_scan(int v, int& excl, int& total, int* s_
     __syncthreads();
 }
 
+// Entries [0, count) of a list, split into one contiguous range per XCD in proportion to
+// its share of the grid (workgroups are dealt to the XCDs round-robin): neighbouring
+// entries, whose halos overlap, are then fetched into one L2.  The calling block takes
+// begin, begin + stride, ... below end.
+struct XcdRange {
+    int begin, end, stride;
+};
+__device__ __forceinline__ XcdRange xcd_range(int count) {
+    const int G = gridDim.x, x = blockIdx.x % kXcds;
+    int before = 0;   // blocks on the XCDs dealt before this one
+    for (int y = 0; y < x; ++y) before += (G - y + kXcds - 1) / kXcds;
+    const int mine = (G - x + kXcds - 1) / kXcds;   // >= 1: this block is one of them
+    XcdRange r;
+    r.begin = (int)((int64_t)count * before / G) + (int)blockIdx.x / kXcds;
+    r.end = (int)((int64_t)count * (before + mine) / G);
+    r.stride = mine;
+    return r;
+}
+
+// The same value, through an identity lane move the compiler cannot see through: work
+// derived from it stays where it is written instead of being hoisted out of a loop and
+// kept live (spilled) across the loop body.  All lanes of each quad must be active.
+__device__ __forceinline__ int opaque_lane_value(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xE4, 0xf, 0xf, false);   // quad_perm [0,1,2,3]
+}
+
 // Spread the low 4 bits of x to the low bit of 4 bytes (bit q -> byte q).  The partial
 // products of x * (1 + 2^7 + 2^14 + 2^21) land on distinct bit positions, so no carries.
 __device__ __forceinline__ uint32_t spread4(uint32_t x) {

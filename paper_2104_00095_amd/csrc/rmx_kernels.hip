@@ -27,7 +27,7 @@ using namespace dev;
 
 // ------------------------------------------------------------------------------------
 // Classification of mask words [wb, we) of solid d by the 4 waves of the block: each wave
-// streams its 16 consecutive 64-cell row segments, ballot-packs the interior predicate
+// streams its 8 consecutive 64-cell row segments, ballot-packs the interior predicate
 // and writes one mask word per segment.  Cells past the row end (x >= n0) are never
 // interior.
 //
@@ -36,10 +36,10 @@ using namespace dev;
 // round-to-nearest a sum of non-negative terms is never below any of its partial sums,
 // so dx*dx >= R*R, or dx*dx + dy*dy >= R*R, already means "not interior" (a non-finite
 // component fails its test as well, as in the full predicate).  The running sum is all a
-// lane keeps, so a wave issues each component's 16 loads at once.  Ellipsoid: the body
+// lane keeps, so a wave issues each component's 8 loads at once.  Ellipsoid: the body
 // coordinates need all three components, read together.
 // ------------------------------------------------------------------------------------
-constexpr int kWaveWords = kChunkWords / 4;   // 16 segments per wave
+constexpr int kWaveWords = kChunkWords / 4;   // 8 segments per wave (60 VGPRs: 8 waves per SIMD)
 constexpr int kSegE = 4;                       // ellipsoid: segments per batch
 
 __device__ __forceinline__ void classify_sphere(const DevSolid* dp, const ShapeR& sh, int wb,
@@ -582,7 +582,8 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
     double* sx = reinterpret_cast<double*>(lds);
     int8_t* sl = reinterpret_cast<int8_t*>(lds + kBrickCells * 24);
     uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * 25);
-    const int tid = threadIdx.x;
+    // re-derived per brick: the staging index math is not kept live across bricks
+    const int tid = opaque_lane_value(threadIdx.x);
     const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
     const int64_t nc = d->ncell;
     const double* __restrict__ xi = d->xi;
@@ -654,8 +655,8 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
 
 // ------------------------------------------------------------------------------------
 // Brick lists: the bucket counts of layers l0..l0+nl-1 form one prefix in LDS
-// (s_pref[0..nl*kBuckets]); entry e of the concatenation is found by bisection.  Blocks
-// stride over the entries.
+// (s_pref[0..nl*kBuckets]); entry e of the concatenation is found by bisection.  The
+// blocks of each XCD stride over a contiguous range of the entries.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int list_prefix(const Batch& b, int l0, int nl, int* s_pref,
                                            int* s_wave) {
@@ -832,7 +833,8 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
     const int nl = b.normal_layers;
     if (nl <= 0) return;
     const int total = list_prefix(b, 1, nl, s_pref, s_wave);
-    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+    const XcdRange rg = xcd_range(total);
+    for (int e = rg.begin; e < rg.end; e += rg.stride) {
         int l = 0;
         const unsigned long long pk = list_entry(b, 1, nl, s_pref, e, &l);
         const int s = uniform_int((int)(pk >> 32));
@@ -847,7 +849,8 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
     }
 }
 
-// One launch per layer: blocks stride over the layer's brick list.
+// One launch per layer: the blocks of each XCD stride over a contiguous range of the
+// layer's brick list.
 template <typename T>
 __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
     HIP_DYNAMIC_SHARED(double, lds_d)
@@ -857,7 +860,8 @@ __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
     __shared__ double s_rlen[13];   // 1/|d| for |d|^2 = 0..12 (radius 2)
     if (threadIdx.x < 13) s_rlen[threadIdx.x] = c_rlen[threadIdx.x];
     const int count = list_prefix(b, l, 1, s_pref, s_wave);
-    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    const XcdRange rg = xcd_range(count);
+    for (int e = rg.begin; e < rg.end; e += rg.stride) {
         int ll = 0;
         const unsigned long long pk = list_entry(b, l, 1, s_pref, e, &ll);
         const int s = uniform_int((int)(pk >> 32));

@@ -98,6 +98,10 @@ inline T __shfl_up(T v, int o, int width = 64) {
     rmx_emu::group_done(width);
     return r;
 }
+struct alignas(16) double2 {
+    double x, y;
+};
+inline double2 make_double2(double a, double b) { return double2{a, b}; }
 inline long long __double_as_longlong(double v) { return rmx_emu_from<long long>(rmx_emu_bits(v)); }
 inline double __longlong_as_double(long long v) { return rmx_emu_from<double>(rmx_emu_bits(v)); }
 inline int __float_as_int(float v) { return rmx_emu_from<int>(rmx_emu_bits(v)); }
