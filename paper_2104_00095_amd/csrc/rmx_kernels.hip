@@ -4,8 +4,9 @@
 // each covering every solid of the batch:
 //   k_classify  streams xi once (coalesced, nontemporal) and packs the interior predicate
 //               phi0(xi) < 0 into a 1-bit mask (wave ballots); zeroes the call's counters.
-//   k_label     per 16 x 16-row tile: L bit-parallel dilations in LDS give the layers
-//               (first dilation reaching a cell = its layer), written as int8 labels; the
+//   k_label     per 16 x 16-row tile: L bit-parallel dilations in LDS, each on the rows
+//               still able to reach the tile, give the layers (first dilation reaching a
+//               cell = its layer), written as int8 labels; the
 //               tile counts its interior and band cells, detects a band truncated by a box
 //               face, and lists the 8^3 bricks holding cells of each layer.
 //   k_normal    sums the tile counts per solid; per listed brick of layers
@@ -156,16 +157,22 @@ __global__ __launch_bounds__(256) void k_classify(Batch b) {
 // Labels of one tile of 16 (y) x 16 (z) rows x tile_w 64-cell words (x); thread (tj, tk)
 // owns one row of the tile.  The region in LDS carries a halo of L rows in y and z and
 // one word on each side in x where the box continues (L <= 16 < 64), so after L dilations
-// through face neighbours (64-bit shifts and ORs) the tile is exact.
+// through face neighbours (64-bit shifts and ORs) the tile is exact; dilation l is formed
+// only on the rows within L - l of the tile, the only ones later dilations read.  Counts
+// go to LDS by atomics, one wave appends the tile's bricks with one round of global
+// atomics for all layers, and full-width tiles write their labels through an LDS
+// transpose, whole 128-byte rows per store instruction.
 // ------------------------------------------------------------------------------------
 constexpr int kRowsPerThread = 9;   // ceil((16 + 2 * 16)^2 / 256)
 
 template <int MAXTW>
 __global__ __launch_bounds__(256) void k_label(Batch b) {
     constexpr int FPL = 4 * 8 * MAXTW;   // brick flags per layer: 2 (y) x 2 (z) x 8 per word
+    constexpr int MW = MAXTW + 2;        // region words per row at most
     HIP_DYNAMIC_SHARED(double, lds_d)
     unsigned long long* lds = reinterpret_cast<unsigned long long*>(lds_d);
-    __shared__ int s_wave[5];
+    __shared__ int s_cnt[kLT];
+    __shared__ int s_trunc;
     __shared__ unsigned char s_bflag[kMaxLayers * FPL];
 
     const int t = blockIdx.x;
@@ -190,15 +197,15 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     const unsigned long long* __restrict__ mask = d->mask;
 
     for (int q = tid; q < L * FPL; q += 256) s_bflag[q] = 0;
-    // Region rows owned by this thread, packed: rj | rk << 8 | in-box << 16 (RJ, RK <= 48).
-    int rinfo[kRowsPerThread];
+    if (tid < kLT) s_cnt[tid] = 0;
+    if (tid == 0) s_trunc = 0;
+    // the mask rows of the region (rows outside the box: empty)
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
         const int rr = tid + 256 * q;
         const int rj = rr % RJ, rk = rr / RJ;
         const int jj = j0 - L + rj, kk = k0 - L + rk;
         const bool ok = rr < R && jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
-        rinfo[q] = rj | (rk << 8) | (ok ? 1 << 16 : 0);
         if (rr < R) {
             for (int w = 0; w < RW; ++w)
                 A[rr * RW + w] = ok ? mask[((int64_t)kk * n1 + jj) * W + xr0 + w] : 0ull;
@@ -234,35 +241,38 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                      (!d->wall_lo[2] && krow < L) || (!d->wall_hi[2] && krow >= n2 - L);
         }
     }
-    {
-        int excl, total;
-        block_scan<4>(cnt0, excl, total, s_wave);
-        if (tid == 0) b.tile_cnt[(int64_t)t * kLT] = total;
-    }
-    if (__syncthreads_or(trunc) && tid == 0) atomicOr(st + ST_FLAGS, FLAG_TRUNCATED);
+    // counts: LDS atomics of the non-zero per-thread counts (no block-wide scan)
+    if (cnt0) atomicAdd(&s_cnt[0], cnt0);
+    if (trunc) s_trunc = 1;
 
     const int by2 = (tk >> 3) * 2 + (tj >> 3);   // which of the tile's 2 x 2 brick rows
     for (int l = 1; l <= L; ++l) {
+        // One dilation step through face neighbours, A -> B, over the rows that can still
+        // reach the tile: D_l is needed only within L - l rows of it, i.e. on region rows
+        // [l, RJ - l) x [l, RK - l) (their neighbours lie inside the region).  A row's
+        // own words come from registers, its four neighbour rows from LDS.
+        const unsigned long long* __restrict__ Ar = A;
+        unsigned long long* __restrict__ Br = B;
+        const int SJ = RJ - 2 * l, S = SJ * (RK - 2 * l);
+        for (int i = tid; i < S; i += 256) {
+            const int rk = l + i / SJ, rj = l + i % SJ;
+            const int jj = j0 - L + rj, kk = k0 - L + rk;
+            const bool rok = jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
+            const int base = (rk * RJ + rj) * RW;
+            unsigned long long c[MW];
 #pragma unroll
-        for (int q = 0; q < kRowsPerThread; ++q) {
-            const int rr = tid + 256 * q;
-            if (rr < R) {
-                const int rj = rinfo[q] & 255, rk = (rinfo[q] >> 8) & 255;
-                const bool rok = (rinfo[q] >> 16) & 1;
-                for (int w = 0; w < RW; ++w) {
-                    const int idx = rr * RW + w;
-                    const unsigned long long c = A[idx];
-                    const unsigned long long left = (w > 0) ? A[idx - 1] : 0ull;
-                    const unsigned long long right = (w < RW - 1) ? A[idx + 1] : 0ull;
-                    unsigned long long v = c | (c << 1) | (c >> 1) | (left >> 63) | (right << 63);
-                    if (rj > 0) v |= A[idx - RW];
-                    if (rj < RJ - 1) v |= A[idx + RW];
-                    if (rk > 0) v |= A[idx - RW * RJ];
-                    if (rk < RK - 1) v |= A[idx + RW * RJ];
-                    const unsigned long long vm =
-                        !rok ? 0ull : (xr0 + w == W - 1 ? tail : ~0ull);
-                    B[idx] = v & vm;
-                }
+            for (int w = 0; w < MW; ++w) c[w] = w < RW ? Ar[base + w] : 0ull;
+#pragma unroll
+            for (int w = 0; w < MW; ++w) {
+                if (w >= RW) break;
+                const int idx = base + w;
+                const unsigned long long left = w > 0 ? c[w - 1] : 0ull;
+                const unsigned long long right = w < MW - 1 ? c[w + 1] : 0ull;
+                const unsigned long long v = c[w] | (c[w] << 1) | (c[w] >> 1) | (left >> 63) |
+                                             (right << 63) | Ar[idx - RW] | Ar[idx + RW] |
+                                             Ar[idx - RW * RJ] | Ar[idx + RW * RJ];
+                const unsigned long long vm = !rok ? 0ull : (xr0 + w == W - 1 ? tail : ~0ull);
+                Br[idx] = v & vm;
             }
         }
         __syncthreads();
@@ -285,45 +295,93 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
             for (int g = 0; g < 8; ++g)
                 if ((nw >> (8 * g)) & 255ull) s_bflag[(l - 1) * FPL + by2 * 8 * MAXTW + w * 8 + g] = 1;
         }
-        int excl, total;
-        block_scan<4>(cnt, excl, total, s_wave);
-        if (tid == 0) b.tile_cnt[(int64_t)t * kLT + l] = total;
+        if (cnt) atomicAdd(&s_cnt[l], cnt);
     }
-    __syncthreads();
+    __syncthreads();   // counts, flags and the last step complete; A/B free
+    if (tid <= L) b.tile_cnt[(int64_t)t * kLT + tid] = s_cnt[tid];
+    if (tid == 0 && s_trunc) atomicOr(st + ST_FLAGS, FLAG_TRUNCATED);
 
     // Bricks holding cells of each layer, appended to the layer's list in this tile's
-    // bucket with one atomic addition per layer.  A brick lies in exactly one tile, so a
-    // tile lists at most FPL bricks per layer and its bucket never overflows.
-    {
+    // bucket: wave 0 counts every layer, reserves all layers' slots with one round of
+    // atomics, then writes the entries.  A brick lies in exactly one tile, so a tile lists
+    // at most FPL bricks per layer and its bucket never overflows.
+    if (tid < 64) {
+        const int lane = tid;
         const int bk = t % kBuckets;
         const int64_t base0 = bucket_base(bk, b.n_tiles, b.tile_w);
         const int64_t cap = bucket_base(bk + 1, b.n_tiles, b.tile_w) - base0;
+        int mytot = 0;   // lane l - 1: bricks of layer l
         for (int l = 1; l <= L; ++l) {
-            const int f = tid < FPL ? s_bflag[(l - 1) * FPL + tid] : 0;
-            int excl, total;
-            block_scan<4>(f, excl, total, s_wave);
-            if (total == 0) continue;   // uniform
-            if (tid == 0) s_wave[4] = atomicAdd(b.bcount + (l - 1) * kBuckets + bk, total);
-            __syncthreads();
-            const int pos = s_wave[4] + excl;
-            if (f) {
-                const int r = tid, yz = r / (8 * MAXTW), xb = r % (8 * MAXTW);
-                const int bx = wx0 * 8 + xb, by = 2 * tyi + (yz & 1), bz = 2 * tzi + (yz >> 1);
-                if (pos < cap)
-                    b.blist[(int64_t)(l - 1) * b.blist_cap + base0 + pos] =
-                        ((unsigned long long)s << 32) |
-                        (unsigned long long)(bx | (by << 10) | (bz << 20));
-                else
-                    atomicOr(st + ST_FLAGS, FLAG_OVERFLOW);
+            int tot = 0;
+            for (int f0 = 0; f0 < FPL; f0 += 64)
+                tot += __popcll(__ballot(f0 + lane < FPL && s_bflag[(l - 1) * FPL + f0 + lane]));
+            if (lane == l - 1) mytot = tot;
+        }
+        int mybase = 0;
+        if (lane < L && mytot > 0) mybase = atomicAdd(b.bcount + lane * kBuckets + bk, mytot);
+        for (int l = 1; l <= L; ++l) {
+            const int lbase = __shfl(mybase, l - 1, 64);
+            int run = 0;
+            for (int f0 = 0; f0 < FPL; f0 += 64) {
+                const int r = f0 + lane;
+                const bool f = r < FPL && s_bflag[(l - 1) * FPL + r];
+                const unsigned long long bal = __ballot(f);
+                if (f) {
+                    const int pos = lbase + run + __popcll(bal & ((1ull << lane) - 1ull));
+                    const int yz = r / (8 * MAXTW), xb = r % (8 * MAXTW);
+                    const int bx = wx0 * 8 + xb, by = 2 * tyi + (yz & 1), bz = 2 * tzi + (yz >> 1);
+                    if (pos < cap)
+                        b.blist[(int64_t)(l - 1) * b.blist_cap + base0 + pos] =
+                            ((unsigned long long)s << 32) |
+                            (unsigned long long)(bx | (by << 10) | (bz << 20));
+                    else
+                        atomicOr(st + ST_FLAGS, FLAG_OVERFLOW);
+                }
+                run += __popcll(bal);
             }
-            __syncthreads();
         }
     }
 
-    if (row_ok) {
-        int8_t* lab0 = d->labels + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64;
-        int8_t* dec0 = d->decisions ? d->decisions + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64
-                                    : nullptr;
+    // Labels: byte = layer where the cell was reached, 0xFF where not.  Full-width tiles
+    // with aligned rows are transposed through LDS so that each store instruction writes
+    // whole 128-byte rows; other tiles write their rows thread by thread.
+    int8_t* lab0 = d->labels + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64;
+    int8_t* dec0 = d->decisions ? d->decisions + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64
+                                : nullptr;
+    const bool full = tw == MAXTW && (wx0 + MAXTW) * 64 <= n0 && (n0 & 7) == 0 &&
+                      (reinterpret_cast<uintptr_t>(d->labels) & 7) == 0 &&
+                      (!d->decisions || (reinterpret_cast<uintptr_t>(d->decisions) & 7) == 0);
+    if (full) {   // uniform
+        unsigned long long* T = lds;   // [256 rows][8 * MAXTW] label words
+#pragma unroll
+        for (int w = 0; w < MAXTW; ++w) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const int sh8 = 8 * g;
+                unsigned long long word =
+                    spread8((uint32_t)(p0[w] >> sh8) & 255u) |
+                    (spread8((uint32_t)(p1[w] >> sh8) & 255u) << 1) |
+                    (spread8((uint32_t)(p2[w] >> sh8) & 255u) << 2) |
+                    (spread8((uint32_t)(p3[w] >> sh8) & 255u) << 3) |
+                    (spread8((uint32_t)(p4[w] >> sh8) & 255u) << 4);
+                word |= spread8((uint32_t)(~prev[w] >> sh8) & 255u) * 0xFFull;
+                T[tid * (8 * MAXTW) + w * 8 + g] = word;
+            }
+        }
+        __syncthreads();
+        constexpr int CPR = 8 * MAXTW;   // 8-byte chunks per tile row
+#pragma unroll
+        for (int h = 0; h < CPR; ++h) {
+            const int ch = tid + 256 * h;
+            const int row = ch / CPR, off = ch % CPR;   // row = tk * 16 + tj
+            const int rj = j0 + row % kTileJ, rk = k0 + row / kTileJ;
+            if (rj < n1 && rk < n2) {
+                const int64_t o = ((int64_t)rk * n1 + rj) * n0 + wx0 * 64 + 8 * off;
+                reinterpret_cast<unsigned long long*>(d->labels + o)[0] = T[row * CPR + off];
+                if (d->decisions) reinterpret_cast<unsigned long long*>(d->decisions + o)[0] = 0ull;
+            }
+        }
+    } else if (row_ok) {
 #pragma unroll
         for (int w = 0; w < MAXTW; ++w) {
             if (w >= tw) break;
@@ -337,7 +395,6 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
 #pragma unroll
                 for (int g = 0; g < 8; ++g) {
                     const int sh8 = 8 * g;
-                    // label byte = layer bits where marked, 0xFF where unmarked
                     unsigned long long word =
                         spread8((uint32_t)(p0[w] >> sh8) & 255u) |
                         (spread8((uint32_t)(p1[w] >> sh8) & 255u) << 1) |
@@ -348,19 +405,19 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                     reinterpret_cast<unsigned long long*>(lab)[g] = word;
                     if (dec) reinterpret_cast<unsigned long long*>(dec)[g] = 0ull;
                 }
-            } else {
-                for (int i = 0; i < nx; ++i) {
-                    int v;
-                    if ((prev[w] >> i) & 1ull) {
-                        v = (int)(((p0[w] >> i) & 1ull) | (((p1[w] >> i) & 1ull) << 1) |
-                                  (((p2[w] >> i) & 1ull) << 2) | (((p3[w] >> i) & 1ull) << 3) |
-                                  (((p4[w] >> i) & 1ull) << 4));
-                    } else {
-                        v = -1;
-                    }
-                    lab[i] = (int8_t)v;
-                    if (dec) dec[i] = 0;
+                continue;
+            }
+            for (int i = 0; i < nx; ++i) {
+                int v;
+                if ((prev[w] >> i) & 1ull) {
+                    v = (int)(((p0[w] >> i) & 1ull) | (((p1[w] >> i) & 1ull) << 1) |
+                              (((p2[w] >> i) & 1ull) << 2) | (((p3[w] >> i) & 1ull) << 3) |
+                              (((p4[w] >> i) & 1ull) << 4));
+                } else {
+                    v = -1;
                 }
+                lab[i] = (int8_t)v;
+                if (dec) dec[i] = 0;
             }
         }
     }
@@ -888,7 +945,9 @@ hipError_t launch_classify(const Batch& b, hipStream_t st) {
 size_t label_lds_bytes(int Lmax, int tile_w, int Wmax) {
     const int RJ = kTileJ + 2 * Lmax, RK = kTileK + 2 * Lmax;
     const int RW = tile_w + 2 < Wmax ? tile_w + 2 : Wmax;
-    return sizeof(unsigned long long) * 2 * (size_t)RW * RJ * RK;
+    const size_t region = sizeof(unsigned long long) * 2 * (size_t)RW * RJ * RK;
+    const size_t rows = (size_t)256 * 64 * tile_w;   // transposed labels of a tile
+    return region > rows ? region : rows;
 }
 
 hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st) {

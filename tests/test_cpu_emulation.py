@@ -56,6 +56,7 @@ def _runs():
         "persistent_refused": (sphere, 0, PERSISTENT, ()),
         "statuses_batched": (trunc, 0, BATCHED, ()),
         "statuses_per_solid": (trunc, 0, PER_SOLID, ()),
+        "sphere64": (synth.sphere32(n=64, n_layers=3), 0, BATCHED, ()),
         "edge_sphere": (edges[0], 0, BATCHED, ()),
         "edge_ellipsoid": (edges[1], 0, BATCHED, ()),
     }
@@ -88,7 +89,8 @@ def _check(w, outs, precision):
 
 
 @pytest.mark.parametrize("name", ["sphere16", "ellipsoid24", "suspension3",
-                                  "suspension3_per_solid", "suspension3_fp32_graph"])
+                                  "suspension3_per_solid", "suspension3_fp32_graph",
+                                  "sphere64"])
 def test_emulated_kernels_match_oracle(emulated, name):
     w, prec, st, outs = emulated[name]
     assert st == 0
