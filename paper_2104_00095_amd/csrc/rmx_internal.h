@@ -11,7 +11,7 @@ constexpr int kTileJ = 16;                   // rows of a label tile along y
 constexpr int kTileK = 16;                   // rows of a label tile along z
 constexpr int kMaxTileW = 4;                 // 64-cell words of a label tile along x
 constexpr int kXcds = 8;                     // XCDs (workgroups are dealt round-robin)
-constexpr int kChunkWords = 32;              // mask words per classification chunk
+constexpr int kChunkWords = 16;              // mask words per classification chunk
 constexpr int kLT = kMaxLayers + 1;          // per-tile counts: interior, layers 1..16
 // Brick lists are split into buckets (tile t appends to bucket t % kBuckets) so that no
 // device-wide counter takes more than a few dozen atomic additions per call.

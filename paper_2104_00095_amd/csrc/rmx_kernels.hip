@@ -2,7 +2,7 @@
 // 2104.00095, section "Extrapolation of xi(x,t)"; SI "Weighting scheme for weighted least
 // squares-based extrapolation", eq. (weight)).  One call is a chain of L + 3 launches,
 // each covering every solid of the batch:
-//   k_classify  streams xi once (coalesced, nontemporal) and packs the interior predicate
+//   k_classify  streams xi once (coalesced) and packs the interior predicate
 //               phi0(xi) < 0 into a 1-bit mask (wave ballots); zeroes the call's counters.
 //   k_label     per 16 x 16-row tile: L bit-parallel dilations in LDS, each on the rows
 //               still able to reach the tile, give the layers (first dilation reaching a
@@ -28,19 +28,19 @@ using namespace dev;
 
 // ------------------------------------------------------------------------------------
 // Classification of mask words [wb, we) of solid d by the 4 waves of the block: each wave
-// streams its 8 consecutive 64-cell row segments, ballot-packs the interior predicate
-// and writes one mask word per segment.  Cells past the row end (x >= n0) are never
-// interior.
+// streams its 4 consecutive 64-cell row segments, ballot-packs the interior predicate
+// and writes one mask word per segment (the wave's words in one store).  Cells past the
+// row end (x >= n0) are never interior.
 //
 // Sphere: the components are read in turn, each only where the decision is still open,
 // which leaves it unchanged: the test is ((dx*dx + dy*dy) + dz*dz) < R*R, and in
 // round-to-nearest a sum of non-negative terms is never below any of its partial sums,
 // so dx*dx >= R*R, or dx*dx + dy*dy >= R*R, already means "not interior" (a non-finite
 // component fails its test as well, as in the full predicate).  The running sum is all a
-// lane keeps, so a wave issues each component's 8 loads at once.  Ellipsoid: the body
+// lane keeps, so a wave issues each component's 4 loads at once.  Ellipsoid: the body
 // coordinates need all three components, read together.
 // ------------------------------------------------------------------------------------
-constexpr int kWaveWords = kChunkWords / 4;   // 8 segments per wave (60 VGPRs: 8 waves per SIMD)
+constexpr int kWaveWords = kChunkWords / 4;   // 4 segments per wave
 constexpr int kSegE = 4;                       // ellipsoid: segments per batch
 
 __device__ __forceinline__ void classify_sphere(const DevSolid* dp, const ShapeR& sh, int wb,
@@ -63,7 +63,7 @@ __device__ __forceinline__ void classify_sphere(const DevSolid* dp, const ShapeR
         const int x = wx * 64 + lane;
         c[u] = (w0 + u < we && x < n0) ? row * n0 + x : -1;
         p[u] = __builtin_nan("");
-        if (c[u] >= 0) p[u] = __builtin_nontemporal_load(xi + c[u]);
+        if (c[u] >= 0) p[u] = xi[c[u]];
         if (++wx == W) {
             wx = 0;
             ++row;
@@ -77,18 +77,20 @@ __device__ __forceinline__ void classify_sphere(const DevSolid* dp, const ShapeR
 #pragma unroll
     for (int u = 0; u < kWaveWords; ++u) {
         double v = __builtin_nan("");
-        if (p[u] < T) v = __builtin_nontemporal_load(xi + ncell + c[u]);
+        if (p[u] < T) v = xi[ncell + c[u]];
         const double dy = v - sh.c1;
         p[u] = p[u] + dy * dy;
     }
+    unsigned long long mw = 0ull;   // lane u keeps mask word u
 #pragma unroll
     for (int u = 0; u < kWaveWords; ++u) {
         double v = __builtin_nan("");
-        if (p[u] < T) v = __builtin_nontemporal_load(xi + 2 * ncell + c[u]);
+        if (p[u] < T) v = xi[2 * ncell + c[u]];
         const double dz = v - sh.c2;
         const unsigned long long m = __ballot((p[u] + dz * dz) < T);
-        if (lane == 0 && w0 + u < we) mask[w0 + u] = m;
+        if (lane == u) mw = m;
     }
+    if (lane < kWaveWords && w0 + lane < we) mask[w0 + lane] = mw;   // one store
 }
 
 __device__ __forceinline__ void classify_ellipsoid(const DevSolid* dp, const ShapeR& sh,
