@@ -28,6 +28,7 @@ struct Plan {
     int normal_layers = 0;
     int tile_w = 1;
     int extrap_blocks = 1;
+    int normal_blocks = 1;
     size_t lds_bytes = 0;
     int64_t total_words = 0;
     int64_t total_cells = 0;

@@ -772,7 +772,8 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
                                              int bx, int by, int bz, double* s_phi,
                                              unsigned char* s_flag, int8_t* s_lab,
                                              uint16_t* s_list, int* s_wave) {
-    const int tid = threadIdx.x;
+    // re-derived per brick: the index math is not kept live across bricks
+    const int tid = opaque_lane_value(threadIdx.x);
     const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
     const int64_t nc = d->ncell;
     const int ox = kBrick * bx - 1, oy = kBrick * by - 1, oz = kBrick * bz - 1;
@@ -798,21 +799,37 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
         s_flag[r + kNSpan * kNSpan] = 1;
     }
     __syncthreads();
-    // compact the needed cells (four region cells per thread)
-    int cnt = 0;
+    // compact the needed cells: region cell q = tid + 256 h, by ballots (the list's order
+    // does not matter)
+    int total = 0;
+    {
+        const int lane = tid & 63, wid = tid >> 6;
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        unsigned long long bal[4];
+        int wsum = 0;
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        const int q = tid * 4 + h;
-        cnt += (q < kNCells && s_flag[q]) ? 1 : 0;
-    }
-    int excl, total;
-    block_scan<4>(cnt, excl, total, s_wave);
+        for (int h = 0; h < 4; ++h) {
+            const int q = tid + 256 * h;
+            bal[h] = __ballot(q < kNCells && s_flag[q]);
+            wsum += __popcll(bal[h]);
+        }
+        if (lane == 0) s_wave[wid] = wsum;
+        __syncthreads();
+        int pos = 0;
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        const int q = tid * 4 + h;
-        if (q < kNCells && s_flag[q]) s_list[excl++] = (uint16_t)q;
+        for (int i = 0; i < 4; ++i) {
+            const int t = s_wave[i];
+            if (i < wid) pos += t;
+            total += t;
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int q = tid + 256 * h;
+            if ((bal[h] >> lane) & 1ull) s_list[pos + __popcll(bal[h] & lt)] = (uint16_t)q;
+            pos += __popcll(bal[h]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // phi0 of each needed cell once (defined: inside the box with a finite xi)
     const ShapeR sh = load_shape(d);
     const double* __restrict__ f = d->xi_normal;
@@ -856,9 +873,7 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
         d->normals[2 * nc + cell] = g[2];
         nzero += (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0);
     }
-    int zx, ztot;
-    block_scan<4>(nzero, zx, ztot, s_wave);
-    if (tid == 0 && ztot) atomicAdd(st + ST_NONORMAL, (unsigned long long)ztot);
+    if (nzero) atomicAdd(st + ST_NONORMAL, (unsigned long long)nzero);   // rare
 }
 
 __global__ __launch_bounds__(256) void k_normal(Batch b) {

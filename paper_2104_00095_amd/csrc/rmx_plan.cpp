@@ -162,9 +162,14 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     // A tile lists at most 32 bricks per 64-cell word and layer (2 x 2 x 8).
     p->blist_cap = (int64_t)tiles * 32 * tw;
     p->normal_layers = std::min(opt->normal_layers, p->Lmax);
-    // Blocks striding over the brick lists.
+    // Blocks striding over the brick lists: no more than the bricks a list can hold (a
+    // layer's list holds each brick of the boxes at most once).
+    int64_t bricks = 0;
+    for (const DevSolid& d : p->solids) bricks += (int64_t)d.nbx * d.nby * d.nbz;
     const int eb = tune.extrap_blocks > 0 ? tune.extrap_blocks : 3 * std::max(cu, 1);
-    p->extrap_blocks = std::max(eb, 1);
+    p->extrap_blocks = (int)std::max<int64_t>(std::min<int64_t>(eb, bricks), 1);
+    p->normal_blocks = (int)std::max<int64_t>(
+        std::min<int64_t>(3 * std::max(cu, 1), bricks * std::max(p->normal_layers, 1)), 1);
 
     // Workspace layout.
     size_t off = 0;
@@ -289,7 +294,7 @@ hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,
     } while (0)
     RMX_TIMED(RMX_PHASE_CLASSIFY, launch_classify(b, st));
     RMX_TIMED(RMX_PHASE_LABEL, launch_label(b, p.lds_bytes, st));
-    RMX_TIMED(RMX_PHASE_NORMAL, launch_normal(b, p.extrap_blocks, st));
+    RMX_TIMED(RMX_PHASE_NORMAL, launch_normal(b, p.normal_blocks, st));
     for (int l = 1; l <= p.Lmax; ++l)
         RMX_TIMED(RMX_PHASE_EXTRAP + l - 1, launch_extrap(b, l, precision, p.extrap_blocks, st));
 #undef RMX_TIMED
