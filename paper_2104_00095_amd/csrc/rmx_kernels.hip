@@ -14,11 +14,11 @@
 //               the normals of the brick's cells of that layer by central differences, from
 //               the field before any write.
 //   k_extrap    one launch per layer, ascending: a block stages a listed brick with a
-//               halo of r_s (xi and labels, 12^3 cells) in LDS; a group of 4, 8 or 16
-//               lanes per cell of the layer (as many as keep the brick's cells in one pass)
-//               gathers the (2r+1)^3 box from LDS, accumulates the 4x4 normal-equation
-//               moments, reduces them by DPP moves, decides degeneracy by an exact
-//               integer determinant, solves by Cholesky in FP64 and writes xi_e.
+//               halo of r_s (xi and labels, 12^3 cells, one round trip) in LDS; a group
+//               of 4, 8 or 16 lanes per cell of the layer (as many as keep the brick's
+//               cells in one pass) gathers the (2r+1)^3 box from LDS, accumulates the 4x4
+//               normal-equation moments, reduces them by DPP moves, decides degeneracy by
+//               an exact integer determinant, solves by Cholesky in FP64 and writes xi_e.
 // The work is bandwidth- and latency-bound, with 4x4 systems per cell: no MFMA.
 #include "rmx_device.h"
 
@@ -649,9 +649,9 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
     const int8_t* __restrict__ labels = d->labels;
     const int ox = kBrick * bx - kBrickHalo, oy = kBrick * by - kBrickHalo,
               oz = kBrick * bz - kBrickHalo;
-    // Stage the labels of the 12^3 cells (outside the box: -1), then xi of the cells that
-    // can carry data for layer l (0 <= label < l); the others are staged as 0 and never
-    // enter a sum (their weight is selected to 0).
+    // Stage labels and xi of the 12^3 cells (outside the box: label -1, xi 0), every load
+    // issued together: one round trip.  Cells that cannot carry data for layer l (label
+    // outside [0, l)) enter no sum: their weight is selected to 0.
     constexpr int kH = (kBrickCells + 255) / 256;
 #pragma unroll
     for (int h = 0; h < kH; ++h) {
@@ -661,31 +661,25 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
         const int gx = ox + x, gy = oy + y, gz = oz + z;
         const bool in = q < kBrickCells && (unsigned)gx < (unsigned)n0 &&
                         (unsigned)gy < (unsigned)n1 && (unsigned)gz < (unsigned)n2;
-        const int lbv = in ? (int)labels[(gz * n1 + gy) * n0 + gx] : -1;
-        if (q < kBrickCells) sl[q] = (int8_t)lbv;
-    }
-#pragma unroll 1
-    for (int h = 0; h < kH; ++h) {
-        const int q = tid + 256 * h;
-        if (q >= kBrickCells) break;
-        const int lbv = sl[q];   // written by this thread above
-        const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
-                  z = q / (kBrickSpan * kBrickSpan);
-        const int c = ((oz + z) * n1 + (oy + y)) * n0 + (ox + x);
-        const bool use = lbv >= 0 && lbv < l;   // only cells inside the box
+        const int c = in ? (gz * n1 + gy) * n0 + gx : 0;
+        int lbv = -1;
         double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        if (use) {
+        if (in) {
+            lbv = labels[c];
             v0 = xi[c];
             v1 = xi[nc + c];
             v2 = xi[2 * nc + c];
         }
-        sx[q] = v0;
-        sx[kBrickCells + q] = v1;
-        sx[2 * kBrickCells + q] = v2;
+        if (q < kBrickCells) {
+            sl[q] = (int8_t)lbv;
+            sx[q] = v0;
+            sx[kBrickCells + q] = v1;
+            sx[2 * kBrickCells + q] = v2;
+        }
     }
     __syncthreads();
     // the layer-l cells of the brick interior, compacted
-    int mine[2], cnt = 0;
+    int mine[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int q = tid + 256 * h;
@@ -693,14 +687,25 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
                   z = kBrickHalo + q / (kBrick * kBrick);
         const int idx = (z * kBrickSpan + y) * kBrickSpan + x;
         mine[h] = sl[idx] == l ? idx : -1;
-        cnt += mine[h] >= 0;
     }
-    int excl, total;
-    block_scan<4>(cnt, excl, total, s_wave);
+    int total = 0;
+    {   // by ballots: wave sums, then each cell's place within its wave
+        const int lane = tid & 63, wid = tid >> 6;
+        const unsigned long long b0 = __ballot(mine[0] >= 0), b1 = __ballot(mine[1] >= 0);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        if (lane == 0) s_wave[wid] = __popcll(b0) + __popcll(b1);
+        __syncthreads();
+        int wb = 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-        if (mine[h] >= 0) cells[excl++] = (uint16_t)mine[h];
-    __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+            const int t = s_wave[i];
+            if (i < wid) wb += t;
+            total += t;
+        }
+        if (mine[0] >= 0) cells[wb + __popcll(b0 & lt)] = (uint16_t)mine[0];
+        if (mine[1] >= 0) cells[wb + __popcll(b0) + __popcll(b1 & lt)] = (uint16_t)mine[1];
+        __syncthreads();
+    }
 
     // lanes per cell: as many as keep every cell of the brick in one pass of the block
     if (total <= 256 / 16)
