@@ -33,10 +33,11 @@ struct Plan {
     int64_t total_words = 0;
     int64_t total_cells = 0;
     int64_t blist_cap = 0;
+    int64_t dlist_cap = 0;
     // workspace layout (byte offsets); [0, desc_bytes) is uploaded from the host
     size_t off_desc = 0, off_tile_solid = 0, desc_bytes = 0;
     size_t off_stats = 0, off_tile_cnt = 0, off_bcount = 0, off_mask = 0, off_normals = 0;
-    size_t off_blist = 0;
+    size_t off_blist = 0, off_dcount = 0, off_dlist = 0;
     size_t ws_bytes = 0;
     // red zones between regions (CPU emulation build only): (offset, bytes)
     std::vector<std::pair<size_t, size_t>> gaps;

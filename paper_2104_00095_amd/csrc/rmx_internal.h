@@ -85,6 +85,9 @@ struct Batch {
     unsigned long long* stats;  // [n_solids][kStatWords], zeroed by the classification
     int32_t* bcount;         // [kMaxLayers][kBuckets] bricks listed, zeroed likewise
     unsigned long long* blist;  // [Lmax][blist_cap]: solid << 32 | bz << 20 | by << 10 | bx
+    int64_t dlist_cap;       // dense brick-list entries per layer: the bricks of all boxes
+    int32_t* dcount;         // [kMaxLayers] bricks of each layer, written by the normal kernel
+    unsigned long long* dlist;  // [Lmax][dlist_cap]: each layer's bricks, contiguous
 };
 
 // Bucket b of a layer's brick list holds the bricks of tiles t = b (mod kBuckets), at

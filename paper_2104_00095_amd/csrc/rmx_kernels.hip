@@ -720,7 +720,8 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
 // ------------------------------------------------------------------------------------
 // Brick lists: the bucket counts of layers l0..l0+nl-1 form one prefix in LDS
 // (s_pref[0..nl*kBuckets]); entry e of the concatenation is found by bisection.  The
-// blocks of each XCD stride over a contiguous range of the entries.
+// normal kernel walks the bucketed lists this way and copies them into dense per-layer
+// lists for the fits.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int list_prefix(const Batch& b, int l0, int nl, int* s_pref,
                                            int* s_wave) {
@@ -909,9 +910,21 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
         if (tid < kLT) b.stats[(int64_t)s * kStatWords + tid] = s_acc[tid];
         __syncthreads();
     }
+    // Dense per-layer brick lists for the fits: entry e of the bucketed lists of layers
+    // 1..Lmax goes to its rank within its layer (bucket order), and each layer's count to
+    // dcount.  The prefix over all layers also serves the normals' layers 1..nl.
+    const int tot = list_prefix(b, 1, b.Lmax, s_pref, s_wave);
+    if (blockIdx.x == 0 && tid < b.Lmax)
+        b.dcount[tid] = s_pref[(tid + 1) * kBuckets] - s_pref[tid * kBuckets];
+    for (int e = blockIdx.x * 256 + tid; e < tot; e += gridDim.x * 256) {
+        int layer = 1;
+        const unsigned long long pk = list_entry(b, 1, b.Lmax, s_pref, e, &layer);
+        const int64_t i = e - s_pref[(layer - 1) * kBuckets];
+        if (i < b.dlist_cap) b.dlist[(int64_t)(layer - 1) * b.dlist_cap + i] = pk;
+    }
     const int nl = b.normal_layers;
     if (nl <= 0) return;
-    const int total = list_prefix(b, 1, nl, s_pref, s_wave);
+    const int total = s_pref[nl * kBuckets];
     const XcdRange rg = xcd_range(total);
     for (int e = rg.begin; e < rg.end; e += rg.stride) {
         int l = 0;
@@ -928,21 +941,22 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
     }
 }
 
-// One launch per layer: the blocks of each XCD stride over a contiguous range of the
-// layer's brick list.
+// One launch per layer over the layer's dense brick list (built by the normal kernel):
+// the blocks of each XCD stride over a contiguous range of it, so neighbouring bricks,
+// whose halos overlap, share one L2.
 template <typename T>
 __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
     HIP_DYNAMIC_SHARED(double, lds_d)
     unsigned char* lds = reinterpret_cast<unsigned char*>(lds_d);
     __shared__ int s_wave[4];
-    __shared__ int s_pref[kBuckets + 1];
     __shared__ double s_rlen[13];   // 1/|d| for |d|^2 = 0..12 (radius 2)
     if (threadIdx.x < 13) s_rlen[threadIdx.x] = c_rlen[threadIdx.x];
-    const int count = list_prefix(b, l, 1, s_pref, s_wave);
+    const unsigned long long* dl = b.dlist + (int64_t)(l - 1) * b.dlist_cap;
+    const int count = uniform_int((int)min((int64_t)b.dcount[l - 1], b.dlist_cap));
+    __syncthreads();   // s_rlen
     const XcdRange rg = xcd_range(count);
     for (int e = rg.begin; e < rg.end; e += rg.stride) {
-        int ll = 0;
-        const unsigned long long pk = list_entry(b, l, 1, s_pref, e, &ll);
+        const unsigned long long pk = dl[e];
         const int s = uniform_int((int)(pk >> 32));
         const int bx = uniform_int((int)(pk & 1023ull));
         const int by = uniform_int((int)((pk >> 10) & 1023ull));

@@ -168,6 +168,7 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     for (const DevSolid& d : p->solids) bricks += (int64_t)d.nbx * d.nby * d.nbz;
     const int eb = tune.extrap_blocks > 0 ? tune.extrap_blocks : 3 * std::max(cu, 1);
     p->extrap_blocks = (int)std::max<int64_t>(std::min<int64_t>(eb, bricks), 1);
+    p->dlist_cap = std::max<int64_t>(bricks, 1);
     p->normal_blocks = (int)std::max<int64_t>(
         std::min<int64_t>(3 * std::max(cu, 1), bricks * std::max(p->normal_layers, 1)), 1);
 
@@ -192,6 +193,11 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     p->off_blist = off;
     off = next_region(p, off, sizeof(unsigned long long) * (size_t)std::max(p->Lmax, 1) *
                                   (size_t)p->blist_cap);
+    p->off_dcount = off;
+    off = next_region(p, off, sizeof(int32_t) * kMaxLayers);
+    p->off_dlist = off;
+    off = next_region(p, off, sizeof(unsigned long long) * (size_t)std::max(p->Lmax, 1) *
+                                  (size_t)p->dlist_cap);
     p->ws_bytes = off;
     return RMX_OK;
 }
@@ -224,6 +230,9 @@ void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
     b->tile_cnt = reinterpret_cast<int32_t*>(base + p->off_tile_cnt);
     b->bcount = reinterpret_cast<int32_t*>(base + p->off_bcount);
     b->blist = reinterpret_cast<unsigned long long*>(base + p->off_blist);
+    b->dlist_cap = p->dlist_cap;
+    b->dcount = reinterpret_cast<int32_t*>(base + p->off_dcount);
+    b->dlist = reinterpret_cast<unsigned long long*>(base + p->off_dlist);
 }
 
 void pack_desc(const Plan& p, void* host) {

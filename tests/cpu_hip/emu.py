@@ -34,7 +34,7 @@ def build(sanitize=True):
 
 
 def run(w, tmpdir, r_s=2, r_max=4, normal_layers=2, precision=0, flags=0, reps=1,
-        xi_normal=None, timeout=600, pre_flags=()):
+        xi_normal=None, timeout=600, pre_flags=(), cus=None):
     """Write workload `w` to tmpdir, run the emulated library, return
     (status, [(xi_out, labels, decisions, stats_raw)])."""
     os.makedirs(tmpdir, exist_ok=True)
@@ -63,6 +63,8 @@ def run(w, tmpdir, r_s=2, r_max=4, normal_layers=2, precision=0, flags=0, reps=1
         os.remove(pre)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1")
+    if cus is not None:   # compute units the emulated device reports
+        env["RMX_EMU_CUS"] = str(int(cus))
     subprocess.run([build(), tmpdir], check=True, timeout=timeout, env=env)
     st = int(open(os.path.join(tmpdir, "status.txt")).read())
     outs = []

@@ -148,7 +148,9 @@ hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipDeviceSynchronize() { return hipSuccess; }
 hipError_t hipGetLastError() { return hipSuccess; }
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
-    *v = a == hipDeviceAttributeMaxSharedMemoryPerBlock ? 160 * 1024 : 1;
+    // compute units: 1, or RMX_EMU_CUS (to exercise grids spread over several XCDs)
+    const char* cus = std::getenv("RMX_EMU_CUS");
+    *v = a == hipDeviceAttributeMaxSharedMemoryPerBlock ? 160 * 1024 : (cus ? std::atoi(cus) : 1);
     return hipSuccess;
 }
 hipError_t hipMalloc(void** p, size_t n) {

@@ -44,13 +44,15 @@ def _runs():
     susp = synth.suspension(n_solids=3, grid_n=(24, 24, 40), h=1 / 24)
     edges = edge_workloads()
     trunc = _truncation_batch()
-    # name: (workload, precision, flags, calls made first on the same context)
+    # name: (workload, precision, flags, calls made first on the same context[, CUs])
     return {
         "sphere16": (sphere, 0, BATCHED, ()),
         "ellipsoid24": (ell, 0, BATCHED, ()),
         "suspension3": (susp, 0, BATCHED, ()),
         "suspension3_per_solid": (susp, 0, PER_SOLID, ()),
         "suspension3_fp32_graph": (susp, 1, GRAPH, ()),
+        # 5 CUs: 15 fit blocks over 8 XCDs, two blocks on some and one on others
+        "suspension3_cus5": (susp, 0, BATCHED, (), 5),
         "repeated_calls": (susp, 0, BATCHED, (BATCHED, GRAPH, BATCHED)),
         "autotune_then_call": (sphere, 0, BATCHED, (AUTOTUNE,)),
         "persistent_refused": (sphere, 0, PERSISTENT, ()),
@@ -68,9 +70,9 @@ def emulated():
     root = tempfile.mkdtemp(prefix="rmx_emu_")
 
     def one(item):
-        name, (w, prec, flags, pre) = item
+        name, (w, prec, flags, pre, *cus) = item
         st, outs = emu.run(w, os.path.join(root, name), precision=prec, flags=flags,
-                           pre_flags=pre)
+                           pre_flags=pre, cus=cus[0] if cus else None)
         return name, (w, prec, st, outs)
 
     with ThreadPoolExecutor(max_workers=4) as ex:
@@ -90,7 +92,7 @@ def _check(w, outs, precision):
 
 @pytest.mark.parametrize("name", ["sphere16", "ellipsoid24", "suspension3",
                                   "suspension3_per_solid", "suspension3_fp32_graph",
-                                  "sphere64"])
+                                  "suspension3_cus5", "sphere64"])
 def test_emulated_kernels_match_oracle(emulated, name):
     w, prec, st, outs = emulated[name]
     assert st == 0
