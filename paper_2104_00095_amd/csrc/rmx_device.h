@@ -488,61 +488,5 @@ __device__ __forceinline__ void normal_at(const ShapeR& sh, const double* __rest
     }
 }
 
-// Weighted moments from one (weight, offset, centred value) datum.
-template <typename T>
-__device__ __forceinline__ void add_datum(Moments<T>& acc, T tw, int dx, int dy, int dz,
-                                          T v0, T v1, T v2, bool counted) {
-    const T fx = (T)dx, fy = (T)dy, fz = (T)dz;
-    const T wx = tw * fx, wy = tw * fy, wz = tw * fz;
-    acc.m[0] += tw;
-    acc.m[1] += wx;
-    acc.m[2] += wy;
-    acc.m[3] += wz;
-    acc.m[4] += wx * fx;
-    acc.m[5] += wx * fy;
-    acc.m[6] += wx * fz;
-    acc.m[7] += wy * fy;
-    acc.m[8] += wy * fz;
-    acc.m[9] += wz * fz;
-    acc.r[0] += tw * v0;
-    acc.r[1] += tw * v1;
-    acc.r[2] += tw * v2;
-    acc.r[3] += wx * v0;
-    acc.r[4] += wx * v1;
-    acc.r[5] += wx * v2;
-    acc.r[6] += wy * v0;
-    acc.r[7] += wy * v1;
-    acc.r[8] += wy * v2;
-    acc.r[9] += wz * v0;
-    acc.r[10] += wz * v1;
-    acc.r[11] += wz * v2;
-    const int ce = counted ? 1 : 0;
-    acc.g[0] += ce * (1 + ((dx * dx) << 16));
-    acc.g[1] += ce * (dx + ((dx * dy) << 16));
-    acc.g[2] += ce * (dy + ((dx * dz) << 16));
-    acc.g[3] += ce * (dz + ((dy * dy) << 16));
-    acc.g[4] += ce * ((dy * dz) + ((dz * dz) << 16));
-}
-
-// Weight of offset (dx, dy, dz) per eq. (weight); false if it is zero (ineligible or in
-// front of the interface).  The sign test is the exact expression
-// (dx gx + dy gy) + dz gz < 0, without contraction.
-__device__ __forceinline__ bool weight_of(int dx, int dy, int dz, bool use_normal, double g0,
-                                          double g1, double g2, double rgn, double& w) {
-    double ww = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
-    if (use_normal) {
-#pragma clang fp contract(off)
-        const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
-        const double dot = (fx * g0 + fy * g1) + fz * g2;
-        if (!(dot < 0.0)) {
-            w = 0.0;
-            return false;
-        }
-        ww = (-dot * c_rlen[dx * dx + dy * dy + dz * dz] * rgn) * ww;
-    }
-    w = ww;
-    return true;
-}
-
 }  // namespace dev
 }  // namespace rmx

@@ -105,10 +105,6 @@ inline T __shfl_up(T v, int o, int width = 64) {
     rmx_emu::group_done(width);
     return r;
 }
-struct alignas(16) double2 {
-    double x, y;
-};
-inline double2 make_double2(double a, double b) { return double2{a, b}; }
 inline long long __double_as_longlong(double v) { return rmx_emu_from<long long>(rmx_emu_bits(v)); }
 inline double __longlong_as_double(long long v) { return rmx_emu_from<double>(rmx_emu_bits(v)); }
 inline int __float_as_int(float v) { return rmx_emu_from<int>(rmx_emu_bits(v)); }
@@ -128,17 +124,6 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int, int, boo
     (void)old;
     return r;
 }
-// LDS-DMA copy: each lane of the wave writes its `size` bytes (one dword, or three or four
-// consecutive dwords) at lds + off + lane * size, the wave's lanes consecutively.  Other
-// sizes are refused.  Done at once: the emulated wait and barrier that follow find it
-// complete.
-template <typename P>
-inline void __builtin_amdgcn_global_load_lds(const void* g, P lds, unsigned size, int off, int) {
-    if (size != 4 && size != 12 && size != 16) std::abort();
-    unsigned char* p = reinterpret_cast<unsigned char*>((uintptr_t)lds);
-    std::memcpy(p + off + (threadIdx.x % 64) * size, g, size);
-}
-inline void __builtin_amdgcn_s_waitcnt(int) {}
 inline int __builtin_amdgcn_readfirstlane(int v) {
     uint64_t* s = rmx_emu::group_exchange((uint64_t)(uint32_t)v, 64);
     const int r = (int)(uint32_t)s[0];
@@ -206,8 +191,6 @@ hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t* 
 hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
 hipError_t hipGraphExecDestroy(hipGraphExec_t e);
 hipError_t hipGraphDestroy(hipGraph_t g);
-enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize };
-inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
 namespace rmx_emu {
 // Blocks run one after another (static __shared__ variables are one copy); the threads
 // of a block run concurrently.
