@@ -6,10 +6,11 @@
 //               phi0(xi) < 0 into a 1-bit mask (wave ballots); zeroes the call's counters.
 //   k_label     per 16 x 16-row tile: L bit-parallel dilations in LDS, each on the rows
 //               still able to reach the tile, give the layers (first dilation reaching a
-//               cell = its layer), written as int8 labels; the
-//               tile counts its interior and band cells, detects a band truncated by a box
-//               face, and lists the 8^3 bricks holding cells of each layer.
-//   k_normal    sums the tile counts per solid; per listed brick of layers
+//               cell = its layer), written as int8 labels; the tile counts its interior
+//               and band cells, detects a band truncated by a box face, and lists the 8^3
+//               bricks holding cells of each layer (64 buckets per layer).
+//   k_normal    sums the tile counts per solid; copies each layer's bucketed brick list
+//               into a dense list with its count; per listed brick of layers
 //               1..normal_layers, evaluates phi0(xi) once per needed cell (LDS) and forms
 //               the normals of the brick's cells of that layer by central differences, from
 //               the field before any write.
