@@ -103,12 +103,38 @@ KERNEL_SOURCES = ("paper_2104_00095_amd/csrc/rmx_kernels.hip",
                   "paper_2104_00095_amd/csrc/rmx_internal.h")
 
 
+def _code_only(text):
+    """Source text without comments and whitespace (string and character literals kept):
+    what changes the compiled kernels."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            if not c.isspace():
+                out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def kernel_source_hash():
+    """SHA-256 of the kernel sources' code (comments and whitespace ignored)."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
@@ -116,7 +142,7 @@ def committed_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE counters, each scaled
     by the same counter on a plain device copy of known size) from the committed summary
     profiles/<kernel>_<workload>_counters.md, if it was taken on the current kernel
-    sources; else None."""
+    code; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
@@ -413,8 +439,8 @@ def main():
                          "scaling the FETCH_SIZE / WRITE_SIZE counters) and print its rate")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(solids are independent; the sharding design is in DESIGN.md).",
+        print("bench.py measures one GPU: there is no multi-GPU path (solids are "
+              "independent, so a batch would split by solid across GPUs with no exchange).",
               file=sys.stderr)
         sys.exit(2)
 
