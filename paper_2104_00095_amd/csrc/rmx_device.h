@@ -68,6 +68,67 @@ __device__ __forceinline__ double pick3(int i, double a, double b, double c) {
     return i == 0 ? a : (i == 1 ? b : c);
 }
 
+// |x| within [2^-200, 2^200] (false for 0, NaN and infinities).
+__device__ __forceinline__ bool mid_range(double x) {
+    const double a = fabs(x);
+    return a >= 0x1p-200 && a <= 0x1p200;
+}
+
+// a / b, correctly rounded, for a and b of mid_range magnitude: the reciprocal refined by
+// two Newton steps, then one residual correction.  These are the steps of the hardware's
+// division sequence, whose scale and fix-up steps change nothing for such operands (no
+// exponent near an overflow or underflow bound, quotient within 2^+-400).  Written out,
+// the divisions of one bisection step no longer wait on each other for the single
+// condition register that the sequence's scale and fused-multiply-add steps share.
+__device__ __forceinline__ double div_mid(double a, double b) {
+    const double y0 = __builtin_amdgcn_rcp(b);
+    const double y1 = fma(y0, fma(-b, y0, 1.0), y0);
+    const double y2 = fma(y1, fma(-b, y1, 1.0), y1);
+    const double q = a * y2;
+    return fma(fma(-b, q, a), y2, q);
+}
+
+// Bisection of the multiplier on [s0, s1] until the midpoint equals an end of the bracket
+// (or the function is exactly 0, or not a number); w_i: coordinate i is non-zero.
+struct Bracket {
+    double s0, s1;
+};
+template <bool kMid>
+__device__ __forceinline__ Bracket ellipsoid_bisect(double c0, double c1, double c2, double d0,
+                                                    double d1, double d2, bool w0, bool w1,
+                                                    bool w2, double s0, double s1) {
+#pragma clang fp contract(off)
+    for (int it = 0; it < 4096; ++it) {
+        const double sm = 0.5 * (s0 + s1);
+        if (sm <= s0 || sm >= s1) break;
+        double f = 0.0;
+        if (kMid) {
+            // all three quotients at once (a term of a zero coordinate is formed and
+            // dropped); f >= +0 throughout, so adding +0 for it changes nothing
+            const double t0 = div_mid(c0, sm + d0), t1 = div_mid(c1, sm + d1),
+                         t2 = div_mid(c2, sm + d2);
+            f = f + (w0 ? t0 * t0 : 0.0);
+            f = f + (w1 ? t1 * t1 : 0.0);
+            f = f + (w2 ? t2 * t2 : 0.0);
+        } else {
+            if (w0) { const double t = c0 / (sm + d0); f = f + t * t; }
+            if (w1) { const double t = c1 / (sm + d1); f = f + t * t; }
+            if (w2) { const double t = c2 / (sm + d2); f = f + t * t; }
+        }
+        f = f - 1.0;
+        if (f > 0.0) {
+            s0 = sm;
+        } else if (f < 0.0) {
+            s1 = sm;
+        } else {
+            s0 = sm;
+            s1 = sm;
+            break;
+        }
+    }
+    return {s0, s1};
+}
+
 // Distance from body point y to the ellipsoid with semi-axes e: Lagrange multiplier of
 // the closest point measured from the pole of the shortest axis among the non-zero
 // coordinates, bisected until the midpoint equals an end of the bracket; the off-plane
@@ -118,24 +179,17 @@ __device__ inline double ellipsoid_distance(double e0, double e1, double e2, dou
     if (u2 > 0.0) { const double p = e2 * u2; sq = sq + p * p; }
     double s0 = em * pick3(m, u0, u1, u2);
     double s1 = sqrt(sq);
-    for (int it = 0; it < 4096; ++it) {
-        const double sm = 0.5 * (s0 + s1);
-        if (sm <= s0 || sm >= s1) break;
-        double f = 0.0;
-        if (u0 > 0.0) { const double t = (e0 * u0) / (sm + d0); f = f + t * t; }
-        if (u1 > 0.0) { const double t = (e1 * u1) / (sm + d1); f = f + t * t; }
-        if (u2 > 0.0) { const double t = (e2 * u2) / (sm + d2); f = f + t * t; }
-        f = f - 1.0;
-        if (f > 0.0) {
-            s0 = sm;
-        } else if (f < 0.0) {
-            s1 = sm;
-        } else {
-            s0 = sm;
-            s1 = sm;
-            break;
-        }
-    }
+    // Every midpoint lies in [s0, s1], so (rounding being monotone) every denominator
+    // sm + d_i (d_i >= 0 where u_i > 0) lies between s0 + d_i and s1 + d_i.
+    const double c0 = e0 * u0, c1 = e1 * u1, c2 = e2 * u2;
+    const bool w0 = u0 > 0.0, w1 = u1 > 0.0, w2 = u2 > 0.0;
+    const bool mid = (!w0 || (mid_range(c0) && mid_range(s0 + d0) && mid_range(s1 + d0))) &&
+                     (!w1 || (mid_range(c1) && mid_range(s0 + d1) && mid_range(s1 + d1))) &&
+                     (!w2 || (mid_range(c2) && mid_range(s0 + d2) && mid_range(s1 + d2)));
+    const Bracket br = mid ? ellipsoid_bisect<true>(c0, c1, c2, d0, d1, d2, w0, w1, w2, s0, s1)
+                           : ellipsoid_bisect<false>(c0, c1, c2, d0, d1, d2, w0, w1, w2, s0, s1);
+    s0 = br.s0;
+    s1 = br.s1;
     const double s = 0.5 * (s0 + s1);
     double D = 0.0;
     {

@@ -169,8 +169,10 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     const int eb = tune.extrap_blocks > 0 ? tune.extrap_blocks : 3 * std::max(cu, 1);
     p->extrap_blocks = (int)std::max<int64_t>(std::min<int64_t>(eb, bricks), 1);
     p->dlist_cap = std::max<int64_t>(bricks, 1);
+    // normal: blocks go through their bricks' ellipsoid bisections one at a time, so more
+    // resident blocks than the fits use, and the dispatcher balances the bricks' costs
     p->normal_blocks = (int)std::max<int64_t>(
-        std::min<int64_t>(3 * std::max(cu, 1), bricks * std::max(p->normal_layers, 1)), 1);
+        std::min<int64_t>(8 * std::max(cu, 1), bricks * std::max(p->normal_layers, 1)), 1);
 
     // Workspace layout.
     size_t off = 0;
