@@ -94,3 +94,24 @@ def edge_workloads(seed=11, n=16, n_layers=3):
         w.solids.append(synth.Solid((0, 0, 0), (n, n, n), shape, n_layers, xi))
         out.append(w)
     return out
+
+
+def axis_plane_workload(n=24, n_layers=3):
+    """An axis-aligned ellipsoid centred at the origin with xi = (index - n/2) h: body
+    coordinates are exactly 0 on the three centre planes, and +-1e-230 on half of two of
+    them.  The distance's bisection then runs with zero coordinates and with coordinates far
+    below 2^-200, the two cases where a quotient term is dropped or takes the plain
+    division."""
+    h = 1.0 / n
+    t = (np.arange(n) - n // 2) * h
+    xi = np.empty((3, n, n, n))
+    xi[0] = t[None, None, :]
+    xi[1] = t[None, :, None]
+    xi[2] = t[:, None, None]
+    m = n // 2
+    xi[2, m, :, :m] = 1e-230
+    xi[1, :, m, m:] = -1e-230
+    shape = synth.ellipsoid_shape(np.zeros(3), [0.3, 0.2, 0.25], np.eye(3))
+    w = synth.Workload("axis_planes", (n, n, n), h, (0.0, 0.0, 0.0))
+    w.solids.append(synth.Solid((0, 0, 0), (n, n, n), shape, n_layers, xi))
+    return w

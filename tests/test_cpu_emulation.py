@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
-from tests.helpers import edge_workloads, rel_err, run_oracle
+from tests.helpers import axis_plane_workload, edge_workloads, rel_err, run_oracle
 
 emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
@@ -61,6 +61,7 @@ def _runs():
         "sphere64": (synth.sphere32(n=64, n_layers=3), 0, BATCHED, ()),
         "edge_sphere": (edges[0], 0, BATCHED, ()),
         "edge_ellipsoid": (edges[1], 0, BATCHED, ()),
+        "axis_planes": (axis_plane_workload(), 0, BATCHED, ()),
     }
 
 
@@ -128,9 +129,10 @@ def test_emulated_statuses(emulated, name):
     _check(w, outs, prec)
 
 
-@pytest.mark.parametrize("name", ["edge_sphere", "edge_ellipsoid"])
+@pytest.mark.parametrize("name", ["edge_sphere", "edge_ellipsoid", "axis_planes"])
 def test_emulated_nonfinite_and_boundary(emulated, name):
-    """Classification edge cases against the oracle: NaN and infinite components, cells
-    exactly on |xi - c|^2 = R^2 or on an axis; a sphere and a rotated ellipsoid."""
+    """Edge cases against the oracle: NaN and infinite components, cells exactly on
+    |xi - c|^2 = R^2 or on an axis (a sphere and a rotated ellipsoid); body coordinates
+    exactly 0 or +-1e-230 in the cells whose distance the normals need."""
     w, prec, st, outs = emulated[name]
     _check(w, outs, prec)

@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 from paper_2104_00095_amd import synth
-from tests.helpers import edge_workloads, oracle_problem, rel_err, run_oracle
+from tests.helpers import (axis_plane_workload, edge_workloads, oracle_problem, rel_err,
+                           run_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -249,6 +250,16 @@ def test_nonfinite_and_boundary(ctx, mode):
     for w in edge_workloads():
         st, gpu = run_gpu(ctx, w, 0, flags=MODES[mode])
         compare(w, gpu, 0, tag="edge")
+
+
+@pytest.mark.parametrize("mode", MODE_PARAMS)
+def test_ellipsoid_axis_planes(ctx, mode):
+    """Body coordinates exactly 0 and far below 2^-200 in the cells whose phi0 the normals
+    need: the bisection's dropped terms and its plain-division path."""
+    w = axis_plane_workload()
+    st, gpu = run_gpu(ctx, w, 0, flags=MODES[mode])
+    assert st == 0
+    compare(w, gpu, 0, tag="axis_planes")
 
 
 def test_persistent_launch_refused(ctx):
