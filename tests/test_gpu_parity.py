@@ -115,6 +115,19 @@ def test_suspension_batched_full(ctx, precision, mode):
     print("suspension rel err", compare(w, gpu, precision, tag="susp"))
 
 
+@pytest.mark.parametrize("seed", range(31, 39))
+def test_small_suspensions(ctx, seed):
+    """Eight random batches of 8 small ellipsoids (semi-axes 2-5 cells, arbitrary
+    rotations), L from 2 to 5, FP64 and FP32-accumulate in turn: strongly curved bands for
+    the distance, the normals and the rank tests."""
+    w = synth.suspension(seed=seed, n_solids=8, grid_n=(48, 48, 64), h=1 / 48,
+                         n_layers=2 + seed % 4)
+    precision = seed % 2
+    st, gpu = run_gpu(ctx, w, precision)
+    assert st == 0
+    compare(w, gpu, precision, tag=f"small_susp{seed}")
+
+
 @pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("precision", [0, 1])
 def test_cavity256_full(ctx, precision, mode):
