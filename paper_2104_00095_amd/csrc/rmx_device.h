@@ -88,8 +88,47 @@ __device__ __forceinline__ double div_mid(double a, double b) {
     return fma(fma(-b, q, a), y2, q);
 }
 
+// f(s) = sum over the non-zero coordinates of (c_i / (s + d_i))^2, minus 1, in the
+// bisection's arithmetic.
+template <bool kMid>
+__device__ __forceinline__ double ell_f(double sm, double c0, double c1, double c2, double d0,
+                                        double d1, double d2, bool w0, bool w1, bool w2) {
+#pragma clang fp contract(off)
+    double f = 0.0;
+    if (kMid) {
+        // all three quotients at once (a term of a zero coordinate is formed and dropped);
+        // f >= +0 throughout, so adding +0 for it changes nothing
+        const double t0 = div_mid(c0, sm + d0), t1 = div_mid(c1, sm + d1),
+                     t2 = div_mid(c2, sm + d2);
+        f = f + (w0 ? t0 * t0 : 0.0);
+        f = f + (w1 ? t1 * t1 : 0.0);
+        f = f + (w2 ? t2 * t2 : 0.0);
+    } else {
+        if (w0) { const double t = c0 / (sm + d0); f = f + t * t; }
+        if (w1) { const double t = c1 / (sm + d1); f = f + t * t; }
+        if (w2) { const double t = c2 / (sm + d2); f = f + t * t; }
+    }
+    return f - 1.0;
+}
+
+// 1/x to a few ulps: the hardware reciprocal and one Newton step.
+__device__ __forceinline__ double rcp_refined(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 // Bisection of the multiplier on [s0, s1] until the midpoint equals an end of the bracket
-// (or the function is exactly 0, or not a number); w_i: coordinate i is non-zero.
+// (or f is exactly 0, or not a number); w_i: coordinate i is non-zero.
+//
+// The computed f is non-increasing in s on [s0, s1]: each operation is correctly rounded
+// and monotone in its operands there (s + d_i, d_i >= 0, grows with s; c_i / x with
+// c_i >= 0 shrinks as x > 0 grows; t * t for t >= 0 and the sums grow with their
+// operands).  So once f(a) > 0 has been computed, every midpoint sm <= a has f(sm) > 0
+// and moves s0 without an evaluation; likewise sm >= b once f(b) < 0.  The midpoints, and
+// so the final bracket, are those of evaluating every step.  a and b lie 2^-44 (relative)
+// either side of a few Newton steps on g(s) = F(s)^(-1/2) - 1 (F = f + 1, close to
+// linear in s), taken in approximate arithmetic; each is used only once its own f has
+// the needed sign.
 struct Bracket {
     double s0, s1;
 };
@@ -98,24 +137,32 @@ __device__ __forceinline__ Bracket ellipsoid_bisect(double c0, double c1, double
                                                     double d1, double d2, bool w0, bool w1,
                                                     bool w2, double s0, double s1) {
 #pragma clang fp contract(off)
+    double s = s0;
+    for (int k = 0; k < 6; ++k) {
+        double F = 0.0, G = 0.0;   // F = sum t_i^2, G = sum t_i^2 / (s + d_i)
+        if (w0) { const double y = rcp_refined(s + d0), t = c0 * y; F = F + t * t; G = G + (t * t) * y; }
+        if (w1) { const double y = rcp_refined(s + d1), t = c1 * y; F = F + t * t; G = G + (t * t) * y; }
+        if (w2) { const double y = rcp_refined(s + d2), t = c2 * y; F = F + t * t; G = G + (t * t) * y; }
+        double r = __builtin_amdgcn_rsq(F);
+        r = r * (1.5 - (0.5 * F) * (r * r));                   // F^(-1/2)
+        const double step = (r - 1.0) * rcp_refined(G * (r * r * r));   // g / g'
+        s = fmin(fmax(s - step, s0), s1);                      // (a NaN step leaves s0 or s1)
+    }
+    const double pa = fmax(s * (1.0 - 0x1p-44), s0), pb = fmin(s * (1.0 + 0x1p-44), s1);
+    const double a = ell_f<kMid>(pa, c0, c1, c2, d0, d1, d2, w0, w1, w2) > 0.0
+                         ? pa : -__builtin_huge_val();
+    const double b = ell_f<kMid>(pb, c0, c1, c2, d0, d1, d2, w0, w1, w2) < 0.0
+                         ? pb : __builtin_huge_val();
     for (int it = 0; it < 4096; ++it) {
         const double sm = 0.5 * (s0 + s1);
         if (sm <= s0 || sm >= s1) break;
-        double f = 0.0;
-        if (kMid) {
-            // all three quotients at once (a term of a zero coordinate is formed and
-            // dropped); f >= +0 throughout, so adding +0 for it changes nothing
-            const double t0 = div_mid(c0, sm + d0), t1 = div_mid(c1, sm + d1),
-                         t2 = div_mid(c2, sm + d2);
-            f = f + (w0 ? t0 * t0 : 0.0);
-            f = f + (w1 ? t1 * t1 : 0.0);
-            f = f + (w2 ? t2 * t2 : 0.0);
-        } else {
-            if (w0) { const double t = c0 / (sm + d0); f = f + t * t; }
-            if (w1) { const double t = c1 / (sm + d1); f = f + t * t; }
-            if (w2) { const double t = c2 / (sm + d2); f = f + t * t; }
-        }
-        f = f - 1.0;
+        double f;
+        if (sm <= a)
+            f = 1.0;    // f(sm) >= f(a) > 0
+        else if (sm >= b)
+            f = -1.0;   // f(sm) <= f(b) < 0
+        else
+            f = ell_f<kMid>(sm, c0, c1, c2, d0, d1, d2, w0, w1, w2);
         if (f > 0.0) {
             s0 = sm;
         } else if (f < 0.0) {

@@ -127,6 +127,7 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int, int, boo
 // Reciprocal: the hardware's is approximate; the quotient it seeds is refined to the
 // correctly rounded one, so an exact reciprocal serves.
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
+inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
 inline int __builtin_amdgcn_readfirstlane(int v) {
     uint64_t* s = rmx_emu::group_exchange((uint64_t)(uint32_t)v, 64);
     const int r = (int)(uint32_t)s[0];
