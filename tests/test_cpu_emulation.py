@@ -59,6 +59,10 @@ def _runs():
         "statuses_batched": (trunc, 0, BATCHED, ()),
         "statuses_per_solid": (trunc, 0, PER_SOLID, ()),
         "sphere64": (synth.sphere32(n=64, n_layers=3), 0, BATCHED, ()),
+        # 64 CUs: 125 fit blocks for a few dozen bricks per layer (most blocks find no
+        # brick of their own)
+        "ellipsoid40_cus64": (synth.ellipsoid128(n=40, n_layers=4), 0, BATCHED, (), 64),
+        "ellipsoid40_cus64_fp32": (synth.ellipsoid128(n=40, n_layers=4), 1, BATCHED, (), 64),
         "edge_sphere": (edges[0], 0, BATCHED, ()),
         "edge_ellipsoid": (edges[1], 0, BATCHED, ()),
         "axis_planes": (axis_plane_workload(), 0, BATCHED, ()),
@@ -93,7 +97,8 @@ def _check(w, outs, precision):
 
 @pytest.mark.parametrize("name", ["sphere16", "ellipsoid24", "suspension3",
                                   "suspension3_per_solid", "suspension3_fp32_graph",
-                                  "suspension3_cus5", "sphere64"])
+                                  "suspension3_cus5", "sphere64", "ellipsoid40_cus64",
+                                  "ellipsoid40_cus64_fp32"])
 def test_emulated_kernels_match_oracle(emulated, name):
     w, prec, st, outs = emulated[name]
     assert st == 0
