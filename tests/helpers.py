@@ -115,3 +115,32 @@ def axis_plane_workload(n=24, n_layers=3):
     w = synth.Workload("axis_planes", (n, n, n), h, (0.0, 0.0, 0.0))
     w.solids.append(synth.Solid((0, 0, 0), (n, n, n), shape, n_layers, xi))
     return w
+
+
+def plates_workload(a=4, gap=3, p=0.3, q=0.7, n_layers=2):
+    """Two one-cell-thick interior plates, at x = a and x = a + gap, spanning the whole
+    13 x 9 x 9 box in y and z.  Plate cells hold xi = (p or q, (j - 4)^2, 0) and are
+    interior for a sphere of radius 1000 at the origin; every other cell is undefined
+    (NaN), so the band is labelled by distance along x only.  The separate normal field
+    xi_normal = (500 + i/4, 0, 0) has phi0 = i/4 - 500 exactly, so every band cell's normal
+    is g = (1/4, 0, 0): a datum carries the normal factor only where dx < 0.
+
+    Returns (workload, xi_normal).  With the paper's options (r_s = 2, r_max = 4, normal
+    factor on layers <= 2) the layer-1 cells on the row (j, k) = (4, 4) take these paths:
+      x = a - 1, a + 1, a + 2: the positive-weight data lie on one plate (or none) at every
+        radius -> F1 (kernel weights only, radius 4), data on both plates;
+      x = a + gap + 1: positive-weight data on plate b (dx = -1) and, from radius 4 on,
+        plate a (dx = -4) -> fitted with the normal factor at radius 4."""
+    n0, n1, n2 = 13, 9, 9
+    xi = np.full((3, n2, n1, n0), np.nan)
+    jj = np.arange(n1, dtype=np.float64)
+    for x, v in ((a, p), (a + gap, q)):
+        xi[0, :, :, x] = v
+        xi[1, :, :, x] = ((jj - 4.0) ** 2)[None, :]
+        xi[2, :, :, x] = 0.0
+    xn = np.zeros((3, n2, n1, n0))
+    xn[0] = (500.0 + 0.25 * np.arange(n0))[None, None, :]
+    w = synth.Workload("plates", (n0, n1, n2), 1.0, (0.0, 0.0, 0.0))
+    w.solids.append(synth.Solid((0, 0, 0), (n0, n1, n2),
+                                synth.sphere_shape((0.0, 0.0, 0.0), 1000.0), n_layers, xi))
+    return w, xn

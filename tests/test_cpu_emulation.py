@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
-from tests.helpers import axis_plane_workload, edge_workloads, rel_err, run_oracle
+from tests.helpers import (axis_plane_workload, edge_workloads, plates_workload, rel_err,
+                           run_oracle)
 
 emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
@@ -44,7 +45,9 @@ def _runs():
     susp = synth.suspension(n_solids=3, grid_n=(24, 24, 40), h=1 / 24)
     edges = edge_workloads()
     trunc = _truncation_batch()
-    # name: (workload, precision, flags, calls made first on the same context[, CUs])
+    plates, plates_xn = plates_workload()
+    # name: (workload, precision, flags, calls made first on the same context[, options:
+    # "cus" = compute units of the emulated device, "xi_normal" = per-solid normal fields])
     return {
         "sphere16": (sphere, 0, BATCHED, ()),
         "ellipsoid24": (ell, 0, BATCHED, ()),
@@ -52,7 +55,7 @@ def _runs():
         "suspension3_per_solid": (susp, 0, PER_SOLID, ()),
         "suspension3_fp32_graph": (susp, 1, GRAPH, ()),
         # 5 CUs: 15 fit blocks over 8 XCDs, two blocks on some and one on others
-        "suspension3_cus5": (susp, 0, BATCHED, (), 5),
+        "suspension3_cus5": (susp, 0, BATCHED, (), {"cus": 5}),
         "repeated_calls": (susp, 0, BATCHED, (BATCHED, GRAPH, BATCHED)),
         "autotune_then_call": (sphere, 0, BATCHED, (AUTOTUNE,)),
         "persistent_refused": (sphere, 0, PERSISTENT, ()),
@@ -61,11 +64,16 @@ def _runs():
         "sphere64": (synth.sphere32(n=64, n_layers=3), 0, BATCHED, ()),
         # 64 CUs: 125 fit blocks for a few dozen bricks per layer (most blocks find no
         # brick of their own)
-        "ellipsoid40_cus64": (synth.ellipsoid128(n=40, n_layers=4), 0, BATCHED, (), 64),
-        "ellipsoid40_cus64_fp32": (synth.ellipsoid128(n=40, n_layers=4), 1, BATCHED, (), 64),
+        "ellipsoid40_cus64": (synth.ellipsoid128(n=40, n_layers=4), 0, BATCHED, (),
+                              {"cus": 64}),
+        "ellipsoid40_cus64_fp32": (synth.ellipsoid128(n=40, n_layers=4), 1, BATCHED, (),
+                                   {"cus": 64}),
         "edge_sphere": (edges[0], 0, BATCHED, ()),
         "edge_ellipsoid": (edges[1], 0, BATCHED, ()),
         "axis_planes": (axis_plane_workload(), 0, BATCHED, ()),
+        # F1 and a normal-weighted radius-4 fit (gathers from global memory)
+        "plates": (plates, 0, BATCHED, (), {"xi_normal": [plates_xn]}),
+        "plates_fp32_per_solid": (plates, 1, PER_SOLID, (), {"xi_normal": [plates_xn]}),
     }
 
 
@@ -75,18 +83,20 @@ def emulated():
     root = tempfile.mkdtemp(prefix="rmx_emu_")
 
     def one(item):
-        name, (w, prec, flags, pre, *cus) = item
+        name, (w, prec, flags, pre, *extra) = item
+        o = extra[0] if extra else {}
         st, outs = emu.run(w, os.path.join(root, name), precision=prec, flags=flags,
-                           pre_flags=pre, cus=cus[0] if cus else None)
-        return name, (w, prec, st, outs)
+                           pre_flags=pre, cus=o.get("cus"), xi_normal=o.get("xi_normal"))
+        return name, (w, prec, st, outs, o.get("xi_normal"))
 
     with ThreadPoolExecutor(max_workers=4) as ex:
         return dict(ex.map(one, _runs().items()))
 
 
-def _check(w, outs, precision):
-    for (xo, lab, dec, _), s in zip(outs, w.solids):
-        st, xr, lr, dr, _ = run_oracle(w, s)
+def _check(w, outs, precision, xi_normal=None):
+    for i, ((xo, lab, dec, _), s) in enumerate(zip(outs, w.solids)):
+        st, xr, lr, dr, _ = run_oracle(w, s, xi_normal=None if xi_normal is None
+                                       else xi_normal[i])
         assert np.array_equal(lab, lr)
         if st == 0:
             assert np.array_equal(dec, dr)
@@ -100,38 +110,38 @@ def _check(w, outs, precision):
                                   "suspension3_cus5", "sphere64", "ellipsoid40_cus64",
                                   "ellipsoid40_cus64_fp32"])
 def test_emulated_kernels_match_oracle(emulated, name):
-    w, prec, st, outs = emulated[name]
+    w, prec, st, outs, xn = emulated[name]
     assert st == 0
-    _check(w, outs, prec)
+    _check(w, outs, prec, xn)
 
 
 def test_emulated_repeated_calls(emulated):
     """Calls of different forms on one context (shared workspace, descriptors cached
     between identical calls), each on a fresh copy of the field, before the checked call."""
-    w, prec, st, outs = emulated["repeated_calls"]
+    w, prec, st, outs, xn = emulated["repeated_calls"]
     assert st == 0
-    _check(w, outs, prec)
+    _check(w, outs, prec, xn)
 
 
 def test_emulated_autotune_then_call(emulated):
     """The autotuner (every candidate launch shape, xi saved and restored) followed by the
     checked call with the tuned shapes: the result must still be the oracle's."""
-    w, prec, st, outs = emulated["autotune_then_call"]
+    w, prec, st, outs, xn = emulated["autotune_then_call"]
     assert st == 0
-    _check(w, outs, prec)
+    _check(w, outs, prec, xn)
 
 
 def test_emulated_persistent_refused(emulated):
-    w, prec, st, outs = emulated["persistent_refused"]
+    w, prec, st, outs, xn = emulated["persistent_refused"]
     assert st == -11
 
 
 @pytest.mark.parametrize("name", ["statuses_batched", "statuses_per_solid"])
 def test_emulated_statuses(emulated, name):
     """Truncated band, no interior cell and L = 0 in one batch."""
-    w, prec, st, outs = emulated[name]
+    w, prec, st, outs, xn = emulated[name]
     assert st == -7
-    _check(w, outs, prec)
+    _check(w, outs, prec, xn)
 
 
 @pytest.mark.parametrize("name", ["edge_sphere", "edge_ellipsoid", "axis_planes"])
@@ -139,5 +149,16 @@ def test_emulated_nonfinite_and_boundary(emulated, name):
     """Edge cases against the oracle: NaN and infinite components, cells exactly on
     |xi - c|^2 = R^2 or on an axis (a sphere and a rotated ellipsoid); body coordinates
     exactly 0 or +-1e-230 in the cells whose distance the normals need."""
-    w, prec, st, outs = emulated[name]
-    _check(w, outs, prec)
+    w, prec, st, outs, xn = emulated[name]
+    _check(w, outs, prec, xn)
+
+
+@pytest.mark.parametrize("name", ["plates", "plates_fp32_per_solid"])
+def test_emulated_f1_and_grown_normal_fit(emulated, name):
+    """Two plates with the normal fixed along +x: F1 on whole planes of layer-1 cells and
+    a normal-weighted fit at radius 4 (tests/helpers plates_workload)."""
+    w, prec, st, outs, xn = emulated[name]
+    assert st == 0
+    _check(w, outs, prec, xn)
+    dec = outs[0][2]
+    assert np.all(dec[:, :, [3, 5, 6]] == 32) and dec[4, 4, 8] == 4

@@ -204,6 +204,46 @@ def test_degenerate_paths(ctx, mode):
 
 
 @pytest.mark.parametrize("mode", MODE_PARAMS)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_f1_and_grown_normal_fit(ctx, precision, mode):
+    """Two one-cell plates with the normal fixed along +x (tests/helpers
+    ``plates_workload``): whole planes of layer-1 cells whose positive-weight data stay
+    coplanar up to r_max take F1 (kernel weights at radius 4), and the plane beyond the
+    second plate is fitted with the normal factor at radius 4.  Both are the radius-4
+    gathers from global memory, with and without the normal factor."""
+    from tests.helpers import plates_workload
+    w, xn = plates_workload()
+    st, gpu = run_gpu(ctx, w, precision, flags=MODES[mode], xi_normal=[xn])
+    assert st == 0
+    compare(w, gpu, precision, xi_normal=[xn], tag="plates")
+    dec, stats = gpu[0][2], gpu[0][3]
+    assert stats["n_f1"] >= 3 * 81
+    assert np.all(dec[:, :, [3, 5, 6]] == 32)
+    assert dec[4, 4, 8] == 4
+
+
+@pytest.mark.parametrize("mode", MODE_PARAMS)
+def test_normal_factor_half_space(ctx, mode):
+    """The half-space probe whose layer-1 value has a closed form under eq. (weight) (the
+    oracle pin test_normal_factor_value_closed_form): interior k <= 3, xi = ((i-4)^2, 0, 0),
+    normals along +z from a separate field."""
+    n0, n1, n2 = 9, 9, 8
+    xi = np.full((3, n2, n1, n0), np.nan)
+    xi[0, :4] = ((np.arange(n0) - 4.0) ** 2)[None, None, :]
+    xi[1, :4] = 0.0
+    xi[2, :4] = 0.0
+    xn = np.zeros_like(xi)
+    xn[2] = (500.0 + 0.25 * np.arange(n2))[:, None, None]
+    w = synth.Workload("half_space", (n0, n1, n2), 1.0, (0.0, 0.0, 0.0))
+    w.solids.append(synth.Solid((0, 0, 0), (n0, n1, n2),
+                                synth.sphere_shape((0.0, 0.0, 0.0), 1000.0), 3, xi))
+    st, gpu = run_gpu(ctx, w, 0, flags=MODES[mode], xi_normal=[xn])
+    assert st == 0
+    compare(w, gpu, 0, xi_normal=[xn], tag="half_space")
+    assert gpu[0][2][4, 4, 4] == 2
+
+
+@pytest.mark.parametrize("mode", MODE_PARAMS)
 @pytest.mark.parametrize("r_s,normal_layers", [(1, 2), (2, 0), (3, 4)])
 def test_option_variants(ctx, r_s, normal_layers, mode):
     w = synth.sphere32(seed=7)

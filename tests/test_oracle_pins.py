@@ -265,6 +265,110 @@ def test_normal_factor_zero_in_front_of_interface():
     assert np.max(np.abs(out2[:, 4, 4, 4] - out0[:, 4, 4, 4])) > 1e-6
 
 
+def _plane_mean(d_plane, r, weight, response):
+    """Weighted mean of response(dy, dz) over one full plane (the data at offset d_plane
+    along the plate normal, every in-plane offset within the Chebyshev radius r)."""
+    num = den = 0.0
+    for a in range(-r, r + 1):
+        for b in range(-r, r + 1):
+            w = weight(d_plane, a, b)
+            num += w * response(a, b)
+            den += w
+    return num / den
+
+
+def _two_plane_intercept(d1, m1, d2, m2):
+    """Value at 0 of the affine WLS fit to data on two full planes d = d1, d2 whose
+    weights and responses are even in both in-plane offsets: the in-plane slopes vanish by
+    symmetry, and the two-group model in d is saturated, so the fitted values on the
+    planes are the planes' weighted means m1, m2 and the intercept lies on their line."""
+    return m1 + (m2 - m1) * (0.0 - d1) / (d2 - d1)
+
+
+def _w_kernel(d, a, b):
+    """SI eq. (weight), layers > 2: 2^-(|di|+|dj|+|dk|)."""
+    return 2.0 ** -(abs(d) + abs(a) + abs(b))
+
+
+def _w_cosine(d, a, b, power=1, norm=1):
+    """SI eq. (weight), layers <= 2, with the normal along the plate normal pointing away
+    from the data at d < 0: max(0, x'.n / |x'|) 2^-(...), where x' = x_e - x_d = -delta, so
+    x'.n / |x'| = -d / |delta|.  `power` and `norm` give the wrong variants the pins must
+    reject: the cosine squared, or x'.n divided by |x'|^norm (norm = 0: no division)."""
+    ln = math.sqrt(d * d + a * a + b * b)
+    c = max(0.0, -d) / ln ** norm
+    return (c ** power) * _w_kernel(d, a, b)
+
+
+def test_normal_factor_value_closed_form():
+    """The value of a layer-1 fit with the normal factor of eq. (weight).  Interior is the
+    half-space k <= 3 with xi = ((i - 4)^2, 0, 0); a separate normal field puts grad phi0
+    along +z at the target e = (4, 4, 4).  The positive-weight data are the full planes
+    dk = -1, -2 of the radius-2 box, with weights cos * 2^-(|di|+|dj|+|dk|), cos = -dk/|d|,
+    even in di and dj.  So the fitted value is the line through the two planes' weighted
+    means of di^2 at dk = 0: 2 m(-1) - m(-2).  The cosine squared, or x'.n not divided by
+    |x'| (or divided by |x'|^2), gives a different value."""
+    p, xi = _half_space_quadratic(2)
+    p.normal_layers = 2
+    xn = np.zeros_like(xi)
+    xn[2] = (500.0 + 0.25 * np.arange(xi.shape[1]))[:, None, None]
+    st, out, lab, dec, stats = oracle.extrapolate(p, xi, xi_normal=xn)
+    assert st == 0 and lab[4, 4, 4] == 1 and dec[4, 4, 4] == 2
+
+    def expect(**kw):
+        m = [_plane_mean(d, 2, lambda d_, a, b: _w_cosine(d_, a, b, **kw),
+                         lambda a, b: float(a * a)) for d in (-1, -2)]
+        return _two_plane_intercept(-1, m[0], -2, m[1])
+
+    got = out[0, 4, 4, 4]
+    assert abs(got - expect()) < 1e-14
+    assert abs(out[1, 4, 4, 4]) < 1e-15 and abs(out[2, 4, 4, 4]) < 1e-15
+    for wrong in (dict(power=2), dict(norm=0), dict(norm=2)):
+        assert abs(got - expect(**wrong)) > 1e-4, wrong
+
+
+def test_f1_fallback_and_grown_normal_fit():
+    """Two one-cell plates (x = 4 and x = 7), the normal fixed along +x (tests/helpers
+    ``plates_workload``).  On the row (j, k) = (4, 4):
+      * x = 3, 5, 6 have their positive-weight data on one plate (or none) at every radius
+        up to r_max = 4, so the rank test fails until F1 drops the normal factor and fits
+        both plates at radius 4 with the kernel weights;
+      * x = 8 sees plate 7 at dx = -1 and, from radius 4 on, plate 4 at dx = -4: it is
+        fitted at radius 4 with the normal factor.
+    Each value is the two-plane intercept of the plates' weighted means: xi_x from the
+    plate values, xi_y from the means of dy^2 (kernel weights: separable; normal factor:
+    the cosine couples the plane's offsets)."""
+    from tests.helpers import plates_workload
+    P, Q = 0.3, 0.7
+    w, xn = plates_workload(p=P, q=Q)
+    s = w.solids[0]
+    st, out, lab, dec, stats = run_oracle(w, s, xi_normal=xn)
+    assert st == 0
+    assert [int(v) for v in lab[4, 4, :]] == [-1, -1, 2, 1, 0, 1, 1, 0, 1, 2, -1, -1, -1]
+
+    def dy2(a, b):
+        return float(a * a)
+
+    cases = {3: ((1, P), (4, Q), _w_kernel, oracle.DEC_F1),
+             5: ((-1, P), (2, Q), _w_kernel, oracle.DEC_F1),
+             6: ((-2, P), (1, Q), _w_kernel, oracle.DEC_F1),
+             8: ((-1, Q), (-4, P), _w_cosine, 4)}
+    for x, ((d1, v1), (d2, v2), wf, code) in cases.items():
+        assert dec[4, 4, x] == code, (x, dec[4, 4, x])
+        ex = _two_plane_intercept(d1, v1, d2, v2)
+        my = _two_plane_intercept(d1, _plane_mean(d1, 4, wf, dy2), d2,
+                                  _plane_mean(d2, 4, wf, dy2))
+        assert abs(out[0, 4, 4, x] - ex) < 1e-14, (x, out[0, 4, 4, x], ex)
+        assert abs(out[1, 4, 4, x] - my) < 1e-13, (x, out[1, 4, 4, x], my)
+        assert abs(out[2, 4, 4, x]) < 1e-15
+    # the kernel-weighted mean (F2) would have given another value at x = 3
+    f2 = (P / 2 + Q / 16) / (1 / 2 + 1 / 16)
+    assert abs(out[0, 4, 4, 3] - f2) > 1e-3
+    # F1 on every cell of planes x = 3, 5, 6 (interior rows of the plates included)
+    assert stats[19] == int(np.sum((dec & 63) == oracle.DEC_F1)) > 3 * 9 * 9 - 1
+    assert stats[19] >= 3 * 9 * 9
+
+
 # ------------------------------------------------------------------------------------------
 # Local linear model (main text: WLS local linear model, xi_e = beta x_e).
 # ------------------------------------------------------------------------------------------
@@ -355,6 +459,47 @@ def test_wls_matches_library_lstsq():
         sw = np.sqrt(np.array(wts))[:, None]
         beta = np.linalg.lstsq(sw * np.array(rows), sw * np.array(vals), rcond=None)[0]
         assert np.max(np.abs(beta[0] - out[:, k, j, i])) < 1e-13
+
+
+def test_wls_with_normal_factor_matches_library_lstsq():
+    """The same cross-check on layers 1-2, where eq. (weight) multiplies the kernel by the
+    cosine max(0, x'.n / |x'|), x' = x_e - x_d, n the unit gradient of phi0(xi) at the
+    target.  The gradient comes from the oracle's normal (pinned above by exact linear
+    differences and one-sided walls); the weights and the solve are computed here, from
+    the definition, with a library least-squares solve.  Only cells fitted at radius 2
+    are taken (their data set is the radius-2 box)."""
+    w = synth.sphere32(n_layers=4)
+    s = w.solids[0]
+    p = oracle_problem(w, s)
+    st, out, lab, dec, stats = run_oracle(w, s)
+    assert st == 0
+    rng = np.random.default_rng(4)
+    n2, n1, n0 = lab.shape
+    cells = np.argwhere((lab >= 1) & (lab <= 2) & (dec == 2))
+    assert len(cells) > 1000
+    for k, j, i in cells[rng.choice(len(cells), 80, replace=False)]:
+        le = lab[k, j, i]
+        g = oracle.normal(p, s.xi, int(i), int(j), int(k))
+        n = g / np.linalg.norm(g)
+        rows, vals, wts = [], [], []
+        for dk in range(-2, 3):
+            for dj in range(-2, 3):
+                for di in range(-2, 3):
+                    kk, jj, ii = k + dk, j + dj, i + di
+                    if not (0 <= kk < n2 and 0 <= jj < n1 and 0 <= ii < n0):
+                        continue
+                    if not 0 <= lab[kk, jj, ii] < le:
+                        continue
+                    xp = -np.array([di, dj, dk], dtype=np.float64)   # x_e - x_d, cells
+                    cos = float(xp @ n) / float(np.linalg.norm(xp))
+                    if cos <= 0.0:
+                        continue
+                    rows.append([1.0, di, dj, dk])
+                    vals.append(out[:, kk, jj, ii])
+                    wts.append(cos * 2.0 ** -(abs(di) + abs(dj) + abs(dk)))
+        sw = np.sqrt(np.array(wts))[:, None]
+        beta = np.linalg.lstsq(sw * np.array(rows), sw * np.array(vals), rcond=None)[0]
+        assert np.max(np.abs(beta[0] - out[:, k, j, i])) < 1e-13, (k, j, i)
 
 
 # ------------------------------------------------------------------------------------------
