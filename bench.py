@@ -60,7 +60,8 @@ def time_calls(ctx, dw, opt, steps, warmup):
 
 
 def profile_phases(ctx, dw, opt, steps):
-    """Per-kernel average duration (ms) from HIP events around every launch."""
+    """Per-phase (total ms, launches) over `steps` profiled calls, from HIP events placed
+    around every launch on the launch stream."""
     import torch
     from paper_2104_00095_amd import rmx
     popt = rmx.options(opt.r_s, opt.r_max, opt.normal_layers, opt.precision,
@@ -71,8 +72,17 @@ def profile_phases(ctx, dw, opt, steps):
     for _ in range(steps):
         ctx.extrapolate_raw(dw.grid, arr, len(dw.solids), popt, h)
     torch.cuda.synchronize()
-    prof = ctx.profile_read()
-    return {k: (ms / n, n) for k, (ms, n) in prof.items()}
+    return ctx.profile_read()
+
+
+# Phases of the profiler -> the kernel that runs them (each layer's fit is one launch of
+# the same fit kernel).
+KERNEL_NAMES = {"classify": "k_classify", "label": "k_label", "normal": "k_normal",
+                "extrap": "k_extrap"}
+
+
+def kernel_of(phase):
+    return "extrap" if phase.startswith("extrap") else phase
 
 
 def classify_bytes(w):
@@ -159,34 +169,61 @@ def committed_traffic(kernel, workload):
         return None
 
 
-def kernel_bytes(phase, w, stats, normal_layers=2, decisions=False, cls_bytes=None):
-    """Algorithmic HBM bytes of one launch of a kernel (the minimum it must move):
-    classify reads xi under its early-out rule (see classify_bytes; at most 24 B/cell)
-    and writes the 1-bit mask; label reads the mask and
-    writes int8 labels (and decisions); normal reads xi (24 B) and writes the normal
-    (24 B) of each cell of layers 1..normal_layers; the fit of layer l writes xi (24 B)
-    and the decision (1 B) of each cell of the layer and reads its normal (24 B) where one
-    is used (the staged neighbourhoods are re-reads of data the chain wrote just before)."""
+def model_bytes(kernel, w, stats):
+    """The call's algorithmic HBM bytes attributed to a kernel by the byte model
+    B = 24 |D| + 1 |D| + 24 N_band: classification reads xi of every box cell once (24 B),
+    labelling writes one int8 label per box cell, and the fits write 24 B per band cell.
+    The normal kernel moves nothing the model counts (None)."""
     cells = w.box_cells
-    band = [sum(s["n_band"][l] for s in stats) for l in range(17)]
-    dec = 1 if decisions else 0
-    if phase == "classify":
-        return cls_bytes if cls_bytes is not None else 24 * cells + cells / 8
-    if phase == "label":
-        return cells / 8 + (1 + dec) * cells
-    if phase == "normal":
-        return 48 * sum(band[1:normal_layers + 1])
-    if phase.startswith("extrap"):
-        l = int(phase[6:])
-        return (24 + dec + (24 if l <= normal_layers else 0)) * band[l]
+    nb = sum(sum(s["n_band"][1:17]) for s in stats)
+    return {"classify": 24.0 * cells, "label": 1.0 * cells, "normal": None,
+            "extrap": 24.0 * nb}[kernel]
+
+
+def kernel_table(phases, calls, w, stats, cls_bytes):
+    """Per kernel: time per call, launches per call, average launch duration, the byte
+    model's bytes per call and per launch, and the achieved fraction of the HBM peak."""
+    agg = {}
+    for ph, (ms, n) in phases.items():
+        k = kernel_of(ph)
+        a = agg.setdefault(k, [0.0, 0])
+        a[0] += ms
+        a[1] += n
+    out = {}
+    for k, (ms, n) in agg.items():
+        b = model_bytes(k, w, stats)
+        lpc = n / calls
+        e = {"kernel": KERNEL_NAMES[k], "ms_per_call": ms / calls, "launches_per_call": lpc,
+             "avg_launch_ms": ms / n, "model_bytes_per_call": b}
+        if b is not None:
+            e["model_bytes_per_launch"] = b / lpc
+            e["hbm_frac"] = b / (ms / calls * 1e-3) / (HBM_PEAK_GBS * 1e9)
+        out[k] = e
+    if "classify" in out:
+        # the exact early-out reads only what the predicate needs (fewer bytes than the
+        # model's 24 B per cell on a sphere)
+        e = out["classify"]
+        e["early_out_bytes"] = cls_bytes
+        e["early_out_hbm_frac"] = cls_bytes / (e["avg_launch_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
     return None
 
 
 def cpu_baseline(w, seconds, gpu=None, r_s=2, r_max=4, normal_layers=2):
     """The oracle as it stands, on this host's cores, on whole calls of the same workload
-    until `seconds` of CPU work have run (at least one call).  `gpu`: {precision: per-solid
-    (xi, labels) of one GPU call on the same input}; the oracle's output of its first call
-    is compared with them (labels equal; relative max-norm error of xi over the band)."""
+    until `seconds` of CPU work have run (at least one call); then the same on one thread
+    for half as long.  `gpu`: {precision: per-solid (xi, labels) of one GPU call on the same
+    input}; the oracle's output of its first call is compared with them (labels equal;
+    relative max-norm error of xi over the band)."""
     import numpy as np
     import oracle
     cores = len(os.sched_getaffinity(0))
@@ -195,24 +232,32 @@ def cpu_baseline(w, seconds, gpu=None, r_s=2, r_max=4, normal_layers=2):
                                                    s.shape.rot),
                                  s.n_layers, r_s=r_s, r_max=r_max, normal_layers=normal_layers)
              for s in w.solids]
-    calls, band, t0 = 0, 0, time.perf_counter()
-    first = None
-    while True:
-        outs = []
-        for p, s in zip(probs, w.solids):
-            st, xo, lab, dec, stats = oracle.extrapolate(p, s.xi, nthreads=cores)
-            band += int(stats[1:17].sum())
-            if first is None:
-                outs.append((xo, lab))
-        if first is None:
-            first = outs
-        calls += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    res = {"value": band / el, "unit": "band cells/s", "cores": cores, "kind": "oracle",
+
+    def run(threads, secs, keep):
+        calls, band, t0 = 0, 0, time.perf_counter()
+        first = None
+        while True:
+            outs = []
+            for p, s in zip(probs, w.solids):
+                st, xo, lab, dec, stats = oracle.extrapolate(p, s.xi, nthreads=threads)
+                band += int(stats[1:17].sum())
+                if keep and first is None:
+                    outs.append((xo, lab))
+            if keep and first is None:
+                first = outs
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= secs:
+                return band / el, calls, el, first
+
+    rate, calls, el, first = run(cores, seconds, True)
+    rate1, calls1, el1, _ = run(1, seconds / 2, False)
+    res = {"value": rate, "unit": "band cells/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(),
            "sample": f"{calls} whole calls of {w.name} ({len(w.solids)} solid(s)), "
-                     f"{el:.1f} s wall, OpenMP threads = {cores}"}
+                     f"{el:.1f} s wall, OpenMP threads = {cores}",
+           "one_thread": {"value": rate1, "unit": "band cells/s",
+                          "sample": f"{calls1} whole calls, {el1:.1f} s wall, 1 thread"}}
     for prec, g in (gpu or {}).items():
         worst, same = 0.0, True
         for (xo, lo), (xg, lg) in zip(first, g):
@@ -433,6 +478,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--shapes", default=None,
+                    help="TILE_W,EXTRAP_BLOCKS: use these launch shapes instead of autotuning "
+                         "(for profiles: only the timed shapes are launched)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (the reference for "
@@ -460,7 +508,11 @@ def main():
     flags = rmx.FLAG_GRAPH if args.graph else 0
     opt = rmx.options(precision=prec, flags=flags)
     tuned = None
-    if not args.no_autotune:
+    if args.shapes:
+        tw, eb = (int(v) for v in args.shapes.split(","))
+        ctx.set_tuning(dw.grid, dw.solids, tw, eb, rmx.options(precision=prec))
+        tuned = {"tile_w": tw, "extrap_blocks": eb, "ms": None}
+    elif not args.no_autotune:
         log("autotune (label tile width, blocks per layer fit)")
         tuned = ctx.autotune(dw.grid, dw.solids, rmx.options(precision=prec), reps=5)
     log("timing")
@@ -472,16 +524,25 @@ def main():
     prof_calls = max(10, min(args.steps, 50))
     phases = profile_phases(ctx, dw, opt, prof_calls)
     cb = classify_bytes(w)
-    kb = {k: kernel_bytes(k, w, stats, cls_bytes=cb) for k in phases}
-    dom = max((k for k in phases if kb[k] is not None),
-              key=lambda k: phases[k][0])
-    dom_ms = phases[dom][0]
-    dom_bytes = kb[dom]
-    roof = {"bound": "hbm", "kernel": dom, "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "traffic": committed_traffic(dom, args.workload),
-            "kernel_ms": dom_ms, "algorithmic_bytes": dom_bytes}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    kt = kernel_table(phases, prof_calls, w, stats, cb)
+    # the dominant kernel: the most time per call (summed over its launches)
+    dom = max(kt, key=lambda k: kt[k]["ms_per_call"])
+    d = kt[dom]
+    if d["model_bytes_per_call"] is None:
+        roof = {"bound": "latency", "kernel": d["kernel"], "achieved": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+    else:
+        per_launch = d["model_bytes_per_launch"]
+        roof = {"bound": "hbm", "kernel": d["kernel"],
+                "achieved": per_launch / (d["avg_launch_ms"] * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "traffic": committed_traffic(d["kernel"], args.workload),
+                "bytes_per_launch": per_launch, "avg_launch_ms": d["avg_launch_ms"],
+                "launches_per_call": d["launches_per_call"],
+                "byte_model": {"classify": "24 B read per box cell",
+                               "label": "1 B written per box cell",
+                               "extrap": "24 B written per band cell of the layer"}[dom]}
+        roof["frac"] = roof["achieved"] / roof["peak"]
     B = 25 * cells + 24 * nb
 
     variants = {}
@@ -545,11 +606,7 @@ def main():
         "call_roofline": {"bound": "hbm", "algorithmic_bytes": B,
                           "achieved": B / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)},
-        "kernels": {k: {"ms": v[0], "launches_per_call": v[1] / prof_calls,
-                        "algorithmic_bytes": kb[k],
-                        "hbm_frac": (kb[k] / (v[0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
-                        if kb[k] else None}
-                    for k, v in phases.items()},
+        "kernels": kt,
         "cpu_baseline": cpu,
         "variants": variants,
     }

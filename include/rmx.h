@@ -195,6 +195,14 @@ int rmx_autotune(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
                  int32_t n_solids, const rmx_options* opt, void* hip_stream, int32_t reps,
                  rmx_tuning* best);
 
+/* Keep launch shapes `t` (HOST; t->ms is ignored) for later calls of this batch's shape
+ * class on this context, as rmx_autotune would after choosing them, without timing
+ * anything: a shape found by an earlier autotuner run, or one fixed for a profile.
+ * tile_w must be 1, 2 or 4 and fit the LDS for this batch's layer count (else RMX_E_ARG);
+ * extrap_blocks >= 1.  Allocates nothing on the device. */
+int rmx_set_tuning(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
+                   int32_t n_solids, const rmx_options* opt, const rmx_tuning* t);
+
 /* Profiling (tracing): wait for every call made with RMX_FLAG_PROFILE since the last
  * read, then write per phase the summed kernel time in ms (ms[RMX_N_PHASES], HOST) and
  * the number of launches (launches[RMX_N_PHASES], HOST), and reset the sums. */

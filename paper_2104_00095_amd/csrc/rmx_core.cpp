@@ -19,6 +19,7 @@ namespace {
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 constexpr int kDefaultCus = 256;
 
+
 void drop_graphs(rmx_ctx* c) {
     for (auto& kv : c->graphs) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
@@ -48,8 +49,8 @@ int ensure_ws(rmx_ctx* c, size_t need) {
 }
 
 // Pinned staging buffer for the descriptor upload; waits if the slot's previous copy is
-// still in flight.
-int get_stage(rmx_ctx* c, size_t bytes, Staging** out) {
+// still in flight.  no_alloc: a slot smaller than `bytes` is an error, not a reallocation.
+int get_stage(rmx_ctx* c, size_t bytes, Staging** out, bool no_alloc = false) {
     Staging& s = c->stage[c->stage_next];
     c->stage_next = (c->stage_next + 1) % rmx_ctx::kRing;
     if (s.pending) {
@@ -57,6 +58,7 @@ int get_stage(rmx_ctx* c, size_t bytes, Staging** out) {
         s.pending = false;
     }
     if (s.size < bytes) {
+        if (no_alloc) return RMX_E_WORKSPACE;
         if (s.host) (void)hipHostFree(s.host);
         s.host = nullptr;
         const size_t sz = std::max<size_t>(bytes, 1 << 16);
@@ -71,23 +73,19 @@ int get_stage(rmx_ctx* c, size_t bytes, Staging** out) {
     return RMX_OK;
 }
 
-uint64_t call_key(const rmx_grid* const* g, const rmx_solid* s, int n, const rmx_options* o) {
-    uint64_t h = 1469598103934665603ull;
-    for (int i = 0; i < n; ++i) h = fnv1a(g[i], sizeof(rmx_grid), h);
-    h = fnv1a(s, sizeof(*s) * (size_t)n, h);
+uint64_t options_key(const rmx_options* o) {
     rmx_options oo = *o;
     oo.flags &= RMX_FLAG_PER_SOLID;
-    h = fnv1a(&oo, sizeof(oo), h);
-    return h;
+    return fnv1a(&oo, sizeof(oo), 1469598103934665603ull);
 }
 
-bool desc_current(const rmx_ctx* c, uint64_t h, size_t len) {
-    return c->desc_valid && c->desc_ws == c->ws && c->desc_hash == h && c->desc_len == len;
+bool desc_current(const rmx_ctx* c, const void* ws, uint64_t h, size_t len) {
+    return c->desc_valid && c->desc_ws == ws && c->desc_hash == h && c->desc_len == len;
 }
 
-void desc_mark(rmx_ctx* c, uint64_t h, size_t len) {
+void desc_mark(rmx_ctx* c, const void* ws, uint64_t h, size_t len) {
     c->desc_valid = true;
-    c->desc_ws = c->ws;
+    c->desc_ws = ws;
     c->desc_hash = h;
     c->desc_len = len;
 }
@@ -119,39 +117,42 @@ uint64_t tune_key(const Plan& p) {
            ((uint64_t)p.normal_layers << 48);
 }
 
-int run_batch(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
-              const rmx_options* opt, hipStream_t st, bool use_graph, size_t stats_off,
-              bool want_stats, const Tuning* force) {
-    Plan p;
-    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, &p);
+int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
+              const rmx_options* opt, const Tuning* force, Plan* p) {
+    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, p);
     if (rc != RMX_OK) return rc;
     Tuning tn{};
     if (force) {
         tn = *force;
     } else {
-        const auto it = c->tuned.find(tune_key(p));
+        const auto it = c->tuned.find(tune_key(*p));
         if (it != c->tuned.end()) tn = it->second;
     }
-    if (tn.tile_w || tn.extrap_blocks) {
-        rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, &p);
-        if (rc != RMX_OK) return rc;
-    }
-    rc = ensure_ws(c, p.ws_bytes);
-    if (rc != RMX_OK) return rc;
+    if (tn.tile_w || tn.extrap_blocks) rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, p);
+    return rc;
+}
+
+int launch_planned(rmx_ctx* c, Plan& p, int n, const rmx_options* opt, hipStream_t st,
+                   bool use_graph, size_t stats_off, bool want_stats, void* ws, size_t ws_size,
+                   bool no_alloc) {
+    if (p.ws_bytes > ws_size) return RMX_E_WORKSPACE;
+    int rc = RMX_OK;
     Batch b{};
-    bind(&p, c->ws, opt, &b);
+    bind(&p, ws, opt, &b);
 #ifdef RMX_EMU_REDZONES
-    rmx_emu_poison_gaps(c->ws, c->ws_size, p.gaps);
+    rmx_emu_poison_gaps(ws, ws_size, p.gaps);
 #endif
     c->desc_host.resize(p.desc_bytes);
     pack_desc(p, c->desc_host.data());
     const uint64_t dh = fnv1a(c->desc_host.data(), p.desc_bytes, 1469598103934665603ull);
 
     if (use_graph) {
-        const uint64_t key = call_key(grids, solids, n, opt) ^ (dh * 31u) ^
+        // the descriptors (boxes, walls, shapes, field pointers) and the options fix
+        // every kernel argument of the chain
+        const uint64_t key = options_key(opt) ^ (dh * 31u) ^
                              ((uint64_t)p.tile_w << 56) ^ ((uint64_t)p.extrap_blocks << 40);
         auto it = c->graphs.find(key);
-        if (it == c->graphs.end() || it->second.ws_base != c->ws) {
+        if (it == c->graphs.end() || it->second.ws_base != ws) {
             if (it != c->graphs.end()) {
                 (void)hipGraphExecDestroy(it->second.exec);
                 (void)hipGraphDestroy(it->second.graph);
@@ -160,12 +161,12 @@ int run_batch(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
             // Descriptors live in the workspace; a graph replays with the same workspace,
             // so they are written once, synchronously, before capture.
             if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
-            if (hipMemcpy(c->ws, c->desc_host.data(), p.desc_bytes, hipMemcpyHostToDevice) !=
+            if (hipMemcpy(ws, c->desc_host.data(), p.desc_bytes, hipMemcpyHostToDevice) !=
                 hipSuccess)
                 return RMX_E_HIP;
-            desc_mark(c, dh, p.desc_bytes);
+            desc_mark(c, ws, dh, p.desc_bytes);
             GraphEntry ge;
-            ge.ws_base = c->ws;
+            ge.ws_base = ws;
             if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) !=
                 hipSuccess)
                 return RMX_E_HIP;
@@ -179,29 +180,29 @@ int run_batch(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
                 return RMX_E_HIP;
             }
             it = c->graphs.emplace(key, ge).first;
-        } else if (!desc_current(c, dh, p.desc_bytes)) {
+        } else if (!desc_current(c, ws, dh, p.desc_bytes)) {
             // another call rewrote the descriptors since the capture: restore them
             if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
-            if (hipMemcpy(c->ws, c->desc_host.data(), p.desc_bytes, hipMemcpyHostToDevice) !=
+            if (hipMemcpy(ws, c->desc_host.data(), p.desc_bytes, hipMemcpyHostToDevice) !=
                 hipSuccess)
                 return RMX_E_HIP;
-            desc_mark(c, dh, p.desc_bytes);
+            desc_mark(c, ws, dh, p.desc_bytes);
         }
         if (hipGraphLaunch(it->second.exec, st) != hipSuccess) return RMX_E_HIP;
     } else {
         // Upload the descriptors unless the workspace already holds these exact bytes
         // (calls on one context are ordered on one stream).
-        if (!desc_current(c, dh, p.desc_bytes)) {
+        if (!desc_current(c, ws, dh, p.desc_bytes)) {
             Staging* sg = nullptr;
-            rc = get_stage(c, p.desc_bytes, &sg);
+            rc = get_stage(c, p.desc_bytes, &sg, no_alloc);
             if (rc != RMX_OK) return rc;
             std::memcpy(sg->host, c->desc_host.data(), p.desc_bytes);
-            if (hipMemcpyAsync(c->ws, sg->host, p.desc_bytes, hipMemcpyHostToDevice, st) !=
+            if (hipMemcpyAsync(ws, sg->host, p.desc_bytes, hipMemcpyHostToDevice, st) !=
                 hipSuccess)
                 return RMX_E_HIP;
             if (hipEventRecord(sg->ev, st) != hipSuccess) return RMX_E_HIP;
             sg->pending = true;
-            desc_mark(c, dh, p.desc_bytes);
+            desc_mark(c, ws, dh, p.desc_bytes);
         }
         Profiler* prof = (opt->flags & RMX_FLAG_PROFILE) ? &c->prof : nullptr;
         if (enqueue(p, b, opt->precision, st, prof) != hipSuccess) return RMX_E_HIP;
@@ -213,6 +214,28 @@ int run_batch(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
             return RMX_E_HIP;
     }
     return RMX_OK;
+}
+
+int finish_sync(rmx_ctx* c, hipStream_t st, int n_solids, rmx_solid_stats* stats) {
+    if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
+    c->tmp_stats.resize(n_solids);
+    convert_stats(c->stats_host, n_solids, c->tmp_stats.data());
+    if (stats) std::memcpy(stats, c->tmp_stats.data(), sizeof(rmx_solid_stats) * n_solids);
+    for (int i = 0; i < n_solids; ++i)
+        if (c->tmp_stats[i].status < 0) return c->tmp_stats[i].status;
+    return RMX_OK;
+}
+
+int run_batch(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
+              const rmx_options* opt, hipStream_t st, bool use_graph, size_t stats_off,
+              bool want_stats, const Tuning* force) {
+    Plan p;
+    int rc = plan_call(c, grids, solids, n, opt, force, &p);
+    if (rc != RMX_OK) return rc;
+    rc = ensure_ws(c, p.ws_bytes);
+    if (rc != RMX_OK) return rc;
+    return launch_planned(c, p, n, opt, st, use_graph, stats_off, want_stats, c->ws,
+                          c->ws_size, false);
 }
 
 }  // namespace rmx
@@ -344,13 +367,7 @@ int rmx_extrapolate(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
         if (rc != RMX_OK) return rc;
     }
     if (!sync) return RMX_OK;
-    if (hipStreamSynchronize(st) != hipSuccess) return RMX_E_HIP;
-    c->tmp_stats.resize(n_solids);
-    convert_stats(c->stats_host, n_solids, c->tmp_stats.data());
-    if (stats) std::memcpy(stats, c->tmp_stats.data(), sizeof(rmx_solid_stats) * n_solids);
-    for (int i = 0; i < n_solids; ++i)
-        if (c->tmp_stats[i].status < 0) return c->tmp_stats[i].status;
-    return RMX_OK;
+    return finish_sync(c, st, n_solids, stats);
 }
 
 int rmx_autotune(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
@@ -446,6 +463,29 @@ int rmx_autotune(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int3
     best->tile_w = win.tile_w;
     best->extrap_blocks = win.extrap_blocks;
     best->ms = win_ms;
+    return RMX_OK;
+}
+
+int rmx_set_tuning(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
+                   int32_t n_solids, const rmx_options* opt, const rmx_tuning* t) {
+    if (!c || !grid || !solids || n_solids < 1 || !t) return RMX_E_ARG;
+    if (t->tile_w != 1 && t->tile_w != 2 && t->tile_w != 4) return RMX_E_ARG;
+    if (t->extrap_blocks < 1) return RMX_E_ARG;
+    rmx_options def;
+    rmx_default_options(&def);
+    if (!opt) opt = &def;
+    int rc = validate_options(opt);
+    if (rc != RMX_OK) return rc;
+    for (int i = 0; i < n_solids; ++i)
+        if ((rc = validate_solid(grid, solids + i, false)) != RMX_OK) return rc;
+    c->grid_ptrs.assign(n_solids, grid);
+    Plan probe;
+    rc = plan(c->grid_ptrs.data(), solids, n_solids, opt, c->lds_limit, c->cus, Tuning{}, &probe);
+    if (rc != RMX_OK) return rc;
+    int Wmax = 1;
+    for (const auto& d : probe.solids) Wmax = std::max(Wmax, d.W);
+    if (label_lds_bytes(probe.Lmax, t->tile_w, Wmax) > c->lds_limit) return RMX_E_ARG;
+    c->tuned[tune_key(probe)] = Tuning{t->tile_w, t->extrap_blocks};
     return RMX_OK;
 }
 

@@ -38,7 +38,7 @@ struct rmx_ctx {
     int stage_next = 0;
     // what the workspace's descriptor region holds now
     bool desc_valid = false;
-    void* desc_ws = nullptr;
+    const void* desc_ws = nullptr;
     uint64_t desc_hash = 0;
     size_t desc_len = 0;
     std::vector<char> desc_host;
@@ -58,8 +58,21 @@ namespace rmx {
 int ctx_stats_host(rmx_ctx* c, size_t n);
 // Shape class of a planned call (the key of the tuned launch shapes).
 uint64_t tune_key(const Plan& p);
-// Enqueue one batched call on `st` (descriptor upload, kernels, optional statistics
-// read-back into stats_host + stats_off).  `force` overrides the tuned launch shapes.
+// Plan one batched call: the batch with the tuned launch shapes applied (`force`, if
+// given, overrides them).
+int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
+              const rmx_options* opt, const Tuning* force, Plan* p);
+// Enqueue a planned call on `st` with its workspace at [ws, ws + ws_size): descriptor
+// upload, kernels, optional statistics read-back into stats_host + stats_off.  no_alloc:
+// nothing is allocated (a staging buffer too small is RMX_E_WORKSPACE).
+int launch_planned(rmx_ctx* c, Plan& p, int n, const rmx_options* opt, hipStream_t st,
+                   bool use_graph, size_t stats_off, bool want_stats, void* ws, size_t ws_size,
+                   bool no_alloc);
+// Wait for `st`, convert the statistics of n_solids solids into `stats` (nullable) and
+// return the first negative per-solid status, else RMX_OK.
+int finish_sync(rmx_ctx* c, hipStream_t st, int n_solids, rmx_solid_stats* stats);
+// Enqueue one batched call on `st` in the context's own workspace (grown on demand).
+// `force` overrides the tuned launch shapes.
 int run_batch(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
               const rmx_options* opt, hipStream_t st, bool use_graph, size_t stats_off,
               bool want_stats, const Tuning* force);

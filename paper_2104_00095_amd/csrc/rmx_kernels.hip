@@ -168,6 +168,43 @@ __global__ __launch_bounds__(256) void k_classify(Batch b) {
 // ------------------------------------------------------------------------------------
 constexpr int kRowsPerThread = 9;   // ceil((16 + 2 * 16)^2 / 256)
 
+// Labels of a tile with no layer cell: -1 everywhere (and decision 0).  Whole-width tiles
+// with 16-byte aligned rows store 16-byte chunks, consecutive threads on consecutive
+// chunks of a row; other tiles store their rows byte by byte.
+template <int MAXTW>
+__device__ __forceinline__ void label_tile_empty(const DevSolid* d, int wx0, int tw, int j0,
+                                                 int k0) {
+    const int tid = threadIdx.x;
+    const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
+    const int xs = wx0 * 64, nx = min(64 * tw, n0 - xs);
+    const bool wide = nx == 64 * MAXTW && (n0 & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(d->labels) & 15) == 0 &&
+                      (!d->decisions || (reinterpret_cast<uintptr_t>(d->decisions) & 15) == 0);
+    if (wide) {
+        constexpr int CPR = 4 * MAXTW;   // 16-byte chunks per row
+        const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u), zero = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int h = 0; h < CPR; ++h) {
+            const int c = tid + 256 * h;
+            const int row = c / CPR, off = c % CPR;
+            const int jj = j0 + row % kTileJ, kk = k0 + row / kTileJ;
+            if (jj < n1 && kk < n2) {
+                const int64_t o = ((int64_t)kk * n1 + jj) * n0 + xs + 16 * off;
+                *reinterpret_cast<uint4*>(d->labels + o) = ones;
+                if (d->decisions) *reinterpret_cast<uint4*>(d->decisions + o) = zero;
+            }
+        }
+        return;
+    }
+    const int jj = j0 + tid % kTileJ, kk = k0 + tid / kTileJ;
+    if (jj >= n1 || kk >= n2) return;
+    const int64_t o = ((int64_t)kk * n1 + jj) * n0 + xs;
+    for (int i = 0; i < nx; ++i) {
+        d->labels[o + i] = (int8_t)-1;
+        if (d->decisions) d->decisions[o + i] = 0;
+    }
+}
+
 template <int MAXTW>
 __global__ __launch_bounds__(256) void k_label(Batch b) {
     constexpr int FPL = 4 * 8 * MAXTW;   // brick flags per layer: 2 (y) x 2 (z) x 8 per word
@@ -202,16 +239,38 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     for (int q = tid; q < L * FPL; q += 256) s_bflag[q] = 0;
     if (tid < kLT) s_cnt[tid] = 0;
     if (tid == 0) s_trunc = 0;
-    // the mask rows of the region (rows outside the box: empty)
+    // The mask rows of the region (rows outside the box: empty).  Every load of the
+    // thread is issued into registers before the first LDS store, so they overlap instead
+    // of each waiting for the previous one.
+    unsigned long long mv[kRowsPerThread][MW];
+    unsigned long long any = 0ull;
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
         const int rr = tid + 256 * q;
         const int rj = rr % RJ, rk = rr / RJ;
         const int jj = j0 - L + rj, kk = k0 - L + rk;
         const bool ok = rr < R && jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
+        const int64_t base = ok ? ((int64_t)kk * n1 + jj) * W + xr0 : 0;
+#pragma unroll
+        for (int w = 0; w < MW; ++w) {
+            mv[q][w] = (ok && w < RW) ? mask[base + w] : 0ull;
+            any |= mv[q][w];
+        }
+    }
+    // A tile whose whole region holds no interior cell has no layer cell either: its
+    // labels are all -1 (decisions 0), its counts 0, and it lists no brick.
+    if (!__syncthreads_or(any != 0ull)) {
+        if (tid <= L) b.tile_cnt[(int64_t)t * kLT + tid] = 0;
+        label_tile_empty<MAXTW>(d, wx0, tw, j0, k0);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+        const int rr = tid + 256 * q;
         if (rr < R) {
-            for (int w = 0; w < RW; ++w)
-                A[rr * RW + w] = ok ? mask[((int64_t)kk * n1 + jj) * W + xr0 + w] : 0ull;
+#pragma unroll
+            for (int w = 0; w < MW; ++w)
+                if (w < RW) A[rr * RW + w] = mv[q][w];
         }
     }
     __syncthreads();
@@ -650,32 +709,38 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
     const int8_t* __restrict__ labels = d->labels;
     const int ox = kBrick * bx - kBrickHalo, oy = kBrick * by - kBrickHalo,
               oz = kBrick * bz - kBrickHalo;
-    // Stage labels and xi of the 12^3 cells (outside the box: label -1, xi 0), every load
-    // issued together: one round trip.  Cells that cannot carry data for layer l (label
-    // outside [0, l)) enter no sum: their weight is selected to 0.
+    // Stage labels and xi of the 12^3 cells (outside the box: label -1, xi 0).  All loads
+    // of the thread are issued before its first LDS store (the stores cannot be moved
+    // above them), so the staging costs one round trip.  Cells that cannot carry data for
+    // layer l (label outside [0, l)) enter no sum: their weight is selected to 0.
+    // (A cell outside the box loads cell 0 of the box, always there, and is replaced by
+    // label -1 and xi 0 when stored: no load waits on a branch.)
     constexpr int kH = (kBrickCells + 255) / 256;
+    int lbv[kH];
+    bool inb[kH];
+    double v0[kH], v1[kH], v2[kH];
 #pragma unroll
     for (int h = 0; h < kH; ++h) {
         const int q = tid + 256 * h;
         const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
                   z = q / (kBrickSpan * kBrickSpan);
         const int gx = ox + x, gy = oy + y, gz = oz + z;
-        const bool in = q < kBrickCells && (unsigned)gx < (unsigned)n0 &&
-                        (unsigned)gy < (unsigned)n1 && (unsigned)gz < (unsigned)n2;
-        const int c = in ? (gz * n1 + gy) * n0 + gx : 0;
-        int lbv = -1;
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        if (in) {
-            lbv = labels[c];
-            v0 = xi[c];
-            v1 = xi[nc + c];
-            v2 = xi[2 * nc + c];
-        }
+        inb[h] = q < kBrickCells && (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+                 (unsigned)gz < (unsigned)n2;
+        const int c = inb[h] ? (gz * n1 + gy) * n0 + gx : 0;
+        lbv[h] = labels[c];
+        v0[h] = xi[c];
+        v1[h] = xi[nc + c];
+        v2[h] = xi[2 * nc + c];
+    }
+#pragma unroll
+    for (int h = 0; h < kH; ++h) {
+        const int q = tid + 256 * h;
         if (q < kBrickCells) {
-            sl[q] = (int8_t)lbv;
-            sx[q] = v0;
-            sx[kBrickCells + q] = v1;
-            sx[2 * kBrickCells + q] = v2;
+            sl[q] = inb[h] ? (int8_t)lbv[h] : (int8_t)-1;
+            sx[q] = inb[h] ? v0[h] : 0.0;
+            sx[kBrickCells + q] = inb[h] ? v1[h] : 0.0;
+            sx[2 * kBrickCells + q] = inb[h] ? v2[h] : 0.0;
         }
     }
     __syncthreads();
@@ -729,15 +794,19 @@ __device__ __forceinline__ int list_prefix(const Batch& b, int l0, int nl, int* 
     const int n = nl * kBuckets;   // <= 1024: four counts per thread
     int v[4], sum = 0;
 #pragma unroll
+    for (int q = 0; q < 4; ++q) {   // the four loads first
+        const int i = threadIdx.x * 4 + q;
+        v[q] = i < n ? b.bcount[(l0 - 1) * kBuckets + i] : 0;
+    }
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = threadIdx.x * 4 + q;
-        v[q] = 0;
         if (i < n) {
             const int bk = i % kBuckets;
             const int64_t cap = bucket_base(bk + 1, b.n_tiles, b.tile_w) -
                                 bucket_base(bk, b.n_tiles, b.tile_w);
             // entries past a bucket's capacity were never written (reported as overflow)
-            v[q] = (int)min((int64_t)b.bcount[(l0 - 1) * kBuckets + i], cap);
+            v[q] = (int)min((int64_t)v[q], cap);
         }
         sum += v[q];
     }
@@ -785,12 +854,19 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
     const int64_t nc = d->ncell;
     const int ox = kBrick * bx - 1, oy = kBrick * by - 1, oz = kBrick * bz - 1;
     for (int q = tid; q < kNCells; q += 256) s_flag[q] = 0;
-    for (int q = tid; q < kBrick * kBrick * kBrick; q += 256) {
+    const int8_t* __restrict__ labels = d->labels;
+    int8_t lv[2];   // both label loads issued before the LDS stores
+    bool inb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 256 * h;
         const int x = q % kBrick, y = (q / kBrick) % kBrick, z = q / (kBrick * kBrick);
         const int gx = ox + 1 + x, gy = oy + 1 + y, gz = oz + 1 + z;
-        const bool in = gx < n0 && gy < n1 && gz < n2;
-        s_lab[q] = in ? d->labels[((int64_t)gz * n1 + gy) * n0 + gx] : (int8_t)-1;
+        inb[h] = gx < n0 && gy < n1 && gz < n2;
+        lv[h] = labels[inb[h] ? ((int64_t)gz * n1 + gy) * n0 + gx : 0];
     }
+    s_lab[tid] = inb[0] ? lv[0] : (int8_t)-1;
+    s_lab[tid + 256] = inb[1] ? lv[1] : (int8_t)-1;
     __syncthreads();
     // a cell of layer l needs phi0 at itself and at its six face neighbours
     for (int q = tid; q < kBrick * kBrick * kBrick; q += 256) {
@@ -837,19 +913,33 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
         }
         __syncthreads();
     }
-    // phi0 of each needed cell once (defined: inside the box with a finite xi)
+    // phi0 of each needed cell once (defined: inside the box with a finite xi).  A thread
+    // has at most 4 of the <= 1000 cells; their loads are all issued first.
     const ShapeR sh = load_shape(d);
     const double* __restrict__ f = d->xi_normal;
-    for (int i = tid; i < total; i += 256) {
-        const int r = s_list[i];
+    constexpr int kNPer = (kNCells + 255) / 256;
+    double f0[kNPer], f1[kNPer], f2[kNPer];
+    bool fin[kNPer];
+#pragma unroll
+    for (int h = 0; h < kNPer; ++h) {
+        const int i = tid + 256 * h;
+        const int r = i < total ? s_list[i] : 0;
         const int x = r % kNSpan, y = (r / kNSpan) % kNSpan, z = r / (kNSpan * kNSpan);
         const int gx = ox + x, gy = oy + y, gz = oz + z;
-        const bool in = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
-                        (unsigned)gz < (unsigned)n2;
-        const int64_t c = in ? ((int64_t)gz * n1 + gy) * n0 + gx : 0;
-        const double x0 = f[c], x1 = f[nc + c], x2 = f[2 * nc + c];
-        const bool def = in && finite3(x0, x1, x2);
-        s_phi[r] = def ? phi0(sh, x0, x1, x2) : 0.0;
+        fin[h] = i < total && (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+                 (unsigned)gz < (unsigned)n2;
+        const int64_t c = fin[h] ? ((int64_t)gz * n1 + gy) * n0 + gx : 0;
+        f0[h] = f[c];   // (c = 0, always in the box, where the cell is not needed)
+        f1[h] = f[nc + c];
+        f2[h] = f[2 * nc + c];
+    }
+#pragma unroll 1
+    for (int h = 0; h < kNPer; ++h) {
+        const int i = tid + 256 * h;
+        if (i >= total) break;
+        const int r = s_list[i];
+        const bool def = fin[h] && finite3(f0[h], f1[h], f2[h]);
+        s_phi[r] = def ? phi0(sh, f0[h], f1[h], f2[h]) : 0.0;
         s_flag[r] = def ? 3 : 1;
     }
     __syncthreads();
@@ -900,10 +990,16 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
         unsigned long long acc[kLT];
 #pragma unroll
         for (int l = 0; l < kLT; ++l) acc[l] = 0ull;
-        for (int t = d->tile_base + tid; t < d->tile_base + d->n_tiles; t += 256)
+        const int L = d->L;
+        for (int t = d->tile_base + tid; t < d->tile_base + d->n_tiles; t += 256) {
+            // every count of the tile loaded at once (entries past L hold no count of
+            // this call and are dropped)
+            int v[kLT];
 #pragma unroll
-            for (int l = 0; l < kLT; ++l)
-                if (l <= d->L) acc[l] += (unsigned)b.tile_cnt[(int64_t)t * kLT + l];
+            for (int l = 0; l < kLT; ++l) v[l] = b.tile_cnt[(int64_t)t * kLT + l];
+#pragma unroll
+            for (int l = 0; l < kLT; ++l) acc[l] += l <= L ? (unsigned)v[l] : 0u;
+        }
 #pragma unroll
         for (int l = 0; l < kLT; ++l)
             if (acc[l]) atomicAdd(&s_acc[l], acc[l]);

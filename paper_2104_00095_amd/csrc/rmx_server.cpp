@@ -390,15 +390,28 @@ int rmx_server_submit(rmx_server* s, int64_t sim_id, const rmx_options* opt, int
 int rmx_server_wait(rmx_server* s, int64_t ticket, rmx_solid_stats* stats, double* latency_s) {
     if (!s) return RMX_E_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return RMX_E_NOTFOUND;
-    s->cv_done.wait(lk, [&] { return it->second.done; });
+    if (s->reqs.find(ticket) == s->reqs.end()) return RMX_E_NOTFOUND;
+    // The lock is released while waiting: a submit may rehash `reqs` (invalidating
+    // iterators) and another waiter of the same ticket may take the result and erase it,
+    // so the request is looked up again by its ticket each time this waiter wakes.
+    bool gone = false;
+    s->cv_done.wait(lk, [&] {
+        const auto w = s->reqs.find(ticket);
+        if (w == s->reqs.end()) {
+            gone = true;
+            return true;
+        }
+        return w->second.done;
+    });
+    if (gone) return RMX_E_NOTFOUND;
+    const auto it = s->reqs.find(ticket);
     const Req& r = it->second;
     if (stats && !r.stats.empty())
         std::memcpy(stats, r.stats.data(), sizeof(rmx_solid_stats) * r.stats.size());
     if (latency_s) *latency_s = r.latency;
     const int status = r.status;
     s->reqs.erase(it);
+    s->cv_done.notify_all();   // another waiter of this ticket now finds it gone
     return status;
 }
 

@@ -30,6 +30,7 @@ EXPORTS = [
     "rmx_extrapolate", "rmx_status_string", "rmx_server_create", "rmx_server_register",
     "rmx_server_field", "rmx_server_submit", "rmx_server_wait", "rmx_server_release",
     "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read", "rmx_autotune",
+    "rmx_set_tuning",
 ]
 
 
@@ -114,6 +115,8 @@ def lib():
         L.rmx_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         L.rmx_autotune.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, P(Options), vp,
                                    ctypes.c_int32, P(Tuning)]
+        L.rmx_set_tuning.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, P(Options),
+                                     P(Tuning)]
         for name in EXPORTS:
             if name != "rmx_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -209,10 +212,24 @@ def _stream_handle(stream):
     return ctypes.c_void_p(int(stream.cuda_stream))
 
 
+def _torch_device_first(device: int):  # noqa: ARG001 - every device is initialised
+    """Initialise torch's GPU runtime before the library's.  PyTorch wheels for ROCm carry
+    their own copy of the HIP and HSA runtimes; when the library's (system) runtime opens
+    the device first, torch's copy then finds no GPU.  Initialised in this order, both
+    work on the same device, and torch tensors can be passed to the library."""
+    try:
+        import torch
+    except ImportError:   # the C ABI alone needs no torch
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 class Context:
     """An rmx context on one device (workspace, graph cache)."""
 
     def __init__(self, device: int = 0, workspace_bytes: int = 0):
+        _torch_device_first(device)
         self.h = ctypes.c_void_p()
         st = lib().rmx_create(int(device), int(workspace_bytes), ctypes.byref(self.h))
         if st != OK:
@@ -249,6 +266,17 @@ class Context:
         if check and st < 0 and st != E_TRUNCATED:
             raise RmxError(st, "rmx_extrapolate")
         return st, ([s.as_dict() for s in stats] if want_stats else None)
+
+    def set_tuning(self, g: Grid, solids: Sequence[Solid], tile_w: int, extrap_blocks: int,
+                   opt: Optional[Options] = None):
+        """Keep the given launch shapes for this batch's shape class (no timing)."""
+        arr = (Solid * len(solids))(*solids)
+        t = Tuning()
+        t.tile_w, t.extrap_blocks, t.ms = int(tile_w), int(extrap_blocks), 0.0
+        st = lib().rmx_set_tuning(self.h, ctypes.byref(g), arr, len(solids),
+                                  ctypes.byref(opt) if opt else None, ctypes.byref(t))
+        if st != OK:
+            raise RmxError(st, "rmx_set_tuning")
 
     def profile_read(self):
         """{phase: (total ms, launches)} for the profiled calls since the last read."""
@@ -312,6 +340,7 @@ class Server:
     """Request loop admitting extrapolation jobs by HBM budget (rmx_server_*)."""
 
     def __init__(self, device: int, hbm_budget_bytes: int, n_streams: int = 4):
+        _torch_device_first(device)
         self.h = ctypes.c_void_p()
         st = lib().rmx_server_create(int(device), int(hbm_budget_bytes), int(n_streams),
                                      ctypes.byref(self.h))

@@ -29,8 +29,13 @@
 #define __constant__
 #define __shared__ static
 #define __launch_bounds__(...)
-#define __align__(n) alignas(n)
+#define __align__(n) __attribute__((aligned(n)))
 #define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(rmx_emu::dyn_lds());
+
+struct alignas(16) uint4 {
+    unsigned x, y, z, w;
+};
+inline uint4 make_uint4(unsigned x, unsigned y, unsigned z, unsigned w) { return {x, y, z, w}; }
 
 struct dim3 {
     unsigned x = 1, y = 1, z = 1;
@@ -170,6 +175,12 @@ template <typename T>
 inline hipError_t hipMalloc(T** p, size_t n) { return hipMalloc(reinterpret_cast<void**>(p), n); }
 hipError_t hipFree(void* p);
 hipError_t hipHostMalloc(void** p, size_t n, unsigned flags);
+// A __device__ variable is host storage here: its address is the symbol's own.
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+    *p = const_cast<void*>(sym);
+    return hipSuccess;
+}
 template <typename T>
 inline hipError_t hipHostMalloc(T** p, size_t n, unsigned flags) {
     return hipHostMalloc(reinterpret_cast<void**>(p), n, flags);
