@@ -176,6 +176,23 @@ int rmx_extrapolate(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
                     int32_t n_solids, const rmx_options* opt, void* hip_stream,
                     rmx_solid_stats* stats);
 
+/* Allocation-free variant of rmx_extrapolate, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and statuses as rmx_extrapolate (the same kernels),
+ * but the workspace is a fixed array of 64 MiB per device, reserved in the library's
+ * device code and held until the process ends, and nothing is allocated: no device,
+ * pinned or graph memory.  Limits, checked on the host before anything is enqueued:
+ * the call's workspace (rmx_workspace_size, about 25 B per box cell with normals) must
+ * not exceed 64 MiB and its descriptors 256 KiB, else RMX_E_WORKSPACE; with `stats` or
+ * RMX_FLAG_SYNC at most 4096 solids (else RMX_E_WORKSPACE); RMX_FLAG_GRAPH and
+ * RMX_FLAG_PROFILE are refused (RMX_E_ARG).  Every such call on one device shares that
+ * device's array, which keeps the last call's contents; calls that overlap on one device
+ * (other contexts, other streams, other host threads) race on it and must be serialised
+ * by the caller. */
+int rmx_extrapolate_noalloc(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
+                            int32_t n_solids, const rmx_options* opt, void* hip_stream,
+                            rmx_solid_stats* stats);
+
 const char* rmx_status_string(int status);
 
 /* Autotuner.  Launch shapes that change no result: the label tile width (1, 2 or 4 words

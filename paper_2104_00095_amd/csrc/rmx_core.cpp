@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -19,6 +20,35 @@ namespace {
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 constexpr int kDefaultCus = 256;
 
+// Workspace of the allocation-free entry point (rmx_extrapolate_noalloc): one array per
+// device the library runs on, held until the process ends, shared by every such call on
+// that device (calls that overlap on one device race on it).  In host code `scratch` is
+// a host-side stand-in for the symbol, not device memory: its device address is taken
+// once per device, with that device current (scratch_address, from rmx_create), and
+// only that address is ever passed to kernels or copies.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Pinned host buffers a context allocates at creation, so that the allocation-free entry
+// point finds them in place: descriptor staging slots and per-solid statistics.
+constexpr size_t kStageBytes = size_t(256) << 10;
+constexpr int kPreallocStatsSolids = 4096;
+
+int scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return RMX_E_ARG;
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return RMX_E_HIP;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return RMX_OK;
+}
 
 void drop_graphs(rmx_ctx* c) {
     for (auto& kv : c->graphs) {
@@ -277,6 +307,21 @@ int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out) {
         rmx_destroy(c);
         return RMX_E_HIP;
     }
+    // Set-up of the allocation-free entry point: this device's scratch address (device
+    // current), fixed-size pinned staging slots and statistics.
+    if (scratch_address(device, &c->scratch) != RMX_OK ||
+        ctx_stats_host(c, (size_t)kStatWords * kPreallocStatsSolids) != RMX_OK) {
+        rmx_destroy(c);
+        return RMX_E_HIP;
+    }
+    for (auto& s : c->stage) {
+        if (hipHostMalloc(&s.host, kStageBytes, hipHostMallocDefault) != hipSuccess) {
+            s.host = nullptr;
+            rmx_destroy(c);
+            return RMX_E_HIP;
+        }
+        s.size = kStageBytes;
+    }
     if (workspace_bytes > 0) {
         if (hipMalloc(&c->ws, workspace_bytes) != hipSuccess) {
             c->ws = nullptr;
@@ -364,6 +409,49 @@ int rmx_extrapolate(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     } else {
         rc = run_batch(c, c->grid_ptrs.data(), solids, n_solids, opt, st, use_graph, 0, sync,
                        nullptr);
+        if (rc != RMX_OK) return rc;
+    }
+    if (!sync) return RMX_OK;
+    return finish_sync(c, st, n_solids, stats);
+}
+
+int rmx_extrapolate_noalloc(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
+                            int32_t n_solids, const rmx_options* opt, void* hip_stream,
+                            rmx_solid_stats* stats) {
+    if (!c || !grid || !solids || n_solids < 1) return RMX_E_ARG;
+    rmx_options def;
+    rmx_default_options(&def);
+    if (!opt) opt = &def;
+    int rc = validate_options(opt);
+    if (rc != RMX_OK) return rc;
+    for (int i = 0; i < n_solids; ++i)
+        if ((rc = validate_solid(grid, solids + i)) != RMX_OK) return rc;
+    if ((opt->flags & RMX_FLAG_PERSISTENT) && !(opt->flags & RMX_FLAG_PER_SOLID))
+        return RMX_E_DISABLED;
+    // graph capture by the library and profiling events would allocate
+    if (opt->flags & (RMX_FLAG_GRAPH | RMX_FLAG_PROFILE)) return RMX_E_ARG;
+    if (!c->scratch) return RMX_E_HIP;
+    const bool sync = stats || (opt->flags & RMX_FLAG_SYNC);
+    if (sync && c->stats_host_n < (size_t)kStatWords * n_solids) return RMX_E_WORKSPACE;
+    if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
+    // Plan every launch first: nothing is enqueued unless all of them fit the scratch
+    // array and the staging slots.
+    const bool per_solid = (opt->flags & RMX_FLAG_PER_SOLID) != 0;
+    const int calls = per_solid ? n_solids : 1;
+    c->grid_ptrs.assign(n_solids, grid);
+    c->noalloc_plans.resize(calls);
+    for (int i = 0; i < calls; ++i) {
+        Plan& p = c->noalloc_plans[i];
+        rc = plan_call(c, c->grid_ptrs.data() + (per_solid ? i : 0), solids + (per_solid ? i : 0),
+                       per_solid ? 1 : n_solids, opt, nullptr, &p);
+        if (rc != RMX_OK) return rc;
+        if (p.ws_bytes > kScratchBytes || p.desc_bytes > kStageBytes) return RMX_E_WORKSPACE;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < calls; ++i) {
+        rc = launch_planned(c, c->noalloc_plans[i], per_solid ? 1 : n_solids, opt, st, false,
+                            (size_t)kStatWords * (per_solid ? i : 0), sync, c->scratch,
+                            kScratchBytes, true);
         if (rc != RMX_OK) return rc;
     }
     if (!sync) return RMX_OK;

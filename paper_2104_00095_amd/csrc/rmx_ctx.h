@@ -49,6 +49,8 @@ struct rmx_ctx {
     std::unordered_map<uint64_t, rmx::Tuning> tuned;   // launch shapes per tune_key
     std::vector<rmx_solid_stats> tmp_stats;
     std::vector<const rmx_grid*> grid_ptrs;
+    void* scratch = nullptr;   // device address of this device's allocation-free workspace
+    std::vector<rmx::Plan> noalloc_plans;
     rmx::Profiler prof;
 };
 

@@ -30,7 +30,7 @@ EXPORTS = [
     "rmx_extrapolate", "rmx_status_string", "rmx_server_create", "rmx_server_register",
     "rmx_server_field", "rmx_server_submit", "rmx_server_wait", "rmx_server_release",
     "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read", "rmx_autotune",
-    "rmx_set_tuning",
+    "rmx_set_tuning", "rmx_extrapolate_noalloc",
 ]
 
 
@@ -115,6 +115,8 @@ def lib():
         L.rmx_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         L.rmx_autotune.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, P(Options), vp,
                                    ctypes.c_int32, P(Tuning)]
+        L.rmx_extrapolate_noalloc.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32,
+                                              P(Options), vp, P(SolidStats)]
         L.rmx_set_tuning.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, P(Options),
                                      P(Tuning)]
         for name in EXPORTS:
@@ -265,6 +267,20 @@ class Context:
                                    stats)
         if check and st < 0 and st != E_TRUNCATED:
             raise RmxError(st, "rmx_extrapolate")
+        return st, ([s.as_dict() for s in stats] if want_stats else None)
+
+    def extrapolate_noalloc(self, g: Grid, solids: Sequence[Solid],
+                            opt: Optional[Options] = None, stream=None,
+                            want_stats: bool = True, check: bool = True):
+        """The allocation-free call (rmx_extrapolate_noalloc): same results, the workspace
+        is the library's fixed per-device array; returns (status, [stats] or None)."""
+        arr = (Solid * len(solids))(*solids)
+        stats = (SolidStats * len(solids))() if want_stats else None
+        st = lib().rmx_extrapolate_noalloc(self.h, ctypes.byref(g), arr, len(solids),
+                                           ctypes.byref(opt) if opt else None,
+                                           _stream_handle(stream), stats)
+        if check and st < 0 and st != E_TRUNCATED:
+            raise RmxError(st, "rmx_extrapolate_noalloc")
         return st, ([s.as_dict() for s in stats] if want_stats else None)
 
     def set_tuning(self, g: Grid, solids: Sequence[Solid], tile_w: int, extrap_blocks: int,

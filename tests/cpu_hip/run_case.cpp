@@ -91,14 +91,21 @@ int main(int argc, char** argv) {
                 tmp[i].xi = x;
             }
             rmx_options po = o;
-            po.flags = pf;
-            rmx_extrapolate(ctx, &g, tmp.data(), ns, &po, nullptr, stats.data());
+            po.flags = pf & ~4096u;
+            if (pf & 4096u)
+                rmx_extrapolate_noalloc(ctx, &g, tmp.data(), ns, &po, nullptr, stats.data());
+            else
+                rmx_extrapolate(ctx, &g, tmp.data(), ns, &po, nullptr, stats.data());
             for (int i = 0; i < ns; ++i) hipFree(tmp[i].xi);
         }
         std::fclose(pre);
     }
-    for (int r = 0; r < reps; ++r) st = rmx_extrapolate(ctx, &g, sol.data(), ns, &o, nullptr,
-                                                         stats.data());
+    // flag bit 4096 (not a library flag): the measured call is the allocation-free entry
+    const bool noalloc = (o.flags & 4096u) != 0;
+    o.flags &= ~4096u;
+    for (int r = 0; r < reps; ++r)
+        st = noalloc ? rmx_extrapolate_noalloc(ctx, &g, sol.data(), ns, &o, nullptr, stats.data())
+                     : rmx_extrapolate(ctx, &g, sol.data(), ns, &o, nullptr, stats.data());
     FILE* out = std::fopen((dir + "/status.txt").c_str(), "w");
     std::fprintf(out, "%d\n", st);
     std::fclose(out);

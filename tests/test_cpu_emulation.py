@@ -24,6 +24,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host c
 TOL = {0: 1e-12, 1: 1e-5}
 BATCHED, PER_SOLID, GRAPH, PERSISTENT = 0, 4, 2, 16
 AUTOTUNE = 1024   # (run_case: run the autotuner on the fields first)
+NOALLOC = 4096    # (run_case: make the call through the allocation-free entry point)
 
 
 def _truncation_batch():
@@ -74,6 +75,10 @@ def _runs():
         # F1 and a normal-weighted radius-4 fit (gathers from global memory)
         "plates": (plates, 0, BATCHED, (), {"xi_normal": [plates_xn]}),
         "plates_fp32_per_solid": (plates, 1, PER_SOLID, (), {"xi_normal": [plates_xn]}),
+        # the allocation-free entry point (the static scratch array), after calls of both
+        # entry points on a larger batch (the scratch keeps their contents)
+        "noalloc": (sphere, 0, NOALLOC, (BATCHED, NOALLOC | PER_SOLID)),
+        "noalloc_suspension_per_solid": (susp, 1, NOALLOC | PER_SOLID, (NOALLOC,)),
     }
 
 
@@ -162,3 +167,12 @@ def test_emulated_f1_and_grown_normal_fit(emulated, name):
     _check(w, outs, prec, xn)
     dec = outs[0][2]
     assert np.all(dec[:, :, [3, 5, 6]] == 32) and dec[4, 4, 8] == 4
+
+
+@pytest.mark.parametrize("name", ["noalloc", "noalloc_suspension_per_solid"])
+def test_emulated_noalloc_entry(emulated, name):
+    """rmx_extrapolate_noalloc on the static scratch array, after earlier calls on the same
+    context left their contents there."""
+    w, prec, st, outs, xn = emulated[name]
+    assert st == 0
+    _check(w, outs, prec, xn)
