@@ -149,7 +149,7 @@ uint64_t tune_key(const Plan& p) {
 
 int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
               const rmx_options* opt, const Tuning* force, Plan* p) {
-    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, p);
+    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, p, c->normal_per_cu);
     if (rc != RMX_OK) return rc;
     Tuning tn{};
     if (force) {
@@ -158,7 +158,8 @@ int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
         const auto it = c->tuned.find(tune_key(*p));
         if (it != c->tuned.end()) tn = it->second;
     }
-    if (tn.tile_w || tn.extrap_blocks) rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, p);
+    if (tn.tile_w || tn.extrap_blocks)
+        rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, p, c->normal_per_cu);
     return rc;
 }
 
@@ -298,6 +299,7 @@ int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) ==
             hipSuccess && v > 0)
         c->cus = v;
+    c->normal_per_cu = normal_blocks_per_cu();
     for (auto& s : c->stage)
         if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
             rmx_destroy(c);

@@ -71,9 +71,11 @@ int validate_options(const rmx_options* opt);
 // need_fields = false: the field pointers are not checked (sizing, server templates).
 int validate_solid(const rmx_grid* grid, const rmx_solid* s, bool need_fields = true);
 
-// Plan a batch: solid i lives on grid grids[i].  `cu` = compute units of the device.
+// Plan a batch: solid i lives on grid grids[i].  `cu` = compute units of the device,
+// `normal_per_cu` = blocks of the normal kernel resident per compute unit.
 int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,
-         const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p);
+         const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p,
+         int normal_per_cu = 4);
 void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b);
 void pack_desc(const Plan& p, void* host);
 hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,

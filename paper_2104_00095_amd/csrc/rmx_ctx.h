@@ -29,6 +29,7 @@ struct rmx_ctx {
     int device = 0;
     size_t lds_limit = 65536;
     int cus = 256;
+    int normal_per_cu = 4;   // resident blocks of the normal kernel per compute unit
     bool fixed = false;
     bool exact_ws = false;   // grow the workspace to exactly what a call needs (server)
     void* ws = nullptr;

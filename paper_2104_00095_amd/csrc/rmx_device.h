@@ -9,6 +9,19 @@ namespace dev {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// A load through the global address space.  Pointers read from the descriptors are
+// generic, and generic (flat) loads may complete out of order with LDS accesses, so the
+// compiler waits for all of them at once; global loads complete in issue order, and a
+// use waits only for the loads issued before it.  (The host emulation of the kernels
+// defines RMX_GLOBAL_AS away.)
+#ifndef RMX_GLOBAL_AS
+#define RMX_GLOBAL_AS __attribute__((address_space(1)))
+#endif
+template <typename T>
+__device__ __forceinline__ T load_global(const T* p) {
+    return *(const RMX_GLOBAL_AS T*)p;
+}
+
 // ------------------------------------------------------------------------------------
 // phi0 and the interior predicate.  Evaluated without contraction, in the fixed order the
 // interface documents, so that the interior decision and the normal's sign test are

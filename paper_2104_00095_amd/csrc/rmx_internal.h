@@ -38,7 +38,11 @@ constexpr int kBrick = 8;
 constexpr int kBrickHalo = 2;
 constexpr int kBrickSpan = kBrick + 2 * kBrickHalo;                // 12
 constexpr int kBrickCells = kBrickSpan * kBrickSpan * kBrickSpan;  // 1728
-constexpr size_t kBrickLds = kBrickCells * 25 + 512 * 2;          // xi, labels, cell list
+// LDS of a brick: staged xi (FP64, or FP32 offsets in the reduced-precision form), one
+// state byte per cell, and the list of the brick's layer cells.
+constexpr size_t brick_lds_bytes(int precision) {
+    return kBrickCells * (3 * (precision == 1 ? 4 : 8) + 1) + 512 * 2;
+}
 
 // One solid as the kernels see it.
 struct DevSolid {
@@ -102,6 +106,8 @@ hipError_t launch_classify(const Batch& b, hipStream_t st);
 size_t label_lds_bytes(int Lmax, int tile_w, int Wmax);
 hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st);
 hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st);
+// Blocks of the normal kernel resident per compute unit (occupancy, queried once).
+int normal_blocks_per_cu();
 hipError_t launch_extrap(const Batch& b, int layer, int precision, int blocks,
                          hipStream_t st);
 

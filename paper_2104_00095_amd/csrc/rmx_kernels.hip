@@ -168,6 +168,12 @@ __global__ __launch_bounds__(256) void k_classify(Batch b) {
 // ------------------------------------------------------------------------------------
 constexpr int kRowsPerThread = 9;   // ceil((16 + 2 * 16)^2 / 256)
 
+// Brick r of a tile's layer-l flags (r = brick row pair * 8 * MAXTW + 8 w + g).
+template <int MAXTW>
+__device__ __forceinline__ bool brick_flag(const unsigned int* s_bmask, int l, int r) {
+    return (s_bmask[(l - 1) * 4 + r / (8 * MAXTW)] >> (r % (8 * MAXTW))) & 1u;
+}
+
 // Labels of a tile with no layer cell: -1 everywhere (and decision 0).  Whole-width tiles
 // with 16-byte aligned rows store 16-byte chunks, consecutive threads on consecutive
 // chunks of a row; other tiles store their rows byte by byte.
@@ -213,7 +219,8 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     unsigned long long* lds = reinterpret_cast<unsigned long long*>(lds_d);
     __shared__ int s_cnt[kLT];
     __shared__ int s_trunc;
-    __shared__ unsigned char s_bflag[kMaxLayers * FPL];
+    __shared__ unsigned int s_bmask[kMaxLayers * 4];   // bricks holding layer-l cells:
+                                                        // [l-1][2 x 2 brick rows], bit 8w + g
 
     const int t = blockIdx.x;
     const int s = uniform_int(b.tile_solid[t]);
@@ -228,15 +235,16 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     const int wx0 = txi * MAXTW, tw = min(MAXTW, W - wx0);
     const int xr0 = max(0, wx0 - 1), xr1 = min(W, wx0 + tw + 1);
     const int RW = xr1 - xr0;
+    const int RS = RW | 1;   // row stride in words: odd, so that rows fall on distinct banks
     const int j0 = tyi * kTileJ, k0 = tzi * kTileK;
     const int RJ = kTileJ + 2 * L, RK = kTileK + 2 * L;
     const int R = RJ * RK;
     unsigned long long* A = lds;
-    unsigned long long* B = lds + (size_t)RW * R;
+    unsigned long long* B = lds + (size_t)RS * R;
     const unsigned long long tail = (n0 & 63) ? ((1ull << (n0 & 63)) - 1ull) : ~0ull;
     const unsigned long long* __restrict__ mask = d->mask;
 
-    for (int q = tid; q < L * FPL; q += 256) s_bflag[q] = 0;
+    for (int q = tid; q < L * 4; q += 256) s_bmask[q] = 0u;
     if (tid < kLT) s_cnt[tid] = 0;
     if (tid == 0) s_trunc = 0;
     // The mask rows of the region (rows outside the box: empty).  Every load of the
@@ -270,7 +278,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
         if (rr < R) {
 #pragma unroll
             for (int w = 0; w < MW; ++w)
-                if (w < RW) A[rr * RW + w] = mv[q][w];
+                if (w < RW) A[rr * RS + w] = mv[q][w];
         }
     }
     __syncthreads();
@@ -278,7 +286,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     const int tj = tid % kTileJ, tk = tid / kTileJ;
     const int jrow = j0 + tj, krow = k0 + tk;
     const bool row_ok = jrow < n1 && krow < n2;
-    const int my = ((tk + L) * RJ + (tj + L)) * RW + (wx0 - xr0);
+    const int my = ((tk + L) * RJ + (tj + L)) * RS + (wx0 - xr0);
     unsigned long long prev[MAXTW], p0[MAXTW], p1[MAXTW], p2[MAXTW], p3[MAXTW], p4[MAXTW];
     int cnt0 = 0;
     bool trunc = false;
@@ -303,8 +311,11 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                      (!d->wall_lo[2] && krow < L) || (!d->wall_hi[2] && krow >= n2 - L);
         }
     }
-    // counts: LDS atomics of the non-zero per-thread counts (no block-wide scan)
-    if (cnt0) atomicAdd(&s_cnt[0], cnt0);
+    // counts: wave sums, then one LDS atomic per wave
+    const int lane = tid & 63;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt0 += __shfl_xor(cnt0, o, 64);
+    if (lane == 0 && cnt0) atomicAdd(&s_cnt[0], cnt0);
     if (trunc) s_trunc = 1;
 
     const int by2 = (tk >> 3) * 2 + (tj >> 3);   // which of the tile's 2 x 2 brick rows
@@ -320,7 +331,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
             const int rk = l + i / SJ, rj = l + i % SJ;
             const int jj = j0 - L + rj, kk = k0 - L + rk;
             const bool rok = jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
-            const int base = (rk * RJ + rj) * RW;
+            const int base = (rk * RJ + rj) * RS;
             unsigned long long c[MW];
 #pragma unroll
             for (int w = 0; w < MW; ++w) c[w] = w < RW ? Ar[base + w] : 0ull;
@@ -331,8 +342,8 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                 const unsigned long long left = w > 0 ? c[w - 1] : 0ull;
                 const unsigned long long right = w < MW - 1 ? c[w + 1] : 0ull;
                 const unsigned long long v = c[w] | (c[w] << 1) | (c[w] >> 1) | (left >> 63) |
-                                             (right << 63) | Ar[idx - RW] | Ar[idx + RW] |
-                                             Ar[idx - RW * RJ] | Ar[idx + RW * RJ];
+                                             (right << 63) | Ar[idx - RS] | Ar[idx + RS] |
+                                             Ar[idx - RS * RJ] | Ar[idx + RS * RJ];
                 const unsigned long long vm = !rok ? 0ull : (xr0 + w == W - 1 ? tail : ~0ull);
                 Br[idx] = v & vm;
             }
@@ -342,6 +353,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
         A = B;
         B = tmp;
         int cnt = 0;
+        unsigned int fl = 0u;   // bricks of this row holding a layer-l cell: bit 8w + g
 #pragma unroll
         for (int w = 0; w < MAXTW; ++w) {
             const unsigned long long dl = (row_ok && w < tw) ? A[my + w] : 0ull;
@@ -355,9 +367,19 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
             cnt += __popcll(nw);
 #pragma unroll
             for (int g = 0; g < 8; ++g)
-                if ((nw >> (8 * g)) & 255ull) s_bflag[(l - 1) * FPL + by2 * 8 * MAXTW + w * 8 + g] = 1;
+                if ((nw >> (8 * g)) & 255ull) fl |= 1u << (w * 8 + g);
         }
-        if (cnt) atomicAdd(&s_cnt[l], cnt);
+        // Wave sums of the counts; the flags ORed over the lanes of one brick row pair (a
+        // wave's lanes share tk >> 3; lane bit 3 is tj >> 3): then a few LDS atomics.
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0 && cnt) atomicAdd(&s_cnt[l], cnt);
+        fl |= __shfl_xor(fl, 1, 64);
+        fl |= __shfl_xor(fl, 2, 64);
+        fl |= __shfl_xor(fl, 4, 64);
+        fl |= __shfl_xor(fl, 16, 64);
+        fl |= __shfl_xor(fl, 32, 64);
+        if ((lane & 0x37) == 0 && fl) atomicOr(&s_bmask[(l - 1) * 4 + by2], fl);
     }
     __syncthreads();   // counts, flags and the last step complete; A/B free
     if (tid <= L) b.tile_cnt[(int64_t)t * kLT + tid] = s_cnt[tid];
@@ -367,8 +389,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     // bucket: wave 0 counts every layer, reserves all layers' slots with one round of
     // atomics, then writes the entries.  A brick lies in exactly one tile, so a tile lists
     // at most FPL bricks per layer and its bucket never overflows.
-    if (tid < 64) {
-        const int lane = tid;
+    if (tid < 64) {   // (lane == tid)
         const int bk = t % kBuckets;
         const int64_t base0 = bucket_base(bk, b.n_tiles, b.tile_w);
         const int64_t cap = bucket_base(bk + 1, b.n_tiles, b.tile_w) - base0;
@@ -376,7 +397,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
         for (int l = 1; l <= L; ++l) {
             int tot = 0;
             for (int f0 = 0; f0 < FPL; f0 += 64)
-                tot += __popcll(__ballot(f0 + lane < FPL && s_bflag[(l - 1) * FPL + f0 + lane]));
+                tot += __popcll(__ballot(f0 + lane < FPL && brick_flag<MAXTW>(s_bmask, l, f0 + lane)));
             if (lane == l - 1) mytot = tot;
         }
         int mybase = 0;
@@ -386,7 +407,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
             int run = 0;
             for (int f0 = 0; f0 < FPL; f0 += 64) {
                 const int r = f0 + lane;
-                const bool f = r < FPL && s_bflag[(l - 1) * FPL + r];
+                const bool f = r < FPL && brick_flag<MAXTW>(s_bmask, l, r);
                 const unsigned long long bal = __ballot(f);
                 if (f) {
                     const int pos = lbase + run + __popcll(bal & ((1ull << lane) - 1ull));
@@ -414,7 +435,8 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                       (reinterpret_cast<uintptr_t>(d->labels) & 7) == 0 &&
                       (!d->decisions || (reinterpret_cast<uintptr_t>(d->decisions) & 7) == 0);
     if (full) {   // uniform
-        unsigned long long* T = lds;   // [256 rows][8 * MAXTW] label words
+        constexpr int TS = 8 * MAXTW + 1;   // padded row stride: rows on distinct banks
+        unsigned long long* T = lds;         // [256 rows][TS] label words
 #pragma unroll
         for (int w = 0; w < MAXTW; ++w) {
 #pragma unroll
@@ -427,7 +449,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                     (spread8((uint32_t)(p3[w] >> sh8) & 255u) << 3) |
                     (spread8((uint32_t)(p4[w] >> sh8) & 255u) << 4);
                 word |= spread8((uint32_t)(~prev[w] >> sh8) & 255u) * 0xFFull;
-                T[tid * (8 * MAXTW) + w * 8 + g] = word;
+                T[tid * TS + w * 8 + g] = word;
             }
         }
         __syncthreads();
@@ -439,7 +461,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
             const int rj = j0 + row % kTileJ, rk = k0 + row / kTileJ;
             if (rj < n1 && rk < n2) {
                 const int64_t o = ((int64_t)rk * n1 + rj) * n0 + wx0 * 64 + 8 * off;
-                reinterpret_cast<unsigned long long*>(d->labels + o)[0] = T[row * CPR + off];
+                reinterpret_cast<unsigned long long*>(d->labels + o)[0] = T[row * TS + off];
                 if (d->decisions) reinterpret_cast<unsigned long long*>(d->decisions + o)[0] = 0ull;
             }
         }
@@ -488,67 +510,76 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
 // ------------------------------------------------------------------------------------
 // Extrapolation of the layer-l cells of one brick, staged in LDS.
 // ------------------------------------------------------------------------------------
-// Moments of the eligible data of radius r_s = 2 around staged cell idx.  A lane takes
-// whole rows (dy, dz); within a row the five data (dx = -2..2) are first summed into row
-// moments (sum w, sum w dx, sum w dx^2, sum w v, sum w dx v), which then update the
-// 4 x 4 normal matrix and the right-hand sides once per row.  Branch-free: a datum outside
-// the eligible set (or behind the interface) enters with weight 0 and a zero value
-// (selects, so a non-finite value of an ineligible cell cannot leak in).  The integer
-// moments of the eligible offsets (for the exact rank test) are summed the same way.
-template <int NL, typename T>
-__device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
-                                           const int8_t* __restrict__ sl,
-                                           const double* __restrict__ s_rlen, int idx, int le,
-                                           bool use_normal, double g0, double g1, double g2,
-                                           double rgn, double a0, double a1, double a2,
-                                           int lq, Moments<T>& acc) {
+// Staged cell states (one byte per cell of the 12^3 region).
+constexpr uint8_t kStNone = 0;   // carries no data for layer l (outside the box, unmarked,
+                                 // or in layer l or above); its staged xi is 0
+constexpr uint8_t kStData = 1;   // a datum for layer l: label in [0, l)
+constexpr uint8_t kStTarget = 2; // a cell of layer l
+
+// Moments of the eligible data of radius r_s = 2 around staged cell idx.  The staged
+// values are xi - A for the brick's anchor A (0 where the cell carries no data), so a
+// datum enters as w * v with no selection of the value.  A lane takes whole rows
+// (dy, dz); within a row the five data (dx = -2..2) are first summed into row moments
+// (sum w, sum w dx, sum w dx^2, sum w v, sum w dx v), which then update the 4 x 4 normal
+// matrix and the right-hand sides once per row.  Eq. (weight): w = 2^-(|dx|+|dy|+|dz|),
+// times, with the normal, (x_e - x_d).n / |x_e - x_d| where that is positive; the sign
+// is decided on (dx gx + dy gy) + dz gz, in that order, without contraction.  The integer
+// moments of the positive-weight offsets (for the exact rank test) are summed the same way.
+template <int NL, bool NRM, typename T>
+__device__ __forceinline__ void gather_lds(const T* __restrict__ sx,
+                                           const uint8_t* __restrict__ ss,
+                                           const double* __restrict__ s_rlen, int idx,
+                                           double g0, double g1, double g2, double rgn, int lq,
+                                           Moments<T>& acc) {
     constexpr int S = kBrickSpan, S2 = kBrickSpan * kBrickSpan;
 #pragma unroll 1
     for (int row = lq; row < 25; row += NL) {
         const int dy = row % 5 - 2, dz = row / 5 - 2;
         const int rb = idx + dz * S2 + dy * S;
-        int lab[5];
-        double v0[5], v1[5], v2[5];
+        int st[5];
+        T v0[5], v1[5], v2[5];
 #pragma unroll
         for (int u = 0; u < 5; ++u) {
             const int q = rb + u - 2;
-            lab[u] = sl[q];
+            st[u] = ss[q];
             v0[u] = sx[q];
             v1[u] = sx[kBrickCells + q];
             v2[u] = sx[2 * kBrickCells + q];
         }
         const int rowd2 = dy * dy + dz * dz;
         const double rowbase = ldexp(1.0, -(abs(dy) + abs(dz)));   // 2^-(|dy|+|dz|), exact
+        double ry = 0.0, rz = 0.0;
+        if (NRM) {
+#pragma clang fp contract(off)
+            ry = (double)dy * g1;
+            rz = (double)dz * g2;
+        }
         T s0 = T(0), s1 = T(0), s2 = T(0);
         T t0[3] = {T(0), T(0), T(0)}, t1[3] = {T(0), T(0), T(0)};
         int n = 0, nx = 0, nxx = 0;
 #pragma unroll
         for (int u = 0; u < 5; ++u) {
             const int dx = u - 2;
-            bool e = lab[u] >= 0 && lab[u] < le;
+            bool e = st[u] == kStData;
             double ww = rowbase * (dx == 0 ? 1.0 : (dx == 1 || dx == -1 ? 0.5 : 0.25));
-            if (use_normal) {
+            if (NRM) {
 #pragma clang fp contract(off)
-                const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
-                const double dot = (fx * g0 + fy * g1) + fz * g2;
+                const double dot = ((double)dx * g0 + ry) + rz;
                 e = e && (dot < 0.0);
                 ww = (-dot * s_rlen[dx * dx + rowd2] * rgn) * ww;
             }
             const T w = e ? (T)ww : T(0);
-            const T p0 = w * (e ? (T)(v0[u] - a0) : T(0));
-            const T p1 = w * (e ? (T)(v1[u] - a1) : T(0));
-            const T p2 = w * (e ? (T)(v2[u] - a2) : T(0));
             s0 += w;
-            t0[0] += p0;
-            t0[1] += p1;
-            t0[2] += p2;
+            t0[0] = fma(w, v0[u], t0[0]);
+            t0[1] = fma(w, v1[u], t0[1]);
+            t0[2] = fma(w, v2[u], t0[2]);
             if (dx != 0) {   // resolved at compile time (the loop is unrolled)
-                const T fx = (T)dx;
-                s1 += fx * w;
-                s2 += (fx * fx) * w;
-                t1[0] += fx * p0;
-                t1[1] += fx * p1;
-                t1[2] += fx * p2;
+                const T wx = (T)dx * w;
+                s1 += wx;
+                s2 = fma((T)dx, wx, s2);
+                t1[0] = fma(wx, v0[u], t1[0]);
+                t1[1] = fma(wx, v1[u], t1[1]);
+                t1[2] = fma(wx, v2[u], t1[2]);
             }
             const int ei = e ? 1 : 0;
             n += ei;
@@ -558,20 +589,20 @@ __device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
         const T fy = (T)dy, fz = (T)dz;
         acc.m[0] += s0;
         acc.m[1] += s1;
-        acc.m[2] += fy * s0;
-        acc.m[3] += fz * s0;
+        acc.m[2] = fma(fy, s0, acc.m[2]);
+        acc.m[3] = fma(fz, s0, acc.m[3]);
         acc.m[4] += s2;
-        acc.m[5] += fy * s1;
-        acc.m[6] += fz * s1;
-        acc.m[7] += (fy * fy) * s0;
-        acc.m[8] += (fy * fz) * s0;
-        acc.m[9] += (fz * fz) * s0;
+        acc.m[5] = fma(fy, s1, acc.m[5]);
+        acc.m[6] = fma(fz, s1, acc.m[6]);
+        acc.m[7] = fma(fy * fy, s0, acc.m[7]);
+        acc.m[8] = fma(fy * fz, s0, acc.m[8]);
+        acc.m[9] = fma(fz * fz, s0, acc.m[9]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             acc.r[c] += t0[c];
             acc.r[3 + c] += t1[c];
-            acc.r[6 + c] += fy * t0[c];
-            acc.r[9 + c] += fz * t0[c];
+            acc.r[6 + c] = fma(fy, t0[c], acc.r[6 + c]);
+            acc.r[9 + c] = fma(fz, t0[c], acc.r[9 + c]);
         }
         acc.g[0] += n + (nxx << 16);
         acc.g[1] += nx + ((dy * nx) << 16);
@@ -581,14 +612,17 @@ __device__ __forceinline__ void gather_lds(const double* __restrict__ sx,
     }
 }
 
-// The fits of the compacted layer-l cells of a staged brick, NL lanes per cell.
+// The fits of the compacted layer-l cells of a staged brick, NL lanes per cell.  Values
+// are relative to the brick's anchor A: xi_e = A + the fitted intercept.
 template <int NL, typename T>
 __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
                                           unsigned long long* st, int l, int ox, int oy, int oz,
-                                          int total, unsigned char* lds, const double* s_rlen) {
-    const double* sx = reinterpret_cast<const double*>(lds);
-    const int8_t* sl = reinterpret_cast<const int8_t*>(lds + kBrickCells * 24);
-    const uint16_t* cells = reinterpret_cast<const uint16_t*>(lds + kBrickCells * 25);
+                                          int total, unsigned char* lds, const double* s_rlen,
+                                          const double* s_anchor) {
+    const T* sx = reinterpret_cast<const T*>(lds);
+    const uint8_t* ss = reinterpret_cast<const uint8_t*>(lds + kBrickCells * 3 * sizeof(T));
+    const uint16_t* cells =
+        reinterpret_cast<const uint16_t*>(lds + kBrickCells * (3 * sizeof(T) + 1));
     const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
     const int64_t nc = d->ncell;
     const double* __restrict__ xi = d->xi;
@@ -617,25 +651,7 @@ __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
             gn1 = d->normals[nc + cell];
             gn2 = d->normals[2 * nc + cell];
         }
-        // Anchor (centring datum): the first face neighbour in a lower layer in the order
-        // -x, +x, -y, +y, -z, +z.  One exists: the neighbour the cell was labelled from.
-        const int nb[6] = {idx - 1, idx + 1, idx - kBrickSpan, idx + kBrickSpan,
-                           idx - kBrickSpan * kBrickSpan, idx + kBrickSpan * kBrickSpan};
-        const int32_t nbg[6] = {cell - 1, cell + 1, cell - n0, cell + n0, cell - n0 * n1,
-                                cell + n0 * n1};
-        int aidx = idx;
         cx.anchor = cell;
-#pragma unroll
-        for (int q = 5; q >= 0; --q) {
-            const int lb = sl[nb[q]];
-            if (lb >= 0 && lb < l) {
-                aidx = nb[q];
-                cx.anchor = nbg[q];
-            }
-        }
-        cx.a0 = sx[aidx];
-        cx.a1 = sx[kBrickCells + aidx];
-        cx.a2 = sx[2 * kBrickCells + aidx];
         cx.g0 = gn0;
         cx.g1 = gn1;
         cx.g2 = gn2;
@@ -656,11 +672,18 @@ __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
             const bool un = has_normal && !f1 && !f2;
             Moments<T> acc;
             zero(acc);
-            if (r == kBrickHalo)
-                gather_lds<NL, T>(sx, sl, s_rlen, idx, l, un, cx.g0, cx.g1, cx.g2, cx.rgn, cx.a0,
-                              cx.a1, cx.a2, lq, acc);
-            else
+            if (r == kBrickHalo) {
+                if (un)
+                    gather_lds<NL, true, T>(sx, ss, s_rlen, idx, cx.g0, cx.g1, cx.g2, cx.rgn, lq,
+                                            acc);
+                else
+                    gather_lds<NL, false, T>(sx, ss, s_rlen, idx, 0.0, 0.0, 0.0, 0.0, lq, acc);
+            } else {
+                cx.a0 = s_anchor[0];
+                cx.a1 = s_anchor[1];
+                cx.a2 = s_anchor[2];
                 gather_any<NL, T>(cx, r, un, lq, acc);
+            }
             reduce_lanes<NL>(acc);
             if (f2) {
                 const double sw = (double)acc.m[0];
@@ -682,9 +705,9 @@ __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
             }
         }
         if (lq == 0) {
-            d->xi[cell] = cx.a0 + res[0];
-            d->xi[nc + cell] = cx.a1 + res[1];
-            d->xi[2 * nc + cell] = cx.a2 + res[2];
+            d->xi[cell] = s_anchor[0] + res[0];
+            d->xi[nc + cell] = s_anchor[1] + res[1];
+            d->xi[2 * nc + cell] = s_anchor[2] + res[2];
             if (d->decisions) d->decisions[cell] = (int8_t)(code + (no_normal ? kDecNoNormal : 0));
             if (code == kDecF1) atomicAdd(st + ST_F1, 1ull);
             if (code == kDecF2) atomicAdd(st + ST_F2, 1ull);
@@ -697,27 +720,29 @@ template <typename T>
 __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
                                              unsigned long long* st, int l, int bx, int by,
                                              int bz, unsigned char* lds, int* s_wave,
-                                             const double* s_rlen) {
-    double* sx = reinterpret_cast<double*>(lds);
-    int8_t* sl = reinterpret_cast<int8_t*>(lds + kBrickCells * 24);
-    uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * 25);
+                                             double* s_anchor, const double* s_rlen) {
+    T* sx = reinterpret_cast<T*>(lds);
+    uint8_t* ss = reinterpret_cast<uint8_t*>(lds + kBrickCells * 3 * sizeof(T));
+    uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * (3 * sizeof(T) + 1));
     // re-derived per brick: the staging index math is not kept live across bricks
     const int tid = opaque_lane_value(threadIdx.x);
+    const int lane = tid & 63, wid = tid >> 6;
     const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
     const int64_t nc = d->ncell;
     const double* __restrict__ xi = d->xi;
     const int8_t* __restrict__ labels = d->labels;
     const int ox = kBrick * bx - kBrickHalo, oy = kBrick * by - kBrickHalo,
               oz = kBrick * bz - kBrickHalo;
-    // Stage labels and xi of the 12^3 cells (outside the box: label -1, xi 0).  All loads
-    // of the thread are issued before its first LDS store (the stores cannot be moved
-    // above them), so the staging costs one round trip.  Cells that cannot carry data for
-    // layer l (label outside [0, l)) enter no sum: their weight is selected to 0.
-    // (A cell outside the box loads cell 0 of the box, always there, and is replaced by
-    // label -1 and xi 0 when stored: no load waits on a branch.)
+    // Stage labels and xi of the 12^3 cells.  All loads of the thread are issued before
+    // its first LDS store (the stores cannot be moved above them), so the staging costs
+    // one round trip.  A cell outside the box loads cell 0 of the box, always there, and
+    // is replaced by "no data": no load waits on a branch.
+    // The labels are loaded first: the anchor search below needs only them (loads
+    // complete in issue order), so it overlaps the xi loads still in flight.
     constexpr int kH = (kBrickCells + 255) / 256;
-    int lbv[kH];
-    bool inb[kH];
+    int lraw[kH];  // the label loaded (cell 0's outside the box)
+    int cidx[kH];  // the cell loaded (0 outside the box)
+    unsigned inmask = 0u;   // bit h: cell h of the thread lies in the box
     double v0[kH], v1[kH], v2[kH];
 #pragma unroll
     for (int h = 0; h < kH; ++h) {
@@ -725,22 +750,61 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
         const int x = q % kBrickSpan, y = (q / kBrickSpan) % kBrickSpan,
                   z = q / (kBrickSpan * kBrickSpan);
         const int gx = ox + x, gy = oy + y, gz = oz + z;
-        inb[h] = q < kBrickCells && (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
-                 (unsigned)gz < (unsigned)n2;
-        const int c = inb[h] ? (gz * n1 + gy) * n0 + gx : 0;
-        lbv[h] = labels[c];
-        v0[h] = xi[c];
-        v1[h] = xi[nc + c];
-        v2[h] = xi[2 * nc + c];
+        const bool in = q < kBrickCells && (unsigned)gx < (unsigned)n0 &&
+                        (unsigned)gy < (unsigned)n1 && (unsigned)gz < (unsigned)n2;
+        cidx[h] = in ? (gz * n1 + gy) * n0 + gx : 0;
+        inmask |= in ? 1u << h : 0u;
+        lraw[h] = load_global(labels + cidx[h]);
     }
+#pragma unroll
+    for (int h = 0; h < kH; ++h) {
+        const int c = cidx[h];
+        v0[h] = load_global(xi + c);
+        v1[h] = load_global(xi + nc + c);
+        v2[h] = load_global(xi + 2 * nc + c);
+    }
+    // nothing that uses a loaded label may be scheduled above the xi loads
+    __builtin_amdgcn_sched_barrier(0);
+    int lbv[kH];   // the cell's label, -1 outside the box
+#pragma unroll
+    for (int h = 0; h < kH; ++h) lbv[h] = (inmask >> h) & 1u ? lraw[h] : -1;
+    // The brick's anchor A: xi of the first staged cell (in staging order) that carries
+    // data for layer l; one exists, since every layer-l cell has a face neighbour in layer
+    // l - 1.  Staged values are xi - A: the fit is invariant to the shift, and the
+    // offsets are small (the region spans 12 cells), which keeps the moments accurate and
+    // lets the reduced-precision form hold them in FP32.
+    // (The wave's first such cell: staged cells q = tid + 256 h are in order of h first,
+    // so it is the lowest lane of the first slot h whose ballot is not empty.)
+    int qf = 0x7fffffff;
+#pragma unroll
+    for (int h = kH - 1; h >= 0; --h) {
+        const unsigned long long m = __ballot(lbv[h] >= 0 && lbv[h] < l);
+        if (m) qf = 256 * h + 64 * wid + __builtin_ctzll(m);
+    }
+    if (lane == 0) s_wave[wid] = qf;
+    __syncthreads();
+    const int qa = min(min(s_wave[0], s_wave[1]), min(s_wave[2], s_wave[3]));
+    if (qa != 0x7fffffff && (qa & 255) == tid) {
+#pragma unroll
+        for (int h = 0; h < kH; ++h)
+            if (h == (qa >> 8)) {
+                s_anchor[0] = v0[h];
+                s_anchor[1] = v1[h];
+                s_anchor[2] = v2[h];
+            }
+    }
+    if (qa == 0x7fffffff && tid == 0) s_anchor[0] = s_anchor[1] = s_anchor[2] = 0.0;
+    __syncthreads();
+    const double A0 = s_anchor[0], A1 = s_anchor[1], A2 = s_anchor[2];
 #pragma unroll
     for (int h = 0; h < kH; ++h) {
         const int q = tid + 256 * h;
         if (q < kBrickCells) {
-            sl[q] = inb[h] ? (int8_t)lbv[h] : (int8_t)-1;
-            sx[q] = inb[h] ? v0[h] : 0.0;
-            sx[kBrickCells + q] = inb[h] ? v1[h] : 0.0;
-            sx[2 * kBrickCells + q] = inb[h] ? v2[h] : 0.0;
+            const bool data = lbv[h] >= 0 && lbv[h] < l;
+            ss[q] = data ? kStData : (lbv[h] == l ? kStTarget : kStNone);
+            sx[q] = data ? (T)(v0[h] - A0) : T(0);
+            sx[kBrickCells + q] = data ? (T)(v1[h] - A1) : T(0);
+            sx[2 * kBrickCells + q] = data ? (T)(v2[h] - A2) : T(0);
         }
     }
     __syncthreads();
@@ -752,13 +816,13 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
         const int x = kBrickHalo + q % kBrick, y = kBrickHalo + (q / kBrick) % kBrick,
                   z = kBrickHalo + q / (kBrick * kBrick);
         const int idx = (z * kBrickSpan + y) * kBrickSpan + x;
-        mine[h] = sl[idx] == l ? idx : -1;
+        mine[h] = ss[idx] == kStTarget ? idx : -1;
     }
     int total = 0;
     {   // by ballots: wave sums, then each cell's place within its wave
-        const int lane = tid & 63, wid = tid >> 6;
         const unsigned long long b0 = __ballot(mine[0] >= 0), b1 = __ballot(mine[1] >= 0);
         const unsigned long long lt = (1ull << lane) - 1ull;
+        __syncthreads();   // (s_wave was read for the anchor)
         if (lane == 0) s_wave[wid] = __popcll(b0) + __popcll(b1);
         __syncthreads();
         int wb = 0;
@@ -775,11 +839,11 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
 
     // lanes per cell: as many as keep every cell of the brick in one pass of the block
     if (total <= 256 / 16)
-        fit_cells<16, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen);
+        fit_cells<16, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen, s_anchor);
     else if (total <= 256 / 8)
-        fit_cells<8, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen);
+        fit_cells<8, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen, s_anchor);
     else
-        fit_cells<4, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen);
+        fit_cells<4, T>(b, d, st, l, ox, oy, oz, total, lds, s_rlen, s_anchor);
     __syncthreads();   // the LDS is reused by the next brick
 }
 
@@ -863,7 +927,7 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
         const int x = q % kBrick, y = (q / kBrick) % kBrick, z = q / (kBrick * kBrick);
         const int gx = ox + 1 + x, gy = oy + 1 + y, gz = oz + 1 + z;
         inb[h] = gx < n0 && gy < n1 && gz < n2;
-        lv[h] = labels[inb[h] ? ((int64_t)gz * n1 + gy) * n0 + gx : 0];
+        lv[h] = load_global(labels + (inb[h] ? ((int64_t)gz * n1 + gy) * n0 + gx : 0));
     }
     s_lab[tid] = inb[0] ? lv[0] : (int8_t)-1;
     s_lab[tid + 256] = inb[1] ? lv[1] : (int8_t)-1;
@@ -913,33 +977,20 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
         }
         __syncthreads();
     }
-    // phi0 of each needed cell once (defined: inside the box with a finite xi).  A thread
-    // has at most 4 of the <= 1000 cells; their loads are all issued first.
+    // phi0 of each needed cell once (defined: inside the box with a finite xi)
     const ShapeR sh = load_shape(d);
     const double* __restrict__ f = d->xi_normal;
-    constexpr int kNPer = (kNCells + 255) / 256;
-    double f0[kNPer], f1[kNPer], f2[kNPer];
-    bool fin[kNPer];
-#pragma unroll
-    for (int h = 0; h < kNPer; ++h) {
-        const int i = tid + 256 * h;
-        const int r = i < total ? s_list[i] : 0;
+    for (int i = tid; i < total; i += 256) {
+        const int r = s_list[i];
         const int x = r % kNSpan, y = (r / kNSpan) % kNSpan, z = r / (kNSpan * kNSpan);
         const int gx = ox + x, gy = oy + y, gz = oz + z;
-        fin[h] = i < total && (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
-                 (unsigned)gz < (unsigned)n2;
-        const int64_t c = fin[h] ? ((int64_t)gz * n1 + gy) * n0 + gx : 0;
-        f0[h] = f[c];   // (c = 0, always in the box, where the cell is not needed)
-        f1[h] = f[nc + c];
-        f2[h] = f[2 * nc + c];
-    }
-#pragma unroll 1
-    for (int h = 0; h < kNPer; ++h) {
-        const int i = tid + 256 * h;
-        if (i >= total) break;
-        const int r = s_list[i];
-        const bool def = fin[h] && finite3(f0[h], f1[h], f2[h]);
-        s_phi[r] = def ? phi0(sh, f0[h], f1[h], f2[h]) : 0.0;
+        const bool in = (unsigned)gx < (unsigned)n0 && (unsigned)gy < (unsigned)n1 &&
+                        (unsigned)gz < (unsigned)n2;
+        const int64_t c = in ? ((int64_t)gz * n1 + gy) * n0 + gx : 0;
+        const double x0 = load_global(f + c), x1 = load_global(f + nc + c),
+                     x2 = load_global(f + 2 * nc + c);
+        const bool def = in && finite3(x0, x1, x2);
+        s_phi[r] = def ? phi0(sh, x0, x1, x2) : 0.0;
         s_flag[r] = def ? 3 : 1;
     }
     __syncthreads();
@@ -1000,9 +1051,16 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
 #pragma unroll
             for (int l = 0; l < kLT; ++l) acc[l] += l <= L ? (unsigned)v[l] : 0u;
         }
+        // wave sums first: one LDS atomic per wave and count
 #pragma unroll
-        for (int l = 0; l < kLT; ++l)
-            if (acc[l]) atomicAdd(&s_acc[l], acc[l]);
+        for (int l = 0; l < kLT; ++l) {
+            if (l <= L) {   // uniform
+                unsigned long long v = acc[l];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                if ((tid & 63) == 0 && v) atomicAdd(&s_acc[l], v);
+            }
+        }
         __syncthreads();
         if (tid < kLT) b.stats[(int64_t)s * kStatWords + tid] = s_acc[tid];
         __syncthreads();
@@ -1046,6 +1104,7 @@ __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
     HIP_DYNAMIC_SHARED(double, lds_d)
     unsigned char* lds = reinterpret_cast<unsigned char*>(lds_d);
     __shared__ int s_wave[4];
+    __shared__ double s_anchor[3];
     __shared__ double s_rlen[13];   // 1/|d| for |d|^2 = 0..12 (radius 2)
     if (threadIdx.x < 13) s_rlen[threadIdx.x] = c_rlen[threadIdx.x];
     const unsigned long long* dl = b.dlist + (int64_t)(l - 1) * b.dlist_cap;
@@ -1060,7 +1119,7 @@ __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
         const int bz = uniform_int((int)((pk >> 20) & 1023ull));
         unsigned long long* st = b.stats + (int64_t)s * kStatWords;
         if (st[ST_FLAGS] & FLAG_TRUNCATED) continue;   // uniform: whole block skips
-        extrap_brick<T>(b, b.solids + s, st, l, bx, by, bz, lds, s_wave, s_rlen);
+        extrap_brick<T>(b, b.solids + s, st, l, bx, by, bz, lds, s_wave, s_anchor, s_rlen);
     }
 }
 
@@ -1078,8 +1137,8 @@ hipError_t launch_classify(const Batch& b, hipStream_t st) {
 size_t label_lds_bytes(int Lmax, int tile_w, int Wmax) {
     const int RJ = kTileJ + 2 * Lmax, RK = kTileK + 2 * Lmax;
     const int RW = tile_w + 2 < Wmax ? tile_w + 2 : Wmax;
-    const size_t region = sizeof(unsigned long long) * 2 * (size_t)RW * RJ * RK;
-    const size_t rows = (size_t)256 * 64 * tile_w;   // transposed labels of a tile
+    const size_t region = sizeof(unsigned long long) * 2 * (size_t)(RW | 1) * RJ * RK;
+    const size_t rows = (size_t)256 * 8 * (8 * tile_w + 1);   // transposed labels of a tile
     return region > rows ? region : rows;
 }
 
@@ -1095,6 +1154,17 @@ hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st) {
     return hipGetLastError();
 }
 
+int normal_blocks_per_cu() {
+    static const int n = [] {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_normal, 256, 0) != hipSuccess ||
+            v < 1)
+            v = 4;
+        return v;
+    }();
+    return n;
+}
+
 hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st) {
     hipLaunchKernelGGL(k_normal, dim3(blocks), dim3(256), 0, st, b);
     return hipGetLastError();
@@ -1103,9 +1173,11 @@ hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st) {
 hipError_t launch_extrap(const Batch& b, int layer, int precision, int blocks,
                          hipStream_t st) {
     if (precision == 1)
-        hipLaunchKernelGGL(k_extrap<float>, dim3(blocks), dim3(256), kBrickLds, st, b, layer);
+        hipLaunchKernelGGL(k_extrap<float>, dim3(blocks), dim3(256), brick_lds_bytes(1), st, b,
+                           layer);
     else
-        hipLaunchKernelGGL(k_extrap<double>, dim3(blocks), dim3(256), kBrickLds, st, b, layer);
+        hipLaunchKernelGGL(k_extrap<double>, dim3(blocks), dim3(256), brick_lds_bytes(0), st, b,
+                           layer);
     return hipGetLastError();
 }
 

@@ -89,7 +89,8 @@ int validate_solid(const rmx_grid* grid, const rmx_solid* sp, bool need_fields) 
 }
 
 int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,
-         const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p) {
+         const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p,
+         int normal_per_cu) {
     p->n_solids = n_solids;
     p->solids.assign(n_solids, DevSolid{});
     p->tile_solid.clear();
@@ -106,7 +107,7 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     if (tw != 1 && tw != 2 && tw != 4) tw = Wmax >= 3 ? 4 : (Wmax == 2 ? 2 : 1);
     while (tw > 1 && label_lds_bytes(p->Lmax, tw, Wmax) > lds_limit) tw /= 2;
     p->lds_bytes = label_lds_bytes(p->Lmax, tw, Wmax);
-    if (p->lds_bytes > lds_limit || kBrickLds > lds_limit) return RMX_E_LAYERS;
+    if (p->lds_bytes > lds_limit || brick_lds_bytes(0) > lds_limit) return RMX_E_LAYERS;
     p->tile_w = tw;
     int64_t words = 0, cells = 0;
     int tiles = 0, chunks = 0;
@@ -169,10 +170,12 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     const int eb = tune.extrap_blocks > 0 ? tune.extrap_blocks : 3 * std::max(cu, 1);
     p->extrap_blocks = (int)std::max<int64_t>(std::min<int64_t>(eb, bricks), 1);
     p->dlist_cap = std::max<int64_t>(bricks, 1);
-    // normal: blocks go through their bricks' ellipsoid bisections one at a time, so more
-    // resident blocks than the fits use, and the dispatcher balances the bricks' costs
+    // normal: as many blocks as are resident at once (each block scans the brick lists
+    // once, then strides over its bricks), no more than the bricks of its layers
     p->normal_blocks = (int)std::max<int64_t>(
-        std::min<int64_t>(8 * std::max(cu, 1), bricks * std::max(p->normal_layers, 1)), 1);
+        std::min<int64_t>((int64_t)std::max(normal_per_cu, 1) * std::max(cu, 1),
+                          bricks * std::max(p->normal_layers, 1)),
+        1);
 
     // Workspace layout.
     size_t off = 0;

@@ -30,6 +30,8 @@
 #define __shared__ static
 #define __launch_bounds__(...)
 #define __align__(n) __attribute__((aligned(n)))
+#define RMX_GLOBAL_AS   // host memory is the only address space here
+inline void __builtin_amdgcn_sched_barrier(int) {}   // instruction scheduling: nothing to do
 #define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(rmx_emu::dyn_lds());
 
 struct alignas(16) uint4 {
@@ -175,6 +177,12 @@ template <typename T>
 inline hipError_t hipMalloc(T** p, size_t n) { return hipMalloc(reinterpret_cast<void**>(p), n); }
 hipError_t hipFree(void* p);
 hipError_t hipHostMalloc(void** p, size_t n, unsigned flags);
+// Blocks resident per compute unit: the emulation runs blocks in turn, so any count works.
+template <typename F>
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, F, int, size_t) {
+    *n = 2;
+    return hipSuccess;
+}
 // A __device__ variable is host storage here: its address is the symbol's own.
 #define HIP_SYMBOL(x) (&(x))
 inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
