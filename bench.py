@@ -78,7 +78,7 @@ def profile_phases(ctx, dw, opt, steps):
 # Phases of the profiler -> the kernel that runs them (each layer's fit is one launch of
 # the same fit kernel).
 KERNEL_NAMES = {"classify": "k_classify", "label": "k_label", "normal": "k_normal",
-                "extrap": "k_extrap"}
+                "extrap": "k_extrap", "band": "k_band"}
 
 
 def kernel_of(phase):
@@ -177,7 +177,7 @@ def model_bytes(kernel, w, stats):
     cells = w.box_cells
     nb = sum(sum(s["n_band"][1:17]) for s in stats)
     return {"classify": 24.0 * cells, "label": 1.0 * cells, "normal": None,
-            "extrap": 24.0 * nb}[kernel]
+            "extrap": 24.0 * nb, "band": 24.0 * nb}[kernel]
 
 
 def kernel_table(phases, calls, w, stats, cls_bytes):
@@ -473,6 +473,8 @@ def main():
     ap.add_argument("--workload", default="cavity256")
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--graph", action="store_true", help="replay the launch chain as a hipGraph")
+    ap.add_argument("--persistent", action="store_true",
+                    help="the band work (normals and every layer's fits) in one persistent launch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -505,7 +507,7 @@ def main():
     dw = fields.upload(w)
     ctx = rmx.Context(0)
     prec = PRECISIONS[args.precision]
-    flags = rmx.FLAG_GRAPH if args.graph else 0
+    flags = (rmx.FLAG_GRAPH if args.graph else 0) | (rmx.FLAG_PERSISTENT if args.persistent else 0)
     opt = rmx.options(precision=prec, flags=flags)
     tuned = None
     if args.shapes:
@@ -541,7 +543,8 @@ def main():
                 "launches_per_call": d["launches_per_call"],
                 "byte_model": {"classify": "24 B read per box cell",
                                "label": "1 B written per box cell",
-                               "extrap": "24 B written per band cell of the layer"}[dom]}
+                               "extrap": "24 B written per band cell of the layer",
+                               "band": "24 B written per band cell"}[dom]}
         roof["frac"] = roof["achieved"] / roof["peak"]
     B = 25 * cells + 24 * nb
 
@@ -601,6 +604,7 @@ def main():
         "config": {"workload": args.workload, "grid": list(w.grid_n), "solids": len(w.solids),
                    "n_layers": max(s.n_layers for s in w.solids), "band_cells": nb,
                    "box_cells": cells, "precision": args.precision, "graph": args.graph,
+                   "persistent": args.persistent,
                    "launch_shapes": tuned},
         "roofline": roof,
         "call_roofline": {"bound": "hbm", "algorithmic_bytes": B,

@@ -59,7 +59,8 @@ extern "C" {
 #define RMX_E_BUDGET (-8)      /* server: request can never fit the HBM budget             */
 #define RMX_E_BUSY (-9)        /* server: submission queue full                            */
 #define RMX_E_NOTFOUND (-10)   /* server: unknown simulation or ticket                     */
-#define RMX_E_DISABLED (-11)   /* the requested launch form is switched off in this build  */
+#define RMX_E_DISABLED (-11)   /* the requested launch form is switched off in this build
+                                  (no form is switched off at present)                     */
 
 #define RMX_MAX_LAYERS 16
 #define RMX_MAX_RADIUS 4
@@ -74,16 +75,21 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
 #define RMX_FLAG_PER_SOLID 4u  /* plain form: one launch chain per solid, in order        */
 #define RMX_FLAG_PROFILE 8u    /* record HIP events around every kernel of the chain (not
                                   with RMX_FLAG_GRAPH); read with rmx_profile_read         */
-#define RMX_FLAG_PERSISTENT 16u /* all phases of the batch in ONE persistent launch whose
-                                  work items wait on per-slab counters.  Switched off:
-                                  such a call fails with RMX_E_DISABLED.                   */
+#define RMX_FLAG_PERSISTENT 16u /* the band work of the whole batch -- the normals and the
+                                  fits of every layer, over the compacted brick lists -- in
+                                  ONE persistent launch (after the classification and the
+                                  labelling, two dense launches): blocks take bricks by
+                                  ticket from per-XCD queues in layer order, and an item of
+                                  layer l waits (bounded) until layer l - 1 is complete.  A
+                                  wait that runs out reports RMX_E_HIP for the call.       */
 
 /* Kernel phases reported by rmx_profile_read. */
 #define RMX_PHASE_CLASSIFY 0
 #define RMX_PHASE_LABEL 1
 #define RMX_PHASE_NORMAL 2      /* per-solid counts and the normals of layers <= nl      */
 #define RMX_PHASE_EXTRAP 3      /* + (layer - 1), layers 1..RMX_MAX_LAYERS               */
-#define RMX_N_PHASES 19
+#define RMX_PHASE_BAND 19       /* the persistent band launch (RMX_FLAG_PERSISTENT)       */
+#define RMX_N_PHASES 20
 
 /* Grid: M x N x O cells; cell (i,j,k) has centre origin + (idx + 1/2) h (SI, "Variable
  * arrangement"; isotropic spacing as in the paper's runs).  The fit is invariant to h
@@ -164,9 +170,9 @@ int rmx_workspace_size(const rmx_grid* grid, const rmx_solid* solids, int32_t n_
 /* Extrapolate n_solids solids, each independently, enqueued on `hip_stream` (a
  * hipStream_t; NULL = the default stream).  Arguments are validated on the host first
  * (nothing is enqueued on error).  By default the whole batch runs as one chain of
- * kernels, each covering every solid (classify, label, scan, normals, one fit per layer);
- * RMX_FLAG_PER_SOLID runs one chain per solid instead (the plain form), and
- * RMX_FLAG_PERSISTENT is refused with RMX_E_DISABLED.  Calls on one context are ordered
+ * kernels, each covering every solid (classify, label, normals, one fit per layer);
+ * RMX_FLAG_PERSISTENT puts the normals and every layer's fits in one persistent launch;
+ * RMX_FLAG_PER_SOLID runs one chain per solid instead (the plain form).  Calls on one context are ordered
  * on its workspace: issue them on one stream (or serialise them).
  * If `stats` (HOST, n_solids entries) is non-NULL or
  * RMX_FLAG_SYNC is set, the call waits for the stream, fills `stats` and returns the

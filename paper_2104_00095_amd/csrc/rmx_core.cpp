@@ -149,7 +149,8 @@ uint64_t tune_key(const Plan& p) {
 
 int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
               const rmx_options* opt, const Tuning* force, Plan* p) {
-    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, p, c->normal_per_cu);
+    const int bpc = c->band_per_cu[opt->precision == RMX_FP32_ACCUM ? 1 : 0];
+    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, p, c->normal_per_cu, bpc);
     if (rc != RMX_OK) return rc;
     Tuning tn{};
     if (force) {
@@ -159,7 +160,7 @@ int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
         if (it != c->tuned.end()) tn = it->second;
     }
     if (tn.tile_w || tn.extrap_blocks)
-        rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, p, c->normal_per_cu);
+        rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, p, c->normal_per_cu, bpc);
     return rc;
 }
 
@@ -300,6 +301,8 @@ int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out) {
             hipSuccess && v > 0)
         c->cus = v;
     c->normal_per_cu = normal_blocks_per_cu();
+    c->band_per_cu[0] = band_blocks_per_cu(RMX_FP64);
+    c->band_per_cu[1] = band_blocks_per_cu(RMX_FP32_ACCUM);
     for (auto& s : c->stage)
         if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
             rmx_destroy(c);
@@ -390,9 +393,6 @@ int rmx_extrapolate(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     if (rc != RMX_OK) return rc;
     for (int i = 0; i < n_solids; ++i)
         if ((rc = validate_solid(grid, solids + i)) != RMX_OK) return rc;
-    // The single persistent launch is switched off (a GPU memory fault of unknown cause).
-    if ((opt->flags & RMX_FLAG_PERSISTENT) && !(opt->flags & RMX_FLAG_PER_SOLID))
-        return RMX_E_DISABLED;
     if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const bool sync = stats || (opt->flags & RMX_FLAG_SYNC);
@@ -428,8 +428,6 @@ int rmx_extrapolate_noalloc(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* s
     if (rc != RMX_OK) return rc;
     for (int i = 0; i < n_solids; ++i)
         if ((rc = validate_solid(grid, solids + i)) != RMX_OK) return rc;
-    if ((opt->flags & RMX_FLAG_PERSISTENT) && !(opt->flags & RMX_FLAG_PER_SOLID))
-        return RMX_E_DISABLED;
     // graph capture by the library and profiling events would allocate
     if (opt->flags & (RMX_FLAG_GRAPH | RMX_FLAG_PROFILE)) return RMX_E_ARG;
     if (!c->scratch) return RMX_E_HIP;

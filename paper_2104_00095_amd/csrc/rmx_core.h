@@ -29,6 +29,8 @@ struct Plan {
     int tile_w = 1;
     int extrap_blocks = 1;
     int normal_blocks = 1;
+    bool persistent = false;   // the band work in one persistent launch
+    int band_blocks = 1;
     size_t lds_bytes = 0;
     int64_t total_words = 0;
     int64_t total_cells = 0;
@@ -37,7 +39,7 @@ struct Plan {
     // workspace layout (byte offsets); [0, desc_bytes) is uploaded from the host
     size_t off_desc = 0, off_tile_solid = 0, desc_bytes = 0;
     size_t off_stats = 0, off_tile_cnt = 0, off_bcount = 0, off_mask = 0, off_normals = 0;
-    size_t off_blist = 0, off_dcount = 0, off_dlist = 0;
+    size_t off_blist = 0, off_dcount = 0, off_dlist = 0, off_band = 0;
     size_t ws_bytes = 0;
     // red zones between regions (CPU emulation build only): (offset, bytes)
     std::vector<std::pair<size_t, size_t>> gaps;
@@ -75,7 +77,7 @@ int validate_solid(const rmx_grid* grid, const rmx_solid* s, bool need_fields = 
 // `normal_per_cu` = blocks of the normal kernel resident per compute unit.
 int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,
          const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p,
-         int normal_per_cu = 4);
+         int normal_per_cu = 4, int band_per_cu = 2);
 void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b);
 void pack_desc(const Plan& p, void* host);
 hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,

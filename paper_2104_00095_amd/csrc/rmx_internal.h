@@ -27,6 +27,7 @@ constexpr int ST_F2 = 20;
 constexpr int ST_FLAGS = 21;
 constexpr unsigned long long FLAG_TRUNCATED = 1ull;
 constexpr unsigned long long FLAG_OVERFLOW = 2ull;   // brick list full (never expected)
+constexpr unsigned long long FLAG_TIMEOUT = 4ull;    // a bounded wait of the band launch ran out
 
 constexpr int kDecF1 = 32;
 constexpr int kDecF2 = 33;
@@ -72,6 +73,15 @@ struct DevSolid {
     unsigned long long* mask;  // [n2 * n1][W]
 };
 
+// Control words of the persistent band launch (in the workspace, zeroed by the
+// classification of the call).
+struct BandCtl {
+    int taken[kMaxLayers + 1][kXcds];  // items handed out from each queue of each phase
+    int done[kMaxLayers + 1];          // items completed per phase (0: normals, l: layer l)
+    int err;                           // a bounded wait ran out
+    int pad[14];
+};
+
 // Device tables of one batched call (all in the workspace).
 struct Batch {
     const DevSolid* solids;
@@ -92,6 +102,7 @@ struct Batch {
     int64_t dlist_cap;       // dense brick-list entries per layer: the bricks of all boxes
     int32_t* dcount;         // [kMaxLayers] bricks of each layer, written by the normal kernel
     unsigned long long* dlist;  // [Lmax][dlist_cap]: each layer's bricks, contiguous
+    BandCtl* band;           // the persistent band launch's counters
 };
 
 // Bucket b of a layer's brick list holds the bricks of tiles t = b (mod kBuckets), at
@@ -110,5 +121,9 @@ hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st);
 int normal_blocks_per_cu();
 hipError_t launch_extrap(const Batch& b, int layer, int precision, int blocks,
                          hipStream_t st);
+// The persistent band launch (normals and every layer's fits in one launch).
+size_t band_lds_bytes(int precision);
+int band_blocks_per_cu(int precision);
+hipError_t launch_band(const Batch& b, int precision, int blocks, hipStream_t st);
 
 }  // namespace rmx

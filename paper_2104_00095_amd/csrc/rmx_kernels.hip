@@ -146,6 +146,8 @@ __global__ __launch_bounds__(256) void k_classify(Batch b) {
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 256) b.stats[i] = 0ull;
         for (int i = threadIdx.x; i < kMaxLayers * kBuckets; i += 256) b.bcount[i] = 0;
+        const int nctl = (int)(sizeof(BandCtl) / sizeof(int));
+        for (int i = threadIdx.x; i < nctl; i += 256) reinterpret_cast<int*>(b.band)[i] = 0;
     }
     for (int chunk = blockIdx.x; chunk < b.n_chunks; chunk += gridDim.x) {
         const int s = uniform_int(find_solid_by_chunk(b.solids, b.n_solids, chunk));
@@ -1024,16 +1026,10 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
     if (nzero) atomicAdd(st + ST_NONORMAL, (unsigned long long)nzero);   // rare
 }
 
-__global__ __launch_bounds__(256) void k_normal(Batch b) {
-    __shared__ int s_wave[4];
-    __shared__ int s_pref[kMaxLayers * kBuckets + 1];
-    __shared__ unsigned long long s_acc[kLT];
-    __shared__ double s_phi[kNCells];
-    __shared__ unsigned char s_flag[kNCells];
-    __shared__ int8_t s_lab[kBrick * kBrick * kBrick];
-    __shared__ uint16_t s_list[kNCells];
+// Per-solid interior and band counts, the sums of the solids' tile counts, into the
+// statistics (blocks b, b + gridDim.x, ... take solids b, ...).
+__device__ __forceinline__ void solid_counts(const Batch& b, unsigned long long* s_acc) {
     const int tid = threadIdx.x;
-    // per-solid interior and band counts: the sums of the solid's tile counts
     for (int s = blockIdx.x; s < b.n_solids; s += gridDim.x) {
         const DevSolid* d = b.solids + s;
         if (tid < kLT) s_acc[tid] = 0ull;
@@ -1065,6 +1061,18 @@ __global__ __launch_bounds__(256) void k_normal(Batch b) {
         if (tid < kLT) b.stats[(int64_t)s * kStatWords + tid] = s_acc[tid];
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_normal(Batch b) {
+    __shared__ int s_wave[4];
+    __shared__ int s_pref[kMaxLayers * kBuckets + 1];
+    __shared__ unsigned long long s_acc[kLT];
+    __shared__ double s_phi[kNCells];
+    __shared__ unsigned char s_flag[kNCells];
+    __shared__ int8_t s_lab[kBrick * kBrick * kBrick];
+    __shared__ uint16_t s_list[kNCells];
+    const int tid = threadIdx.x;
+    solid_counts(b, s_acc);
     // Dense per-layer brick lists for the fits: entry e of the bucketed lists of layers
     // 1..Lmax goes to its rank within its layer (bucket order), and each layer's count to
     // dcount.  The prefix over all layers also serves the normals' layers 1..nl.
@@ -1123,6 +1131,214 @@ __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
     }
 }
 
+
+// ------------------------------------------------------------------------------------
+// Persistent band launch: the normals and the fits of every layer of the whole batch in
+// ONE launch, over the compacted brick lists.  Work items are bricks: phase 0 the bricks
+// of layers 1..normal_layers (normals), phase l the bricks of layer l (fits).  Each phase
+// is split into kQueues contiguous slices, one queue each, in proportion to the blocks of
+// queue x (blocks b with b % kQueues == x): neighbouring bricks, whose halos overlap, are
+// then mostly fitted on one XCD (the hardware deals blocks to the XCDs round-robin).  A
+// block takes items of its current phase from its own queue, then from any queue with
+// items left, and moves to the next phase only once every queue of its phase is
+// exhausted.  An item of phase p > 0 waits until every item of phase p - 1 is complete
+// (layers in ascending order, "Extrapolation of xi"; the normals are taken from the field
+// before any fit writes).  A block publishes its finished items of a phase (one release,
+// one count) when it leaves the phase, before it can wait; it acquires once per phase it
+// enters, and polls without ordering: an ordered poll would invalidate the XCD's L2 on
+// every read.  Since no block reaches phase p before all items of phase p - 1 were
+// handed out, each to a block that is running, the lowest unfinished phase always has
+// its items in blocks that do not wait: no deadlock, whatever the residency.  Every wait
+// is bounded: past the bound the call's error flag is set, the item is skipped (still
+// counted), and every wave reaches the end.
+// ------------------------------------------------------------------------------------
+constexpr int kQueues = kXcds;
+constexpr int kBandSpin = 1 << 20;   // polls of a bounded wait (each an acquire load and a
+                                     // short sleep: about a second in all)
+
+// Shared memory of the band kernel, carved from its dynamic LDS (no static LDS: the
+// block's whole state lies in its own allocation).
+struct BandLds {
+    unsigned char* work;   // a brick's fit staging, or a brick's normal scratch
+    double* s_phi;
+    unsigned char* s_flag;
+    int8_t* s_lab;
+    uint16_t* s_list;
+    int* s_pref;           // [kMaxLayers * kBuckets + 1]
+    int* s_wave;           // [4]
+    int* s_ctl;            // [4]: ticket, wait result
+    double* s_anchor;      // [3]
+    double* s_rlen;        // [13]
+    unsigned long long* s_acc;  // [kLT]
+};
+
+__host__ __device__ constexpr size_t band_small_bytes() {
+    return sizeof(int) * (kMaxLayers * kBuckets + 1 + 4 + 4) + sizeof(double) * (3 + 13) +
+           sizeof(unsigned long long) * kLT + 64;
+}
+
+__device__ __forceinline__ BandLds band_lds(unsigned char* lds, size_t work_bytes) {
+    BandLds L;
+    L.work = lds;
+    L.s_phi = reinterpret_cast<double*>(lds);
+    L.s_flag = lds + sizeof(double) * kNCells;
+    L.s_lab = reinterpret_cast<int8_t*>(L.s_flag + kNCells);
+    L.s_list = reinterpret_cast<uint16_t*>(lds + sizeof(double) * kNCells + kNCells +
+                                           kBrick * kBrick * kBrick);
+    unsigned char* sm = lds + ((work_bytes + 15) & ~size_t(15));
+    L.s_anchor = reinterpret_cast<double*>(sm);
+    L.s_rlen = L.s_anchor + 3;
+    L.s_acc = reinterpret_cast<unsigned long long*>(L.s_rlen + 13);
+    L.s_pref = reinterpret_cast<int*>(L.s_acc + kLT);
+    L.s_wave = L.s_pref + kMaxLayers * kBuckets + 1;
+    L.s_ctl = L.s_wave + 4;
+    return L;
+}
+
+// Items of phase p (0: bricks of layers 1..nl; p >= 1: bricks of layer p).
+__device__ __forceinline__ int phase_items(const int* s_pref, int p, int nl) {
+    return p == 0 ? s_pref[nl * kBuckets] : s_pref[p * kBuckets] - s_pref[(p - 1) * kBuckets];
+}
+
+// Slice [lo, hi) of a phase's n items held by queue x of nq, over G blocks.
+__device__ __forceinline__ void queue_slice(int n, int G, int nq, int x, int* lo, int* hi) {
+    int before = 0;   // blocks of the queues before x
+    for (int y = 0; y < x; ++y) before += (G - y + nq - 1) / nq;
+    const int mine = (G - x + nq - 1) / nq;
+    *lo = (int)((int64_t)n * before / G);
+    *hi = (int)((int64_t)n * (before + mine) / G);
+}
+
+// Wave 0 of a block: the next item of the block's phase *ph (advanced past exhausted
+// phases); returns its index within the phase, or -1 once every phase is exhausted.
+__device__ int band_take(BandCtl* ctl, const int* s_pref, int nl, int Lmax, int q, int nq,
+                         int* ph) {
+    const int lane = threadIdx.x;
+    const int G = gridDim.x;
+    for (; *ph <= Lmax; ++*ph) {
+        const int p = *ph;
+        const int n = phase_items(s_pref, p, nl);
+        int lo, hi;
+        queue_slice(n, G, nq, q, &lo, &hi);
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&ctl->taken[p][q], 1);
+        t = __shfl(t, 0);
+        if (t < hi - lo) return lo + t;
+        // the other queues: lane i < nq - 1 looks at queue (q + 1 + i) % nq
+        for (;;) {
+            const int x = (q + 1 + lane) % nq;
+            int xlo = 0, xhi = 0, left = 0;
+            if (lane < nq - 1) {
+                queue_slice(n, G, nq, x, &xlo, &xhi);
+                left = __hip_atomic_load(&ctl->taken[p][x], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) < xhi - xlo;
+            }
+            const unsigned long long m = __ballot(left);
+            if (m == 0ull) break;   // phase exhausted
+            const int src = __ffsll((long long)m) - 1;
+            int u = 0;
+            if (lane == src) u = atomicAdd(&ctl->taken[p][x], 1);
+            u = __shfl(u, src);
+            const int ulo = __shfl(xlo, src), uhi = __shfl(xhi, src);
+            if (u < uhi - ulo) return ulo + u;
+        }
+    }
+    return -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 3) void k_band(Batch b, int work_bytes) {
+    HIP_DYNAMIC_SHARED(double, lds_d)
+    const BandLds L = band_lds(reinterpret_cast<unsigned char*>(lds_d), (size_t)work_bytes);
+    BandCtl* ctl = b.band;
+    const int tid = threadIdx.x;
+    if (tid < 13) L.s_rlen[tid] = c_rlen[tid];
+    solid_counts(b, L.s_acc);
+    list_prefix(b, 1, b.Lmax, L.s_pref, L.s_wave);   // (ends with a barrier)
+    const int nl = b.normal_layers;
+    const int nq = gridDim.x < kQueues ? (int)gridDim.x : kQueues;
+    const int q = blockIdx.x % nq;
+    int ph = 0, err = 0;
+    int ready = 0;              // phases before this one are complete and acquired
+    int pend = 0, pend_ph = 0;  // items of phase pend_ph done here and not yet published
+    for (;;) {
+        if (tid < 64) {
+            int p = ph;
+            const int it = band_take(ctl, L.s_pref, nl, b.Lmax, q, nq, &p);
+            if (tid == 0) {
+                L.s_ctl[0] = it;
+                L.s_ctl[2] = p;
+            }
+        }
+        __syncthreads();
+        const int item = L.s_ctl[0];
+        const int p = L.s_ctl[2];
+        __syncthreads();   // (s_ctl is rewritten by the next take)
+        ph = p;
+        // publish this block's finished items of an earlier phase before anything waits:
+        // every thread's stores (one release), then their count
+        if (pend > 0 && (item < 0 || p != pend_ph)) {
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) atomicAdd(&ctl->done[pend_ph], pend);
+            pend = 0;
+        }
+        if (item < 0) break;   // every phase is exhausted
+        bool run = !err;
+        if (p > ready) {
+            // wait until every item of phase p - 1 is complete (polled without ordering,
+            // then one acquire for the whole block)
+            if (tid == 0) {
+                const int need = phase_items(L.s_pref, p - 1, nl);
+                int ok = 1, spins = 0;
+                while (__hip_atomic_load(&ctl->done[p - 1], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (++spins > kBandSpin ||
+                        __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        atomicOr(&ctl->err, 1);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                L.s_ctl[1] = ok;
+            }
+            __syncthreads();
+            const int ok = L.s_ctl[1];
+            run = run && ok;
+            err = !ok || err;
+            // every thread: its later loads see what the finished items stored
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (ok) ready = p;
+        }
+        if (run) {
+            const int e = p == 0 ? item : L.s_pref[(p - 1) * kBuckets] + item;
+            int layer = 1;
+            const unsigned long long pk = list_entry(b, 1, b.Lmax, L.s_pref, e, &layer);
+            const int s = uniform_int((int)(pk >> 32));
+            const int bx = uniform_int((int)(pk & 1023ull));
+            const int by = uniform_int((int)((pk >> 10) & 1023ull));
+            const int bz = uniform_int((int)((pk >> 20) & 1023ull));
+            layer = uniform_int(layer);
+            unsigned long long* st = b.stats + (int64_t)s * kStatWords;
+            if (!(st[ST_FLAGS] & FLAG_TRUNCATED)) {   // uniform: no fit follows a truncation
+                if (p == 0)
+                    normal_brick(b.solids + s, st, layer, bx, by, bz, L.s_phi, L.s_flag, L.s_lab,
+                                 L.s_list, L.s_wave);
+                else
+                    extrap_brick<T>(b, b.solids + s, st, p, bx, by, bz, L.work, L.s_wave,
+                                    L.s_anchor, L.s_rlen);
+            }
+        }
+        ++pend;   // (a skipped item counts too)
+        pend_ph = p;
+        __syncthreads();   // the item's LDS is free for the next one
+    }
+    if (err && tid == 0)
+        for (int s = 0; s < b.n_solids; ++s)
+            atomicOr(b.stats + (int64_t)s * kStatWords + ST_FLAGS, FLAG_TIMEOUT);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------
@@ -1167,6 +1383,49 @@ int normal_blocks_per_cu() {
 
 hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st) {
     hipLaunchKernelGGL(k_normal, dim3(blocks), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+size_t band_lds_bytes(int precision) {
+    const size_t normal = sizeof(double) * kNCells + kNCells + kBrick * kBrick * kBrick +
+                          sizeof(uint16_t) * kNCells;
+    const size_t fit = brick_lds_bytes(precision);
+    const size_t work = fit > normal ? fit : normal;
+    return ((work + 15) & ~size_t(15)) + band_small_bytes();
+}
+
+// Blocks per CU of the persistent launch: one, when one fits.  Each block releases (an L2
+// write-back of its XCD) when it leaves a phase and acquires (an L2 invalidation) when it
+// enters one; with more blocks per CU these operations thrash the L2 more than the added
+// residency hides latency (one block per CU measured twice as fast as three).
+int band_blocks_per_cu(int precision) {
+    static const int n[2] = {
+        [] {
+            int v = 0;
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_band<double>, 256,
+                                                                band_lds_bytes(0)) == hipSuccess &&
+                           v >= 1
+                       ? 1
+                       : 0;
+        }(),
+        [] {
+            int v = 0;
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_band<float>, 256,
+                                                                band_lds_bytes(1)) == hipSuccess &&
+                           v >= 1
+                       ? 1
+                       : 0;
+        }()};
+    return n[precision == 1 ? 1 : 0];
+}
+
+hipError_t launch_band(const Batch& b, int precision, int blocks, hipStream_t st) {
+    const size_t lds = band_lds_bytes(precision);
+    const int work = (int)(lds - band_small_bytes());
+    if (precision == 1)
+        hipLaunchKernelGGL(k_band<float>, dim3(blocks), dim3(256), lds, st, b, work);
+    else
+        hipLaunchKernelGGL(k_band<double>, dim3(blocks), dim3(256), lds, st, b, work);
     return hipGetLastError();
 }
 

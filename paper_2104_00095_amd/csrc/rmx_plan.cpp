@@ -90,7 +90,7 @@ int validate_solid(const rmx_grid* grid, const rmx_solid* sp, bool need_fields) 
 
 int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,
          const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p,
-         int normal_per_cu) {
+         int normal_per_cu, int band_per_cu) {
     p->n_solids = n_solids;
     p->solids.assign(n_solids, DevSolid{});
     p->tile_solid.clear();
@@ -176,6 +176,10 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
         std::min<int64_t>((int64_t)std::max(normal_per_cu, 1) * std::max(cu, 1),
                           bricks * std::max(p->normal_layers, 1)),
         1);
+    // persistent band launch: the resident blocks (at least one per queue)
+    p->persistent = (opt->flags & RMX_FLAG_PERSISTENT) != 0;
+    p->band_blocks = std::max(std::max(band_per_cu, 1) * std::max(cu, 1), kXcds);
+    if (p->persistent && band_lds_bytes(opt->precision) > lds_limit) return RMX_E_LAYERS;
 
     // Workspace layout.
     size_t off = 0;
@@ -203,6 +207,8 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     p->off_dlist = off;
     off = next_region(p, off, sizeof(unsigned long long) * (size_t)std::max(p->Lmax, 1) *
                                   (size_t)p->dlist_cap);
+    p->off_band = off;
+    off = next_region(p, off, sizeof(BandCtl));
     p->ws_bytes = off;
     return RMX_OK;
 }
@@ -238,6 +244,7 @@ void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
     b->dlist_cap = p->dlist_cap;
     b->dcount = reinterpret_cast<int32_t*>(base + p->off_dcount);
     b->dlist = reinterpret_cast<unsigned long long*>(base + p->off_dlist);
+    b->band = reinterpret_cast<BandCtl*>(base + p->off_band);
 }
 
 void pack_desc(const Plan& p, void* host) {
@@ -308,6 +315,10 @@ hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,
     } while (0)
     RMX_TIMED(RMX_PHASE_CLASSIFY, launch_classify(b, st));
     RMX_TIMED(RMX_PHASE_LABEL, launch_label(b, p.lds_bytes, st));
+    if (p.persistent) {
+        RMX_TIMED(RMX_PHASE_BAND, launch_band(b, precision, p.band_blocks, st));
+        return hipSuccess;
+    }
     RMX_TIMED(RMX_PHASE_NORMAL, launch_normal(b, p.normal_blocks, st));
     for (int l = 1; l <= p.Lmax; ++l)
         RMX_TIMED(RMX_PHASE_EXTRAP + l - 1, launch_extrap(b, l, precision, p.extrap_blocks, st));
@@ -326,7 +337,7 @@ void convert_stats(const unsigned long long* dev, int n, rmx_solid_stats* out) {
         o.n_no_normal = (int64_t)s[ST_NONORMAL];
         o.n_f1 = (int64_t)s[ST_F1];
         o.n_f2 = (int64_t)s[ST_F2];
-        if (s[ST_FLAGS] & FLAG_OVERFLOW)
+        if (s[ST_FLAGS] & (FLAG_OVERFLOW | FLAG_TIMEOUT))
             o.status = RMX_E_HIP;
         else if (s[ST_FLAGS] & FLAG_TRUNCATED)
             o.status = RMX_E_TRUNCATED;

@@ -369,7 +369,6 @@ int rmx_server_submit(rmx_server* s, int64_t sim_id, const rmx_options* opt, int
     if (opt) o = *opt;
     int rc = validate_options(&o);
     if (rc != RMX_OK) return rc;
-    if ((o.flags & RMX_FLAG_PERSISTENT) && !(o.flags & RMX_FLAG_PER_SOLID)) return RMX_E_DISABLED;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return RMX_E_ARG;
     auto it = s->sims.find(sim_id);

@@ -3,8 +3,8 @@
 // Test infrastructure only.  A block's threads are host threads; __syncthreads and the
 // cross-lane operations are barriers over the block, the 64-lane wave or the shuffle
 // group.  Blocks of a launch run one after another, so a kernel's __shared__ variables can
-// be statics; device memory is host memory.  Kernels whose blocks wait on each other work
-// when the launch has a single block (the host shim reports one CU, one block per CU).
+// be statics; device memory is host memory.  The persistent kernel, whose blocks wait on
+// each other, runs all its blocks at once (see hipLaunchKernelGGL below).
 #pragma once
 #include <algorithm>
 #include <atomic>
@@ -32,6 +32,7 @@
 #define __align__(n) __attribute__((aligned(n)))
 #define RMX_GLOBAL_AS   // host memory is the only address space here
 inline void __builtin_amdgcn_sched_barrier(int) {}   // instruction scheduling: nothing to do
+#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(rmx_emu::dyn_lds());
 
 struct alignas(16) uint4 {
@@ -177,10 +178,11 @@ template <typename T>
 inline hipError_t hipMalloc(T** p, size_t n) { return hipMalloc(reinterpret_cast<void**>(p), n); }
 hipError_t hipFree(void* p);
 hipError_t hipHostMalloc(void** p, size_t n, unsigned flags);
-// Blocks resident per compute unit: the emulation runs blocks in turn, so any count works.
+// Blocks resident per compute unit: one (a concurrent launch runs 256 host threads per
+// block).
 template <typename F>
 inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, F, int, size_t) {
-    *n = 2;
+    *n = 1;
     return hipSuccess;
 }
 // A __device__ variable is host storage here: its address is the symbol's own.
@@ -215,9 +217,14 @@ hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
 hipError_t hipGraphExecDestroy(hipGraphExec_t e);
 hipError_t hipGraphDestroy(hipGraph_t g);
 namespace rmx_emu {
-// Blocks run one after another (static __shared__ variables are one copy); the threads
-// of a block run concurrently.
-void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, std::function<void()> body);
+// Blocks run one after another (static __shared__ variables are one copy), or all at once
+// for `concurrent` launches; the threads of a block run concurrently.
+void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, std::function<void()> body,
+            bool concurrent = false);
 }
-#define hipLaunchKernelGGL(K, G, B, L, S, ...) \
-    rmx_emu::launch((G), (B), (L), (S), [=]() { K(__VA_ARGS__); })
+// The persistent band kernel (k_band<...>) keeps its whole block state in dynamic LDS and
+// its blocks wait on each other: its launches run every block concurrently, each with its
+// own LDS.  Other kernels run their blocks in turn.
+#define hipLaunchKernelGGL(K, G, B, L, S, ...)                                          \
+    rmx_emu::launch((G), (B), (L), (S), [=]() { K(__VA_ARGS__); },                      \
+                    std::strncmp(#K, "k_band", 6) == 0)

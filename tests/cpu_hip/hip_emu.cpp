@@ -40,6 +40,7 @@ struct Capture {
     dim3 grid, block;
     size_t lds;
     std::function<void()> body;
+    bool concurrent;
 };
 hipStream_t g_capturing = nullptr;
 std::vector<Capture> g_captured;
@@ -99,12 +100,39 @@ static void run(dim3 grid, dim3 block, size_t lds, const std::function<void()>& 
     for (auto& x : th) x.join();
 }
 
-void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, std::function<void()> body) {
+// Every block of the launch at once (grid.x * block.x host threads), each block with its
+// own barriers and LDS: for kernels whose blocks wait on each other.
+static void run_concurrent(dim3 grid, dim3 block, size_t lds,
+                           const std::function<void()>& body) {
+    gridDim_ = grid;
+    blockDim_ = block;
+    std::vector<std::unique_ptr<Block>> blks(grid.x);
+    for (auto& b : blks) {
+        b = std::make_unique<Block>();
+        init_block(*b, (int)block.x, lds);
+    }
+    std::vector<std::thread> th;
+    for (unsigned g = 0; g < grid.x; ++g)
+        for (int t = 0; t < (int)block.x; ++t)
+            th.emplace_back([&, g, t]() {
+                block_ = blks[g].get();
+                threadIdx_ = dim3(t);
+                blockIdx_ = dim3(g);
+                body();
+            });
+    for (auto& x : th) x.join();
+}
+
+void launch(dim3 grid, dim3 block, size_t lds, hipStream_t st, std::function<void()> body,
+            bool concurrent) {
     if (st && st == g_capturing) {
-        g_captured.push_back(Capture{grid, block, lds, body});
+        g_captured.push_back(Capture{grid, block, lds, body, concurrent});
         return;
     }
-    run(grid, block, lds, body);
+    if (concurrent)
+        run_concurrent(grid, block, lds, body);
+    else
+        run(grid, block, lds, body);
 }
 
 struct Graph {
@@ -124,7 +152,12 @@ hipError_t end_capture(hipStream_t, hipGraph_t* g) {
     return hipSuccess;
 }
 void replay(hipGraph_t g) {
-    for (auto& c : reinterpret_cast<Graph*>(g)->nodes) run(c.grid, c.block, c.lds, c.body);
+    for (auto& c : reinterpret_cast<Graph*>(g)->nodes) {
+        if (c.concurrent)
+            run_concurrent(c.grid, c.block, c.lds, c.body);
+        else
+            run(c.grid, c.block, c.lds, c.body);
+    }
 }
 void destroy(hipGraph_t g) { delete reinterpret_cast<Graph*>(g); }
 

@@ -114,5 +114,5 @@ def test_null_context_and_status_strings():
     assert L.rmx_extrapolate(None, ctypes.byref(g), ctypes.byref(d), 1, None, None, None) \
         == rmx.E_ARG
     assert rmx.status_string(rmx.E_TRUNCATED) == "band truncated by the box"
-    assert rmx.status_string(rmx.E_DISABLED) == "launch form switched off in this build"
+    assert rmx.status_string(rmx.E_DISABLED).startswith("launch form switched off")
     assert rmx.status_string(0) == "ok"

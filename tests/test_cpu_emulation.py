@@ -59,7 +59,15 @@ def _runs():
         "suspension3_cus5": (susp, 0, BATCHED, (), {"cus": 5}),
         "repeated_calls": (susp, 0, BATCHED, (BATCHED, GRAPH, BATCHED)),
         "autotune_then_call": (sphere, 0, BATCHED, (AUTOTUNE,)),
-        "persistent_refused": (sphere, 0, PERSISTENT, ()),
+        # the persistent band launch: every block of it runs at once (they wait on each
+        # other's layers), after other forms on the same context, with graph replay
+        "persistent": (sphere, 0, PERSISTENT, ()),
+        "persistent_suspension_fp32": (susp, 1, PERSISTENT, ()),
+        "persistent_graph_after_chain": (susp, 0, PERSISTENT | GRAPH, (BATCHED, PERSISTENT)),
+        "persistent_statuses": (trunc, 0, PERSISTENT, ()),
+        "persistent_plates": (plates, 0, PERSISTENT, (), {"xi_normal": [plates_xn]}),
+        # 12 blocks: 8 queues, four of them with two blocks
+        "persistent_cus12": (susp, 0, PERSISTENT, (), {"cus": 12}),
         "statuses_batched": (trunc, 0, BATCHED, ()),
         "statuses_per_solid": (trunc, 0, PER_SOLID, ()),
         "sphere64": (synth.sphere32(n=64, n_layers=3), 0, BATCHED, ()),
@@ -136,9 +144,24 @@ def test_emulated_autotune_then_call(emulated):
     _check(w, outs, prec, xn)
 
 
-def test_emulated_persistent_refused(emulated):
-    w, prec, st, outs, xn = emulated["persistent_refused"]
-    assert st == -11
+@pytest.mark.parametrize("name", ["persistent", "persistent_suspension_fp32",
+                                  "persistent_graph_after_chain", "persistent_plates",
+                                  "persistent_cus12"])
+def test_emulated_persistent_band_launch(emulated, name):
+    """The normals and every layer's fits in one persistent launch whose blocks take
+    bricks by ticket and wait for the previous layer: the oracle's labels, decisions and
+    xi."""
+    w, prec, st, outs, xn = emulated[name]
+    assert st == 0
+    _check(w, outs, prec, xn)
+
+
+def test_emulated_persistent_statuses(emulated):
+    """A truncated solid, one with no interior cell and one with L = 0 beside an ordinary
+    solid, through the persistent launch."""
+    w, prec, st, outs, xn = emulated["persistent_statuses"]
+    assert st == -7
+    _check(w, outs, prec, xn)
 
 
 @pytest.mark.parametrize("name", ["statuses_batched", "statuses_per_solid"])

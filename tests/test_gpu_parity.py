@@ -15,9 +15,9 @@ from tests.helpers import (axis_plane_workload, edge_workloads, oracle_problem, 
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-12, 1: 1e-5}
-# Launch forms: every solid of the call in one chain of launches (default), and one chain
-# per solid (the plain form).
-MODES = {"batched": 0, "per_solid": 4}
+# Launch forms: every solid of the call in one chain of launches (default), one chain per
+# solid (the plain form), and the band work in one persistent launch.
+MODES = {"batched": 0, "per_solid": 4, "persistent": 16}
 MODE_PARAMS = sorted(MODES)
 
 
@@ -315,14 +315,20 @@ def test_ellipsoid_axis_planes(ctx, mode):
     compare(w, gpu, 0, tag="axis_planes")
 
 
-def test_persistent_launch_refused(ctx):
-    """The switched-off persistent form is refused on the host, before any launch."""
-    from paper_2104_00095_amd import fields, rmx
-    w = synth.sphere32()
-    dw = fields.upload(w)
-    st, _ = ctx.extrapolate(dw.grid, dw.solids, rmx.options(flags=rmx.FLAG_PERSISTENT),
-                            check=False)
-    assert st == rmx.E_DISABLED
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_equals_chain(ctx, precision):
+    """The persistent band launch runs the same per-brick arithmetic as the chain of
+    launches: labels, decisions, statistics and xi are bitwise those of the chain, on a
+    batch of ellipsoids, a sphere and a ragged ellipsoid box."""
+    from paper_2104_00095_amd import rmx
+    for w in (synth.suspension(n_solids=12, grid_n=(64, 64, 128), h=1.0 / 64),
+              synth.sphere32(), synth.ellipsoid128(n=48, n_layers=5)):
+        st, chain = run_gpu(ctx, w, precision)
+        st2, pers = run_gpu(ctx, w, precision, flags=rmx.FLAG_PERSISTENT)
+        assert st == st2 == 0
+        for (xa, la, da, sa), (xb, lb, db, sb) in zip(chain, pers):
+            assert np.array_equal(la, lb) and np.array_equal(da, db) and sa == sb
+            assert np.array_equal(xa.view(np.uint64), xb.view(np.uint64))
 
 
 @pytest.mark.parametrize("mode", MODE_PARAMS)

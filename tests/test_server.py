@@ -131,8 +131,8 @@ def test_budget_admission_and_errors():
         assert ei.value.status == rmx.E_NOTFOUND
         assert srv.wait(123456789)[0] == rmx.E_NOTFOUND
         with pytest.raises(rmx.RmxError) as ei:
-            srv.submit(a, rmx.options(flags=rmx.FLAG_PERSISTENT))
-        assert ei.value.status == rmx.E_DISABLED
+            srv.submit(a, rmx.options(r_s=0))
+        assert ei.value.status == rmx.E_ARG
         srv.release(a)
         with pytest.raises(rmx.RmxError) as ei:
             srv.release(a)
