@@ -7,7 +7,10 @@ numpy arrays into it.
 
 What it computes follows Lin, Derr & Rycroft (arXiv 2104.00095): section "Extrapolation
 of xi(x,t)" and the SI section "Weighting scheme for weighted least squares-based
-extrapolation", eq. (weight).  See ``rmx_oracle.c`` for the step-by-step account.
+extrapolation", eq. (weight) (``rmx_oracle.c``); and the SI "Timestepping algorithm",
+steps 5-7 and 11, with the advective term of eq. (adv_terms) and the Godunov face states
+of "Evaluating the advective term" (``rmx_step_oracle.c``).  See the C files for the
+step-by-step account.
 """
 from __future__ import annotations
 
@@ -19,6 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rmx_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "rmx_step_oracle.c")]
 _LIB = os.path.join(_HERE, "librmx_oracle.so")
 
 # Decision codes (one per cell): 0 = not a band cell, r = fitted with search radius r,
@@ -55,13 +59,18 @@ class Problem(ctypes.Structure):
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or _stale():
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
-             "-Wall", "-o", tmp, _SRC, "-lm"])
+             "-Wall", "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def _stale() -> bool:
+    return not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
+                                           for f in _SRCS)
 
 
 _lib = None
@@ -70,7 +79,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER
@@ -91,6 +100,13 @@ def lib():
         L.orc_normal.argtypes = [P(Problem), ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_void_p]
         L.orc_normal.restype = None
+        L.orc_predict.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 6 + \
+            [ctypes.c_double, ctypes.c_void_p]
+        L.orc_predict.restype = ctypes.c_int
+        L.orc_correct.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 5
+        L.orc_correct.restype = None
+        L.orc_slope4.argtypes = [ctypes.c_void_p]
+        L.orc_slope4.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -171,3 +187,72 @@ def normal(problem: Problem, field: np.ndarray, i: int, j: int, k: int) -> np.nd
     f = np.ascontiguousarray(field, dtype=np.float64)
     lib().orc_normal(ctypes.byref(problem), _ptr(f), int(i), int(j), int(k), _ptr(g))
     return g
+
+
+# ---------------------------------------------------------------------------------------
+# Time step around the extrapolation (SI "Timestepping algorithm", steps 5-7 and 11).
+# ---------------------------------------------------------------------------------------
+def slope4(q) -> float:
+    """Colella's fourth-order limited slope at the centre of five values."""
+    a = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(5))
+    return float(lib().orc_slope4(_ptr(a)))
+
+
+def predict(ext, n_layers, xi_n, labels_n, u, uf, dt, h, xi_next):
+    """Step 5: writes the predictor into ``xi_next`` (float64 [3, e2, e1, e0], modified in
+    place: predicted cells get the value, the rest of the old band NaN, unmarked cells
+    are left as they are).  ``uf`` = (x-faces [e2, e1, e0+1], y-faces [e2, e1+1, e0],
+    z-faces [e2+1, e1, e0]).  Returns 1 if an interior cell could not be predicted."""
+    e = np.ascontiguousarray(np.asarray(ext, dtype=np.int32))
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xi_n, u) + tuple(uf)]
+    lab = np.ascontiguousarray(labels_n, dtype=np.int8)
+    assert xi_next.flags.c_contiguous and xi_next.dtype == np.float64
+    lam = float(dt) / float(h)
+    return int(lib().orc_predict(_ptr(e), int(n_layers), _ptr(arrs[0]), _ptr(lab),
+                                 _ptr(arrs[1]), _ptr(arrs[2]), _ptr(arrs[3]), _ptr(arrs[4]),
+                                 lam, _ptr(xi_next)))
+
+
+def correct(ext, n_layers, xi_n, labels_n, xi_next, labels_next, xi_half):
+    """Step 7: writes xi^{n+1/2} into ``xi_half`` (modified in place) on the cells labelled
+    at step n + 1."""
+    e = np.ascontiguousarray(np.asarray(ext, dtype=np.int32))
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (xi_n, xi_next)]
+    ln = np.ascontiguousarray(labels_n, dtype=np.int8)
+    lx = np.ascontiguousarray(labels_next, dtype=np.int8)
+    lib().orc_correct(_ptr(e), int(n_layers), _ptr(a[0]), _ptr(ln), _ptr(a[1]), _ptr(lx),
+                      _ptr(xi_half))
+
+
+def step(problem: Problem, xi_n, labels_n, u, uf, dt, h, xi_next_init, xi_half_init,
+         nthreads: int = 0):
+    """One time step of the reference map around the extrapolation, in the paper's order:
+    predictor (step 5) -> extrapolation from the predicted interior (step 6) -> corrector
+    (step 7).  Restoring xi^{n+1} (step 11) is keeping the returned xi_next.
+
+    The extrapolation sees the predicted cells only: every other cell is undefined for
+    it, so the interior at n + 1 is the predicted cells with phi0(xi^{n+1}) < 0.  The
+    returned xi_next holds the predictor on the predicted cells, NaN on the rest of the
+    old band, the extrapolated band at n + 1, and the caller's values elsewhere.
+    Returns (status, xi_next, labels_next, decisions, stats, xi_half)."""
+    e = tuple(int(v) for v in problem.ext)
+    L = int(problem.n_layers)
+    xi_next = np.ascontiguousarray(xi_next_init, dtype=np.float64).copy()
+    trunc = predict(e, L, xi_n, labels_n, u, uf, dt, h, xi_next)
+    # the field the extrapolation is given: the predicted cells, undefined elsewhere
+    lab_n = np.asarray(labels_n)
+    pred = (lab_n >= 0) & (lab_n <= L - 4)
+    kk, jj, ii = np.meshgrid(np.arange(e[2]), np.arange(e[1]), np.arange(e[0]), indexing="ij")
+    pred &= (ii >= 3) & (ii <= e[0] - 4) & (jj >= 3) & (jj <= e[1] - 4) & (kk >= 3) & \
+        (kk <= e[2] - 4)
+    work = np.where(pred[None], xi_next, np.nan)
+    st, ext_out, labels_next, dec, stats = extrapolate(problem, work, nthreads=nthreads)
+    if trunc and st >= 0:
+        st = E_TRUNCATED
+    if st == OK:
+        band = (labels_next >= 1) & (labels_next <= L)
+        xi_next = np.where(band[None], ext_out, xi_next)
+    xi_half = np.ascontiguousarray(xi_half_init, dtype=np.float64).copy()
+    if st == OK:
+        correct(e, L, xi_n, labels_n, xi_next, labels_next, xi_half)
+    return st, xi_next, labels_next, dec, stats, xi_half
