@@ -442,6 +442,98 @@ def serving_variants(ctx, n_requests=2000, rate=200.0, n_streams=4, log=print):
     return out
 
 
+def step_variant(ctx, steps=100, warmup=10, n_layers=6, precision=0):
+    """One time step (rmx_step: predictor, extrapolation from the predicted interior,
+    corrector) on cavity256 with L = 6, advected by the cavity's own flow (plus a drift
+    along z) at CFL 0.4.  Set-up, not timed: the band of step n by one extrapolation call.
+    Timed: `steps` steps from the same state (xi^n is an input, so every step does the same
+    work), HIP events on the launch stream; per-kernel times from RMX_FLAG_PROFILE.
+    Byte models: predictor 96 B per predicted cell (xi^n, u^n, the face velocities, xi^{n+1})
+    + 1 B label read and 1/8 B mask write per box cell; transverse faces 144 B per cell
+    labelled <= L-2 (xi^n, u^n read, 12 doubles written); corrector 74 B per cell labelled
+    at n + 1."""
+    import numpy as np
+    import torch
+    from paper_2104_00095_amd import fields, rmx, synth
+    w = synth.cavity256(n_layers=n_layers)
+    dw = fields.upload(w)
+    st, stats = ctx.extrapolate(dw.grid, dw.solids, rmx.options())
+    assert st == 0
+    vel = synth.step_velocity(w)
+    dt = synth.step_dt(w, 0.4)
+    s = w.solids[0]
+    dev = "cuda"
+    xi_n = dw.xi[0]
+    lab_n = dw.labels[0]
+    u = torch.from_numpy(vel[0].u).to(dev)
+    uf = tuple(torch.from_numpy(f).to(dev) for f in vel[0].uf)
+    xi_next = torch.zeros_like(xi_n)
+    lab_next = torch.zeros_like(lab_n)
+    xi_half = torch.zeros_like(xi_n)
+    shp = rmx.shape(s.shape.kind, s.shape.centre, s.shape.semi, s.shape.rot)
+    sol = rmx.step_solid(s.lo, s.ext, shp, s.n_layers, xi_n, lab_n, u, uf, xi_next, lab_next,
+                         xi_half)
+    arr = (rmx.StepSolid * 1)(sol)
+    opt = rmx.options(precision=precision)
+    stream = torch.cuda.current_stream()
+    h = rmx._stream_handle(stream)
+    st, sstats = ctx.step(dw.grid, [sol], dt, opt)
+    assert st == 0, st
+    for _ in range(warmup):
+        ctx.step_raw(dw.grid, arr, 1, opt, dt, h)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.step_raw(dw.grid, arr, 1, opt, dt, h)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # per-kernel times
+    ctx.profile_read()
+    popt = rmx.options(precision=precision, flags=rmx.FLAG_PROFILE)
+    reps = max(10, steps // 5)
+    for _ in range(reps):
+        ctx.step_raw(dw.grid, arr, 1, popt, dt, h)
+    torch.cuda.synchronize()
+    ph = ctx.profile_read()
+    # cell counts for the byte models (host, from the labels of both steps)
+    ln = lab_n.cpu().numpy()
+    lx = lab_next.cpu().numpy()
+    L = n_layers
+    e2, e1_, e0_ = ln.shape
+    k, j, i = np.meshgrid(np.arange(e2), np.arange(e1_), np.arange(e0_), indexing="ij")
+    inside = (i >= 3) & (i <= e0_ - 4) & (j >= 3) & (j <= e1_ - 4) & (k >= 3) & (k <= e2 - 4)
+    n_pred = int(((ln >= 0) & (ln <= L - 4) & inside).sum())
+    n_trans = int(((ln >= 0) & (ln <= L - 2)).sum())
+    n_corr = int(((lx >= 0) & (lx <= L)).sum())
+    box = ln.size
+    nb = int(((lx >= 1) & (lx <= L)).sum())
+    model = {"step_trans": 144.0 * n_trans, "step_predict": 96.0 * n_pred + 1.125 * box,
+             "step_correct": 74.0 * n_corr}
+    kern = {}
+    for name, (tms, n) in ph.items():
+        per = tms / n
+        e = {"avg_launch_ms": per, "launches_per_step": n / reps}
+        if name in model:
+            e["model_bytes"] = model[name]
+            e["hbm_frac"] = model[name] / (per * 1e-3) / (HBM_PEAK_GBS * 1e9)
+        kern[name] = e
+    dom = max(("step_trans", "step_predict", "step_correct"), key=lambda k: kern[k]["avg_launch_ms"])
+    out = {"workload": f"step_cavity256_L{L}", "ms_per_step": ms,
+           "predicted_cells": n_pred, "band_cells": nb, "box_cells": box,
+           "predicted_cells_per_s": n_pred / (ms * 1e-3), "band_cells_per_s": nb / (ms * 1e-3),
+           "dt": dt, "precision": precision, "kernels": kern,
+           "step_roofline": {"bound": "hbm", "kernel": f"k_{dom}",
+                             "achieved": model[dom] / (kern[dom]["avg_launch_ms"] * 1e-3) / 1e9,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": kern[dom]["hbm_frac"]}}
+    del dw, u, uf, xi_next, lab_next, xi_half
+    torch.cuda.empty_cache()
+    return out
+
+
 def make_workload(name):
     from paper_2104_00095_amd import synth
     if name == "cavity256":
@@ -473,6 +565,9 @@ def main():
     ap.add_argument("--workload", default="cavity256")
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--graph", action="store_true", help="replay the launch chain as a hipGraph")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only time the time-step variant (predictor + extrapolation + "
+                         "corrector on cavity256, L = 6) and print it")
     ap.add_argument("--persistent", action="store_true",
                     help="the band work (normals and every layer's fits) in one persistent launch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -500,6 +595,13 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.step_only:
+        ctx = rmx.Context(0)
+        log("time step (cavity256, L = 6)")
+        print(json.dumps(step_variant(ctx, args.steps, args.warmup,
+                                      precision=PRECISIONS[args.precision])), flush=True)
+        ctx.close()
         return
 
     log(f"generating {args.workload}")
@@ -579,6 +681,8 @@ def main():
             variants[name] = f
         del dws
         torch.cuda.empty_cache()
+        log("variants: time step")
+        variants["step_cavity256"] = step_variant(ctx, args.steps, args.warmup)
         if not args.no_serving:
             variants["serving"] = serving_variants(ctx, args.serving_requests, log=log)
 

@@ -89,7 +89,10 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
 #define RMX_PHASE_NORMAL 2      /* per-solid counts and the normals of layers <= nl      */
 #define RMX_PHASE_EXTRAP 3      /* + (layer - 1), layers 1..RMX_MAX_LAYERS               */
 #define RMX_PHASE_BAND 19       /* the persistent band launch (RMX_FLAG_PERSISTENT)       */
-#define RMX_N_PHASES 20
+#define RMX_PHASE_STEP_TRANS 20   /* rmx_step: transverse face states                     */
+#define RMX_PHASE_STEP_PREDICT 21 /* rmx_step: predictor and the interior mask at n + 1   */
+#define RMX_PHASE_STEP_CORRECT 22 /* rmx_step: corrector                                  */
+#define RMX_N_PHASES 23
 
 /* Grid: M x N x O cells; cell (i,j,k) has centre origin + (idx + 1/2) h (SI, "Variable
  * arrangement"; isotropic spacing as in the paper's runs).  The fit is invariant to h
@@ -198,6 +201,60 @@ int rmx_extrapolate(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
 int rmx_extrapolate_noalloc(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
                             int32_t n_solids, const rmx_options* opt, void* hip_stream,
                             rmx_solid_stats* stats);
+
+/* ---- one time step around the extrapolation ------------------------------------------
+ * SI "Timestepping algorithm", steps 5, 6, 7 and 11, with SI "Evaluating the advective
+ * term" (eq. (adv_terms); the Taylor-expanded face states of xi; the Godunov-type
+ * upwinding scheme; Colella's fourth-order monotonicity-limited normal slopes; upwinded
+ * tangential derivatives):
+ *   5. predictor xi^{n+1} = xi^n - dt [(u.grad) xi]^{n+1/2} (eq. (dis_xi_adv)) on every
+ *      cell labelled 0..L-4 at step n that is at least 3 cells inside the box (its face
+ *      states read only defined maps of the labelled band: the stencil reaches 3 cells
+ *      along an axis, L1 distance 4); the rest of the old band (labels 0..L at n) becomes
+ *      undefined (NaN); other cells of xi_next are left as they are;
+ *   6. extrapolation from the predicted interior (cells above with phi0(xi^{n+1}) < 0) into
+ *      layers 1..L, exactly as rmx_extrapolate, into xi_next / labels_next / decisions;
+ *   7. corrector xi_half = (xi^n + xi^{n+1}) / 2 on cells labelled at n + 1 that were
+ *      labelled at n, xi^{n+1} on cells labelled only at n + 1; others left as they are;
+ *  11. restoring xi^{n+1} is the caller keeping xi_next (swap xi_n <-> xi_next and
+ *      labels_n <-> labels_next for the next step: no copy).
+ * Readings: the face state of xi is chosen by the sign of the given face-normal velocity,
+ * which also advects (the caller's MAC velocity at n + 1/2); the transverse expansions use
+ * the cell velocity u^n and its own limited slope.  Lengths: dt and grid->h; velocities in
+ * length per time.  Requires L >= 5 (so that cells entering the solid, labelled <= 1 at
+ * step n, are predicted).  An interior cell of step n closer than 3 cells to a box face
+ * cannot be predicted: the solid reports RMX_E_TRUNCATED (its labels at n + 1 are
+ * written, its band and xi_half are not), as does a band that would leave the box.
+ * Layouts: xi_n, u, xi_next, xi_half SoA [3][ext2][ext1][ext0] FP64; labels [ext2][ext1]
+ * [ext0] int8; uf[0] [ext2][ext1][ext0+1] (x-faces, face i between cells i-1 and i),
+ * uf[1] [ext2][ext1+1][ext0], uf[2] [ext2+1][ext1][ext0].  All DEVICE, caller-owned; the
+ * inputs are read only; xi_n must not alias xi_next or xi_half. */
+typedef struct {
+    int32_t lo[3];
+    int32_t ext[3];
+    rmx_shape phi0;
+    int32_t n_layers;         /* L >= 5                                                   */
+    const double* xi_n;       /* DEVICE, in: xi^n, defined where labels_n is 0..L          */
+    const int8_t* labels_n;   /* DEVICE, in: labels of step n                              */
+    const double* u;          /* DEVICE, in: cell-centred velocity u^n                     */
+    const double* uf[3];      /* DEVICE, in: face-normal velocities at n + 1/2             */
+    double* xi_next;          /* DEVICE, out: xi^{n+1} (predictor + extrapolated band)     */
+    int8_t* labels_next;      /* DEVICE, out: labels of step n + 1                         */
+    double* xi_half;          /* DEVICE, out: xi^{n+1/2}                                   */
+    int8_t* decisions;        /* DEVICE, out, nullable: as for rmx_extrapolate             */
+} rmx_step_solid;
+
+/* One time step of every solid of the batch, enqueued on hip_stream as one chain (three
+ * step kernels around the extrapolation's label, normal and layer-fit launches; no
+ * classification pass: the predictor writes the interior mask).  dt > 0, finite.  Options
+ * as for rmx_extrapolate (RMX_FLAG_SYNC, RMX_FLAG_PROFILE, precision, radii, normal
+ * layers); RMX_FLAG_GRAPH, RMX_FLAG_PER_SOLID and RMX_FLAG_PERSISTENT are RMX_E_ARG.
+ * stats (HOST, nullable, n_solids entries) implies a wait, as for rmx_extrapolate.  The
+ * workspace grows by 96 B per box cell (transverse face states) on top of the
+ * extrapolation's. */
+int rmx_step(rmx_ctx* ctx, const rmx_grid* grid, const rmx_step_solid* solids,
+             int32_t n_solids, const rmx_options* opt, double dt, void* hip_stream,
+             rmx_solid_stats* stats);
 
 const char* rmx_status_string(int status);
 

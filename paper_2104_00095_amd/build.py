@@ -10,7 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librmx.so")
-SOURCES = ["rmx_kernels.hip", "rmx_plan.cpp", "rmx_core.cpp", "rmx_server.cpp"]
+SOURCES = ["rmx_kernels.hip", "rmx_step.hip", "rmx_plan.cpp", "rmx_core.cpp", "rmx_server.cpp"]
+# Per-file flags: the time-step kernels evaluate their arithmetic in the written order.
+EXTRA = {"rmx_step.hip": ["-ffp-contract=off"]}
 # No packed-FP32 instructions; device code for gfx950 only.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -21,7 +23,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = ["hipcc"] + HIPFLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        cmd = ["hipcc"] + HIPFLAGS + EXTRA.get(src, []) + ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
                                       "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd.insert(1, "-xhip")

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -164,10 +165,32 @@ int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
     return rc;
 }
 
+// A time step's launches: transverse faces, predictor (with the interior mask), the
+// extrapolation chain from the labels on, corrector.
+static hipError_t step_chain(const Plan& p, const Batch& b, const StepBatch& sb, int precision,
+                             hipStream_t st, Profiler* prof) {
+    hipError_t e;
+    Profiler::Rec rec{};
+    auto timed = [&](int phase, auto&& launch) -> hipError_t {
+        if (prof && (e = prof->begin(phase, st, &rec)) != hipSuccess) return e;
+        if ((e = launch()) != hipSuccess) return e;
+        if (prof && (e = prof->end(rec, st)) != hipSuccess) return e;
+        return hipSuccess;
+    };
+    if ((e = timed(RMX_PHASE_STEP_TRANS, [&] { return launch_step_trans(sb, st); })) != hipSuccess)
+        return e;
+    if ((e = timed(RMX_PHASE_STEP_PREDICT, [&] { return launch_step_predict(sb, st); })) !=
+        hipSuccess)
+        return e;
+    if ((e = enqueue(p, b, precision, st, prof, false)) != hipSuccess) return e;
+    return timed(RMX_PHASE_STEP_CORRECT, [&] { return launch_step_correct(sb, st); });
+}
+
 int launch_planned(rmx_ctx* c, Plan& p, int n, const rmx_options* opt, hipStream_t st,
                    bool use_graph, size_t stats_off, bool want_stats, void* ws, size_t ws_size,
-                   bool no_alloc) {
+                   bool no_alloc, const StepBatch* step) {
     if (p.ws_bytes > ws_size) return RMX_E_WORKSPACE;
+    if (step && use_graph) return RMX_E_ARG;
     int rc = RMX_OK;
     Batch b{};
     bind(&p, ws, opt, &b);
@@ -237,7 +260,18 @@ int launch_planned(rmx_ctx* c, Plan& p, int n, const rmx_options* opt, hipStream
             desc_mark(c, ws, dh, p.desc_bytes);
         }
         Profiler* prof = (opt->flags & RMX_FLAG_PROFILE) ? &c->prof : nullptr;
-        if (enqueue(p, b, opt->precision, st, prof) != hipSuccess) return RMX_E_HIP;
+        if (step) {
+            StepBatch sb = *step;
+            sb.solids = b.solids;
+            sb.n_solids = b.n_solids;
+            sb.total_words = b.total_words;
+            sb.stats = b.stats;
+            sb.bcount = b.bcount;
+            sb.band = b.band;
+            if (step_chain(p, b, sb, opt->precision, st, prof) != hipSuccess) return RMX_E_HIP;
+        } else if (enqueue(p, b, opt->precision, st, prof) != hipSuccess) {
+            return RMX_E_HIP;
+        }
     }
     if (want_stats) {
         if (hipMemcpyAsync(c->stats_host + stats_off, b.stats,
@@ -352,6 +386,7 @@ int rmx_destroy(rmx_ctx* c) {
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->ws) (void)hipFree(c->ws);
+    if (c->step_ws) (void)hipFree(c->step_ws);
     delete c;
     return RMX_OK;
 }
@@ -413,6 +448,99 @@ int rmx_extrapolate(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
                        nullptr);
         if (rc != RMX_OK) return rc;
     }
+    if (!sync) return RMX_OK;
+    return finish_sync(c, st, n_solids, stats);
+}
+
+int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t n_solids,
+             const rmx_options* opt, double dt, void* hip_stream, rmx_solid_stats* stats) {
+    if (!c || !grid || !ss || n_solids < 1) return RMX_E_ARG;
+    rmx_options def;
+    rmx_default_options(&def);
+    if (!opt) opt = &def;
+    int rc = validate_options(opt);
+    if (rc != RMX_OK) return rc;
+    if (opt->flags & (RMX_FLAG_GRAPH | RMX_FLAG_PER_SOLID | RMX_FLAG_PERSISTENT))
+        return RMX_E_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return RMX_E_ARG;
+    // The extrapolation part works on xi^{n+1} and the labels of step n + 1.
+    std::vector<rmx_solid> sol(n_solids);
+    for (int i = 0; i < n_solids; ++i) {
+        const rmx_step_solid& t = ss[i];
+        if (!t.xi_n || !t.labels_n || !t.u || !t.uf[0] || !t.uf[1] || !t.uf[2] ||
+            !t.xi_next || !t.labels_next || !t.xi_half)
+            return RMX_E_ARG;
+        if (t.xi_n == t.xi_next || t.xi_n == t.xi_half || t.xi_next == t.xi_half)
+            return RMX_E_ARG;
+        rmx_solid& s = sol[i];
+        s = rmx_solid{};
+        for (int a = 0; a < 3; ++a) {
+            s.lo[a] = t.lo[a];
+            s.ext[a] = t.ext[a];
+        }
+        s.phi0 = t.phi0;
+        s.n_layers = t.n_layers;
+        s.xi = t.xi_next;
+        s.xi_normal = nullptr;
+        s.labels = t.labels_next;
+        s.decisions = t.decisions;
+        if ((rc = validate_solid(grid, &s)) != RMX_OK) return rc;
+        if (t.n_layers < 5) return RMX_E_LAYERS;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const bool sync = stats || (opt->flags & RMX_FLAG_SYNC);
+    if (sync && (rc = ctx_stats_host(c, (size_t)kStatWords * n_solids)) != RMX_OK) return rc;
+    c->grid_ptrs.assign(n_solids, grid);
+    Plan p;
+    if ((rc = plan_call(c, c->grid_ptrs.data(), sol.data(), n_solids, opt, nullptr, &p)) !=
+        RMX_OK)
+        return rc;
+    if ((rc = ensure_ws(c, p.ws_bytes)) != RMX_OK) return rc;
+    // Step workspace: the step descriptors, then 12 doubles per box cell (per axis: the
+    // transverse advecting velocity and the three chosen xi states).
+    const size_t desc = (sizeof(StepDev) * n_solids + 255) & ~size_t(255);
+    const size_t need = desc + sizeof(double) * 12 * (size_t)p.total_cells;
+    if (need > c->step_ws_size) {
+        if (c->fixed) return RMX_E_WORKSPACE;
+        if (c->step_ws) {
+            if (hipDeviceSynchronize() != hipSuccess) return RMX_E_HIP;
+            (void)hipFree(c->step_ws);
+            c->step_ws = nullptr;
+            c->step_ws_size = 0;
+        }
+        if (hipMalloc(&c->step_ws, need) != hipSuccess) {
+            c->step_ws = nullptr;
+            return RMX_E_HIP;
+        }
+        c->step_ws_size = need;
+    }
+    std::vector<StepDev> sd(n_solids);
+    double* trans = reinterpret_cast<double*>(static_cast<char*>(c->step_ws) + desc);
+    for (int i = 0; i < n_solids; ++i) {
+        const rmx_step_solid& t = ss[i];
+        sd[i].xi_n = t.xi_n;
+        sd[i].labels_n = t.labels_n;
+        sd[i].u = t.u;
+        for (int a = 0; a < 3; ++a) sd[i].uf[a] = t.uf[a];
+        sd[i].xi_half = t.xi_half;
+        sd[i].trans = trans;
+        trans += 12 * p.solids[i].ncell;
+    }
+    Staging* sg = nullptr;
+    if ((rc = get_stage(c, sizeof(StepDev) * n_solids, &sg)) != RMX_OK) return rc;
+    std::memcpy(sg->host, sd.data(), sizeof(StepDev) * n_solids);
+    if (hipMemcpyAsync(c->step_ws, sg->host, sizeof(StepDev) * n_solids,
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(sg->ev, st) != hipSuccess)
+        return RMX_E_HIP;
+    sg->pending = true;
+    StepBatch sb{};
+    sb.steps = static_cast<const StepDev*>(c->step_ws);
+    sb.lam = dt / grid->h;
+    sb.hl = 0.5 * sb.lam;
+    rc = launch_planned(c, p, n_solids, opt, st, false, 0, sync, c->ws, c->ws_size, false, &sb);
+    if (rc != RMX_OK) return rc;
     if (!sync) return RMX_OK;
     return finish_sync(c, st, n_solids, stats);
 }

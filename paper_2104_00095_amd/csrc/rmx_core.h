@@ -80,8 +80,10 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
          int normal_per_cu = 4, int band_per_cu = 2);
 void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b);
 void pack_desc(const Plan& p, void* host);
+// The launch chain of a planned call.  classify = false: the interior mask is already in
+// the workspace (a time step's predictor wrote it), so the chain starts at the labels.
 hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,
-                   Profiler* prof = nullptr);
+                   Profiler* prof = nullptr, bool classify = true);
 void convert_stats(const unsigned long long* dev, int n, rmx_solid_stats* out);
 uint64_t fnv1a(const void* p, size_t n, uint64_t h);
 

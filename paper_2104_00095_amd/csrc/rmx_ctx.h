@@ -7,6 +7,7 @@
 
 #include "rmx.h"
 #include "rmx_core.h"
+#include "rmx_step.h"
 
 namespace rmx {
 
@@ -51,6 +52,8 @@ struct rmx_ctx {
     std::unordered_map<uint64_t, rmx::Tuning> tuned;   // launch shapes per tune_key
     std::vector<rmx_solid_stats> tmp_stats;
     std::vector<const rmx_grid*> grid_ptrs;
+    void* step_ws = nullptr;   // time step: step descriptors + transverse face states
+    size_t step_ws_size = 0;
     void* scratch = nullptr;   // device address of this device's allocation-free workspace
     std::vector<rmx::Plan> noalloc_plans;
     rmx::Profiler prof;
@@ -68,10 +71,13 @@ int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
               const rmx_options* opt, const Tuning* force, Plan* p);
 // Enqueue a planned call on `st` with its workspace at [ws, ws + ws_size): descriptor
 // upload, kernels, optional statistics read-back into stats_host + stats_off.  no_alloc:
-// nothing is allocated (a staging buffer too small is RMX_E_WORKSPACE).
+// nothing is allocated (a staging buffer too small is RMX_E_WORKSPACE).  step (nullable,
+// not with use_graph): a time step -- its predictor writes the interior mask in place of
+// the classification, and its corrector follows the layer fits; the step's own fields of
+// the batch are step->steps, lam and hl (the rest is filled in here).
 int launch_planned(rmx_ctx* c, Plan& p, int n, const rmx_options* opt, hipStream_t st,
                    bool use_graph, size_t stats_off, bool want_stats, void* ws, size_t ws_size,
-                   bool no_alloc);
+                   bool no_alloc, const StepBatch* step = nullptr);
 // Wait for `st`, convert the statistics of n_solids solids into `stats` (nullable) and
 // return the first negative per-solid status, else RMX_OK.
 int finish_sync(rmx_ctx* c, hipStream_t st, int n_solids, rmx_solid_stats* stats);

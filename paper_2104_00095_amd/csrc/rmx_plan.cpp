@@ -304,7 +304,7 @@ Profiler::~Profiler() {
 // synchronises, so the sequence can be captured into a graph.  With a profiler, each
 // launch is bracketed by HIP events on the same stream.
 hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,
-                   Profiler* prof) {
+                   Profiler* prof, bool classify) {
     hipError_t e;
     Profiler::Rec rec{};
 #define RMX_TIMED(phase, call)                                              \
@@ -313,7 +313,7 @@ hipError_t enqueue(const Plan& p, const Batch& b, int precision, hipStream_t st,
         if ((e = (call)) != hipSuccess) return e;                            \
         if (prof && (e = prof->end(rec, st)) != hipSuccess) return e;        \
     } while (0)
-    RMX_TIMED(RMX_PHASE_CLASSIFY, launch_classify(b, st));
+    if (classify) RMX_TIMED(RMX_PHASE_CLASSIFY, launch_classify(b, st));
     RMX_TIMED(RMX_PHASE_LABEL, launch_label(b, p.lds_bytes, st));
     if (p.persistent) {
         RMX_TIMED(RMX_PHASE_BAND, launch_band(b, precision, p.band_blocks, st));

@@ -1,0 +1,42 @@
+// Device tables and launchers of one time step of the reference map around the
+// extrapolation (Lin, Derr & Rycroft, arXiv 2104.00095, SI "Timestepping algorithm",
+// steps 5-7 and 11; SI "Evaluating the advective term").
+#pragma once
+#include "rmx_internal.h"
+
+namespace rmx {
+
+// The step's own fields of one solid (the extrapolation's DevSolid carries xi^{n+1} as
+// xi, the labels at n + 1 as labels, the interior mask and the box).
+struct StepDev {
+    const double* xi_n;       // [3][ncell] xi^n
+    const int8_t* labels_n;   // [ncell] labels at step n
+    const double* u;          // [3][ncell] cell-centred velocity u^n
+    const double* uf[3];      // face-normal velocities: [n2][n1][n0+1], [n2][n1+1][n0],
+                              // [n2+1][n1][n0]
+    double* xi_half;          // [3][ncell] xi^{n+1/2}
+    double* trans;            // [3 axes][4][ncell] transverse faces (scratch)
+};
+
+struct StepBatch {
+    const DevSolid* solids;
+    const StepDev* steps;
+    int32_t n_solids;
+    int32_t pad_;
+    int64_t total_words;      // 64-cell row segments of all boxes
+    unsigned long long* stats;
+    int32_t* bcount;
+    BandCtl* band;
+    double lam;               // dt / h
+    double hl;                // dt / (2 h)
+};
+
+// Transverse face states and advecting velocities (zeroes the call's statistics and
+// counters first, as the classification does in an extrapolation call).
+hipError_t launch_step_trans(const StepBatch& b, hipStream_t st);
+// Predictor, the rest of the old band undefined, the interior mask at n + 1.
+hipError_t launch_step_predict(const StepBatch& b, hipStream_t st);
+// Corrector on the cells labelled at n + 1.
+hipError_t launch_step_correct(const StepBatch& b, hipStream_t st);
+
+}  // namespace rmx

@@ -20,8 +20,9 @@ E_TRUNCATED, E_BUDGET, E_BUSY, E_NOTFOUND, E_DISABLED = -7, -8, -9, -10, -11
 SPHERE, ELLIPSOID = 1, 2
 FP64, FP32_ACCUM = 0, 1
 FLAG_SYNC, FLAG_GRAPH, FLAG_PER_SOLID, FLAG_PROFILE, FLAG_PERSISTENT = 1, 2, 4, 8, 16
-N_PHASES = 20
-PHASES = ["classify", "label", "normal"] + [f"extrap{l}" for l in range(1, 17)] + ["band"]
+N_PHASES = 23
+PHASES = ["classify", "label", "normal"] + [f"extrap{l}" for l in range(1, 17)] + \
+    ["band", "step_trans", "step_predict", "step_correct"]
 MAX_LAYERS = 16
 DEC_F1, DEC_F2, DEC_NO_NORMAL = 32, 33, 64
 
@@ -30,7 +31,7 @@ EXPORTS = [
     "rmx_extrapolate", "rmx_status_string", "rmx_server_create", "rmx_server_register",
     "rmx_server_field", "rmx_server_submit", "rmx_server_wait", "rmx_server_release",
     "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read", "rmx_autotune",
-    "rmx_set_tuning", "rmx_extrapolate_noalloc",
+    "rmx_set_tuning", "rmx_extrapolate_noalloc", "rmx_step",
 ]
 
 
@@ -48,6 +49,15 @@ class Solid(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_int32 * 3), ("ext", ctypes.c_int32 * 3), ("phi0", Shape),
                 ("n_layers", ctypes.c_int32), ("xi", ctypes.c_void_p),
                 ("xi_normal", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("decisions", ctypes.c_void_p)]
+
+
+class StepSolid(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("ext", ctypes.c_int32 * 3), ("phi0", Shape),
+                ("n_layers", ctypes.c_int32), ("xi_n", ctypes.c_void_p),
+                ("labels_n", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("uf", ctypes.c_void_p * 3), ("xi_next", ctypes.c_void_p),
+                ("labels_next", ctypes.c_void_p), ("xi_half", ctypes.c_void_p),
                 ("decisions", ctypes.c_void_p)]
 
 
@@ -119,6 +129,8 @@ def lib():
                                               P(Options), vp, P(SolidStats)]
         L.rmx_set_tuning.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, P(Options),
                                      P(Tuning)]
+        L.rmx_step.argtypes = [vp, P(Grid), P(StepSolid), ctypes.c_int32, P(Options),
+                               ctypes.c_double, vp, P(SolidStats)]
         for name in EXPORTS:
             if name != "rmx_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -207,6 +219,33 @@ def solid(lo, ext, shp: Shape, n_layers, xi, labels, xi_normal=None, decisions=N
     return s
 
 
+def step_solid(lo, ext, shp: Shape, n_layers, xi_n, labels_n, u, uf, xi_next, labels_next,
+               xi_half, decisions=None) -> StepSolid:
+    """One solid's buffers for rmx_step (cuda tensors): xi_n, u, xi_next, xi_half float64
+    [3, e2, e1, e0]; labels_n, labels_next int8 [e2, e1, e0]; uf = (x-faces float64
+    [e2, e1, e0+1], y-faces [e2, e1+1, e0], z-faces [e2+1, e1, e0])."""
+    e = tuple(int(v) for v in ext)
+    f3 = (3, e[2], e[1], e[0])
+    for t in (xi_n, u, xi_next, xi_half):
+        assert tuple(t.shape) == f3 and t.is_contiguous(), t.shape
+    for t in (labels_n, labels_next):
+        assert tuple(t.shape) == f3[1:] and t.is_contiguous(), t.shape
+    for a, want in enumerate([(e[2], e[1], e[0] + 1), (e[2], e[1] + 1, e[0]),
+                              (e[2] + 1, e[1], e[0])]):
+        assert tuple(uf[a].shape) == want and uf[a].is_contiguous(), (a, uf[a].shape)
+    s = StepSolid()
+    s.lo[:] = [int(v) for v in lo]
+    s.ext[:] = list(e)
+    s.phi0 = shp
+    s.n_layers = int(n_layers)
+    s.xi_n, s.labels_n, s.u = _ptr(xi_n), _ptr(labels_n), _ptr(u)
+    s.uf[:] = [_ptr(t) for t in uf]
+    s.xi_next, s.labels_next, s.xi_half = _ptr(xi_next), _ptr(labels_next), _ptr(xi_half)
+    s.decisions = _ptr(decisions)
+    s._keep = (xi_n, labels_n, u, tuple(uf), xi_next, labels_next, xi_half, decisions)
+    return s
+
+
 def _stream_handle(stream):
     if stream is None:
         import torch
@@ -282,6 +321,25 @@ class Context:
         if check and st < 0 and st != E_TRUNCATED:
             raise RmxError(st, "rmx_extrapolate_noalloc")
         return st, ([s.as_dict() for s in stats] if want_stats else None)
+
+    def step(self, g: Grid, solids: Sequence[StepSolid], dt: float,
+             opt: Optional[Options] = None, stream=None, want_stats: bool = True,
+             check: bool = True):
+        """One time step of every solid (rmx_step): predictor, extrapolation from the
+        predicted interior, corrector; returns (status, [stats dict per solid] or None)."""
+        arr = (StepSolid * len(solids))(*solids)
+        stats = (SolidStats * len(solids))() if want_stats else None
+        st = lib().rmx_step(self.h, ctypes.byref(g), arr, len(solids),
+                            ctypes.byref(opt) if opt else None, float(dt),
+                            _stream_handle(stream), stats)
+        if check and st < 0 and st != E_TRUNCATED:
+            raise RmxError(st, "rmx_step")
+        return st, ([s.as_dict() for s in stats] if want_stats else None)
+
+    def step_raw(self, g: Grid, arr, n: int, opt: Options, dt: float, stream_handle):
+        """rmx_step on a prebuilt StepSolid array, no statistics (timing loops)."""
+        return lib().rmx_step(self.h, ctypes.byref(g), arr, n, ctypes.byref(opt), float(dt),
+                              stream_handle, None)
 
     def set_tuning(self, g: Grid, solids: Sequence[Solid], tile_w: int, extrap_blocks: int,
                    opt: Optional[Options] = None):

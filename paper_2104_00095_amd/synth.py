@@ -22,6 +22,10 @@ Workloads (the paper's simulation states are not available; these stand in for t
 * ``serving_trace``-- 2000 requests from 100 simulations x 20 steps, Poisson arrivals at
                       200/s, grids {32, 64, 96, 128, 192}^3, 1-64 ellipsoids per
                       simulation (semi-axes U[0.05, 0.2]), L in {4, 5, 6}, FP32/FP64.
+* ``step_velocity``-- the velocity a time step advects with: the cavity's cellular flow
+                      U (sin pi x cos pi y, -cos pi x sin pi y) plus a uniform drift w0 along
+                      z (divergence-free), sampled at cell centres and at face centres of
+                      each solid's box; dt from a CFL number.
 """
 from __future__ import annotations
 
@@ -422,3 +426,51 @@ WORKLOADS = {
     "suspension": suspension,
     "cavity256": cavity256,
 }
+
+
+# ------------------------------------------------------------------------------------------
+# time step: the advecting velocity
+# ------------------------------------------------------------------------------------------
+def flow_velocity(x, y, z, U=1.0, w0=0.3):
+    """(sin pi x cos pi y, -cos pi x sin pi y) U, plus w0 along z."""
+    ux = U * np.sin(math.pi * x) * np.cos(math.pi * y)
+    uy = -U * np.cos(math.pi * x) * np.sin(math.pi * y)
+    uz = np.full(np.broadcast(x, y, z).shape, float(w0))
+    return np.stack(np.broadcast_arrays(ux, uy, uz)).astype(np.float64)
+
+
+@dataclass
+class StepVelocity:
+    u: np.ndarray          # [3, e2, e1, e0] at cell centres
+    uf: tuple              # x-faces [e2, e1, e0+1], y-faces [e2, e1+1, e0], z-faces [e2+1, e1, e0]
+
+
+def step_velocity(w: "Workload", U=1.0, w0=0.3):
+    """Per solid of `w`: the velocity at its cell centres and its face centres."""
+    out = []
+    h, o = w.h, w.origin
+    for s in w.solids:
+        lo, e = s.lo, s.ext
+        x, y, z = cell_centres(lo, e, h, o)
+        u = flow_velocity(x, y, z, U, w0)
+        k, j, i = np.meshgrid(np.arange(e[2]), np.arange(e[1]), np.arange(e[0] + 1),
+                              indexing="ij")
+        ufx = flow_velocity(o[0] + (lo[0] + i) * h, o[1] + (lo[1] + j + 0.5) * h,
+                            o[2] + (lo[2] + k + 0.5) * h, U, w0)[0]
+        k, j, i = np.meshgrid(np.arange(e[2]), np.arange(e[1] + 1), np.arange(e[0]),
+                              indexing="ij")
+        ufy = flow_velocity(o[0] + (lo[0] + i + 0.5) * h, o[1] + (lo[1] + j) * h,
+                            o[2] + (lo[2] + k + 0.5) * h, U, w0)[1]
+        k, j, i = np.meshgrid(np.arange(e[2] + 1), np.arange(e[1]), np.arange(e[0]),
+                              indexing="ij")
+        ufz = flow_velocity(o[0] + (lo[0] + i + 0.5) * h, o[1] + (lo[1] + j + 0.5) * h,
+                            o[2] + (lo[2] + k) * h, U, w0)[2]
+        out.append(StepVelocity(np.ascontiguousarray(u), (np.ascontiguousarray(ufx),
+                                                          np.ascontiguousarray(ufy),
+                                                          np.ascontiguousarray(ufz))))
+    return out
+
+
+def step_dt(w: "Workload", cfl=0.4, U=1.0, w0=0.3) -> float:
+    """dt with max |u_a| dt / h = cfl (per axis)."""
+    return cfl * w.h / max(abs(U), abs(w0))

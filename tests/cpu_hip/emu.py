@@ -12,7 +12,8 @@ CSRC = os.path.join(ROOT, "paper_2104_00095_amd", "csrc")
 EXE = os.path.join(HERE, "run_case_emu")
 CLANG = "/opt/rocm/lib/llvm/bin/clang++"
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("rmx_kernels.hip", "rmx_plan.cpp", "rmx_core.cpp", "rmx_server.cpp")] + \
+           ("rmx_kernels.hip", "rmx_step.hip", "rmx_plan.cpp", "rmx_core.cpp",
+            "rmx_server.cpp")] + \
           [os.path.join(HERE, "hip_emu.cpp"), os.path.join(HERE, "run_case.cpp")]
 
 
@@ -24,7 +25,7 @@ def build(sanitize=True):
         return EXE
     flags = ["-std=c++20", "-g", "-O1", "-fno-omit-frame-pointer", "-Wno-unknown-attributes",
              "-Wno-unused-command-line-argument", "-I", HERE, "-I", os.path.join(ROOT, "include"),
-             "-I", CSRC, "-DRMX_EMU_REDZONES"]
+             "-I", CSRC, "-DRMX_EMU_REDZONES", "-ffp-contract=off"]
     if sanitize:
         flags += ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
     cmd = [CLANG] + flags + ["-x", "c++"] + srcs + ["-o", EXE + ".tmp", "-lpthread"]
@@ -77,3 +78,40 @@ def run(w, tmpdir, r_s=2, r_max=4, normal_layers=2, precision=0, flags=0, reps=1
         raw = open(os.path.join(tmpdir, f"st{i}.bin"), "rb").read()
         outs.append((xo, lab, dec, raw))
     return st, outs
+
+
+def run_step(w, tmpdir, xi_n, labels_n, u, uf, dt, xi_next_init, xi_half_init, r_s=2, r_max=4,
+             normal_layers=2, precision=0, flags=0, timeout=600):
+    """One rmx_step call of the emulated library on workload `w` (boxes, shapes, layers;
+    its xi is ignored).  Per solid: xi_n, labels_n, u, uf = (x, y, z faces), the initial
+    xi_next and xi_half.  Returns (status, [(xi_next, labels_next, decisions, stats_raw,
+    xi_half)])."""
+    import types
+    solids = []
+    for i, s in enumerate(w.solids):
+        solids.append(types.SimpleNamespace(lo=s.lo, ext=s.ext, n_layers=s.n_layers,
+                                            shape=s.shape, xi=xi_next_init[i]))
+    ww = types.SimpleNamespace(solids=solids, grid_n=w.grid_n, h=w.h, origin=w.origin)
+    os.makedirs(tmpdir, exist_ok=True)
+    with open(os.path.join(tmpdir, "step.txt"), "w") as f:
+        f.write(f"{float(dt)!r}\n")
+    for i in range(len(w.solids)):
+        def put(name, a, dtype):
+            np.ascontiguousarray(a, dtype=dtype).tofile(os.path.join(tmpdir, f"{name}{i}.bin"))
+        put("xin", xi_n[i], np.float64)
+        put("labn", labels_n[i], np.int8)
+        put("u", u[i], np.float64)
+        put("ufx", uf[i][0], np.float64)
+        put("ufy", uf[i][1], np.float64)
+        put("ufz", uf[i][2], np.float64)
+        put("xhalf", xi_half_init[i], np.float64)
+    try:
+        st, outs = run(ww, tmpdir, r_s=r_s, r_max=r_max, normal_layers=normal_layers,
+                       precision=precision, flags=flags, timeout=timeout)
+    finally:
+        os.remove(os.path.join(tmpdir, "step.txt"))
+    res = []
+    for i, (xo, lab, dec, raw) in enumerate(outs):
+        half = np.fromfile(os.path.join(tmpdir, f"half{i}.bin"), dtype=np.float64).reshape(xo.shape)
+        res.append((xo, lab, dec, raw, half))
+    return st, res

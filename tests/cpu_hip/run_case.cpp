@@ -1,5 +1,6 @@
-// Runs one rmx_extrapolate call of the CPU-emulated library on a case written by
-// tests/cpu_hip/emu.py and writes the outputs next to it.  Test infrastructure only.
+// Runs one rmx_extrapolate call (or, when the case holds step.txt, one rmx_step call) of
+// the CPU-emulated library on a case written by tests/cpu_hip/emu.py and writes the
+// outputs next to it.  Test infrastructure only.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -71,6 +72,51 @@ int main(int argc, char** argv) {
     int st = rmx_create(0, 0, &ctx);
     if (st) return 3;
     std::vector<rmx_solid_stats> stats(ns);
+    // Time step: xi{i}.bin is the initial content of xi_next; the step's own inputs and
+    // the initial xi_half come from their own files.
+    FILE* sf = std::fopen((dir + "/step.txt").c_str(), "r");
+    if (sf) {
+        double dt = 0.0;
+        if (std::fscanf(sf, "%lf", &dt) != 1) return 2;
+        std::fclose(sf);
+        std::vector<rmx_step_solid> ss(ns);
+        std::vector<double*> half(ns);
+        auto load = [&](const std::string& name, int i) {
+            auto b = slurp((dir + "/" + name + std::to_string(i) + ".bin").c_str());
+            void* d = nullptr;
+            hipMalloc(&d, b.size());
+            std::memcpy(d, b.data(), b.size());
+            return d;
+        };
+        for (int i = 0; i < ns; ++i) {
+            rmx_step_solid& t = ss[i];
+            for (int a = 0; a < 3; ++a) {
+                t.lo[a] = sol[i].lo[a];
+                t.ext[a] = sol[i].ext[a];
+            }
+            t.phi0 = sol[i].phi0;
+            t.n_layers = sol[i].n_layers;
+            t.xi_n = static_cast<double*>(load("xin", i));
+            t.labels_n = static_cast<int8_t*>(load("labn", i));
+            t.u = static_cast<double*>(load("u", i));
+            t.uf[0] = static_cast<double*>(load("ufx", i));
+            t.uf[1] = static_cast<double*>(load("ufy", i));
+            t.uf[2] = static_cast<double*>(load("ufz", i));
+            t.xi_next = sol[i].xi;
+            t.labels_next = sol[i].labels;
+            half[i] = static_cast<double*>(load("xhalf", i));
+            t.xi_half = half[i];
+            t.decisions = sol[i].decisions;
+        }
+        for (int r = 0; r < reps; ++r)
+            st = rmx_step(ctx, &g, ss.data(), ns, &o, dt, nullptr, stats.data());
+        for (int i = 0; i < ns; ++i) {
+            FILE* f = std::fopen((dir + "/half" + std::to_string(i) + ".bin").c_str(), "wb");
+            std::fwrite(half[i], 1, ncell[i] * 3 * sizeof(double), f);
+            std::fclose(f);
+        }
+        reps = 0;   // the extrapolation below is not run
+    }
     // Optional warm-up calls with other flags on fresh copies of the fields (the same
     // context), as a test process does before the measured call.
     FILE* pre = std::fopen((dir + "/pre_flags.txt").c_str(), "r");
@@ -103,7 +149,7 @@ int main(int argc, char** argv) {
     // flag bit 4096 (not a library flag): the measured call is the allocation-free entry
     const bool noalloc = (o.flags & 4096u) != 0;
     o.flags &= ~4096u;
-    for (int r = 0; r < reps; ++r)
+    for (int r = 0; r < reps && !sf; ++r)
         st = noalloc ? rmx_extrapolate_noalloc(ctx, &g, sol.data(), ns, &o, nullptr, stats.data())
                      : rmx_extrapolate(ctx, &g, sol.data(), ns, &o, nullptr, stats.data());
     FILE* out = std::fopen((dir + "/status.txt").c_str(), "w");

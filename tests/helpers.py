@@ -144,3 +144,84 @@ def plates_workload(a=4, gap=3, p=0.3, q=0.7, n_layers=2):
     w.solids.append(synth.Solid((0, 0, 0), (n0, n1, n2),
                                 synth.sphere_shape((0.0, 0.0, 0.0), 1000.0), n_layers, xi))
     return w, xn
+
+
+# ---- time step ------------------------------------------------------------------------
+class StepCase:
+    """Inputs of one time step of workload `w`, all from the seeded generators and the
+    oracle (never from the GPU): per solid xi^n with its band extrapolated by the oracle,
+    the labels of step n, the velocity at cells and faces, the initial contents of the
+    output buffers, and dt."""
+
+    def __init__(self, w, cfl=0.4, r_s=2, r_max=4, normal_layers=2, seed=17):
+        self.w = w
+        self.opts = dict(r_s=r_s, r_max=r_max, normal_layers=normal_layers)
+        self.xi_n, self.labels_n = [], []
+        for s in w.solids:
+            st, xo, lab, _, _ = run_oracle(w, s, **self.opts)
+            assert st == 0, st
+            self.xi_n.append(xo)
+            self.labels_n.append(lab)
+        self.vel = synth.step_velocity(w)
+        self.dt = synth.step_dt(w, cfl)
+        rng = np.random.default_rng(seed)
+        # recognisable contents: cells the step must leave alone keep them
+        self.next_init = [rng.uniform(-9, -8, size=x.shape) for x in self.xi_n]
+        self.half_init = [rng.uniform(8, 9, size=x.shape) for x in self.xi_n]
+
+    def oracle(self):
+        """[(status, xi_next, labels_next, decisions, stats, xi_half)] per solid."""
+        out = []
+        for i, s in enumerate(self.w.solids):
+            p = oracle_problem(self.w, s, **self.opts)
+            v = self.vel[i]
+            out.append(oracle.step(p, self.xi_n[i], self.labels_n[i], v.u, v.uf, self.dt,
+                                   self.w.h, self.next_init[i], self.half_init[i]))
+        return out
+
+
+def predicted_cells(labels_n, L):
+    """Cells the predictor runs on: labelled 0..L-4 at step n, 3 cells inside the box."""
+    e2, e1, e0 = labels_n.shape
+    k, j, i = np.meshgrid(np.arange(e2), np.arange(e1), np.arange(e0), indexing="ij")
+    inside = (i >= 3) & (i <= e0 - 4) & (j >= 3) & (j <= e1 - 4) & (k >= 3) & (k <= e2 - 4)
+    return (labels_n >= 0) & (labels_n <= L - 4) & inside
+
+
+def compare_step(case, got, expect, tol=1e-12, tag=""):
+    """got / expect: per solid (status, xi_next, labels_next, decisions, xi_half).  Labels
+    and decisions equal; predicted cells and the interior's corrector bitwise; the rest of
+    the old band NaN; the extrapolated band and its corrector within tol (relative
+    max-norm); every other cell as the caller left it.  Returns the worst band error."""
+    worst = 0.0
+    for i, s in enumerate(case.w.solids):
+        gst, gx, gl, gd, gh = got[i]
+        est, ex, el, ed, eh = expect[i]
+        L = s.n_layers
+        assert gst == est, (tag, i, gst, est)
+        assert np.array_equal(gl, el), (tag, i, "labels", int((gl != el).sum()))
+        P = predicted_cells(case.labels_n[i], L)
+        old = (case.labels_n[i] >= 0) & (case.labels_n[i] <= L)
+        newband = (el >= 1) & (el <= L) if est == 0 else np.zeros_like(P)
+        # predicted values that the extrapolation does not overwrite
+        Pk = P & ~newband
+        assert np.array_equal(gx[:, Pk].view(np.uint64), ex[:, Pk].view(np.uint64)), \
+            (tag, i, "predictor", int((gx[:, Pk] != ex[:, Pk]).sum()))
+        rest = old & ~P
+        assert np.isnan(gx[:, rest & ~newband]).all() and np.isnan(ex[:, rest & ~newband]).all()
+        untouched = ~(old | newband | P)
+        assert np.array_equal(gx[:, untouched], case.next_init[i][:, untouched]), (tag, i)
+        if est != 0:
+            continue
+        assert np.array_equal(gd[newband], ed[newband]), (tag, i, "decisions")
+        e = rel_err(gx, ex, newband)
+        assert e <= tol, (tag, i, "band", e)
+        worst = max(worst, e)
+        interior = el == 0
+        assert np.array_equal(gh[:, interior].view(np.uint64), eh[:, interior].view(np.uint64)), \
+            (tag, i, "corrector interior")
+        eh_band = rel_err(gh, eh, newband)
+        assert eh_band <= tol, (tag, i, "corrector band", eh_band)
+        labelled = el >= 0
+        assert np.array_equal(gh[:, ~labelled], case.half_init[i][:, ~labelled]), (tag, i)
+    return worst

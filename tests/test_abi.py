@@ -43,6 +43,10 @@ int main(void) {
          offsetof(rmx_solid, decisions), offsetof(rmx_solid_stats, status),
          offsetof(rmx_shape, rot));
   printf("%zu %zu\\n", sizeof(rmx_tuning), offsetof(rmx_tuning, ms));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rmx_step_solid), offsetof(rmx_step_solid, xi_n),
+         offsetof(rmx_step_solid, uf), offsetof(rmx_step_solid, xi_next),
+         offsetof(rmx_step_solid, decisions));
+  printf("%d %d\\n", RMX_N_PHASES, RMX_PHASE_STEP_TRANS);
   return 0;
 }
 """)
@@ -53,8 +57,12 @@ int main(void) {
             ctypes.sizeof(rmx.Options), ctypes.sizeof(rmx.SolidStats),
             rmx.Solid.phi0.offset, rmx.Solid.xi.offset, rmx.Solid.decisions.offset,
             rmx.SolidStats.status.offset, rmx.Shape.rot.offset,
-            ctypes.sizeof(rmx.Tuning), rmx.Tuning.ms.offset]
+            ctypes.sizeof(rmx.Tuning), rmx.Tuning.ms.offset,
+            ctypes.sizeof(rmx.StepSolid), rmx.StepSolid.xi_n.offset, rmx.StepSolid.uf.offset,
+            rmx.StepSolid.xi_next.offset, rmx.StepSolid.decisions.offset,
+            rmx.N_PHASES, rmx.PHASES.index("step_trans")]
     assert [int(v) for v in a] == want
+    assert len(rmx.PHASES) == rmx.N_PHASES
 
 
 def _desc(ext=(32, 32, 32), lo=(0, 0, 0), L=4, kind=1, semi=(0.25,), rot=None):
@@ -112,6 +120,9 @@ def test_null_context_and_status_strings():
     g = rmx.grid((32, 32, 32), 1 / 32)
     d = _desc()
     assert L.rmx_extrapolate(None, ctypes.byref(g), ctypes.byref(d), 1, None, None, None) \
+        == rmx.E_ARG
+    sd = rmx.StepSolid()
+    assert L.rmx_step(None, ctypes.byref(g), ctypes.byref(sd), 1, None, 0.01, None, None) \
         == rmx.E_ARG
     assert rmx.status_string(rmx.E_TRUNCATED) == "band truncated by the box"
     assert rmx.status_string(rmx.E_DISABLED).startswith("launch form switched off")

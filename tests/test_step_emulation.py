@@ -1,0 +1,61 @@
+"""One time step (rmx_step: predictor, extrapolation from the predicted interior,
+corrector) of the library built for the CPU over the host emulation of HIP, under
+AddressSanitizer and UndefinedBehaviorSanitizer, against the oracle's step (SI
+"Timestepping algorithm", steps 5-7).  Predicted cells, the interior mask that follows
+from them, labels and decisions must equal the oracle's bit for bit; the extrapolated band
+meets the FP64 tolerance.  Test infrastructure only."""
+import os
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from paper_2104_00095_amd import rmx, synth
+from tests.helpers import StepCase, compare_step
+
+emu = pytest.importorskip("tests.cpu_hip.emu")
+pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
+
+
+def _workloads():
+    return {
+        "sphere24": synth.sphere32(n=24, n_layers=6),
+        "ellipsoid36": synth.ellipsoid128(n=36, n_layers=6),
+        "suspension3": synth.suspension(n_solids=3, grid_n=(40, 40, 56), h=1.0 / 40,
+                                        n_layers=6),
+        "sphere24_L5": synth.sphere32(n=24, n_layers=5),
+    }
+
+
+@pytest.fixture(scope="module")
+def stepped():
+    emu.build()
+    root = tempfile.mkdtemp(prefix="rmx_emu_step_")
+
+    def one(item):
+        name, w = item
+        case = StepCase(w)
+        st, outs = emu.run_step(w, os.path.join(root, name), case.xi_n, case.labels_n,
+                                [v.u for v in case.vel], [v.uf for v in case.vel], case.dt,
+                                case.next_init, case.half_init)
+        got = []
+        for xo, lab, dec, raw, half in outs:
+            sst = rmx.SolidStats.from_buffer_copy(raw).status
+            got.append((sst, xo, lab, dec, half))
+        return name, (case, st, got)
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        return dict(ex.map(one, _workloads().items()))
+
+
+@pytest.mark.parametrize("name", ["sphere24", "ellipsoid36", "suspension3", "sphere24_L5"])
+def test_emulated_step_matches_oracle(stepped, name):
+    case, st, got = stepped[name]
+    expect = [(o[0], o[1], o[2], o[3], o[5]) for o in case.oracle()]
+    assert st == min([e[0] for e in expect] + [0])
+    compare_step(case, got, expect, tag=name)
+    # the step did something: the solids moved
+    moved = any(((case.labels_n[i] == 0) != (got[i][2] == 0)).any()
+                for i in range(len(got)) if got[i][0] == 0)
+    assert moved
