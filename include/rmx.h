@@ -92,7 +92,8 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
 #define RMX_PHASE_STEP_TRANS 20   /* rmx_step: transverse face states                     */
 #define RMX_PHASE_STEP_PREDICT 21 /* rmx_step: predictor and the interior mask at n + 1   */
 #define RMX_PHASE_STEP_CORRECT 22 /* rmx_step: corrector                                  */
-#define RMX_N_PHASES 23
+#define RMX_PHASE_STEP_FACES 23   /* rmx_step: chosen xi states on the faces              */
+#define RMX_N_PHASES 24
 
 /* Grid: M x N x O cells; cell (i,j,k) has centre origin + (idx + 1/2) h (SI, "Variable
  * arrangement"; isotropic spacing as in the paper's runs).  The fit is invariant to h
@@ -244,14 +245,14 @@ typedef struct {
     int8_t* decisions;        /* DEVICE, out, nullable: as for rmx_extrapolate             */
 } rmx_step_solid;
 
-/* One time step of every solid of the batch, enqueued on hip_stream as one chain (three
+/* One time step of every solid of the batch, enqueued on hip_stream as one chain (four
  * step kernels around the extrapolation's label, normal and layer-fit launches; no
  * classification pass: the predictor writes the interior mask).  dt > 0, finite.  Options
  * as for rmx_extrapolate (RMX_FLAG_SYNC, RMX_FLAG_PROFILE, precision, radii, normal
  * layers); RMX_FLAG_GRAPH, RMX_FLAG_PER_SOLID and RMX_FLAG_PERSISTENT are RMX_E_ARG.
  * stats (HOST, nullable, n_solids entries) implies a wait, as for rmx_extrapolate.  The
- * workspace grows by 96 B per box cell (transverse face states) on top of the
- * extrapolation's. */
+ * step's own workspace holds 240 B per box cell (transverse face states and the
+ * expansions to the faces), on top of the extrapolation's. */
 int rmx_step(rmx_ctx* ctx, const rmx_grid* grid, const rmx_step_solid* solids,
              int32_t n_solids, const rmx_options* opt, double dt, void* hip_stream,
              rmx_solid_stats* stats);

@@ -179,6 +179,9 @@ static hipError_t step_chain(const Plan& p, const Batch& b, const StepBatch& sb,
     };
     if ((e = timed(RMX_PHASE_STEP_TRANS, [&] { return launch_step_trans(sb, st); })) != hipSuccess)
         return e;
+    if ((e = timed(RMX_PHASE_STEP_FACES, [&] { return launch_step_faces(sb, st); })) !=
+        hipSuccess)
+        return e;
     if ((e = timed(RMX_PHASE_STEP_PREDICT, [&] { return launch_step_predict(sb, st); })) !=
         hipSuccess)
         return e;
@@ -497,10 +500,11 @@ int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t
         RMX_OK)
         return rc;
     if ((rc = ensure_ws(c, p.ws_bytes)) != RMX_OK) return rc;
-    // Step workspace: the step descriptors, then 12 doubles per box cell (per axis: the
-    // transverse advecting velocity and the three chosen xi states).
+    // Step workspace: the step descriptors, then 30 doubles per box cell: per axis the
+    // transverse advecting velocity and the three chosen transverse xi states (12), and the
+    // expansions of the three xi components to the cell's +a and -a faces (18).
     const size_t desc = (sizeof(StepDev) * n_solids + 255) & ~size_t(255);
-    const size_t need = desc + sizeof(double) * 12 * (size_t)p.total_cells;
+    const size_t need = desc + sizeof(double) * 30 * (size_t)p.total_cells;
     if (need > c->step_ws_size) {
         if (c->fixed) return RMX_E_WORKSPACE;
         if (c->step_ws) {
@@ -525,7 +529,8 @@ int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t
         for (int a = 0; a < 3; ++a) sd[i].uf[a] = t.uf[a];
         sd[i].xi_half = t.xi_half;
         sd[i].trans = trans;
-        trans += 12 * p.solids[i].ncell;
+        sd[i].faces = trans + 12 * p.solids[i].ncell;
+        trans += 30 * p.solids[i].ncell;
     }
     Staging* sg = nullptr;
     if ((rc = get_stage(c, sizeof(StepDev) * n_solids, &sg)) != RMX_OK) return rc;

@@ -16,6 +16,8 @@ struct StepDev {
                               // [n2+1][n1][n0]
     double* xi_half;          // [3][ncell] xi^{n+1/2}
     double* trans;            // [3 axes][4][ncell] transverse faces (scratch)
+    double* faces;            // [3 axes][2 sides][3][ncell] expansions of xi to the cell's
+                              // +a face (side 0) and -a face (side 1)
 };
 
 struct StepBatch {
@@ -34,6 +36,8 @@ struct StepBatch {
 // Transverse face states and advecting velocities (zeroes the call's statistics and
 // counters first, as the classification does in an extrapolation call).
 hipError_t launch_step_trans(const StepBatch& b, hipStream_t st);
+// Expansions of xi from the cells next to predicted cells to their faces.
+hipError_t launch_step_faces(const StepBatch& b, hipStream_t st);
 // Predictor, the rest of the old band undefined, the interior mask at n + 1.
 hipError_t launch_step_predict(const StepBatch& b, hipStream_t st);
 // Corrector on the cells labelled at n + 1.

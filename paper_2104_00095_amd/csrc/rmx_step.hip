@@ -7,17 +7,20 @@
 //                   axis t: the transverse face between the cell and its +t neighbour --
 //                   the Godunov choice of the advecting t-velocity from its down and up
 //                   expansions, and the chosen expansion of each xi component;
-//   k_step_predict  per predicted cell (labelled 0..L-4 at step n, 3 cells inside the
-//                   box): the face states of xi on its six faces (expansion from each
-//                   side with the tangential terms, chosen by the sign of the face
-//                   velocity), the advective term, xi^{n+1} = xi^n - dt [(u.grad) xi];
+//   k_step_faces    per cell next to a predicted cell (labelled 0..L-4 at step n, 3
+//                   cells inside the box) and per axis a: the expansions of xi from the
+//                   cell to its -a and +a faces with their tangential terms -- each once;
+//   k_step_predict  per predicted cell: the Godunov choice of each of its six face states
+//                   by the sign of the face velocity, the advective term,
+//                   xi^{n+1} = xi^n - dt [(u.grad) xi];
 //                   the rest of the old band becomes undefined (NaN); the interior mask
 //                   of step n + 1 (predicted cells with phi0(xi^{n+1}) < 0) is written
 //                   here, so the extrapolation that follows needs no classification pass;
 //   (extrapolation from that mask: labels, normals, layer fits -- the library's chain)
-//   k_step_correct  per cell labelled at n + 1: xi^{n+1/2} = (xi^n + xi^{n+1}) / 2 where
-//                   the cell was labelled at n too, else xi^{n+1}.
-// Every kernel walks 64-cell row segments, one per wave (the mask word of the segment).
+//   k_step_correct  per cell labelled at n + 1 (unless the solid failed): xi^{n+1/2} =
+//                   (xi^n + xi^{n+1}) / 2 where the cell was labelled at n too, else
+//                   xi^{n+1}.
+// Every kernel takes one 64-cell row segment per wave (the mask word of the segment).
 // The arithmetic is evaluated per value in one fixed order without contraction (this
 // file is compiled with -ffp-contract=off), so the predicted values, and with them the
 // interior decisions, are those of any implementation of the same expressions.
@@ -52,9 +55,15 @@ __device__ __forceinline__ double slope4(double qm2, double qm1, double q0, doub
     return copysign(m, dc);
 }
 
+// Loads of the step's arrays through the global address space (partial waits).
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, int64_t i) {
+    return load_global(p + i);
+}
+
 // Slope of field p at cell x along a stride s.
 __device__ __forceinline__ double slope_at(const double* p, int64_t x, int64_t s) {
-    return slope4(p[x - 2 * s], p[x - s], p[x], p[x + s], p[x + 2 * s]);
+    return slope4(ld(p, x - 2 * s), ld(p, x - s), ld(p, x), ld(p, x + s), ld(p, x + 2 * s));
 }
 
 // Godunov choice of a transverse advecting velocity from its down and up expansions.
@@ -106,29 +115,26 @@ __device__ __forceinline__ Seg segment(const StepBatch& b, int64_t w) {
     return g;
 }
 
+__device__ __forceinline__ int64_t wave_segment() {
+    return (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+}
+
 // ------------------------------------------------------------------------------------
 // Transverse faces.  Block 0 also zeroes the call's statistics and brick counters.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_step_trans(StepBatch b) {
-    if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 256) b.stats[i] = 0ull;
-        for (int i = threadIdx.x; i < kMaxLayers * kBuckets; i += 256) b.bcount[i] = 0;
-        const int nctl = (int)(sizeof(BandCtl) / sizeof(int));
-        for (int i = threadIdx.x; i < nctl; i += 256) reinterpret_cast<int*>(b.band)[i] = 0;
-    }
+__device__ void trans_segment(const StepBatch& b, int64_t w) {
     const double hl = b.hl;
-    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < b.total_words;
-         w += (int64_t)gridDim.x * 4) {
+    {
         const Seg g = segment(b, w);
         const DevSolid* d = b.solids + g.s;
         const StepDev* sd = b.steps + g.s;
         const int L = d->L;
         int lab = -1;
-        if (g.i < d->n0) lab = sd->labels_n[g.c];
+        if (g.i < d->n0) lab = ld(sd->labels_n, g.c);
         // faces that a predicted cell reads lie within L1 distance 2 of it
         const bool act = lab >= 0 && lab <= L - 2;
-        if (__ballot(act) == 0ull) continue;
-        if (!act) continue;
+        if (__ballot(act) == 0ull) return;
+        if (!act) return;
         const int64_t nc = d->ncell;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
@@ -138,7 +144,7 @@ __global__ __launch_bounds__(256) void k_step_trans(StepBatch b) {
             const int64_t s = axis_stride(d, t);
             const int64_t x = g.c, y = g.c + s;
             const double* v = sd->u + t * nc;
-            const double vx = v[x], vy = v[y];
+            const double vx = ld(v, x), vy = ld(v, y);
             const double vd = vx + (0.5 - hl * vx) * slope_at(v, x, s);
             const double vu = vy - (0.5 + hl * vy) * slope_at(v, y, s);
             const double wv = godunov_vel(vd, vu);
@@ -147,12 +153,23 @@ __global__ __launch_bounds__(256) void k_step_trans(StepBatch b) {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const double* p = sd->xi_n + q * nc;
-                const double qd = p[x] + (0.5 - hl * vx) * slope_at(p, x, s);
-                const double qu = p[y] - (0.5 + hl * vy) * slope_at(p, y, s);
+                const double qd = ld(p, x) + (0.5 - hl * vx) * slope_at(p, x, s);
+                const double qu = ld(p, y) - (0.5 + hl * vy) * slope_at(p, y, s);
                 tr[(1 + q) * nc + x] = upwind(wv, qd, qu);
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_step_trans(StepBatch b) {
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 256) b.stats[i] = 0ull;
+        for (int i = threadIdx.x; i < kMaxLayers * kBuckets; i += 256) b.bcount[i] = 0;
+        const int nctl = (int)(sizeof(BandCtl) / sizeof(int));
+        for (int i = threadIdx.x; i < nctl; i += 256) reinterpret_cast<int*>(b.band)[i] = 0;
+    }
+    const int64_t w = wave_segment();
+    if (w < b.total_words) trans_segment(b, w);
 }
 
 // Tangential term along axis t at cell m, component q, without the 1/h: (mean of the
@@ -163,131 +180,199 @@ __device__ __forceinline__ double tangential(const StepDev* sd, const DevSolid* 
     const int64_t nc = d->ncell;
     const int64_t s = axis_stride(d, t);
     const double* tr = sd->trans + (int64_t)t * 4 * nc;
-    const double wm = tr[m - s], wp = tr[m];
-    const double qm = tr[(1 + q) * nc + m - s], qp = tr[(1 + q) * nc + m];
+    const double wm = ld(tr, m - s), wp = ld(tr, m);
+    const double qm = ld(tr, (1 + q) * nc + m - s), qp = ld(tr, (1 + q) * nc + m);
     return (0.5 * (wm + wp)) * (qp - qm);
 }
 
-// Face state of component q on the face between x and x + e_a, chosen by the face
-// velocity uface.
-__device__ __forceinline__ double normal_face(const StepDev* sd, const DevSolid* d, double hl,
-                                              int64_t x, int a, int q, double uface) {
+// Expansion of component q from cell x to its +a face (side = 0, the left state of that
+// face) or to its -a face (side = 1, the right state of that face), with the tangential
+// terms of the other two axes.
+__device__ __forceinline__ double side_state(const StepDev* sd, const DevSolid* d, double hl,
+                                             int64_t x, int a, int q, int side, double tang) {
     const int64_t nc = d->ncell;
     const int64_t s = axis_stride(d, a);
     const double* ua = sd->u + a * nc;
     const double* p = sd->xi_n + q * nc;
-    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-    const double left = (p[x] + (0.5 - hl * ua[x]) * slope_at(p, x, s)) -
-                        hl * (tangential(sd, d, x, t1, q) + tangential(sd, d, x, t2, q));
-    const int64_t y = x + s;
-    const double right = (p[y] - (0.5 + hl * ua[y]) * slope_at(p, y, s)) -
-                         hl * (tangential(sd, d, y, t1, q) + tangential(sd, d, y, t2, q));
-    return upwind(uface, left, right);
+    const double sl = slope_at(p, x, s);
+    if (side == 0) return (ld(p, x) + (0.5 - hl * ld(ua, x)) * sl) - hl * tang;
+    return (ld(p, x) - (0.5 + hl * ld(ua, x)) * sl) - hl * tang;
 }
 
 // Face-normal velocity on the low face of cell (i, j, k) along axis a.
 __device__ __forceinline__ double face_vel(const StepDev* sd, const DevSolid* d, int a, int i,
                                            int j, int k) {
     const int64_t n0 = d->n0, n1 = d->n1;
-    if (a == 0) return sd->uf[0][((int64_t)k * n1 + j) * (n0 + 1) + i];
-    if (a == 1) return sd->uf[1][((int64_t)k * (n1 + 1) + j) * n0 + i];
-    return sd->uf[2][((int64_t)k * n1 + j) * n0 + i];
+    if (a == 0) return ld(sd->uf[0], ((int64_t)k * n1 + j) * (n0 + 1) + i);
+    if (a == 1) return ld(sd->uf[1], ((int64_t)k * (n1 + 1) + j) * n0 + i);
+    return ld(sd->uf[2], ((int64_t)k * n1 + j) * n0 + i);
+}
+
+// A predicted cell: labelled 0..L-4 at step n and 3 cells inside the box.
+__device__ __forceinline__ bool predicted(const StepDev* sd, const DevSolid* d, int i, int j,
+                                          int k) {
+    if (i < 3 || i > d->n0 - 4 || j < 3 || j > d->n1 - 4 || k < 3 || k > d->n2 - 4)
+        return false;
+    const int lab = ld(sd->labels_n, ((int64_t)k * d->n1 + j) * d->n0 + i);
+    return lab >= 0 && lab <= d->L - 4;
+}
+
+// ------------------------------------------------------------------------------------
+// Side states: per cell next to a predicted cell and per axis, the expansions of xi to the
+// cell's +a face (left state of that face) and -a face (right state of that face).
+// faces[(a * 2 + side) * 3 + q][cell].
+// ------------------------------------------------------------------------------------
+__device__ void faces_segment(const StepBatch& b, int64_t w) {
+    const double hl = b.hl;
+    const Seg g = segment(b, w);
+    const DevSolid* d = b.solids + g.s;
+    const StepDev* sd = b.steps + g.s;
+    int lab = -1;
+    if (g.i < d->n0) lab = ld(sd->labels_n, g.c);
+    // a cell whose face a predicted cell reads is within L1 distance 1 of it
+    const bool act = lab >= 0 && lab <= d->L - 3;
+    if (__ballot(act) == 0ull) return;
+    if (!act) return;
+    const int64_t nc = d->ncell;
+    const bool self = predicted(sd, d, g.i, g.j, g.k);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // +a face: read by this cell or by its +a neighbour; -a face: by this cell or by its
+        // -a neighbour
+        const bool hi = self || predicted(sd, d, g.i + (a == 0), g.j + (a == 1), g.k + (a == 2));
+        const bool lo = self || predicted(sd, d, g.i - (a == 0), g.j - (a == 1), g.k - (a == 2));
+        if (!hi && !lo) continue;
+        const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+#pragma unroll 1
+        for (int q = 0; q < 3; ++q) {
+            const double tang = tangential(sd, d, g.c, t1, q) + tangential(sd, d, g.c, t2, q);
+            if (hi)
+                sd->faces[(int64_t)((a * 2 + 0) * 3 + q) * nc + g.c] =
+                    side_state(sd, d, hl, g.c, a, q, 0, tang);
+            if (lo)
+                sd->faces[(int64_t)((a * 2 + 1) * 3 + q) * nc + g.c] =
+                    side_state(sd, d, hl, g.c, a, q, 1, tang);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_step_faces(StepBatch b) {
+    const int64_t w = wave_segment();
+    if (w < b.total_words) faces_segment(b, w);
 }
 
 // ------------------------------------------------------------------------------------
 // Predictor and the interior mask of step n + 1.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_step_predict(StepBatch b) {
-    const double hl = b.hl, lam = b.lam;
+__device__ void predict_segment(const StepBatch& b, int64_t w) {
+    const double lam = b.lam;
     const int lane = threadIdx.x & 63;
-    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < b.total_words;
-         w += (int64_t)gridDim.x * 4) {
-        const Seg g = segment(b, w);
-        const DevSolid* d = b.solids + g.s;
-        const StepDev* sd = b.steps + g.s;
-        const int L = d->L;
-        const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
-        const int64_t nc = d->ncell;
-        int lab = -1;
-        if (g.i < n0) lab = sd->labels_n[g.c];
-        const bool inb = g.i >= 3 && g.i <= n0 - 4 && g.j >= 3 && g.j <= n1 - 4 && g.k >= 3 &&
-                         g.k <= n2 - 4;
-        const bool pred = lab >= 0 && lab <= L - 4 && inb;
-        const bool other = lab >= 0 && lab <= L && !pred;
-        bool inside = false;
-        if (__ballot(lab >= 0) != 0ull) {
-            if (pred) {
-                double nv0 = 0.0, nv1 = 0.0, nv2 = 0.0;
-#pragma unroll 1
-                for (int q = 0; q < 3; ++q) {
-                    double term[3];
+    const Seg g = segment(b, w);
+    const DevSolid* d = b.solids + g.s;
+    const StepDev* sd = b.steps + g.s;
+    const int L = d->L;
+    const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
+    const int64_t nc = d->ncell;
+    int lab = -1;
+    if (g.i < n0) lab = ld(sd->labels_n, g.c);
+    const bool inb =
+        g.i >= 3 && g.i <= n0 - 4 && g.j >= 3 && g.j <= n1 - 4 && g.k >= 3 && g.k <= n2 - 4;
+    const bool pred = lab >= 0 && lab <= L - 4 && inb;
+    const bool other = lab >= 0 && lab <= L && !pred;
+    bool inside = false;
+    if (__ballot(lab >= 0) != 0ull) {
+        if (pred) {
+            double um[3], up[3];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const int64_t s = axis_stride(d, a);
-                        const double um = face_vel(sd, d, a, g.i, g.j, g.k);
-                        const double up = face_vel(sd, d, a, g.i + (a == 0), g.j + (a == 1),
-                                                   g.k + (a == 2));
-                        const double xm = normal_face(sd, d, hl, g.c - s, a, q, um);
-                        const double xp = normal_face(sd, d, hl, g.c, a, q, up);
-                        term[a] = (0.5 * (um + up)) * (xp - xm);
-                    }
-                    const double acc = (term[0] + term[1]) + term[2];
-                    const double v = sd->xi_n[q * nc + g.c] - lam * acc;
-                    d->xi[q * nc + g.c] = v;
-                    nv0 = q == 0 ? v : nv0;
-                    nv1 = q == 1 ? v : nv1;
-                    nv2 = q == 2 ? v : nv2;
-                }
-                inside = interior(load_shape(d), nv0, nv1, nv2);
-            } else if (other) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) d->xi[q * nc + g.c] = __builtin_nan("");
+            for (int a = 0; a < 3; ++a) {
+                um[a] = face_vel(sd, d, a, g.i, g.j, g.k);
+                up[a] = face_vel(sd, d, a, g.i + (a == 0), g.j + (a == 1), g.k + (a == 2));
             }
-        }
-        const unsigned long long m = __ballot(inside);
-        const unsigned long long lost = __ballot(other && lab == 0);
-        if (lane == 0) {
-            d->mask[g.lw] = m;
-            if (lost) atomicOr(b.stats + (int64_t)g.s * kStatWords + ST_FLAGS, FLAG_TRUNCATED);
+            double nv[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                double term[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t s = axis_stride(d, a);
+                    const double* fl = sd->faces + (int64_t)((a * 2 + 0) * 3 + q) * nc;
+                    const double* fr = sd->faces + (int64_t)((a * 2 + 1) * 3 + q) * nc;
+                    // -a face: left state from cell c - e_a, right state from c
+                    const double xm = upwind(um[a], ld(fl, g.c - s), ld(fr, g.c));
+                    // +a face: left state from c, right state from c + e_a
+                    const double xp = upwind(up[a], ld(fl, g.c), ld(fr, g.c + s));
+                    term[a] = (0.5 * (um[a] + up[a])) * (xp - xm);
+                }
+                const double acc = (term[0] + term[1]) + term[2];
+                nv[q] = ld(sd->xi_n, q * nc + g.c) - lam * acc;
+                d->xi[q * nc + g.c] = nv[q];
+            }
+            inside = interior(load_shape(d), nv[0], nv[1], nv[2]);
+        } else if (other) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) d->xi[q * nc + g.c] = __builtin_nan("");
         }
     }
+    const unsigned long long m = __ballot(inside);
+    const unsigned long long lost = __ballot(other && lab == 0);
+    if (lane == 0) {
+        d->mask[g.lw] = m;
+        if (lost) atomicOr(b.stats + (int64_t)g.s * kStatWords + ST_FLAGS, FLAG_TRUNCATED);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_step_predict(StepBatch b) {
+    const int64_t w = wave_segment();
+    if (w < b.total_words) predict_segment(b, w);
 }
 
 // ------------------------------------------------------------------------------------
 // Corrector.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_step_correct(StepBatch b) {
-    for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < b.total_words;
-         w += (int64_t)gridDim.x * 4) {
+__device__ void correct_segment(const StepBatch& b, int64_t w) {
+    {
         const Seg g = segment(b, w);
         const DevSolid* d = b.solids + g.s;
         const StepDev* sd = b.steps + g.s;
         const unsigned long long fl = b.stats[(int64_t)g.s * kStatWords + ST_FLAGS];
-        if (fl & (FLAG_TRUNCATED | FLAG_OVERFLOW | FLAG_TIMEOUT)) continue;   // uniform
+        if (fl & (FLAG_TRUNCATED | FLAG_OVERFLOW | FLAG_TIMEOUT)) return;   // uniform
         const int L = d->L;
-        if (g.i >= d->n0) continue;
-        const int ln = d->labels[g.c];
-        if (ln < 0 || ln > L) continue;
-        const int lo = sd->labels_n[g.c];
+        if (g.i >= d->n0) return;
+        const int ln = ld(d->labels, g.c);
+        if (ln < 0 || ln > L) return;
+        const int lo = ld(sd->labels_n, g.c);
         const bool both = lo >= 0 && lo <= L;
         const int64_t nc = d->ncell;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const double a = d->xi[q * nc + g.c];
-            sd->xi_half[q * nc + g.c] = both ? (sd->xi_n[q * nc + g.c] + a) * 0.5 : a;
+            const double a = ld(d->xi, q * nc + g.c);
+            sd->xi_half[q * nc + g.c] = both ? (ld(sd->xi_n, q * nc + g.c) + a) * 0.5 : a;
         }
     }
 }
 
+__global__ __launch_bounds__(256) void k_step_correct(StepBatch b) {
+    const int64_t w = wave_segment();
+    if (w < b.total_words) correct_segment(b, w);
+}
+
+// One row segment per wave, four waves per block.  (Eight segments per wave, scanned with
+// one round of label loads, measured slower: a wave then works through the active
+// segments of the dense interior one after another.)
 int step_grid(const StepBatch& b) {
     const int64_t blocks = (b.total_words + 3) / 4;
-    return (int)(blocks < 16384 ? (blocks > 0 ? blocks : 1) : 16384);
+    return (int)(blocks > 0 ? blocks : 1);
 }
 
 }  // namespace
 
 hipError_t launch_step_trans(const StepBatch& b, hipStream_t st) {
     hipLaunchKernelGGL(k_step_trans, dim3(step_grid(b)), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_faces(const StepBatch& b, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_faces, dim3(step_grid(b)), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

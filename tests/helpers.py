@@ -212,6 +212,8 @@ def compare_step(case, got, expect, tol=1e-12, tag=""):
         untouched = ~(old | newband | P)
         assert np.array_equal(gx[:, untouched], case.next_init[i][:, untouched]), (tag, i)
         if est != 0:
+            # a failed solid: no band, no corrector
+            assert np.array_equal(gh, case.half_init[i]), (tag, i, "xi_half of a failed solid")
             continue
         assert np.array_equal(gd[newband], ed[newband]), (tag, i, "decisions")
         e = rel_err(gx, ex, newband)
@@ -225,3 +227,13 @@ def compare_step(case, got, expect, tol=1e-12, tag=""):
         labelled = el >= 0
         assert np.array_equal(gh[:, ~labelled], case.half_init[i][:, ~labelled]), (tag, i)
     return worst
+
+
+def wall_sphere(n=24, n_layers=6):
+    """A sphere cut by the grid wall z = 0: interior cells lie within 3 cells of that box
+    face, so a time step cannot predict them (the step reports the solid truncated)."""
+    w = synth.sphere32(n=n, n_layers=n_layers)
+    s = w.solids[0]
+    w.solids[0] = synth.Solid(s.lo, s.ext, synth.sphere_shape((0.5, 0.5, 0.12), 0.25),
+                              s.n_layers, s.xi)
+    return w

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
-from tests.helpers import StepCase, compare_step, rel_err
+from tests.helpers import StepCase, compare_step, rel_err, wall_sphere
 
 pytestmark = pytest.mark.gpu
 
@@ -96,6 +96,17 @@ def test_step_matches_oracle(ctx, name, precision):
     assert any(((case.labels_n[i] == 0) != (got[i][2] == 0)).any() for i in range(len(got)))
 
 
+def test_step_truncated_at_a_wall(ctx):
+    """Interior cells within 3 cells of a box face cannot be predicted: the solid reports
+    truncated, its labels are written, its band and xi^{n+1/2} are not."""
+    from paper_2104_00095_amd import rmx
+    case = StepCase(wall_sphere(32))
+    expect = [(o[0], o[1], o[2], o[3], o[5]) for o in case.oracle()]
+    st, got = gpu_step(ctx, case)
+    assert expect[0][0] == rmx.E_TRUNCATED and st == rmx.E_TRUNCATED
+    compare_step(case, got, expect, tag="wall")
+
+
 def test_step_loop_on_device(ctx):
     """Three steps, buffers swapped on the device between them, against the oracle's
     chain of three steps: labels equal at the end, xi within the FP64 tolerance."""
@@ -161,7 +172,7 @@ def test_step_profile_phases(ctx):
     st, _ = ctx.step(g, d.solids(), case.dt, rmx.options(flags=rmx.FLAG_PROFILE, **case.opts))
     torch.cuda.synchronize()
     ph = ctx.profile_read()
-    for name in ("step_trans", "step_predict", "label", "normal", "extrap1", "extrap6",
-                 "step_correct"):
+    for name in ("step_trans", "step_faces", "step_predict", "label", "normal", "extrap1",
+                 "extrap6", "step_correct"):
         assert name in ph and ph[name][1] == 1, (name, ph)
     assert "classify" not in ph

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import rmx, synth
-from tests.helpers import StepCase, compare_step
+from tests.helpers import StepCase, compare_step, wall_sphere
 
 emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
@@ -25,6 +25,7 @@ def _workloads():
         "suspension3": synth.suspension(n_solids=3, grid_n=(40, 40, 56), h=1.0 / 40,
                                         n_layers=6),
         "sphere24_L5": synth.sphere32(n=24, n_layers=5),
+        "wall_sphere24": wall_sphere(24),
     }
 
 
@@ -59,3 +60,10 @@ def test_emulated_step_matches_oracle(stepped, name):
     moved = any(((case.labels_n[i] == 0) != (got[i][2] == 0)).any()
                 for i in range(len(got)) if got[i][0] == 0)
     assert moved
+
+
+def test_emulated_step_truncated_at_a_wall(stepped):
+    case, st, got = stepped["wall_sphere24"]
+    expect = [(o[0], o[1], o[2], o[3], o[5]) for o in case.oracle()]
+    assert expect[0][0] == rmx.E_TRUNCATED and st == rmx.E_TRUNCATED
+    compare_step(case, got, expect, tag="wall")
