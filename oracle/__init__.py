@@ -7,9 +7,11 @@ numpy arrays into it.
 
 What it computes follows Lin, Derr & Rycroft (arXiv 2104.00095): section "Extrapolation
 of xi(x,t)" and the SI section "Weighting scheme for weighted least squares-based
-extrapolation", eq. (weight) (``rmx_oracle.c``); and the SI "Timestepping algorithm",
+extrapolation", eq. (weight) (``rmx_oracle.c``); the SI "Timestepping algorithm",
 steps 5-7 and 11, with the advective term of eq. (adv_terms) and the Godunov face states
-of "Evaluating the advective term" (``rmx_step_oracle.c``).  See the C files for the
+of "Evaluating the advective term" (``rmx_step_oracle.c``); and the blur-zone consumers:
+eq. (sm_heavi), eq. (mod_heaviside) and the neo-Hookean solid stress of SI "Stress
+calculations" (``rmx_blur_oracle.c``).  See the C files for the
 step-by-step account.
 """
 from __future__ import annotations
@@ -22,7 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rmx_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "rmx_step_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "rmx_step_oracle.c"), os.path.join(_HERE, "rmx_blur_oracle.c")]
 _LIB = os.path.join(_HERE, "librmx_oracle.so")
 
 # Decision codes (one per cell): 0 = not a band cell, r = fitted with search radius r,
@@ -54,6 +56,17 @@ class Problem(ctypes.Structure):
         ("r_s", ctypes.c_int32),
         ("r_max", ctypes.c_int32),
         ("normal_layers", ctypes.c_int32),
+    ]
+
+
+class BlurSolid(ctypes.Structure):
+    _fields_ = [
+        ("lo", ctypes.c_int32 * 3),
+        ("ext", ctypes.c_int32 * 3),
+        ("shape", Shape),
+        ("n_layers", ctypes.c_int32),
+        ("xi", ctypes.c_void_p),
+        ("labels", ctypes.c_void_p),
     ]
 
 
@@ -107,6 +120,15 @@ def lib():
         L.orc_correct.restype = None
         L.orc_slope4.argtypes = [ctypes.c_void_p]
         L.orc_slope4.restype = ctypes.c_double
+        L.orc_heaviside_eps.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_heaviside_eps.restype = ctypes.c_double
+        L.orc_blur.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(BlurSolid), ctypes.c_double,
+                               ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_blur.restype = None
+        L.orc_solid_stress.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(BlurSolid),
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+        L.orc_solid_stress.restype = None
         _lib = L
     return _lib
 
@@ -256,3 +278,56 @@ def step(problem: Problem, xi_n, labels_n, u, uf, dt, h, xi_next_init, xi_half_i
     if st == OK:
         correct(e, L, xi_n, labels_n, xi_next, labels_next, xi_half)
     return st, xi_next, labels_next, dec, stats, xi_half
+
+
+# ---------------------------------------------------------------------------------------
+# Blur-zone consumers (eq. (sm_heavi), eq. (mod_heaviside), SI "Stress calculations").
+# ---------------------------------------------------------------------------------------
+def heaviside_eps(phi: float, eps: float) -> float:
+    return float(lib().orc_heaviside_eps(float(phi), float(eps)))
+
+
+def _blur_solids(solids):
+    """solids: sequence of (lo, ext, Shape, n_layers, xi [3,e2,e1,e0], labels [e2,e1,e0])."""
+    keep = []
+    arr = (BlurSolid * len(solids))()
+    for m, (lo, ext, shape, L, xi, labels) in enumerate(solids):
+        x = np.ascontiguousarray(xi, dtype=np.float64)
+        lab = np.ascontiguousarray(labels, dtype=np.int8)
+        keep += [x, lab]
+        arr[m].lo[:] = [int(v) for v in lo]
+        arr[m].ext[:] = [int(v) for v in ext]
+        arr[m].shape = shape
+        arr[m].n_layers = int(L)
+        arr[m].xi = x.ctypes.data
+        arr[m].labels = lab.ctypes.data
+    return arr, keep
+
+
+def blur(grid_n, solids, eps, H_init, phi_init=None):
+    """Modified Heaviside on the grid (written on cells inside some box; H_init elsewhere)
+    and, if phi_init (one array per solid) is given, phi_m on each box's labelled cells.
+    Returns (H, [phi_m])."""
+    arr, keep = _blur_solids(solids)
+    g = np.ascontiguousarray(np.asarray(grid_n, dtype=np.int32))
+    H = np.ascontiguousarray(H_init, dtype=np.float64).copy()
+    phis = None
+    pp = None
+    if phi_init is not None:
+        phis = [np.ascontiguousarray(p, dtype=np.float64).copy() for p in phi_init]
+        pp = (ctypes.c_void_p * len(phis))(*[p.ctypes.data for p in phis])
+    lib().orc_blur(_ptr(g), len(solids), arr, float(eps), _ptr(H), pp)
+    return H, phis
+
+
+def solid_stress(grid_n, solids, eps, h, G, tau_init):
+    """Blended neo-Hookean stress on the faces: tau_init = three arrays
+    [6, n2 + (a==2), n1 + (a==1), n0 + (a==0)] (faces without a cell in any box keep
+    them).  Returns the three arrays."""
+    arr, keep = _blur_solids(solids)
+    g = np.ascontiguousarray(np.asarray(grid_n, dtype=np.int32))
+    Gs = np.ascontiguousarray(np.asarray(G, dtype=np.float64))
+    tau = [np.ascontiguousarray(t, dtype=np.float64).copy() for t in tau_init]
+    tp = (ctypes.c_void_p * 3)(*[t.ctypes.data for t in tau])
+    lib().orc_solid_stress(_ptr(g), len(solids), arr, float(eps), float(h), _ptr(Gs), tp)
+    return tau
