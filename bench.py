@@ -532,6 +532,78 @@ def step_variant(ctx, steps=100, warmup=10, n_layers=6, precision=0):
     return out
 
 
+def blur_variant(ctx, name, steps=50, warmup=5, eps_cells=2.0):
+    """The blur-zone consumers on a workload after its extrapolation (set-up, not timed):
+    rmx_blur (phi of every solid and the multi-body modified Heaviside on the grid) and
+    rmx_solid_stress (the blended neo-Hookean stress on the faces), each timed over `steps`
+    calls with HIP events on the launch stream.  Byte models: rmx_blur writes 8 B of H per
+    grid cell inside some box and reads 1 B of labels per box cell, plus 24 B of xi read and
+    8 B of phi written per covered cell; rmx_solid_stress writes 48 B per face with a cell
+    inside some box, plus 1 B of labels per box cell and 24 B of xi per covered cell read
+    once.  (Covered: labelled 0..L.)"""
+    import numpy as np
+    import torch
+    from paper_2104_00095_amd import fields, rmx
+    w = make_workload(name)
+    dw = fields.upload(w)
+    st, stats = ctx.extrapolate(dw.grid, dw.solids, rmx.options())
+    assert st == 0, st
+    n0, n1, n2 = w.grid_n
+    H = torch.ones((n2, n1, n0), dtype=torch.float64, device="cuda")
+    phis = [torch.zeros(tuple(x.shape[1:]), dtype=torch.float64, device="cuda") for x in dw.xi]
+    taus = [torch.zeros((6, n2 + (a == 2), n1 + (a == 1), n0 + (a == 0)), dtype=torch.float64,
+                        device="cuda") for a in range(3)]
+    eps = eps_cells * w.h
+    G = [1.0] * len(w.solids)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_h = timed(lambda: ctx.blur(dw.grid, dw.solids, eps, H, phis, stream))
+    ms_t = timed(lambda: ctx.solid_stress(dw.grid, dw.solids, eps, G, taus, stream))
+    # byte models
+    inbox = np.zeros((n2, n1, n0), bool)
+    box_cells = covered = 0
+    for s, lab in zip(w.solids, dw.labels):
+        lo, e = s.lo, s.ext
+        inbox[lo[2]:lo[2] + e[2], lo[1]:lo[1] + e[1], lo[0]:lo[0] + e[0]] = True
+        box_cells += int(np.prod(e))
+        lh = lab.cpu().numpy()
+        covered += int(((lh >= 0) & (lh <= s.n_layers)).sum())
+    n_cells = int(inbox.sum())
+    faces = 0
+    for a in range(3):
+        f = np.zeros((n2 + (a == 2), n1 + (a == 1), n0 + (a == 0)), bool)
+        sl_lo = [slice(0, n2), slice(0, n1), slice(0, n0)]
+        sl_hi = list(sl_lo)
+        sl_hi[2 - a] = slice(1, [n2, n1, n0][2 - a] + 1)
+        f[tuple(sl_lo)] |= inbox
+        f[tuple(sl_hi)] |= inbox
+        faces += int(f.sum())
+    b_h = 8.0 * n_cells + box_cells + 32.0 * covered
+    b_t = 48.0 * faces + box_cells + 24.0 * covered
+    pk = HBM_PEAK_GBS * 1e9
+    out = {"workload": f"blur_{name}", "solids": len(w.solids), "eps_cells": eps_cells,
+           "grid_cells_in_boxes": n_cells, "faces_written": faces, "covered_cells": covered,
+           "blur": {"ms": ms_h, "model_bytes": b_h, "hbm_frac": b_h / (ms_h * 1e-3) / pk},
+           "solid_stress": {"ms": ms_t, "model_bytes": b_t,
+                            "hbm_frac": b_t / (ms_t * 1e-3) / pk}}
+    del dw, H, phis, taus
+    torch.cuda.empty_cache()
+    return out
+
+
 def make_workload(name):
     from paper_2104_00095_amd import synth
     if name == "cavity256":
@@ -566,6 +638,8 @@ def main():
     ap.add_argument("--step-only", action="store_true",
                     help="only time the time-step variant (predictor + extrapolation + "
                          "corrector on cavity256, L = 6) and print it")
+    ap.add_argument("--blur-only", action="store_true",
+                    help="only time the blur-zone consumers (suspension and cavity256)")
     ap.add_argument("--persistent", action="store_true",
                     help="the band work (normals and every layer's fits) in one persistent launch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -593,6 +667,13 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.blur_only:
+        ctx = rmx.Context(0)
+        for wl in ("suspension", "cavity256"):
+            log(f"blur-zone consumers ({wl})")
+            print(json.dumps(blur_variant(ctx, wl, max(10, args.steps // 4))), flush=True)
+        ctx.close()
         return
     if args.step_only:
         ctx = rmx.Context(0)
@@ -681,6 +762,9 @@ def main():
         torch.cuda.empty_cache()
         log("variants: time step")
         variants["step_cavity256"] = step_variant(ctx, args.steps, args.warmup)
+        log("variants: blur-zone consumers")
+        for wl in ("suspension", "cavity256"):
+            variants[f"blur_{wl}"] = blur_variant(ctx, wl, max(10, args.steps // 4))
         if not args.no_serving:
             variants["serving"] = serving_variants(ctx, args.serving_requests, log=log)
 

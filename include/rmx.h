@@ -257,6 +257,35 @@ int rmx_step(rmx_ctx* ctx, const rmx_grid* grid, const rmx_step_solid* solids,
              int32_t n_solids, const rmx_options* opt, double dt, void* hip_stream,
              rmx_solid_stats* stats);
 
+/* ---- blur-zone consumers of the extrapolated maps -------------------------------------
+ * Main text, "Blurred interface method and monolithic governing equations": phi = phi0(xi)
+ * and the smoothed Heaviside H_eps of eq. (sm_heavi); SI "Stress calculations": the
+ * neo-Hookean solid stress at cell faces and the multi-body modified Heaviside of
+ * eq. (mod_heaviside).  Inputs are the solids as an extrapolation call left them (xi and
+ * labels of each box: a solid covers the cells it labels 0..L; its blur zone must lie in
+ * its band, i.e. L h > eps).  Both calls are asynchronous on hip_stream.  Sums over solids
+ * run in increasing solid index.
+ *
+ * rmx_blur: on every grid cell inside some box, H = max(1 - sum_m (1 - H_eps(phi_m)), 0)
+ * into H (DEVICE, [n2][n1][n0] of the grid, nullable); cells outside every box are left
+ * as they are (pure fluid: the caller sets them to 1 once).  phi (HOST array of n_solids
+ * DEVICE pointers, nullable, entries nullable): phi_m on the cells of box m labelled 0..L.
+ *
+ * rmx_solid_stress: on every face with a cell inside some box (faces normal to axis a in
+ * tau[a], DEVICE, [6][n2 + (a==2)][n1 + (a==1)][n0 + (a==0)], components xx, yy, zz, xy,
+ * xz, yz): per solid m whose difference stencil at the face is labelled (the two cells,
+ * and their neighbours across both other axes), grad xi at the face (the difference across
+ * the face, the mean of the two cells' centred differences along the other axes),
+ * F = (grad xi)^{-1}, B = F F^T, tau_m = G[m] (B - tr(B)/3 I), weight
+ * w_m = 1 - H_eps(phi0_m((xi(P) + xi(Q)) / 2)); the face gets T = sum w_m tau_m if
+ * S = sum w_m <= 1, else T / S (zero where no solid contributes).  G: HOST, n_solids
+ * shear moduli. */
+int rmx_blur(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+             double eps, double* H, double* const* phi, void* hip_stream);
+int rmx_solid_stress(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids,
+                     int32_t n_solids, double eps, const double* G, double* const* tau,
+                     void* hip_stream);
+
 const char* rmx_status_string(int status);
 
 /* Autotuner.  Launch shapes that change no result: the label tile width (1, 2 or 4 words

@@ -10,9 +10,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librmx.so")
-SOURCES = ["rmx_kernels.hip", "rmx_step.hip", "rmx_plan.cpp", "rmx_core.cpp", "rmx_server.cpp"]
-# Per-file flags: the time-step kernels evaluate their arithmetic in the written order.
-EXTRA = {"rmx_step.hip": ["-ffp-contract=off"]}
+SOURCES = ["rmx_kernels.hip", "rmx_step.hip", "rmx_blur.hip", "rmx_plan.cpp", "rmx_core.cpp",
+           "rmx_server.cpp"]
+# Per-file flags: the time-step and blur-zone kernels evaluate their arithmetic in the
+# written order.
+EXTRA = {"rmx_step.hip": ["-ffp-contract=off"], "rmx_blur.hip": ["-ffp-contract=off"]}
 # No packed-FP32 instructions; device code for gfx950 only.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

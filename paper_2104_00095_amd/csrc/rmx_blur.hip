@@ -1,0 +1,234 @@
+// HIP kernels of the blur-zone consumers of the extrapolated reference maps (Lin, Derr &
+// Rycroft, arXiv 2104.00095):
+//   k_blur_heaviside  per grid cell inside some solid's box: phi_m = phi0_m(xi_m) on the
+//                     cells the solid labels 0..L, the smoothed Heaviside of eq. (sm_heavi),
+//                     and the multi-body modified Heaviside of eq. (mod_heaviside),
+//                     H = max(1 - sum_m (1 - H_eps(phi_m)), 0);
+//   k_blur_stress     per cell face with a cell inside some solid's box (SI "Stress
+//                     calculations"): for each solid whose difference stencil is labelled,
+//                     grad xi by centred differences at the face, F = (grad xi)^{-1},
+//                     B = F F^T, tau_m = G_m (B - tr(B)/3 I), the weight 1 - H_eps(phi_m)
+//                     at the face's xi; the blend T (sum of weights S <= 1) or T / S.
+// A block takes one 8^3 tile of the grid; the solids that can touch it come from a list
+// built on the host (boxes dilated by one cell), visited in ascending order, so every sum
+// runs in the same order as in any other implementation.  Stencil gathers of FP64 fields
+// over the thin blur zones: bandwidth and latency work, no MFMA.
+#include "rmx_blur.h"
+#include "rmx_device.h"
+
+namespace rmx {
+namespace {
+using namespace dev;
+
+constexpr double kPi = 3.141592653589793;
+
+__device__ __forceinline__ double heaviside_eps(double phi, double eps) {
+    if (phi <= -eps) return 0.0;
+    if (phi >= eps) return 1.0;
+    return 0.5 * ((1.0 + phi / eps) + sin(kPi * phi / eps) / kPi);
+}
+
+__device__ __forceinline__ ShapeR blur_shape(const BlurDev& s) {
+    ShapeR r;
+    r.kind = s.kind;
+    r.c0 = s.centre[0]; r.c1 = s.centre[1]; r.c2 = s.centre[2];
+    r.e0 = s.semi[0]; r.e1 = s.semi[1]; r.e2 = s.semi[2];
+    r.r00 = s.rot[0]; r.r01 = s.rot[1]; r.r02 = s.rot[2];
+    r.r10 = s.rot[3]; r.r11 = s.rot[4]; r.r12 = s.rot[5];
+    r.r20 = s.rot[6]; r.r21 = s.rot[7]; r.r22 = s.rot[8];
+    return r;
+}
+
+// Local index of global cell (x, y, z) in the solid's box, or -1.
+__device__ __forceinline__ int64_t local_cell(const BlurDev& s, int x, int y, int z) {
+    const int lx = x - s.lo[0], ly = y - s.lo[1], lz = z - s.lo[2];
+    if (lx < 0 || lx >= s.ext[0] || ly < 0 || ly >= s.ext[1] || lz < 0 || lz >= s.ext[2])
+        return -1;
+    return ((int64_t)lz * s.ext[1] + ly) * s.ext[0] + lx;
+}
+
+__device__ __forceinline__ bool covered(const BlurDev& s, int64_t c) {
+    const int lab = load_global(s.labels + c);
+    return lab >= 0 && lab <= s.L;
+}
+
+__device__ __forceinline__ void xi_at(const BlurDev& s, int64_t c, double v[3]) {
+    const int64_t nc = (int64_t)s.ext[0] * s.ext[1] * s.ext[2];
+    v[0] = load_global(s.xi + c);
+    v[1] = load_global(s.xi + nc + c);
+    v[2] = load_global(s.xi + 2 * nc + c);
+}
+
+// The tile of this block and the cell q (0..511) of it in grid coordinates.
+__device__ __forceinline__ void tile_cell(const BlurBatch& b, int t, int q, int g[3]) {
+    const int tx = t % b.tiles[0], ty = (t / b.tiles[0]) % b.tiles[1];
+    const int tz = t / (b.tiles[0] * b.tiles[1]);
+    g[0] = tx * kBlurTX + q % kBlurTX;
+    g[1] = ty * kBlurTY + (q / kBlurTX) % kBlurTY;
+    g[2] = tz * kBlurTZ + q / (kBlurTX * kBlurTY);
+}
+
+// ------------------------------------------------------------------------------------
+// Modified Heaviside (and phi_m).
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
+    const int t = b.active[blockIdx.x];
+    const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
+    for (int q = threadIdx.x; q < kBlurTileCells; q += 256) {
+        int g[3];
+        tile_cell(b, t, q, g);
+        if (g[0] >= b.grid[0] || g[1] >= b.grid[1] || g[2] >= b.grid[2]) continue;
+        bool any = false;
+        double acc = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const BlurDev& s = b.solids[b.tile_list[e]];
+            const int64_t c = local_cell(s, g[0], g[1], g[2]);
+            if (c < 0) continue;
+            any = true;
+            if (!covered(s, c)) continue;
+            double v[3];
+            xi_at(s, c, v);
+            const double p = phi0(blur_shape(s), v[0], v[1], v[2]);
+            if (s.phi) s.phi[c] = p;
+            acc += 1.0 - heaviside_eps(p, b.eps);
+        }
+        if (!any || !b.H) continue;
+        const double d = 1.0 - acc;
+        b.H[((int64_t)g[2] * b.grid[1] + g[1]) * b.grid[0] + g[0]] = d > 0.0 ? d : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Solid stress at faces.
+// ------------------------------------------------------------------------------------
+// Neo-Hookean stress of solid s at the face between P = f - e_a and Q = f, and its weight;
+// false (no contribution) unless every stencil cell lies in the box and is labelled.
+__device__ bool face_stress(const BlurDev& s, const int f[3], int a, double h, double eps,
+                            double tau[6], double* w) {
+    int P[3] = {f[0], f[1], f[2]};
+    P[a] -= 1;
+    const int64_t cp = local_cell(s, P[0], P[1], P[2]), cq = local_cell(s, f[0], f[1], f[2]);
+    if (cp < 0 || cq < 0 || !covered(s, cp) || !covered(s, cq)) return false;
+    double xp[3], xq[3];
+    xi_at(s, cp, xp);
+    xi_at(s, cq, xq);
+    double J[3][3];   // J[q][b] = d xi_q / d x_b
+#pragma unroll
+    for (int q = 0; q < 3; ++q) J[q][a] = (xq[q] - xp[q]) / h;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (t == a) continue;
+        const int dx = t == 0, dy = t == 1, dz = t == 2;
+        const int64_t c1 = local_cell(s, P[0] - dx, P[1] - dy, P[2] - dz);
+        const int64_t c2 = local_cell(s, P[0] + dx, P[1] + dy, P[2] + dz);
+        const int64_t c3 = local_cell(s, f[0] - dx, f[1] - dy, f[2] - dz);
+        const int64_t c4 = local_cell(s, f[0] + dx, f[1] + dy, f[2] + dz);
+        if (c1 < 0 || c2 < 0 || c3 < 0 || c4 < 0) return false;
+        if (!covered(s, c1) || !covered(s, c2) || !covered(s, c3) || !covered(s, c4))
+            return false;
+        double v1[3], v2[3], v3[3], v4[3];
+        xi_at(s, c1, v1);
+        xi_at(s, c2, v2);
+        xi_at(s, c3, v3);
+        xi_at(s, c4, v4);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) J[q][t] = ((v2[q] - v1[q]) + (v4[q] - v3[q])) / (4.0 * h);
+    }
+    // F = J^{-1} by cofactors
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = (J[0][0] * c00 + J[0][1] * c01) + J[0][2] * c02;
+    double F[3][3];
+    F[0][0] = c00 / det;
+    F[1][0] = c01 / det;
+    F[2][0] = c02 / det;
+    F[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    F[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    F[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    F[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    F[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    F[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    double B[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            B[r][c] = (F[r][0] * F[c][0] + F[r][1] * F[c][1]) + F[r][2] * F[c][2];
+    const double tr3 = ((B[0][0] + B[1][1]) + B[2][2]) / 3.0;
+    const double G = s.G;
+    tau[0] = G * (B[0][0] - tr3);
+    tau[1] = G * (B[1][1] - tr3);
+    tau[2] = G * (B[2][2] - tr3);
+    tau[3] = G * B[0][1];
+    tau[4] = G * B[0][2];
+    tau[5] = G * B[1][2];
+    const double x0 = (xp[0] + xq[0]) * 0.5, x1 = (xp[1] + xq[1]) * 0.5,
+                 x2 = (xp[2] + xq[2]) * 0.5;
+    *w = 1.0 - heaviside_eps(phi0(blur_shape(s), x0, x1, x2), eps);
+    return true;
+}
+
+__device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3], int a) {
+    int P[3] = {f[0], f[1], f[2]};
+    P[a] -= 1;
+    bool any = false;
+    double S = 0.0;
+    double T[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = e0; e < e1; ++e) {
+        const BlurDev& s = b.solids[b.tile_list[e]];
+        const bool inq = f[a] < b.grid[a] && local_cell(s, f[0], f[1], f[2]) >= 0;
+        const bool inp = P[a] >= 0 && local_cell(s, P[0], P[1], P[2]) >= 0;
+        if (!inq && !inp) continue;
+        any = true;
+        double t6[6], w;
+        if (!face_stress(s, f, a, b.h, b.eps, t6, &w)) continue;
+        S += w;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) T[c] += w * t6[c];
+    }
+    if (!any) return;
+    const int64_t n0 = b.grid[0] + (a == 0), n1 = b.grid[1] + (a == 1),
+                  n2 = b.grid[2] + (a == 2);
+    const int64_t nf = n0 * n1 * n2;
+    const int64_t fi = ((int64_t)f[2] * n1 + f[1]) * n0 + f[0];
+    double* out = b.tau[a];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[c * nf + fi] = S <= 1.0 ? T[c] : T[c] / S;
+}
+
+__global__ __launch_bounds__(256) void k_blur_stress(BlurBatch b) {
+    const int t = b.active[blockIdx.x];
+    const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
+    for (int q = threadIdx.x; q < kBlurTileCells; q += 256) {
+        int g[3];
+        tile_cell(b, t, q, g);
+        if (g[0] >= b.grid[0] || g[1] >= b.grid[1] || g[2] >= b.grid[2]) continue;
+#pragma unroll 1
+        for (int a = 0; a < 3; ++a) {
+            // a cell owns its low face along a; the last cell also the face beyond it
+            blend_face(b, e0, e1, g, a);
+            if (g[a] == b.grid[a] - 1) {
+                int f[3] = {g[0], g[1], g[2]};
+                f[a] += 1;
+                blend_face(b, e0, e1, f, a);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_blur_heaviside(const BlurBatch& b, hipStream_t st) {
+    if (b.n_active <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_blur_heaviside, dim3(b.n_active), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_blur_stress(const BlurBatch& b, hipStream_t st) {
+    if (b.n_active <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_blur_stress, dim3(b.n_active), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+}  // namespace rmx

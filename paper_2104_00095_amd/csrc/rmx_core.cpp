@@ -12,6 +12,7 @@
 #include "rmx_core.h"
 #include "rmx_ctx.h"
 #include "rmx_internal.h"
+#include "rmx_blur.h"
 
 using namespace rmx;
 
@@ -390,6 +391,7 @@ int rmx_destroy(rmx_ctx* c) {
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->ws) (void)hipFree(c->ws);
     if (c->step_ws) (void)hipFree(c->step_ws);
+    if (c->blur_ws) (void)hipFree(c->blur_ws);
     delete c;
     return RMX_OK;
 }
@@ -548,6 +550,147 @@ int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t
     if (rc != RMX_OK) return rc;
     if (!sync) return RMX_OK;
     return finish_sync(c, st, n_solids, stats);
+}
+
+// Blur-zone consumers: the solid table and the per-tile candidate lists (boxes dilated by
+// one cell, so that a face sees the solids of its low cell), uploaded to the context's
+// blur workspace on `st`.
+static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int32_t n,
+                      double eps, const double* G, double* const* phi, hipStream_t st,
+                      BlurBatch* b) {
+    if (!c || !grid || !solids || n < 1) return RMX_E_ARG;
+    if (!(eps > 0.0) || !std::isfinite(eps)) return RMX_E_ARG;
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        if ((rc = validate_solid(grid, solids + i)) != RMX_OK) return rc;
+        if (G && !std::isfinite(G[i])) return RMX_E_ARG;
+    }
+    const int64_t TS[3] = {kBlurTX, kBlurTY, kBlurTZ};
+    int64_t T[3], nt = 1;
+    for (int a = 0; a < 3; ++a) {
+        T[a] = (grid->n[a] + TS[a] - 1) / TS[a];
+        nt *= T[a];
+    }
+    if (nt > (int64_t)1 << 30) return RMX_E_ARG;
+    std::vector<int32_t> count(nt + 1, 0);
+    auto tile_range = [&](const rmx_solid& s, int a, int64_t* t0, int64_t* t1) {
+        const int64_t lo = std::max<int64_t>(s.lo[a] - 1, 0);
+        const int64_t hi = std::min<int64_t>(s.lo[a] + s.ext[a] + 1, grid->n[a]);   // excl.
+        *t0 = lo / TS[a];
+        *t1 = (hi - 1) / TS[a];
+    };
+    for (int m = 0; m < n; ++m) {
+        int64_t r[3][2];
+        for (int a = 0; a < 3; ++a) tile_range(solids[m], a, &r[a][0], &r[a][1]);
+        for (int64_t z = r[2][0]; z <= r[2][1]; ++z)
+            for (int64_t y = r[1][0]; y <= r[1][1]; ++y)
+                for (int64_t x = r[0][0]; x <= r[0][1]; ++x) ++count[(z * T[1] + y) * T[0] + x + 1];
+    }
+    for (int64_t t = 0; t < nt; ++t) count[t + 1] += count[t];
+    std::vector<int32_t> list(count[nt]), fill(count.begin(), count.end() - 1), active;
+    for (int m = 0; m < n; ++m) {   // ascending solid index in every tile
+        int64_t r[3][2];
+        for (int a = 0; a < 3; ++a) tile_range(solids[m], a, &r[a][0], &r[a][1]);
+        for (int64_t z = r[2][0]; z <= r[2][1]; ++z)
+            for (int64_t y = r[1][0]; y <= r[1][1]; ++y)
+                for (int64_t x = r[0][0]; x <= r[0][1]; ++x)
+                    list[fill[(z * T[1] + y) * T[0] + x]++] = m;
+    }
+    for (int64_t t = 0; t < nt; ++t)
+        if (count[t + 1] > count[t]) active.push_back((int32_t)t);
+    std::vector<BlurDev> sd(n);
+    for (int m = 0; m < n; ++m) {
+        const rmx_solid& s = solids[m];
+        BlurDev& d = sd[m];
+        d = BlurDev{};
+        for (int a = 0; a < 3; ++a) {
+            d.lo[a] = s.lo[a];
+            d.ext[a] = s.ext[a];
+            d.centre[a] = s.phi0.centre[a];
+        }
+        d.L = s.n_layers;
+        d.kind = s.phi0.kind;
+        if (s.phi0.kind == RMX_SPHERE) {
+            d.semi[0] = d.semi[1] = d.semi[2] = s.phi0.semi_axes[0];
+            for (int q = 0; q < 9; ++q) d.rot[q] = (q % 4 == 0) ? 1.0 : 0.0;
+        } else {
+            for (int a = 0; a < 3; ++a) d.semi[a] = s.phi0.semi_axes[a];
+            for (int q = 0; q < 9; ++q) d.rot[q] = s.phi0.rot[q];
+        }
+        d.xi = s.xi;
+        d.labels = s.labels;
+        d.phi = phi ? phi[m] : nullptr;
+        d.G = G ? G[m] : 0.0;
+    }
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t o_start = al(sizeof(BlurDev) * n);
+    const size_t o_list = o_start + al(sizeof(int32_t) * (nt + 1));
+    const size_t o_active = o_list + al(sizeof(int32_t) * std::max<size_t>(list.size(), 1));
+    const size_t bytes = o_active + sizeof(int32_t) * std::max<size_t>(active.size(), 1);
+    if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
+    if (bytes > c->blur_ws_size) {
+        if (c->fixed) return RMX_E_WORKSPACE;
+        if (c->blur_ws) {
+            if (hipDeviceSynchronize() != hipSuccess) return RMX_E_HIP;
+            (void)hipFree(c->blur_ws);
+            c->blur_ws = nullptr;
+            c->blur_ws_size = 0;
+        }
+        if (hipMalloc(&c->blur_ws, bytes) != hipSuccess) {
+            c->blur_ws = nullptr;
+            return RMX_E_HIP;
+        }
+        c->blur_ws_size = bytes;
+    }
+    Staging* sg = nullptr;
+    if ((rc = get_stage(c, bytes, &sg)) != RMX_OK) return rc;
+    char* h = static_cast<char*>(sg->host);
+    std::memcpy(h, sd.data(), sizeof(BlurDev) * n);
+    std::memcpy(h + o_start, count.data(), sizeof(int32_t) * (nt + 1));
+    if (!list.empty()) std::memcpy(h + o_list, list.data(), sizeof(int32_t) * list.size());
+    if (!active.empty()) std::memcpy(h + o_active, active.data(), sizeof(int32_t) * active.size());
+    if (hipMemcpyAsync(c->blur_ws, h, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(sg->ev, st) != hipSuccess)
+        return RMX_E_HIP;
+    sg->pending = true;
+    char* base = static_cast<char*>(c->blur_ws);
+    *b = BlurBatch{};
+    b->solids = reinterpret_cast<const BlurDev*>(base);
+    b->n_solids = n;
+    for (int a = 0; a < 3; ++a) {
+        b->grid[a] = grid->n[a];
+        b->tiles[a] = (int32_t)T[a];
+    }
+    b->n_active = (int32_t)active.size();
+    b->tile_start = reinterpret_cast<const int32_t*>(base + o_start);
+    b->tile_list = reinterpret_cast<const int32_t*>(base + o_list);
+    b->active = reinterpret_cast<const int32_t*>(base + o_active);
+    b->eps = eps;
+    b->h = grid->h;
+    return RMX_OK;
+}
+
+int rmx_blur(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int32_t n_solids,
+             double eps, double* H, double* const* phi, void* hip_stream) {
+    if (!H && !phi) return RMX_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    BlurBatch b;
+    int rc = blur_setup(c, grid, solids, n_solids, eps, nullptr, phi, st, &b);
+    if (rc != RMX_OK) return rc;
+    b.H = H;
+    return launch_blur_heaviside(b, st) == hipSuccess ? RMX_OK : RMX_E_HIP;
+}
+
+int rmx_solid_stress(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
+                     int32_t n_solids, double eps, const double* G, double* const* tau,
+                     void* hip_stream) {
+    if (!G || !tau || !tau[0] || !tau[1] || !tau[2]) return RMX_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    BlurBatch b;
+    int rc = blur_setup(c, grid, solids, n_solids, eps, G, nullptr, st, &b);
+    if (rc != RMX_OK) return rc;
+    for (int a = 0; a < 3; ++a) b.tau[a] = tau[a];
+    return launch_blur_stress(b, st) == hipSuccess ? RMX_OK : RMX_E_HIP;
 }
 
 int rmx_extrapolate_noalloc(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,

@@ -54,6 +54,8 @@ struct rmx_ctx {
     std::vector<const rmx_grid*> grid_ptrs;
     void* step_ws = nullptr;   // time step: step descriptors + transverse face states
     size_t step_ws_size = 0;
+    void* blur_ws = nullptr;   // blur-zone consumers: solid table and tile lists
+    size_t blur_ws_size = 0;
     void* scratch = nullptr;   // device address of this device's allocation-free workspace
     std::vector<rmx::Plan> noalloc_plans;
     rmx::Profiler prof;

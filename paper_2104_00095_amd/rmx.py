@@ -31,7 +31,7 @@ EXPORTS = [
     "rmx_extrapolate", "rmx_status_string", "rmx_server_create", "rmx_server_register",
     "rmx_server_field", "rmx_server_submit", "rmx_server_wait", "rmx_server_release",
     "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read", "rmx_autotune",
-    "rmx_set_tuning", "rmx_extrapolate_noalloc", "rmx_step",
+    "rmx_set_tuning", "rmx_extrapolate_noalloc", "rmx_step", "rmx_blur", "rmx_solid_stress",
 ]
 
 
@@ -131,6 +131,10 @@ def lib():
                                      P(Tuning)]
         L.rmx_step.argtypes = [vp, P(Grid), P(StepSolid), ctypes.c_int32, P(Options),
                                ctypes.c_double, vp, P(SolidStats)]
+        L.rmx_blur.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, ctypes.c_double, vp, vp,
+                               vp]
+        L.rmx_solid_stress.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, ctypes.c_double,
+                                       vp, vp, vp]
         for name in EXPORTS:
             if name != "rmx_status_string":
                 getattr(L, name).restype = ctypes.c_int
@@ -340,6 +344,32 @@ class Context:
         """rmx_step on a prebuilt StepSolid array, no statistics (timing loops)."""
         return lib().rmx_step(self.h, ctypes.byref(g), arr, n, ctypes.byref(opt), float(dt),
                               stream_handle, None)
+
+    def blur(self, g: Grid, solids: Sequence[Solid], eps: float, H=None, phis=None,
+             stream=None):
+        """Modified Heaviside on the grid (rmx_blur): H cuda float64 [n2, n1, n0] (cells
+        inside some box are written), phis: per solid a cuda float64 [e2, e1, e0] or None."""
+        arr = (Solid * len(solids))(*solids)
+        pp = None
+        if phis is not None:
+            pp = (ctypes.c_void_p * len(solids))(*[_ptr(p) for p in phis])
+        st = lib().rmx_blur(self.h, ctypes.byref(g), arr, len(solids), float(eps), _ptr(H),
+                            pp, _stream_handle(stream))
+        if st != OK:
+            raise RmxError(st, "rmx_blur")
+
+    def solid_stress(self, g: Grid, solids: Sequence[Solid], eps: float, G, taus,
+                     stream=None):
+        """Blended neo-Hookean solid stress on the faces (rmx_solid_stress): taus = three
+        cuda float64 arrays [6, n2 + (a==2), n1 + (a==1), n0 + (a==0)]; G: one shear
+        modulus per solid."""
+        arr = (Solid * len(solids))(*solids)
+        Gs = (ctypes.c_double * len(solids))(*[float(v) for v in G])
+        tp = (ctypes.c_void_p * 3)(*[_ptr(t) for t in taus])
+        st = lib().rmx_solid_stress(self.h, ctypes.byref(g), arr, len(solids), float(eps), Gs,
+                                    tp, _stream_handle(stream))
+        if st != OK:
+            raise RmxError(st, "rmx_solid_stress")
 
     def set_tuning(self, g: Grid, solids: Sequence[Solid], tile_w: int, extrap_blocks: int,
                    opt: Optional[Options] = None):

@@ -12,8 +12,8 @@ CSRC = os.path.join(ROOT, "paper_2104_00095_amd", "csrc")
 EXE = os.path.join(HERE, "run_case_emu")
 CLANG = "/opt/rocm/lib/llvm/bin/clang++"
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("rmx_kernels.hip", "rmx_step.hip", "rmx_plan.cpp", "rmx_core.cpp",
-            "rmx_server.cpp")] + \
+           ("rmx_kernels.hip", "rmx_step.hip", "rmx_blur.hip", "rmx_plan.cpp",
+            "rmx_core.cpp", "rmx_server.cpp")] + \
           [os.path.join(HERE, "hip_emu.cpp"), os.path.join(HERE, "run_case.cpp")]
 
 
@@ -115,3 +115,52 @@ def run_step(w, tmpdir, xi_n, labels_n, u, uf, dt, xi_next_init, xi_half_init, r
         half = np.fromfile(os.path.join(tmpdir, f"half{i}.bin"), dtype=np.float64).reshape(xo.shape)
         res.append((xo, lab, dec, raw, half))
     return st, res
+
+
+def run_blur(w, tmpdir, xi, labels, eps, G, H_init, phi_init, tau_init, timeout=600):
+    """rmx_blur then rmx_solid_stress of the emulated library on workload `w` (boxes,
+    shapes, layers) with the given per-solid xi and labels.  Returns (status, H,
+    [phi per solid], [tau per face orientation])."""
+    import types
+    solids = [types.SimpleNamespace(lo=s.lo, ext=s.ext, n_layers=s.n_layers, shape=s.shape,
+                                    xi=xi[i]) for i, s in enumerate(w.solids)]
+    ww = types.SimpleNamespace(solids=solids, grid_n=w.grid_n, h=w.h, origin=w.origin)
+    os.makedirs(tmpdir, exist_ok=True)
+    with open(os.path.join(tmpdir, "blur.txt"), "w") as f:
+        f.write(f"{float(eps)!r} " + " ".join(repr(float(v)) for v in G) + "\n")
+    put = lambda name, a, dt: np.ascontiguousarray(a, dtype=dt).tofile(
+        os.path.join(tmpdir, name + ".bin"))
+    for i in range(len(w.solids)):
+        put(f"labin{i}", labels[i], np.int8)
+        put(f"phiinit{i}", phi_init[i], np.float64)
+    put("hinit", H_init, np.float64)
+    for a in range(3):
+        put(f"tauinit{a}", tau_init[a], np.float64)
+    try:
+        # the extrapolation runner's own outputs are not produced in this mode
+        os.makedirs(tmpdir, exist_ok=True)
+        for i, s in enumerate(solids):
+            np.ascontiguousarray(s.xi, dtype=np.float64).tofile(os.path.join(tmpdir, f"xi{i}.bin"))
+        lines = [f"{len(solids)} {w.grid_n[0]} {w.grid_n[1]} {w.grid_n[2]} {w.h!r} "
+                 f"{w.origin[0]!r} {w.origin[1]!r} {w.origin[2]!r}", "2 4 2 0 0 1"]
+        for s in solids:
+            sh = s.shape
+            vals = list(s.lo) + list(s.ext) + [s.n_layers, sh.kind]
+            fl = list(map(float, sh.centre)) + list(map(float, sh.semi)) + \
+                list(map(float, np.asarray(sh.rot).reshape(-1)))
+            lines.append(" ".join(str(int(v)) for v in vals) + " " +
+                         " ".join(repr(v) for v in fl) + " 0")
+        with open(os.path.join(tmpdir, "case.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1")
+        subprocess.run([build(), tmpdir], check=True, timeout=timeout, env=env)
+    finally:
+        os.remove(os.path.join(tmpdir, "blur.txt"))
+    st = int(open(os.path.join(tmpdir, "status.txt")).read())
+    get = lambda name, like: np.fromfile(os.path.join(tmpdir, name + ".bin"),
+                                         dtype=np.float64).reshape(like.shape)
+    H = get("hout", H_init)
+    phis = [get(f"phiout{i}", phi_init[i]) for i in range(len(solids))]
+    taus = [get(f"tauout{a}", tau_init[a]) for a in range(3)]
+    return st, H, phis, taus

@@ -1,6 +1,7 @@
-// Runs one rmx_extrapolate call (or, when the case holds step.txt, one rmx_step call) of
-// the CPU-emulated library on a case written by tests/cpu_hip/emu.py and writes the
-// outputs next to it.  Test infrastructure only.
+// Runs one rmx_extrapolate call (or, when the case holds step.txt, one rmx_step call; or,
+// when it holds blur.txt, one rmx_blur and one rmx_solid_stress call) of the CPU-emulated
+// library on a case written by tests/cpu_hip/emu.py and writes the outputs next to it.
+// Test infrastructure only.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -116,6 +117,60 @@ int main(int argc, char** argv) {
             std::fclose(f);
         }
         reps = 0;   // the extrapolation below is not run
+    }
+    // Blur-zone consumers: labels come from labin{i}.bin; eps, then one shear modulus per
+    // solid, in blur.txt; initial H, phi and tau from their own files.
+    FILE* bf = std::fopen((dir + "/blur.txt").c_str(), "r");
+    if (bf) {
+        double eps = 0.0;
+        std::vector<double> G(ns);
+        if (std::fscanf(bf, "%lf", &eps) != 1) return 2;
+        for (int i = 0; i < ns; ++i)
+            if (std::fscanf(bf, "%lf", &G[i]) != 1) return 2;
+        std::fclose(bf);
+        auto load = [&](const std::string& name) {
+            auto b = slurp((dir + "/" + name + ".bin").c_str());
+            void* d = nullptr;
+            hipMalloc(&d, b.size());
+            std::memcpy(d, b.data(), b.size());
+            return std::make_pair(d, b.size());
+        };
+        std::vector<double*> phi(ns);
+        std::vector<size_t> phin(ns);
+        for (int i = 0; i < ns; ++i) {
+            auto lb = load("labin" + std::to_string(i));
+            hipFree(sol[i].labels);
+            sol[i].labels = static_cast<int8_t*>(lb.first);
+            auto pb = load("phiinit" + std::to_string(i));
+            phi[i] = static_cast<double*>(pb.first);
+            phin[i] = pb.second;
+        }
+        auto H = load("hinit");
+        double* tau[3];
+        size_t taun[3];
+        for (int a = 0; a < 3; ++a) {
+            auto t = load("tauinit" + std::to_string(a));
+            tau[a] = static_cast<double*>(t.first);
+            taun[a] = t.second;
+        }
+        st = rmx_blur(ctx, &g, sol.data(), ns, eps, static_cast<double*>(H.first), phi.data(),
+                      nullptr);
+        if (st == RMX_OK)
+            st = rmx_solid_stress(ctx, &g, sol.data(), ns, eps, G.data(), tau, nullptr);
+        hipDeviceSynchronize();
+        auto put = [&](const std::string& name, const void* p, size_t n) {
+            FILE* f = std::fopen((dir + "/" + name + ".bin").c_str(), "wb");
+            std::fwrite(p, 1, n, f);
+            std::fclose(f);
+        };
+        put("hout", H.first, H.second);
+        for (int a = 0; a < 3; ++a) put("tauout" + std::to_string(a), tau[a], taun[a]);
+        for (int i = 0; i < ns; ++i) put("phiout" + std::to_string(i), phi[i], phin[i]);
+        FILE* out = std::fopen((dir + "/status.txt").c_str(), "w");
+        std::fprintf(out, "%d\n", st);
+        std::fclose(out);
+        rmx_destroy(ctx);
+        return 0;
     }
     // Optional warm-up calls with other flags on fresh copies of the fields (the same
     // context), as a test process does before the measured call.

@@ -237,3 +237,82 @@ def wall_sphere(n=24, n_layers=6):
     w.solids[0] = synth.Solid(s.lo, s.ext, synth.sphere_shape((0.5, 0.5, 0.12), 0.25),
                               s.n_layers, s.xi)
     return w
+
+
+# ---- blur-zone consumers ------------------------------------------------------------------
+def blur_pair_workload(n=40, n_layers=6):
+    """Two spheres whose blur zones overlap (gap under one cell), each with its own
+    near-identity affine reference map and its own box; the boxes overlap."""
+    h = 1.0 / n
+    w = synth.Workload("pair", (n, n, n), h, (0.0, 0.0, 0.0))
+    for c, M in (((0.36, 0.5, 0.5), np.array([[1.02, 0.03, 0.0], [-0.02, 0.98, 0.01],
+                                                [0.0, 0.02, 1.0]])),
+                 ((0.64, 0.5, 0.5), np.array([[0.97, 0.0, 0.02], [0.01, 1.03, 0.0],
+                                                [-0.02, 0.0, 1.01]]))):
+        lo = tuple(max(0, int(ci * n) - 13) for ci in c)
+        ext = tuple(min(n, int(ci * n) + 13) - l for ci, l in zip(c, lo))
+        x, y, z = synth.cell_centres(lo, ext, h, w.origin)
+        X = np.stack(np.broadcast_arrays(x, y, z))
+        cc = np.asarray(c)[:, None, None, None]
+        xi = cc + np.einsum("ab,bkji->akji", M, X - cc)
+        w.solids.append(synth.Solid(lo, ext, synth.sphere_shape(c, 0.13), n_layers, xi))
+    return w
+
+
+class BlurCase:
+    """Inputs of the blur-zone consumers for workload `w`: per solid xi and labels from
+    the oracle's extrapolation, eps, one shear modulus per solid, and sentinel contents
+    of the outputs."""
+
+    def __init__(self, w, eps_cells=2.0, seed=23):
+        self.w = w
+        self.eps = eps_cells * w.h
+        self.xi, self.labels = [], []
+        for s in w.solids:
+            st, xo, lab, _, _ = run_oracle(w, s)
+            assert st == 0, st
+            self.xi.append(xo)
+            self.labels.append(lab)
+        rng = np.random.default_rng(seed)
+        self.G = list(rng.uniform(0.5, 3.0, size=len(w.solids)))
+        n0, n1, n2 = w.grid_n
+        self.H_init = np.full((n2, n1, n0), 5.0)
+        self.phi_init = [np.full(x.shape[1:], -6.0) for x in self.xi]
+        self.tau_init = [np.full((6, n2 + (a == 2), n1 + (a == 1), n0 + (a == 0)), 7.0)
+                         for a in range(3)]
+
+    def oracle_solids(self):
+        return [(s.lo, s.ext, oracle_shape(s.shape), s.n_layers, self.xi[i], self.labels[i])
+                for i, s in enumerate(self.w.solids)]
+
+    def oracle(self):
+        sols = self.oracle_solids()
+        H, phis = oracle.blur(self.w.grid_n, sols, self.eps, self.H_init, self.phi_init)
+        taus = oracle.solid_stress(self.w.grid_n, sols, self.eps, self.w.h, self.G,
+                                   self.tau_init)
+        return H, phis, taus
+
+
+def compare_blur(case, got, expect, tag=""):
+    """got / expect: (H, [phi], [tau]).  phi bitwise (phi0 is the same expression on both
+    sides); H within 1e-13; tau within 1e-12 of its largest magnitude; cells and faces the
+    calls must not touch keep their sentinels.  Returns (H error, tau error)."""
+    gH, gphi, gtau = got
+    eH, ephi, etau = expect
+    for i in range(len(ephi)):
+        assert np.array_equal(np.isnan(gphi[i]), np.isnan(ephi[i])), (tag, i)
+        assert np.array_equal(gphi[i].view(np.uint64), ephi[i].view(np.uint64)), \
+            (tag, i, "phi", int((gphi[i] != ephi[i]).sum()))
+    written = eH != case.H_init
+    assert np.array_equal(gH[~written], eH[~written]), (tag, "H untouched")
+    eh = float(np.max(np.abs(gH - eH)))
+    assert eh <= 1e-13, (tag, "H", eh)
+    et = 0.0
+    for a in range(3):
+        scale = max(1.0, float(np.max(np.abs(etau[a][etau[a] != 7.0]))) if (etau[a] != 7.0).any() else 1.0)
+        untouched = etau[a] == 7.0
+        assert np.array_equal(gtau[a] == 7.0, untouched), (tag, a, "tau written faces")
+        e = float(np.max(np.abs(gtau[a] - etau[a]))) / scale
+        assert e <= 1e-12, (tag, a, "tau", e)
+        et = max(et, e)
+    return eh, et
