@@ -56,6 +56,7 @@ class Problem(ctypes.Structure):
         ("r_s", ctypes.c_int32),
         ("r_max", ctypes.c_int32),
         ("normal_layers", ctypes.c_int32),
+        ("adjacency", ctypes.c_int32),
     ]
 
 
@@ -145,7 +146,7 @@ def make_shape(kind, centre, semi, rot=None) -> Shape:
 
 
 def make_problem(grid_n, lo, ext, shape: Shape, n_layers, r_s=2, r_max=4,
-                 normal_layers=2) -> Problem:
+                 normal_layers=2, adjacency=6) -> Problem:
     p = Problem()
     p.grid_n[:] = [int(v) for v in grid_n]
     p.lo[:] = [int(v) for v in lo]
@@ -153,6 +154,7 @@ def make_problem(grid_n, lo, ext, shape: Shape, n_layers, r_s=2, r_max=4,
     p.shape = shape
     p.n_layers = int(n_layers)
     p.r_s, p.r_max, p.normal_layers = int(r_s), int(r_max), int(normal_layers)
+    p.adjacency = int(adjacency)
     return p
 
 

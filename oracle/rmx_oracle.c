@@ -61,6 +61,7 @@ typedef struct {
     int32_t n_layers;       /* L                                                      */
     int32_t r_s, r_max;     /* search radius and its cap                              */
     int32_t normal_layers;  /* eq. (weight) uses the normal for layers <= this (2)    */
+    int32_t adjacency;      /* 6: face neighbours; 26: every cell of the 3^3 cube      */
 } orc_problem;
 
 /* stats layout (int64): [0] interior, [1..16] band cells of layer l, [17] cells whose
@@ -233,6 +234,7 @@ static int check_problem(const orc_problem* p) {
     if (p->n_layers < 0 || p->n_layers > ORC_MAX_LAYERS) return ORC_E_LAYERS;
     if (p->r_s < 1 || p->r_max < p->r_s || p->r_max > ORC_MAX_R) return ORC_E_ARG;
     if (p->normal_layers < 0) return ORC_E_ARG;
+    if (p->adjacency != 6 && p->adjacency != 26) return ORC_E_ARG;
     if (p->shape.kind != 1 && p->shape.kind != 2) return ORC_E_SHAPE;
     int na = (p->shape.kind == 1) ? 1 : 3;
     for (int a = 0; a < na; ++a)
@@ -244,7 +246,8 @@ static int check_problem(const orc_problem* p) {
  * Layer labelling ("Extrapolation of xi", first paragraph; Fig. 1(c)):
  * interior cells are layer 0; every unmarked face neighbour of a layer-(l-1) cell becomes
  * layer l, up to L; growth stops at the grid walls.  Implemented literally as a FIFO
- * breadth-first search.  Returns the number of interior cells, or a negative status.
+ * breadth-first search.  With adjacency 26 (the same section's remark that layers follow
+ * from any adjacency on the grid) the neighbours are the 26 cells of the 3^3 cube.  Returns the number of interior cells, or a negative status.
  * ---------------------------------------------------------------------------------- */
 int64_t orc_label(const orc_problem* p, const double* xi, int8_t* labels, int32_t* truncated) {
     int st = check_problem(p);
@@ -281,18 +284,22 @@ int64_t orc_label(const orc_problem* p, const double* xi, int8_t* labels, int32_
         int lc = labels[c];
         if (lc >= L) continue;
         int64_t i = c % b.n0, j = (c / b.n0) % b.n1, k = c / (b.n0 * b.n1);
-        const int64_t nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
-                                  {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
-        for (int q = 0; q < 6; ++q) {
-            if (nb[q][0] < 0 || nb[q][0] >= b.n0 || nb[q][1] < 0 || nb[q][1] >= b.n1 ||
-                nb[q][2] < 0 || nb[q][2] >= b.n2)
-                continue;
-            int64_t d = cell_index(&b, nb[q][0], nb[q][1], nb[q][2]);
-            if (labels[d] == -1) {
-                labels[d] = (int8_t)(lc + 1);
-                queue[tail++] = d;
-            }
-        }
+        /* the neighbours under the problem's adjacency: offsets with |d|_1 = 1 (faces),
+         * or every non-zero offset of the 3^3 cube */
+        for (int dk = -1; dk <= 1; ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                    int n1 = (di != 0) + (dj != 0) + (dk != 0);
+                    if (n1 == 0 || (p->adjacency == 6 && n1 != 1)) continue;
+                    int64_t x = i + di, y = j + dj, z = k + dk;
+                    if (x < 0 || x >= b.n0 || y < 0 || y >= b.n1 || z < 0 || z >= b.n2)
+                        continue;
+                    int64_t d = cell_index(&b, x, y, z);
+                    if (labels[d] == -1) {
+                        labels[d] = (int8_t)(lc + 1);
+                        queue[tail++] = d;
+                    }
+                }
     }
     free(queue);
     if (truncated) *truncated = trunc;

@@ -12,10 +12,11 @@ def oracle_shape(shape):
     return oracle.make_shape(shape.kind, shape.centre, shape.semi, shape.rot)
 
 
-def oracle_problem(w, s, r_s=2, r_max=4, normal_layers=2, n_layers=None):
+def oracle_problem(w, s, r_s=2, r_max=4, normal_layers=2, n_layers=None, adjacency=6):
     return oracle.make_problem(w.grid_n, s.lo, s.ext, oracle_shape(s.shape),
                                s.n_layers if n_layers is None else n_layers,
-                               r_s=r_s, r_max=r_max, normal_layers=normal_layers)
+                               r_s=r_s, r_max=r_max, normal_layers=normal_layers,
+                               adjacency=adjacency)
 
 
 def run_oracle(w, s, **kw):
@@ -23,6 +24,19 @@ def run_oracle(w, s, **kw):
     nthreads = kw.pop("nthreads", 0)
     p = oracle_problem(w, s, **kw)
     return oracle.extrapolate(p, s.xi, xi_normal=xi_normal, nthreads=nthreads)
+
+
+def linf_distance_labels(mask, L):
+    """Brute force: label = min Chebyshev distance to an interior cell if <= L, else -1
+    (0 on interior cells).  mask is [n2, n1, n0] bool."""
+    idx = np.argwhere(mask)
+    out = np.full(mask.shape, -1, dtype=np.int8)
+    if idx.size == 0:
+        return out
+    allc = np.argwhere(np.ones(mask.shape, dtype=bool))
+    d = np.abs(allc[:, None, :] - idx[None, :, :]).max(axis=2).min(axis=1)
+    out[tuple(allc.T)] = np.where(d <= L, d, -1).astype(np.int8)
+    return out
 
 
 def l1_distance_labels(mask, L, grid_mask_shape=None):

@@ -13,7 +13,8 @@ import pytest
 
 import oracle
 from paper_2104_00095_amd import synth
-from tests.helpers import (cube_symmetries, exact_field, l1_distance_labels, oracle_problem,
+from tests.helpers import (cube_symmetries, exact_field, l1_distance_labels,
+                           linf_distance_labels, oracle_problem,
                            oracle_shape, rel_err, run_oracle)
 
 UNIT_SPHERE = dict(kind=1, centre=(0.0, 0.0, 0.0), semi=(1.0, 1.0, 1.0))
@@ -67,6 +68,42 @@ def test_labels_equal_bruteforce_l1_distance(seed):
     assert n_int == int(mask.sum())
     assert not trunc                        # box == grid: every face is a wall
     assert np.array_equal(lab, l1_distance_labels(mask, L))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_cube_adjacency_labels_equal_bruteforce_chebyshev_distance(seed):
+    """Layers through the 26 cells of the 3^3 cube ("Extrapolation of xi": layers follow
+    from a definition of adjacency on the grid) equal the Chebyshev distance, capped."""
+    rng = np.random.default_rng(1500 + seed)
+    shape = tuple(int(v) for v in rng.integers(3, 13, size=3))
+    mask = _random_mask(rng, shape)
+    L = int(rng.integers(0, 7))
+    xi = synth.tiny_field_from_mask(mask)
+    p = _mask_problem(mask, L)
+    p.adjacency = 26
+    n_int, lab, trunc = oracle.label(p, xi)
+    assert n_int == int(mask.sum()) and not trunc
+    assert np.array_equal(lab, linf_distance_labels(mask, L))
+    # the cube reaches further: never a larger label than through faces
+    p.adjacency = 6
+    _, lab6, _ = oracle.label(p, xi)
+    assert np.all((lab6 < 0) | ((lab >= 0) & (lab <= lab6)))
+
+
+def test_cube_adjacency_extrapolation_reproduces_affine_fields():
+    """The fit is unchanged by the adjacency: an affine field is reproduced on the band
+    that the cube layers define."""
+    w = synth.sphere32(n=20, n_layers=4, affine=True)
+    s = w.solids[0]
+    p = oracle_problem(w, s, adjacency=26)
+    st, xo, lab, dec, stats = oracle.extrapolate(p, s.xi)
+    assert st == 0
+    band = lab > 0
+    assert band.sum() > 0
+    assert np.max(np.abs(xo[:, band] - s.xi[:, band])) < 1e-12
+    # more band cells than through faces
+    st6, _, lab6, _, _ = oracle.extrapolate(oracle_problem(w, s), s.xi)
+    assert (lab > 0).sum() > (lab6 > 0).sum()
 
 
 @pytest.mark.parametrize("seed", range(12))
