@@ -83,6 +83,13 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
                                   layer l waits (bounded) until layer l - 1 is complete.  A
                                   wait that runs out reports RMX_E_HIP for the call.       */
 
+#define RMX_FLAG_ADJ26 32u     /* layers by the 26-neighbour adjacency ("Extrapolation of
+                                  xi", advantage (1): layers follow from any adjacency on the
+                                  grid): every unmarked cell sharing a face, an edge or a
+                                  corner with a layer-(l-1) cell is layer l, so the label is
+                                  the Chebyshev distance to the interior (face neighbours,
+                                  the default, give the L1 distance).  The fit is unchanged. */
+
 /* Kernel phases reported by rmx_profile_read. */
 #define RMX_PHASE_CLASSIFY 0
 #define RMX_PHASE_LABEL 1

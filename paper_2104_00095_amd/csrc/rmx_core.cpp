@@ -107,7 +107,7 @@ int get_stage(rmx_ctx* c, size_t bytes, Staging** out, bool no_alloc = false) {
 
 uint64_t options_key(const rmx_options* o) {
     rmx_options oo = *o;
-    oo.flags &= RMX_FLAG_PER_SOLID;
+    oo.flags &= RMX_FLAG_PER_SOLID | RMX_FLAG_ADJ26;
     return fnv1a(&oo, sizeof(oo), 1469598103934665603ull);
 }
 

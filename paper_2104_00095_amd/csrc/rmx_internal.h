@@ -92,6 +92,8 @@ struct Batch {
     int32_t r_s, r_max;
     int32_t tile_w;          // 64-cell words per label tile along x (1..kMaxTileW)
     int32_t n_chunks;        // classification chunks (kChunkWords mask words each)
+    int32_t adj26;           // layers by the 26-neighbour adjacency (else face neighbours)
+    int32_t pad_adj;
     int64_t total_words;
     int64_t blist_cap;       // brick-list entries per layer: n_tiles * 32 * tile_w
     const int32_t* tile_solid;  // [n_tiles]

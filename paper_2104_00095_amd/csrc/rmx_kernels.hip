@@ -322,10 +322,11 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
 
     const int by2 = (tk >> 3) * 2 + (tj >> 3);   // which of the tile's 2 x 2 brick rows
     for (int l = 1; l <= L; ++l) {
-        // One dilation step through face neighbours, A -> B, over the rows that can still
-        // reach the tile: D_l is needed only within L - l rows of it, i.e. on region rows
-        // [l, RJ - l) x [l, RK - l) (their neighbours lie inside the region).  A row's
-        // own words come from registers, its four neighbour rows from LDS.
+        // One dilation step through face neighbours (or, with the 26-neighbour adjacency,
+        // through every cell of the 3^3 cube), A -> B, over the rows that can still reach
+        // the tile: D_l is needed only within L - l rows of it, i.e. on region rows
+        // [l, RJ - l) x [l, RK - l) (their neighbours lie inside the region).  A row's own
+        // words come from registers, its neighbour rows from LDS.
         const unsigned long long* __restrict__ Ar = A;
         unsigned long long* __restrict__ Br = B;
         const int SJ = RJ - 2 * l, S = SJ * (RK - 2 * l);
@@ -343,9 +344,24 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                 const int idx = base + w;
                 const unsigned long long left = w > 0 ? c[w - 1] : 0ull;
                 const unsigned long long right = w < MW - 1 ? c[w + 1] : 0ull;
-                const unsigned long long v = c[w] | (c[w] << 1) | (c[w] >> 1) | (left >> 63) |
-                                             (right << 63) | Ar[idx - RS] | Ar[idx + RS] |
-                                             Ar[idx - RS * RJ] | Ar[idx + RS * RJ];
+                unsigned long long v = c[w] | (c[w] << 1) | (c[w] >> 1) | (left >> 63) |
+                                       (right << 63);
+                if (!b.adj26) {
+                    v |= Ar[idx - RS] | Ar[idx + RS] | Ar[idx - RS * RJ] | Ar[idx + RS * RJ];
+                } else {
+                    // cube adjacency: the x-dilated words of the eight neighbour rows
+#pragma unroll
+                    for (int dk = -1; dk <= 1; ++dk)
+#pragma unroll
+                        for (int dj = -1; dj <= 1; ++dj) {
+                            if (dj == 0 && dk == 0) continue;
+                            const int q = idx + dj * RS + dk * RS * RJ;
+                            const unsigned long long m = Ar[q];
+                            const unsigned long long ml = w > 0 ? Ar[q - 1] : 0ull;
+                            const unsigned long long mr = w + 1 < RW ? Ar[q + 1] : 0ull;
+                            v |= m | (m << 1) | (m >> 1) | (ml >> 63) | (mr << 63);
+                        }
+                }
                 const unsigned long long vm = !rok ? 0ull : (xr0 + w == W - 1 ? tail : ~0ull);
                 Br[idx] = v & vm;
             }

@@ -233,6 +233,7 @@ void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
     b->r_s = opt->r_s;
     b->r_max = opt->r_max;
     b->tile_w = p->tile_w;
+    b->adj26 = (opt->flags & RMX_FLAG_ADJ26) != 0;
     b->n_chunks = p->n_chunks;
     b->total_words = p->total_words;
     b->blist_cap = p->blist_cap;

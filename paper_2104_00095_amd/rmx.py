@@ -20,6 +20,7 @@ E_TRUNCATED, E_BUDGET, E_BUSY, E_NOTFOUND, E_DISABLED = -7, -8, -9, -10, -11
 SPHERE, ELLIPSOID = 1, 2
 FP64, FP32_ACCUM = 0, 1
 FLAG_SYNC, FLAG_GRAPH, FLAG_PER_SOLID, FLAG_PROFILE, FLAG_PERSISTENT = 1, 2, 4, 8, 16
+FLAG_ADJ26 = 32
 N_PHASES = 24
 PHASES = ["classify", "label", "normal"] + [f"extrap{l}" for l in range(1, 17)] + \
     ["band", "step_trans", "step_predict", "step_correct", "step_faces"]

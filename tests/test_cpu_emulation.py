@@ -22,7 +22,7 @@ emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
 
 TOL = {0: 1e-12, 1: 1e-5}
-BATCHED, PER_SOLID, GRAPH, PERSISTENT = 0, 4, 2, 16
+BATCHED, PER_SOLID, GRAPH, PERSISTENT, ADJ26 = 0, 4, 2, 16, 32
 AUTOTUNE = 1024   # (run_case: run the autotuner on the fields first)
 NOALLOC = 4096    # (run_case: make the call through the allocation-free entry point)
 
@@ -87,6 +87,10 @@ def _runs():
         # entry points on a larger batch (the scratch keeps their contents)
         "noalloc": (sphere, 0, NOALLOC, (BATCHED, NOALLOC | PER_SOLID)),
         "noalloc_suspension_per_solid": (susp, 1, NOALLOC | PER_SOLID, (NOALLOC,)),
+        # layers by the 26-neighbour adjacency, after a face-layer call on the context
+        "adj26_sphere16": (sphere, 0, ADJ26, (BATCHED,)),
+        "adj26_suspension3_fp32_graph": (susp, 1, ADJ26 | GRAPH, (GRAPH,)),
+        "adj26_ellipsoid24_persistent": (ell, 0, ADJ26 | PERSISTENT, ()),
     }
 
 
@@ -106,10 +110,10 @@ def emulated():
         return dict(ex.map(one, _runs().items()))
 
 
-def _check(w, outs, precision, xi_normal=None):
+def _check(w, outs, precision, xi_normal=None, adjacency=6):
     for i, ((xo, lab, dec, _), s) in enumerate(zip(outs, w.solids)):
         st, xr, lr, dr, _ = run_oracle(w, s, xi_normal=None if xi_normal is None
-                                       else xi_normal[i])
+                                       else xi_normal[i], adjacency=adjacency)
         assert np.array_equal(lab, lr)
         if st == 0:
             assert np.array_equal(dec, dr)
@@ -199,3 +203,11 @@ def test_emulated_noalloc_entry(emulated, name):
     w, prec, st, outs, xn = emulated[name]
     assert st == 0
     _check(w, outs, prec, xn)
+
+
+@pytest.mark.parametrize("name", ["adj26_sphere16", "adj26_suspension3_fp32_graph",
+                                  "adj26_ellipsoid24_persistent"])
+def test_emulated_cube_adjacency(emulated, name):
+    w, prec, st, outs, xn = emulated[name]
+    assert st == 0
+    _check(w, outs, prec, xn, adjacency=26)

@@ -47,13 +47,15 @@ def run_gpu(ctx, w, precision=0, r_s=2, r_max=4, normal_layers=2, flags=0,
     return st, out
 
 
-def compare(w, gpu, precision, r_s=2, r_max=4, normal_layers=2, xi_normal=None, tag=""):
+def compare(w, gpu, precision, r_s=2, r_max=4, normal_layers=2, xi_normal=None, tag="",
+            adjacency=6):
     worst = 0.0
     for i, s in enumerate(w.solids):
         xg, lg, dg, stg = gpu[i]
         st, xo, lo, do, so = run_oracle(w, s, r_s=r_s, r_max=r_max,
                                         normal_layers=normal_layers,
-                                        xi_normal=None if xi_normal is None else xi_normal[i])
+                                        xi_normal=None if xi_normal is None else xi_normal[i],
+                                        adjacency=adjacency)
         assert stg["status"] == st, (tag, i, stg["status"], st)
         assert np.array_equal(lg, lo), (tag, i, "labels", int((lg != lo).sum()))
         if dg is not None and st == 0:
@@ -391,3 +393,22 @@ def test_autotune_keeps_inputs_and_results(ctx):
         assert np.array_equal(xa.view(np.uint64), xb.view(np.uint64))
         assert np.array_equal(la, lb) and np.array_equal(da, db)
     print("autotune", best)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", ["sphere32", "ellipsoid48", "suspension12"])
+def test_cube_adjacency_matches_oracle(ctx, name, precision):
+    """Layers by the 26-neighbour adjacency (RMX_FLAG_ADJ26): labels equal the oracle's
+    (Chebyshev distances), decisions and the band as for face layers."""
+    from paper_2104_00095_amd import rmx
+    w = {"sphere32": lambda: synth.sphere32(),
+         "ellipsoid48": lambda: synth.ellipsoid128(n=48, n_layers=5),
+         "suspension12": lambda: synth.suspension(n_solids=12, grid_n=(64, 64, 128),
+                                                  h=1.0 / 64)}[name]()
+    for fl in (0, rmx.FLAG_GRAPH):
+        st, gpu = run_gpu(ctx, w, precision, flags=rmx.FLAG_ADJ26 | fl)
+        assert st == 0
+        compare(w, gpu, precision, tag=f"adj26/{name}/{fl}", adjacency=26)
+    # the face-layer call after it is not affected (graph and tuning keys differ)
+    st, gpu = run_gpu(ctx, w, precision)
+    compare(w, gpu, precision, tag=f"adj6/{name}")
