@@ -293,6 +293,20 @@ int rmx_solid_stress(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids
                      int32_t n_solids, double eps, const double* G, double* const* tau,
                      void* hip_stream);
 
+/* Layers for a blur zone ("Extrapolation of xi", first paragraph: L is chosen so that the
+ * band covers the whole blur zone).  Host only.  *L = the smallest layer count that labels
+ * every cell with phi < eps around a resolved solid (one that holds a ball of radius
+ * sqrt(3) h / 2 beneath every surface point), plus `reach` further layers for the
+ * consumer's stencil: a cell with 0 < phi < eps lies within physical distance
+ * stretch * eps of the surface (stretch >= 1 bounds physical over reference lengths;
+ * 1 for an undeformed map), hence within D = stretch * eps + sqrt(3) h of an interior
+ * cell centre, i.e. within ceil(D / h) layers of the 26-neighbour adjacency
+ * (RMX_FLAG_ADJ26 in flags) or ceil(sqrt(3) D / h) face layers.  h: the largest grid
+ * spacing.  RMX_E_ARG for non-positive or non-finite arguments or reach < 0;
+ * RMX_E_LAYERS if the count exceeds RMX_MAX_LAYERS. */
+int rmx_layers_for_blur(double eps, double h, double stretch, int32_t reach, uint32_t flags,
+                        int32_t* L);
+
 const char* rmx_status_string(int status);
 
 /* Autotuner.  Launch shapes that change no result: the label tile width (1, 2 or 4 words

@@ -693,6 +693,19 @@ int rmx_solid_stress(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     return launch_blur_stress(b, st) == hipSuccess ? RMX_OK : RMX_E_HIP;
 }
 
+int rmx_layers_for_blur(double eps, double h, double stretch, int32_t reach, uint32_t flags,
+                        int32_t* L) {
+    if (!L || !(eps > 0.0) || !(h > 0.0) || !(stretch >= 1.0) || !std::isfinite(eps) ||
+        !std::isfinite(h) || !std::isfinite(stretch) || reach < 0)
+        return RMX_E_ARG;
+    const double D = stretch * eps + std::sqrt(3.0) * h;
+    const double cells = (flags & RMX_FLAG_ADJ26) ? D / h : std::sqrt(3.0) * D / h;
+    const double l = std::ceil(cells) + (double)reach;
+    if (!(l <= RMX_MAX_LAYERS)) return RMX_E_LAYERS;
+    *L = (int32_t)l;
+    return RMX_OK;
+}
+
 int rmx_extrapolate_noalloc(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
                             int32_t n_solids, const rmx_options* opt, void* hip_stream,
                             rmx_solid_stats* stats) {

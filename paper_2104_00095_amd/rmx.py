@@ -33,6 +33,7 @@ EXPORTS = [
     "rmx_server_field", "rmx_server_submit", "rmx_server_wait", "rmx_server_release",
     "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read", "rmx_autotune",
     "rmx_set_tuning", "rmx_extrapolate_noalloc", "rmx_step", "rmx_blur", "rmx_solid_stress",
+    "rmx_layers_for_blur",
 ]
 
 
@@ -134,6 +135,8 @@ def lib():
                                ctypes.c_double, vp, P(SolidStats)]
         L.rmx_blur.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, ctypes.c_double, vp, vp,
                                vp]
+        L.rmx_layers_for_blur.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int32, ctypes.c_uint32, P(ctypes.c_int32)]
         L.rmx_solid_stress.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, ctypes.c_double,
                                        vp, vp, vp]
         for name in EXPORTS:
@@ -222,6 +225,17 @@ def solid(lo, ext, shp: Shape, n_layers, xi, labels, xi_normal=None, decisions=N
     # keep the tensors alive with the descriptor
     s._keep = (xi, labels, xi_normal, decisions)
     return s
+
+
+def layers_for_blur(eps: float, h: float, stretch: float = 1.0, reach: int = 0,
+                    flags: int = 0) -> int:
+    """Layer count whose band covers the blur zone (rmx_layers_for_blur)."""
+    out = ctypes.c_int32(0)
+    st = lib().rmx_layers_for_blur(float(eps), float(h), float(stretch), int(reach),
+                                   int(flags), ctypes.byref(out))
+    if st != OK:
+        raise RmxError(st, "rmx_layers_for_blur")
+    return int(out.value)
 
 
 def step_solid(lo, ext, shp: Shape, n_layers, xi_n, labels_n, u, uf, xi_next, labels_next,
