@@ -57,6 +57,8 @@ class Problem(ctypes.Structure):
         ("r_max", ctypes.c_int32),
         ("normal_layers", ctypes.c_int32),
         ("adjacency", ctypes.c_int32),
+        ("periodic", ctypes.c_int32 * 3),
+        ("spacing", ctypes.c_double * 3),
     ]
 
 
@@ -114,8 +116,7 @@ def lib():
         L.orc_normal.argtypes = [P(Problem), ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_void_p]
         L.orc_normal.restype = None
-        L.orc_predict.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 6 + \
-            [ctypes.c_double, ctypes.c_void_p]
+        L.orc_predict.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 8
         L.orc_predict.restype = ctypes.c_int
         L.orc_correct.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 5
         L.orc_correct.restype = None
@@ -123,12 +124,12 @@ def lib():
         L.orc_slope4.restype = ctypes.c_double
         L.orc_heaviside_eps.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_heaviside_eps.restype = ctypes.c_double
-        L.orc_blur.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(BlurSolid), ctypes.c_double,
-                               ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_blur.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, P(BlurSolid),
+                               ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_blur.restype = None
-        L.orc_solid_stress.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(BlurSolid),
-                                       ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
-                                       ctypes.c_void_p]
+        L.orc_solid_stress.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       P(BlurSolid), ctypes.c_double, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]
         L.orc_solid_stress.restype = None
         _lib = L
     return _lib
@@ -146,7 +147,11 @@ def make_shape(kind, centre, semi, rot=None) -> Shape:
 
 
 def make_problem(grid_n, lo, ext, shape: Shape, n_layers, r_s=2, r_max=4,
-                 normal_layers=2, adjacency=6) -> Problem:
+                 normal_layers=2, adjacency=6, periodic=(0, 0, 0),
+                 spacing=(1.0, 1.0, 1.0)) -> Problem:
+    """One solid's extrapolation problem.  ``spacing``: the cell sizes along x, y, z
+    (only their ratios matter to the extrapolation); ``periodic``: the axes along which
+    the grid wraps (no walls there; the box may run past the grid's end)."""
     p = Problem()
     p.grid_n[:] = [int(v) for v in grid_n]
     p.lo[:] = [int(v) for v in lo]
@@ -155,6 +160,8 @@ def make_problem(grid_n, lo, ext, shape: Shape, n_layers, r_s=2, r_max=4,
     p.n_layers = int(n_layers)
     p.r_s, p.r_max, p.normal_layers = int(r_s), int(r_max), int(normal_layers)
     p.adjacency = int(adjacency)
+    p.periodic[:] = [1 if v else 0 for v in periodic]
+    p.spacing[:] = [float(v) for v in spacing]
     return p
 
 
@@ -222,19 +229,31 @@ def slope4(q) -> float:
     return float(lib().orc_slope4(_ptr(a)))
 
 
+def _spacing(h):
+    """A spacing given as one number (isotropic) or as (Delta_x, Delta_y, Delta_z)."""
+    v = np.asarray(h, dtype=np.float64).reshape(-1)
+    return np.ascontiguousarray(np.repeat(v, 3) if v.size == 1 else v.reshape(3))
+
+
+def _periodic(periodic):
+    return np.ascontiguousarray(np.asarray([1 if v else 0 for v in (periodic or (0, 0, 0))],
+                                           dtype=np.int32))
+
+
 def predict(ext, n_layers, xi_n, labels_n, u, uf, dt, h, xi_next):
     """Step 5: writes the predictor into ``xi_next`` (float64 [3, e2, e1, e0], modified in
     place: predicted cells get the value, the rest of the old band NaN, unmarked cells
     are left as they are).  ``uf`` = (x-faces [e2, e1, e0+1], y-faces [e2, e1+1, e0],
-    z-faces [e2+1, e1, e0]).  Returns 1 if an interior cell could not be predicted."""
+    z-faces [e2+1, e1, e0]).  ``h``: the spacing, one number or one per axis.  Returns 1
+    if an interior cell could not be predicted."""
     e = np.ascontiguousarray(np.asarray(ext, dtype=np.int32))
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xi_n, u) + tuple(uf)]
     lab = np.ascontiguousarray(labels_n, dtype=np.int8)
     assert xi_next.flags.c_contiguous and xi_next.dtype == np.float64
-    lam = float(dt) / float(h)
+    lam = np.ascontiguousarray([float(dt) / float(d) for d in _spacing(h)])
     return int(lib().orc_predict(_ptr(e), int(n_layers), _ptr(arrs[0]), _ptr(lab),
                                  _ptr(arrs[1]), _ptr(arrs[2]), _ptr(arrs[3]), _ptr(arrs[4]),
-                                 lam, _ptr(xi_next)))
+                                 _ptr(lam), _ptr(xi_next)))
 
 
 def correct(ext, n_layers, xi_n, labels_n, xi_next, labels_next, xi_half):
@@ -306,10 +325,10 @@ def _blur_solids(solids):
     return arr, keep
 
 
-def blur(grid_n, solids, eps, H_init, phi_init=None):
+def blur(grid_n, solids, eps, H_init, phi_init=None, periodic=None):
     """Modified Heaviside on the grid (written on cells inside some box; H_init elsewhere)
     and, if phi_init (one array per solid) is given, phi_m on each box's labelled cells.
-    Returns (H, [phi_m])."""
+    ``periodic``: the axes along which the grid wraps.  Returns (H, [phi_m])."""
     arr, keep = _blur_solids(solids)
     g = np.ascontiguousarray(np.asarray(grid_n, dtype=np.int32))
     H = np.ascontiguousarray(H_init, dtype=np.float64).copy()
@@ -318,18 +337,28 @@ def blur(grid_n, solids, eps, H_init, phi_init=None):
     if phi_init is not None:
         phis = [np.ascontiguousarray(p, dtype=np.float64).copy() for p in phi_init]
         pp = (ctypes.c_void_p * len(phis))(*[p.ctypes.data for p in phis])
-    lib().orc_blur(_ptr(g), len(solids), arr, float(eps), _ptr(H), pp)
+    per = _periodic(periodic)
+    lib().orc_blur(_ptr(g), _ptr(per), len(solids), arr, float(eps), _ptr(H), pp)
     return H, phis
 
 
-def solid_stress(grid_n, solids, eps, h, G, tau_init):
+def solid_stress(grid_n, solids, eps, h, G, tau_init, periodic=None):
     """Blended neo-Hookean stress on the faces: tau_init = three arrays
-    [6, n2 + (a==2), n1 + (a==1), n0 + (a==0)] (faces without a cell in any box keep
-    them).  Returns the three arrays."""
+    [6, n2 + (a==2), n1 + (a==1), n0 + (a==0)], without the extra face along a periodic
+    axis a (faces without a cell in any box keep them).  ``h``: the spacing, one number
+    or one per axis.  Returns the three arrays."""
     arr, keep = _blur_solids(solids)
     g = np.ascontiguousarray(np.asarray(grid_n, dtype=np.int32))
     Gs = np.ascontiguousarray(np.asarray(G, dtype=np.float64))
     tau = [np.ascontiguousarray(t, dtype=np.float64).copy() for t in tau_init]
     tp = (ctypes.c_void_p * 3)(*[t.ctypes.data for t in tau])
-    lib().orc_solid_stress(_ptr(g), len(solids), arr, float(eps), float(h), _ptr(Gs), tp)
+    per = _periodic(periodic)
+    hs = _spacing(h)
+    for a in range(3):
+        want = [int(grid_n[2]), int(grid_n[1]), int(grid_n[0])]
+        if not per[a]:
+            want[2 - a] += 1
+        assert tau[a].shape == (6, *want), (a, tau[a].shape, want)
+    lib().orc_solid_stress(_ptr(g), _ptr(per), len(solids), arr, float(eps), _ptr(hs),
+                           _ptr(Gs), tp)
     return tau

@@ -7,7 +7,15 @@
  *   - SI, section "Weighting scheme for weighted least squares-based extrapolation",
  *     equation (weight);
  *   - main text, "Blurred interface method": phi(x,t) = phi0(xi(x,t)), phi0 a signed
- *     distance in reference coordinates; interior cells are those with phi < 0.
+ *     distance in reference coordinates; interior cells are those with phi < 0;
+ *   - SI "Variable arrangement" (spacings Delta x, Delta y, Delta z of the M x N x O
+ *     cells) and SI "Test cases" (periodic domains).
+ *
+ * Readings of the last two: the fit's offsets stay in cells (an affine model's value at
+ * the target does not change when its columns are scaled), and only the normal factor of
+ * eq. (weight) sees the spacings, through the physical x' and gradient.  A solid's box
+ * holds its unwrapped map; along a periodic axis the box may run past the grid's end
+ * (the caller wraps it onto the grid), and no box face there is a wall.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing on the product path loads this file: only the test
  * suite, the smoke check and the benchmark's CPU-baseline leg do.  It shares no code,
@@ -62,6 +70,8 @@ typedef struct {
     int32_t r_s, r_max;     /* search radius and its cap                              */
     int32_t normal_layers;  /* eq. (weight) uses the normal for layers <= this (2)    */
     int32_t adjacency;      /* 6: face neighbours; 26: every cell of the 3^3 cube      */
+    int32_t periodic[3];    /* 1: the grid is periodic along this axis (no walls)      */
+    double spacing[3];      /* Delta x, Delta y, Delta z ("Variable arrangement")      */
 } orc_problem;
 
 /* stats layout (int64): [0] interior, [1..16] band cells of layer l, [17] cells whose
@@ -229,7 +239,15 @@ static void load_xi(const double* xi, const box_dims* b, int64_t c, double v[3])
 static int check_problem(const orc_problem* p) {
     for (int a = 0; a < 3; ++a) {
         if (p->grid_n[a] <= 0 || p->ext[a] <= 0) return ORC_E_ARG;
-        if (p->lo[a] < 0 || p->lo[a] + p->ext[a] > p->grid_n[a]) return ORC_E_BOX;
+        if (!(p->spacing[a] > 0.0) || !isfinite(p->spacing[a])) return ORC_E_ARG;
+        if (p->periodic[a]) {
+            /* the box starts inside the grid and may run past its end (it wraps), but it
+             * never covers a cell twice */
+            if (p->lo[a] < 0 || p->lo[a] >= p->grid_n[a] || p->ext[a] > p->grid_n[a])
+                return ORC_E_BOX;
+        } else if (p->lo[a] < 0 || p->lo[a] + p->ext[a] > p->grid_n[a]) {
+            return ORC_E_BOX;
+        }
     }
     if (p->n_layers < 0 || p->n_layers > ORC_MAX_LAYERS) return ORC_E_LAYERS;
     if (p->r_s < 1 || p->r_max < p->r_s || p->r_max > ORC_MAX_R) return ORC_E_ARG;
@@ -266,12 +284,13 @@ int64_t orc_label(const orc_problem* p, const double* xi, int8_t* labels, int32_
             queue[tail++] = c;
             ++n_int;
             /* The band of an interior cell closer than L to a box face that is not a grid
-             * wall would leave the box. */
+             * wall would leave the box.  A periodic axis has no walls: there the box must
+             * hold the whole band (its fields are the unwrapped map of the solid). */
             int64_t ii = c % b.n0, jj = (c / b.n0) % b.n1, kk = c / (b.n0 * b.n1);
             int64_t idx[3] = {ii, jj, kk};
             for (int a = 0; a < 3; ++a) {
-                int low_wall = (p->lo[a] == 0);
-                int high_wall = (p->lo[a] + p->ext[a] == p->grid_n[a]);
+                int low_wall = !p->periodic[a] && p->lo[a] == 0;
+                int high_wall = !p->periodic[a] && p->lo[a] + p->ext[a] == p->grid_n[a];
                 if (!low_wall && idx[a] < L) trunc = 1;
                 if (!high_wall && (p->ext[a] - 1 - idx[a]) < L) trunc = 1;
             }
@@ -310,7 +329,8 @@ int64_t orc_label(const orc_problem* p, const double* xi, int8_t* labels, int32_
  * Normal at a band cell (SI, weighting scheme): gradient of phi0(xi) by differences of
  * the face neighbours in the given field; central where both neighbours are defined and
  * inside the box, else one-sided with the cell itself (forward first), else 0.
- * Cell units: the grid spacing is isotropic and cancels after normalisation.
+ * In differences per cell: the physical gradient divides component a by Delta_a, which
+ * the weight does.
  * ---------------------------------------------------------------------------------- */
 static int phi_at(const orc_problem* p, const box_dims* b, const double* field, int64_t i,
                   int64_t j, int64_t k, double* out) {
@@ -436,7 +456,10 @@ static int fit_cell(const orc_problem* p, const box_dims* b, const double* xi,
     int32_t(*P)[3] = malloc(sizeof(int32_t[3]) * (size_t)nmax);
     double* W = malloc(sizeof(double) * (size_t)nmax);
     int64_t* D = malloc(sizeof(int64_t) * (size_t)nmax);
-    double gn = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+    /* the physical gradient of phi0(xi) and its length */
+    double gp[3];
+    for (int a = 0; a < 3; ++a) gp[a] = g[a] / p->spacing[a];
+    double gn = sqrt((gp[0] * gp[0] + gp[1] * gp[1]) + gp[2] * gp[2]);
     int code = -1;
 
     /* Pass 0..: radii r_s..r_max with eq. (weight); then F1 (kernel only) at r_max. */
@@ -458,13 +481,18 @@ static int fit_cell(const orc_problem* p, const box_dims* b, const double* xi,
                     double base = ldexp(1.0, -(abs(dx) + abs(dy) + abs(dz)));
                     double w;
                     if (use_normal) {
-                        /* x' = x_e - x_d = -delta h; the weight is positive iff x'.n > 0,
-                         * i.e. iff delta . g < 0, decided on this exact expression. */
+                        /* x' = x_e - x_d = -(dx Delta_x, dy Delta_y, dz Delta_z), physical.
+                         * x'.n > 0 iff delta . g < 0 (the spacings cancel between x' and
+                         * the physical gradient), decided on this exact expression; the
+                         * cosine's magnitude comes from the physical vectors. */
                         double fx = (double)dx, fy = (double)dy, fz = (double)dz;
                         double dot = (fx * g[0] + fy * g[1]) + fz * g[2];
                         if (!(dot < 0.0)) continue;
-                        double dlen = sqrt((fx * fx + fy * fy) + fz * fz);
-                        w = (-dot / (dlen * gn)) * base;
+                        double px = fx * p->spacing[0], py = fy * p->spacing[1],
+                               pz = fz * p->spacing[2];
+                        double pdot = (px * gp[0] + py * gp[1]) + pz * gp[2];
+                        double dlen = sqrt((px * px + py * py) + pz * pz);
+                        w = (fabs(pdot) / (dlen * gn)) * base;
                     } else {
                         w = base;
                     }

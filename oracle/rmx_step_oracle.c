@@ -38,10 +38,11 @@
  *     xi^{n+1} where it is labelled only at step n + 1.
  *
  * Everything is evaluated per cell, on the fly, in the order written here (no FMA
- * contraction: built with -ffp-contract=off).  Lengths are in cells: with lambda = dt/h
- * and hl = lambda / 2, (h/2 - dt u/2) dxi/dx = (1/2 - hl u) S for a per-cell slope S, and
- * dt/2 times a tangential term is hl times (mean transverse velocity) x (difference of
- * the transverse states).
+ * contraction: built with -ffp-contract=off).  Lengths are in cells: with the spacing
+ * Delta_a of axis a ("Variable arrangement"), lambda_a = dt / Delta_a and hl_a =
+ * lambda_a / 2, (Delta_a/2 - dt u_a/2) d xi / d x_a = (1/2 - hl_a u_a) S for a per-cell
+ * slope S along a, and dt/2 times the tangential term along t is hl_t times (mean
+ * transverse velocity) x (difference of the transverse states).
  */
 #include <math.h>
 #include <stdint.h>
@@ -103,7 +104,7 @@ typedef struct {
     const sbox* b;
     const double* xi;   /* xi^n, SoA [3][ncell]             */
     const double* u;    /* cell velocity u^n, SoA [3][ncell] */
-    double hl;          /* dt / (2 h)                        */
+    double hl[3];       /* dt / (2 Delta_a) per axis          */
 } sctx;
 
 /* Transverse face of cell x along axis t, between x (down) and x + e_t (up)
@@ -114,16 +115,17 @@ static void trans_face(const sctx* S, int64_t x, int t, int c, double* vadv, dou
     int64_t nc = S->b->ncell;
     const double* v = S->u + t * nc;   /* the t-component of the velocity */
     const double* q = S->xi + c * nc;
-    double vd = v[x] + (0.5 - S->hl * v[x]) * slope4(v + x, s);
-    double vu = v[x + s] - (0.5 + S->hl * v[x + s]) * slope4(v + x + s, s);
+    double hl = S->hl[t];
+    double vd = v[x] + (0.5 - hl * v[x]) * slope4(v + x, s);
+    double vu = v[x + s] - (0.5 + hl * v[x + s]) * slope4(v + x + s, s);
     double w = godunov_vel(vd, vu);
-    double qd = q[x] + (0.5 - S->hl * v[x]) * slope4(q + x, s);
-    double qu = q[x + s] - (0.5 + S->hl * v[x + s]) * slope4(q + x + s, s);
+    double qd = q[x] + (0.5 - hl * v[x]) * slope4(q + x, s);
+    double qu = q[x + s] - (0.5 + hl * v[x + s]) * slope4(q + x + s, s);
     *vadv = w;
     *xib = upwind(w, qd, qu);
 }
 
-/* Tangential term along axis t at cell m for component c, without the 1/h:
+/* Tangential term along axis t at cell m for component c, without the 1/Delta_t:
  * (mean of the two transverse advecting velocities) x (difference of the two states). */
 static double tangential(const sctx* S, int64_t m, int t, int c) {
     int64_t s = sstep(S->b, t);
@@ -141,11 +143,12 @@ static double normal_face(const sctx* S, int64_t x, int a, int c, double uface) 
     const double* ua = S->u + a * nc;
     const double* q = S->xi + c * nc;
     int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;   /* the other two axes, ascending */
-    double left = (q[x] + (0.5 - S->hl * ua[x]) * slope4(q + x, s)) -
-                  S->hl * (tangential(S, x, t1, c) + tangential(S, x, t2, c));
+    const double* hl = S->hl;
+    double left = (q[x] + (0.5 - hl[a] * ua[x]) * slope4(q + x, s)) -
+                  (hl[t1] * tangential(S, x, t1, c) + hl[t2] * tangential(S, x, t2, c));
     int64_t y = x + s;
-    double right = (q[y] - (0.5 + S->hl * ua[y]) * slope4(q + y, s)) -
-                   S->hl * (tangential(S, y, t1, c) + tangential(S, y, t2, c));
+    double right = (q[y] - (0.5 + hl[a] * ua[y]) * slope4(q + y, s)) -
+                   (hl[t1] * tangential(S, y, t1, c) + hl[t2] * tangential(S, y, t2, c));
     return upwind(uface, left, right);
 }
 
@@ -159,16 +162,16 @@ static double face_vel(const sbox* b, const double* const uf[3], int a, int64_t 
 }
 
 /* Predictor (step 5, eq. (dis_xi_adv) with eq. (adv_terms)):
- * xi^{n+1} = xi^n - lambda sum_a [ (U_{a-} + U_{a+}) / 2 ] (Xi_{a+} - Xi_{a-}).
+ * xi^{n+1} = xi^n - sum_a lambda_a [ (U_{a-} + U_{a+}) / 2 ] (Xi_{a+} - Xi_{a-}).
  * On the predicted cells (see the header) xi_next receives the value; on the rest of
  * the old band NaN; unmarked cells are left untouched.  Returns 1 if an interior cell
  * lies too close to a box face to be predicted, else 0. */
 int orc_predict(const int32_t ext[3], int32_t n_layers, const double* xi_n,
                 const int8_t* labels_n, const double* u, const double* ufx, const double* ufy,
-                const double* ufz, double lam, double* xi_next) {
+                const double* ufz, const double lam[3], double* xi_next) {
     sbox b = {ext[0], ext[1], ext[2], (int64_t)ext[0] * ext[1] * ext[2]};
     const double* uf[3] = {ufx, ufy, ufz};
-    sctx S = {&b, xi_n, u, 0.5 * lam};
+    sctx S = {&b, xi_n, u, {0.5 * lam[0], 0.5 * lam[1], 0.5 * lam[2]}};
     int trunc = 0;
     const int L = n_layers;
     for (int64_t k = 0; k < b.n2; ++k)
@@ -197,8 +200,8 @@ int orc_predict(const int32_t ext[3], int32_t n_layers, const double* xi_n,
                         double xp = normal_face(&S, c, a, q, up);
                         term[a] = (0.5 * (um + up)) * (xp - xm);
                     }
-                    double acc = (term[0] + term[1]) + term[2];
-                    xi_next[q * b.ncell + c] = xi_n[q * b.ncell + c] - lam * acc;
+                    double acc = (lam[0] * term[0] + lam[1] * term[1]) + lam[2] * term[2];
+                    xi_next[q * b.ncell + c] = xi_n[q * b.ncell + c] - acc;
                 }
             }
     return trunc;
