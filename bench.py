@@ -614,6 +614,11 @@ def make_workload(name):
         return synth.suspension()
     if name == "sphere32":
         return synth.sphere32()
+    if name == "periodic_box":
+        # the suspension's size, with unequal spacings and periodic x and z
+        return synth.periodic_box(seed=9, grid_n=(128, 128, 256),
+                                  spacing=(1.0 / 128, 1.0 / 96, 1.0 / 192), n_solids=40,
+                                  n_layers=4, semi_lo=0.04, semi_hi=0.1)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -736,6 +741,10 @@ def main():
         o2 = rmx.options(precision=other, flags=flags)
         f2, _ = run_form(ctx, w, dw, o2, args.steps, args.warmup)
         variants[[k for k, v in PRECISIONS.items() if v == other][0]] = f2
+        # layers by the 26-neighbour adjacency on the same fields (more band cells)
+        fa, _ = run_form(ctx, w, dw, rmx.options(precision=prec, flags=flags | rmx.FLAG_ADJ26),
+                         args.steps, args.warmup)
+        variants["adj26"] = fa
         del dw
         torch.cuda.empty_cache()
         ws = make_workload("suspension")
@@ -759,6 +768,16 @@ def main():
             f, _ = run_form(ctx, ws, dws, rmx.options(precision=pr), args.steps, args.warmup)
             variants[name] = f
         del dws
+        # method variants: periodic x and z with unequal spacings, then the same boxes and
+        # fields with equal spacings (the cost of the spacing-aware normal factor)
+        ws = make_workload("periodic_box")
+        for name, sp in (("periodic_box_unequal", ws.spacing), ("periodic_box_equal", None)):
+            ws.spacing = sp if sp is not None else (0.0, 0.0, 0.0)
+            dws = fields.upload(ws)
+            f, _ = run_form(ctx, ws, dws, rmx.options(), max(20, args.steps // 4), 5)
+            f["solids"] = len(ws.solids)
+            variants[name] = f
+            del dws
         torch.cuda.empty_cache()
         log("variants: time step")
         variants["step_cavity256"] = step_variant(ctx, args.steps, args.warmup)

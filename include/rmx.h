@@ -102,13 +102,26 @@ enum { RMX_FP64 = 0, RMX_FP32_ACCUM = 1 };
 #define RMX_PHASE_STEP_FACES 23   /* rmx_step: chosen xi states on the faces              */
 #define RMX_N_PHASES 24
 
-/* Grid: M x N x O cells; cell (i,j,k) has centre origin + (idx + 1/2) h (SI, "Variable
- * arrangement"; isotropic spacing as in the paper's runs).  The fit is invariant to h
- * and origin with isotropic spacing, which are validated only. */
+/* Grid: M x N x O cells (SI, "Variable arrangement").  Cell (i,j,k) has centre
+ * origin + (idx + 1/2) Delta with Delta_a = spacing[a], or h where spacing[a] is 0 (all
+ * zero: isotropic spacing h, as in the paper's runs).  The extrapolation sees only the
+ * ratios of the spacings: with unequal ones the normal factor of eq. (weight) is the
+ * cosine between the physical offset (dx Delta_x, dy Delta_y, dz Delta_z) and the
+ * physical gradient of phi0(xi); the fit itself stays in cell offsets (its value at the
+ * target does not depend on the scale of its columns).  rmx_step advects with
+ * dt / Delta_a per axis and rmx_solid_stress differentiates with Delta_a.
+ * periodic[a] != 0: the grid wraps along axis a (SI "Test cases": periodic boxes).  A
+ * solid's box then holds its unwrapped map: 0 <= lo[a] < n[a] and ext[a] <= n[a], and the
+ * box may run past n[a] (its local cell l lies on grid cell (lo + l) mod n).  No box face
+ * along a periodic axis is a wall, so a band that reaches one is truncated.  Zero-fill
+ * the struct before setting fields (reserved must be 0). */
 typedef struct {
     int32_t n[3];
     double h;
     double origin[3];
+    double spacing[3];
+    int32_t periodic[3];
+    int32_t reserved;
 } rmx_grid;
 
 /* phi0 in reference coordinates.  Body coordinates y = rot^T (xi - centre); rot is
@@ -301,8 +314,8 @@ int rmx_solid_stress(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids
  * stretch * eps of the surface (stretch >= 1 bounds physical over reference lengths;
  * 1 for an undeformed map), hence within D = stretch * eps + sqrt(3) h of an interior
  * cell centre, i.e. within ceil(D / h) layers of the 26-neighbour adjacency
- * (RMX_FLAG_ADJ26 in flags) or ceil(sqrt(3) D / h) face layers.  h: the largest grid
- * spacing.  RMX_E_ARG for non-positive or non-finite arguments or reach < 0;
+ * (RMX_FLAG_ADJ26 in flags) or ceil(sqrt(3) D / h) face layers.  h: the grid spacing
+ * (equal on the three axes).  RMX_E_ARG for non-positive or non-finite arguments or reach < 0;
  * RMX_E_LAYERS if the count exceeds RMX_MAX_LAYERS. */
 int rmx_layers_for_blur(double eps, double h, double stretch, int32_t reach, uint32_t flags,
                         int32_t* L);

@@ -29,14 +29,17 @@ struct BlurBatch {
     const BlurDev* solids;
     int32_t n_solids;
     int32_t grid[3];
+    int32_t periodic[3];         // 1: the grid wraps along the axis (n faces, not n + 1)
     int32_t tiles[3];            // tiles along x, y, z
     int32_t n_active;
     const int32_t* tile_start;   // [tiles + 1]: candidate solids of each tile (CSR)
     const int32_t* tile_list;    // ascending solid indices (boxes dilated by one cell)
     const int32_t* active;       // tiles with a candidate
-    double eps, h;
+    double eps;
+    double h[3];                 // spacing of each axis
     double* H;                   // [n2][n1][n0] or null
-    double* tau[3];              // [6][n2 + (a==2)][n1 + (a==1)][n0 + (a==0)] or null
+    double* tau[3];              // [6][n2 + f2][n1 + f1][n0 + f0] or null, f_b = 1 if b == a
+                                 // and axis a is walled, else 0
 };
 
 hipError_t launch_blur_heaviside(const BlurBatch& b, hipStream_t st);

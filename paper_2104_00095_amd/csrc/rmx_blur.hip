@@ -11,7 +11,10 @@
 //                     at the face's xi; the blend T (sum of weights S <= 1) or T / S.
 // A block takes one 8^3 tile of the grid; the solids that can touch it come from a list
 // built on the host (boxes dilated by one cell), visited in ascending order, so every sum
-// runs in the same order as in any other implementation.  Stencil gathers of FP64 fields
+// runs in the same order as in any other implementation.  Periodic axes (SI "Test
+// cases"): a box holds the solid's unwrapped map and may run past the grid's end; grid
+// cell g lies at box coordinate (g - lo) mod n there, and difference stencils are taken in
+// box coordinates, so they never join the two ends of a box that spans the axis.  Stencil gathers of FP64 fields
 // over the thin blur zones: bandwidth and latency work, no MFMA.
 #include "rmx_blur.h"
 #include "rmx_device.h"
@@ -39,12 +42,24 @@ __device__ __forceinline__ ShapeR blur_shape(const BlurDev& s) {
     return r;
 }
 
-// Local index of global cell (x, y, z) in the solid's box, or -1.
-__device__ __forceinline__ int64_t local_cell(const BlurDev& s, int x, int y, int z) {
-    const int lx = x - s.lo[0], ly = y - s.lo[1], lz = z - s.lo[2];
-    if (lx < 0 || lx >= s.ext[0] || ly < 0 || ly >= s.ext[1] || lz < 0 || lz >= s.ext[2])
+// Box coordinates l of grid cell g (0 <= g < n) in the solid's box; false outside it.
+__device__ __forceinline__ bool box_coords(const BlurBatch& b, const BlurDev& s, const int g[3],
+                                           int l[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int d = g[a] - s.lo[a];
+        if (b.periodic[a] && d < 0) d += b.grid[a];   // lo and g lie in [0, n)
+        if (d < 0 || d >= s.ext[a]) return false;
+        l[a] = d;
+    }
+    return true;
+}
+
+// Index of the cell at box coordinates (x, y, z), or -1 outside the box.
+__device__ __forceinline__ int64_t box_cell(const BlurDev& s, int x, int y, int z) {
+    if (x < 0 || x >= s.ext[0] || y < 0 || y >= s.ext[1] || z < 0 || z >= s.ext[2])
         return -1;
-    return ((int64_t)lz * s.ext[1] + ly) * s.ext[0] + lx;
+    return ((int64_t)z * s.ext[1] + y) * s.ext[0] + x;
 }
 
 __device__ __forceinline__ bool covered(const BlurDev& s, int64_t c) {
@@ -82,8 +97,9 @@ __global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
         double acc = 0.0;
         for (int e = e0; e < e1; ++e) {
             const BlurDev& s = b.solids[b.tile_list[e]];
-            const int64_t c = local_cell(s, g[0], g[1], g[2]);
-            if (c < 0) continue;
+            int l[3];
+            if (!box_coords(b, s, g, l)) continue;
+            const int64_t c = box_cell(s, l[0], l[1], l[2]);
             any = true;
             if (!covered(s, c)) continue;
             double v[3];
@@ -101,28 +117,29 @@ __global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
 // ------------------------------------------------------------------------------------
 // Solid stress at faces.
 // ------------------------------------------------------------------------------------
-// Neo-Hookean stress of solid s at the face between P = f - e_a and Q = f, and its weight;
-// false (no contribution) unless every stencil cell lies in the box and is labelled.
-__device__ bool face_stress(const BlurDev& s, const int f[3], int a, double h, double eps,
-                            double tau[6], double* w) {
+// Neo-Hookean stress of solid s at the face between the cells at box coordinates
+// P = f - e_a and Q = f, and its weight; false (no contribution) unless every stencil
+// cell lies in the box and is labelled.  h: the spacings.
+__device__ bool face_stress(const BlurDev& s, const int f[3], int a, const double* h,
+                            double eps, double tau[6], double* w) {
     int P[3] = {f[0], f[1], f[2]};
     P[a] -= 1;
-    const int64_t cp = local_cell(s, P[0], P[1], P[2]), cq = local_cell(s, f[0], f[1], f[2]);
+    const int64_t cp = box_cell(s, P[0], P[1], P[2]), cq = box_cell(s, f[0], f[1], f[2]);
     if (cp < 0 || cq < 0 || !covered(s, cp) || !covered(s, cq)) return false;
     double xp[3], xq[3];
     xi_at(s, cp, xp);
     xi_at(s, cq, xq);
     double J[3][3];   // J[q][b] = d xi_q / d x_b
 #pragma unroll
-    for (int q = 0; q < 3; ++q) J[q][a] = (xq[q] - xp[q]) / h;
+    for (int q = 0; q < 3; ++q) J[q][a] = (xq[q] - xp[q]) / h[a];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         if (t == a) continue;
         const int dx = t == 0, dy = t == 1, dz = t == 2;
-        const int64_t c1 = local_cell(s, P[0] - dx, P[1] - dy, P[2] - dz);
-        const int64_t c2 = local_cell(s, P[0] + dx, P[1] + dy, P[2] + dz);
-        const int64_t c3 = local_cell(s, f[0] - dx, f[1] - dy, f[2] - dz);
-        const int64_t c4 = local_cell(s, f[0] + dx, f[1] + dy, f[2] + dz);
+        const int64_t c1 = box_cell(s, P[0] - dx, P[1] - dy, P[2] - dz);
+        const int64_t c2 = box_cell(s, P[0] + dx, P[1] + dy, P[2] + dz);
+        const int64_t c3 = box_cell(s, f[0] - dx, f[1] - dy, f[2] - dz);
+        const int64_t c4 = box_cell(s, f[0] + dx, f[1] + dy, f[2] + dz);
         if (c1 < 0 || c2 < 0 || c3 < 0 || c4 < 0) return false;
         if (!covered(s, c1) || !covered(s, c2) || !covered(s, c3) || !covered(s, c4))
             return false;
@@ -132,7 +149,7 @@ __device__ bool face_stress(const BlurDev& s, const int f[3], int a, double h, d
         xi_at(s, c3, v3);
         xi_at(s, c4, v4);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) J[q][t] = ((v2[q] - v1[q]) + (v4[q] - v3[q])) / (4.0 * h);
+        for (int q = 0; q < 3; ++q) J[q][t] = ((v2[q] - v1[q]) + (v4[q] - v3[q])) / (4.0 * h[t]);
     }
     // F = J^{-1} by cofactors
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
@@ -169,27 +186,36 @@ __device__ bool face_stress(const BlurDev& s, const int f[3], int a, double h, d
     return true;
 }
 
+// The face f along a (between grid cells f - e_a and f; f[a] in [0, n), or n on a walled
+// axis).
 __device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3], int a) {
     int P[3] = {f[0], f[1], f[2]};
-    P[a] -= 1;
+    P[a] -= 1;   // the face's low cell (wrapped on a periodic axis)
+    if (b.periodic[a] && P[a] < 0) P[a] += b.grid[a];
     bool any = false;
     double S = 0.0;
     double T[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int e = e0; e < e1; ++e) {
         const BlurDev& s = b.solids[b.tile_list[e]];
-        const bool inq = f[a] < b.grid[a] && local_cell(s, f[0], f[1], f[2]) >= 0;
-        const bool inp = P[a] >= 0 && local_cell(s, P[0], P[1], P[2]) >= 0;
+        int lq[3], lp[3];
+        const bool inq = f[a] < b.grid[a] && box_coords(b, s, f, lq);
+        const bool inp = P[a] >= 0 && box_coords(b, s, P, lp);
         if (!inq && !inp) continue;
         any = true;
+        // the face seen from the box: Q's box coordinates, or P's one step up along a
+        int q[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[c] = inq ? lq[c] : lp[c] + (c == a && !inq);
         double t6[6], w;
-        if (!face_stress(s, f, a, b.h, b.eps, t6, &w)) continue;
+        if (!face_stress(s, q, a, b.h, b.eps, t6, &w)) continue;
         S += w;
 #pragma unroll
         for (int c = 0; c < 6; ++c) T[c] += w * t6[c];
     }
     if (!any) return;
-    const int64_t n0 = b.grid[0] + (a == 0), n1 = b.grid[1] + (a == 1),
-                  n2 = b.grid[2] + (a == 2);
+    const int64_t n0 = b.grid[0] + (a == 0 && !b.periodic[0]),
+                  n1 = b.grid[1] + (a == 1 && !b.periodic[1]),
+                  n2 = b.grid[2] + (a == 2 && !b.periodic[2]);
     const int64_t nf = n0 * n1 * n2;
     const int64_t fi = ((int64_t)f[2] * n1 + f[1]) * n0 + f[0];
     double* out = b.tau[a];
@@ -206,9 +232,10 @@ __global__ __launch_bounds__(256) void k_blur_stress(BlurBatch b) {
         if (g[0] >= b.grid[0] || g[1] >= b.grid[1] || g[2] >= b.grid[2]) continue;
 #pragma unroll 1
         for (int a = 0; a < 3; ++a) {
-            // a cell owns its low face along a; the last cell also the face beyond it
+            // a cell owns its low face along a; on a walled axis the last cell also the
+            // face beyond it
             blend_face(b, e0, e1, g, a);
-            if (g[a] == b.grid[a] - 1) {
+            if (g[a] == b.grid[a] - 1 && !b.periodic[a]) {
                 int f[3] = {g[0], g[1], g[2]};
                 f[a] += 1;
                 blend_face(b, e0, e1, f, a);

@@ -544,8 +544,10 @@ int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t
     sg->pending = true;
     StepBatch sb{};
     sb.steps = static_cast<const StepDev*>(c->step_ws);
-    sb.lam = dt / grid->h;
-    sb.hl = 0.5 * sb.lam;
+    for (int a = 0; a < 3; ++a) {
+        sb.lam[a] = dt / (grid->spacing[a] > 0.0 ? grid->spacing[a] : grid->h);
+        sb.hl[a] = 0.5 * sb.lam[a];
+    }
     rc = launch_planned(c, p, n_solids, opt, st, false, 0, sync, c->ws, c->ws_size, false, &sb);
     if (rc != RMX_OK) return rc;
     if (!sync) return RMX_OK;
@@ -573,28 +575,37 @@ static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     }
     if (nt > (int64_t)1 << 30) return RMX_E_ARG;
     std::vector<int32_t> count(nt + 1, 0);
-    auto tile_range = [&](const rmx_solid& s, int a, int64_t* t0, int64_t* t1) {
-        const int64_t lo = std::max<int64_t>(s.lo[a] - 1, 0);
-        const int64_t hi = std::min<int64_t>(s.lo[a] + s.ext[a] + 1, grid->n[a]);   // excl.
-        *t0 = lo / TS[a];
-        *t1 = (hi - 1) / TS[a];
+    // The tiles along axis a that the solid's box, dilated by one cell, touches: one run
+    // on a walled axis; on a periodic one the cells wrap, and each tile is listed once.
+    auto axis_tiles = [&](const rmx_solid& s, int a, std::vector<int64_t>* out) {
+        out->clear();
+        const int64_t n = grid->n[a];
+        if (!grid->periodic[a]) {
+            const int64_t lo = std::max<int64_t>(s.lo[a] - 1, 0);
+            const int64_t hi = std::min<int64_t>(s.lo[a] + s.ext[a] + 1, n);   // excl.
+            for (int64_t t = lo / TS[a]; t <= (hi - 1) / TS[a]; ++t) out->push_back(t);
+            return;
+        }
+        std::vector<char> hit(T[a], 0);
+        const int64_t span = std::min<int64_t>(s.ext[a] + 2, n);
+        for (int64_t q = 0; q < span; ++q) hit[((s.lo[a] - 1 + q + n) % n) / TS[a]] = 1;
+        for (int64_t t = 0; t < T[a]; ++t)
+            if (hit[t]) out->push_back(t);
     };
+    std::vector<int64_t> ax[3];
     for (int m = 0; m < n; ++m) {
-        int64_t r[3][2];
-        for (int a = 0; a < 3; ++a) tile_range(solids[m], a, &r[a][0], &r[a][1]);
-        for (int64_t z = r[2][0]; z <= r[2][1]; ++z)
-            for (int64_t y = r[1][0]; y <= r[1][1]; ++y)
-                for (int64_t x = r[0][0]; x <= r[0][1]; ++x) ++count[(z * T[1] + y) * T[0] + x + 1];
+        for (int a = 0; a < 3; ++a) axis_tiles(solids[m], a, &ax[a]);
+        for (int64_t z : ax[2])
+            for (int64_t y : ax[1])
+                for (int64_t x : ax[0]) ++count[(z * T[1] + y) * T[0] + x + 1];
     }
     for (int64_t t = 0; t < nt; ++t) count[t + 1] += count[t];
     std::vector<int32_t> list(count[nt]), fill(count.begin(), count.end() - 1), active;
     for (int m = 0; m < n; ++m) {   // ascending solid index in every tile
-        int64_t r[3][2];
-        for (int a = 0; a < 3; ++a) tile_range(solids[m], a, &r[a][0], &r[a][1]);
-        for (int64_t z = r[2][0]; z <= r[2][1]; ++z)
-            for (int64_t y = r[1][0]; y <= r[1][1]; ++y)
-                for (int64_t x = r[0][0]; x <= r[0][1]; ++x)
-                    list[fill[(z * T[1] + y) * T[0] + x]++] = m;
+        for (int a = 0; a < 3; ++a) axis_tiles(solids[m], a, &ax[a]);
+        for (int64_t z : ax[2])
+            for (int64_t y : ax[1])
+                for (int64_t x : ax[0]) list[fill[(z * T[1] + y) * T[0] + x]++] = m;
     }
     for (int64_t t = 0; t < nt; ++t)
         if (count[t + 1] > count[t]) active.push_back((int32_t)t);
@@ -659,14 +670,15 @@ static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     b->n_solids = n;
     for (int a = 0; a < 3; ++a) {
         b->grid[a] = grid->n[a];
+        b->periodic[a] = grid->periodic[a] ? 1 : 0;
         b->tiles[a] = (int32_t)T[a];
+        b->h[a] = grid->spacing[a] > 0.0 ? grid->spacing[a] : grid->h;
     }
     b->n_active = (int32_t)active.size();
     b->tile_start = reinterpret_cast<const int32_t*>(base + o_start);
     b->tile_list = reinterpret_cast<const int32_t*>(base + o_list);
     b->active = reinterpret_cast<const int32_t*>(base + o_active);
     b->eps = eps;
-    b->h = grid->h;
     return RMX_OK;
 }
 

@@ -492,14 +492,17 @@ struct CellCtx {
     const int8_t* __restrict__ labels;
     int32_t anchor;               // linear index of the anchor datum
     double a0, a1, a2;            // its xi
-    double g0, g1, g2, rgn;       // normal (unnormalised) and 1/|g|
+    double g0, g1, g2, rgn;       // normal (unnormalised) and 1/|g / rho|
+    double r0, r1, r2;            // spacing ratios (rho) when aniso
+    int aniso;
 };
 
 // Accumulate, from global memory, the moments of the eligible data within Chebyshev
 // radius r (used for radii beyond the staged halo).  The (2r+1)^2 rows (dy, dz) of the box
 // are dealt to the NL lanes of the cell.  Eq. (weight): w = 2^-(|dx|+|dy|+|dz|), times
-// the cosine between x_e - x_d = -d h and the normal when use_normal; data with
-// (dx gx + dy gy) + dz gz >= 0 (that exact expression, no contraction) get weight 0.
+// the cosine between x_e - x_d = -(dx rho_x, dy rho_y, dz rho_z) h and the normal when
+// use_normal; data with (dx gx + dy gy) + dz gz >= 0 (that exact expression, no
+// contraction) get weight 0.
 template <int NL, typename T>
 __device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_normal, int lq,
                                         Moments<T>& acc) {
@@ -521,7 +524,10 @@ __device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_no
                 const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
                 const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
                 if (!(dot < 0.0)) continue;
-                ww = (-dot * c_rlen[dx * dx + dy * dy + dz * dz] * cx.rgn) * ww;
+                const double rl =
+                    cx.aniso ? 1.0 / norm3(fx * cx.r0, fy * cx.r1, fz * cx.r2)
+                             : c_rlen[dx * dx + dy * dy + dz * dz];
+                ww = (-dot * rl * cx.rgn) * ww;
             }
             const T tw = (T)ww;
             const T fx = (T)dx, fy = (T)dy, fz = (T)dz;

@@ -59,12 +59,14 @@ struct DevSolid {
     int32_t ntx;             // tiles along x (tile_w words each)
     int32_t chunk_base;      // first classification chunk of the solid
     int32_t nbx, nby, nbz;   // 8^3 bricks along x, y, z
-    int32_t pad0;
+    int32_t aniso;           // unequal spacings: the normal factor takes rho into account
     int64_t ncell;
     int64_t word_base;       // first global mask word
     double centre[3];
     double semi[3];
     double rot[9];
+    double rho[3];           // spacing of each axis over the smallest (1, 1, 1 when equal)
+    double irho[3];          // 1 / rho
     double* xi;
     const double* xi_normal; // field the normals come from (xi if none given)
     double* normals;         // [3][ncell]: unnormalised normals of cells of layers <= nl

@@ -534,6 +534,18 @@ constexpr uint8_t kStNone = 0;   // carries no data for layer l (outside the box
 constexpr uint8_t kStData = 1;   // a datum for layer l: label in [0, l)
 constexpr uint8_t kStTarget = 2; // a cell of layer l
 
+// Reciprocal lengths 1/|x'| (in units of the smallest spacing) of the radius-2 offsets:
+// entry (|dx| * 3 + |dy|) * 3 + |dz| is 1 / |(dx rho_x, dy rho_y, dz rho_z)| (eq. (weight)
+// with the spacings of the axes); d == nullptr or equal spacings: 1 / |d|.
+constexpr int kRlen = 27;
+
+__device__ __forceinline__ double rlen_entry(const DevSolid* d, int e) {
+    const int ax = e / 9, ay = (e / 3) % 3, az = e % 3;
+    if (e == 0) return 0.0;
+    if (d == nullptr || !d->aniso) return c_rlen[ax * ax + ay * ay + az * az];
+    return 1.0 / norm3((double)ax * d->rho[0], (double)ay * d->rho[1], (double)az * d->rho[2]);
+}
+
 // Moments of the eligible data of radius r_s = 2 around staged cell idx.  The staged
 // values are xi - A for the brick's anchor A (0 where the cell carries no data), so a
 // datum enters as w * v with no selection of the value.  A lane takes whole rows
@@ -564,7 +576,7 @@ __device__ __forceinline__ void gather_lds(const T* __restrict__ sx,
             v1[u] = sx[kBrickCells + q];
             v2[u] = sx[2 * kBrickCells + q];
         }
-        const int rowd2 = dy * dy + dz * dz;
+        const int rowi = abs(dy) * 3 + abs(dz);   // s_rlen entry of (0, dy, dz)
         const double rowbase = ldexp(1.0, -(abs(dy) + abs(dz)));   // 2^-(|dy|+|dz|), exact
         double ry = 0.0, rz = 0.0;
         if (NRM) {
@@ -584,7 +596,7 @@ __device__ __forceinline__ void gather_lds(const T* __restrict__ sx,
 #pragma clang fp contract(off)
                 const double dot = ((double)dx * g0 + ry) + rz;
                 e = e && (dot < 0.0);
-                ww = (-dot * s_rlen[dx * dx + rowd2] * rgn) * ww;
+                ww = (-dot * s_rlen[abs(dx) * 9 + rowi] * rgn) * ww;
             }
             const T w = e ? (T)ww : T(0);
             s0 += w;
@@ -674,8 +686,14 @@ __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
         cx.g1 = gn1;
         cx.g2 = gn2;
         cx.rgn = 0.0;
+        cx.r0 = d->rho[0];
+        cx.r1 = d->rho[1];
+        cx.r2 = d->rho[2];
+        cx.aniso = d->aniso;
         const bool has_normal = nrm && (gn0 != 0.0 || gn1 != 0.0 || gn2 != 0.0);
-        if (has_normal) cx.rgn = 1.0 / norm3(gn0, gn1, gn2);
+        // the physical gradient is g / rho up to a common factor (1 / h)
+        if (has_normal)
+            cx.rgn = 1.0 / norm3(gn0 * d->irho[0], gn1 * d->irho[1], gn2 * d->irho[2]);
         const bool no_normal = nrm && !has_normal;
 
         // Passes: radii r_s..r_max with eq. (weight), then F1 (normal factor dropped) at
@@ -735,10 +753,11 @@ __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
 }
 
 template <typename T>
-__device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
-                                             unsigned long long* st, int l, int bx, int by,
-                                             int bz, unsigned char* lds, int* s_wave,
-                                             double* s_anchor, const double* s_rlen) {
+__device__ __forceinline__ void extrap_brick(const Batch& b, int s, unsigned long long* st,
+                                             int l, int bx, int by, int bz,
+                                             unsigned char* lds, int* s_wave,
+                                             double* s_anchor, double* s_rlen, int& tab) {
+    const DevSolid* d = b.solids + s;
     T* sx = reinterpret_cast<T*>(lds);
     uint8_t* ss = reinterpret_cast<uint8_t*>(lds + kBrickCells * 3 * sizeof(T));
     uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * (3 * sizeof(T) + 1));
@@ -801,6 +820,13 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, const DevSolid* d,
     }
     if (lane == 0) s_wave[wid] = qf;
     __syncthreads();
+    // the reciprocal-length table of the solid's spacings, when another one is loaded
+    // (uniform: the table's owner is the same in every thread)
+    const int want = d->aniso ? s : -1;
+    if (want != tab) {
+        if (tid < kRlen) s_rlen[tid] = rlen_entry(d, tid);
+        tab = want;
+    }
     const int qa = min(min(s_wave[0], s_wave[1]), min(s_wave[2], s_wave[3]));
     if (qa != 0x7fffffff && (qa & 255) == tid) {
 #pragma unroll
@@ -1129,8 +1155,9 @@ __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
     unsigned char* lds = reinterpret_cast<unsigned char*>(lds_d);
     __shared__ int s_wave[4];
     __shared__ double s_anchor[3];
-    __shared__ double s_rlen[13];   // 1/|d| for |d|^2 = 0..12 (radius 2)
-    if (threadIdx.x < 13) s_rlen[threadIdx.x] = c_rlen[threadIdx.x];
+    __shared__ double s_rlen[kRlen];
+    if (threadIdx.x < kRlen) s_rlen[threadIdx.x] = rlen_entry(nullptr, threadIdx.x);
+    int tab = -1;   // the loaded table: equal spacings
     const unsigned long long* dl = b.dlist + (int64_t)(l - 1) * b.dlist_cap;
     const int count = uniform_int((int)min((int64_t)b.dcount[l - 1], b.dlist_cap));
     __syncthreads();   // s_rlen
@@ -1143,7 +1170,7 @@ __global__ __launch_bounds__(256, 3) void k_extrap(Batch b, int l) {
         const int bz = uniform_int((int)((pk >> 20) & 1023ull));
         unsigned long long* st = b.stats + (int64_t)s * kStatWords;
         if (st[ST_FLAGS] & FLAG_TRUNCATED) continue;   // uniform: whole block skips
-        extrap_brick<T>(b, b.solids + s, st, l, bx, by, bz, lds, s_wave, s_anchor, s_rlen);
+        extrap_brick<T>(b, s, st, l, bx, by, bz, lds, s_wave, s_anchor, s_rlen, tab);
     }
 }
 
@@ -1184,12 +1211,12 @@ struct BandLds {
     int* s_wave;           // [4]
     int* s_ctl;            // [4]: ticket, wait result
     double* s_anchor;      // [3]
-    double* s_rlen;        // [13]
+    double* s_rlen;        // [kRlen]
     unsigned long long* s_acc;  // [kLT]
 };
 
 __host__ __device__ constexpr size_t band_small_bytes() {
-    return sizeof(int) * (kMaxLayers * kBuckets + 1 + 4 + 4) + sizeof(double) * (3 + 13) +
+    return sizeof(int) * (kMaxLayers * kBuckets + 1 + 4 + 4) + sizeof(double) * (3 + kRlen) +
            sizeof(unsigned long long) * kLT + 64;
 }
 
@@ -1204,7 +1231,7 @@ __device__ __forceinline__ BandLds band_lds(unsigned char* lds, size_t work_byte
     unsigned char* sm = lds + ((work_bytes + 15) & ~size_t(15));
     L.s_anchor = reinterpret_cast<double*>(sm);
     L.s_rlen = L.s_anchor + 3;
-    L.s_acc = reinterpret_cast<unsigned long long*>(L.s_rlen + 13);
+    L.s_acc = reinterpret_cast<unsigned long long*>(L.s_rlen + kRlen);
     L.s_pref = reinterpret_cast<int*>(L.s_acc + kLT);
     L.s_wave = L.s_pref + kMaxLayers * kBuckets + 1;
     L.s_ctl = L.s_wave + 4;
@@ -1268,7 +1295,8 @@ __global__ __launch_bounds__(256, 3) void k_band(Batch b, int work_bytes) {
     const BandLds L = band_lds(reinterpret_cast<unsigned char*>(lds_d), (size_t)work_bytes);
     BandCtl* ctl = b.band;
     const int tid = threadIdx.x;
-    if (tid < 13) L.s_rlen[tid] = c_rlen[tid];
+    if (tid < kRlen) L.s_rlen[tid] = rlen_entry(nullptr, tid);
+    int tab = -1;   // the loaded reciprocal-length table: equal spacings
     solid_counts(b, L.s_acc);
     list_prefix(b, 1, b.Lmax, L.s_pref, L.s_wave);   // (ends with a barrier)
     const int nl = b.normal_layers;
@@ -1342,8 +1370,8 @@ __global__ __launch_bounds__(256, 3) void k_band(Batch b, int work_bytes) {
                     normal_brick(b.solids + s, st, layer, bx, by, bz, L.s_phi, L.s_flag, L.s_lab,
                                  L.s_list, L.s_wave);
                 else
-                    extrap_brick<T>(b, b.solids + s, st, p, bx, by, bz, L.work, L.s_wave,
-                                    L.s_anchor, L.s_rlen);
+                    extrap_brick<T>(b, s, st, p, bx, by, bz, L.work, L.s_wave, L.s_anchor,
+                                    L.s_rlen, tab);
             }
         }
         ++pend;   // (a skipped item counts too)

@@ -62,10 +62,18 @@ int validate_solid(const rmx_grid* grid, const rmx_solid* sp, bool need_fields) 
         if (grid->n[a] <= 0) return RMX_E_ARG;
     if (!(grid->h > 0.0) || !std::isfinite(grid->h) || !finite_all(grid->origin, 3))
         return RMX_E_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (!(grid->spacing[a] >= 0.0) || !std::isfinite(grid->spacing[a])) return RMX_E_ARG;
+    if (grid->reserved != 0) return RMX_E_ARG;
     const rmx_solid& s = *sp;
     for (int a = 0; a < 3; ++a) {
         if (s.ext[a] <= 0 || s.lo[a] < 0 || s.ext[a] > kMaxExtent) return RMX_E_BOX;
-        if ((int64_t)s.lo[a] + s.ext[a] > grid->n[a]) return RMX_E_BOX;
+        if (grid->periodic[a]) {
+            // the box starts on the grid and may wrap, but covers no cell twice
+            if (s.lo[a] >= grid->n[a] || s.ext[a] > grid->n[a]) return RMX_E_BOX;
+        } else if ((int64_t)s.lo[a] + s.ext[a] > grid->n[a]) {
+            return RMX_E_BOX;
+        }
     }
     const int64_t ncell = (int64_t)s.ext[0] * s.ext[1] * s.ext[2];
     if (ncell > (int64_t)0x7fffffff - 64) return RMX_E_BOX;
@@ -123,9 +131,20 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
         d.tz = (d.n2 + kTileK - 1) / kTileK;
         d.L = s.n_layers;
         d.kind = s.phi0.kind;
+        for (int a = 0; a < 3; ++a) {   // a periodic axis has no walls
+            d.wall_lo[a] = !g->periodic[a] && s.lo[a] == 0;
+            d.wall_hi[a] = !g->periodic[a] && s.lo[a] + s.ext[a] == g->n[a];
+        }
+        // spacing ratios for the normal factor of eq. (weight)
+        double sp[3], smin = 0.0;
         for (int a = 0; a < 3; ++a) {
-            d.wall_lo[a] = s.lo[a] == 0;
-            d.wall_hi[a] = s.lo[a] + s.ext[a] == g->n[a];
+            sp[a] = g->spacing[a] > 0.0 ? g->spacing[a] : g->h;
+            smin = a == 0 ? sp[0] : std::min(smin, sp[a]);
+        }
+        d.aniso = !(sp[0] == sp[1] && sp[1] == sp[2]);
+        for (int a = 0; a < 3; ++a) {
+            d.rho[a] = d.aniso ? sp[a] / smin : 1.0;
+            d.irho[a] = d.aniso ? 1.0 / d.rho[a] : 1.0;
         }
         d.ncell = (int64_t)d.n0 * d.n1 * d.n2;
         d.word_base = words;

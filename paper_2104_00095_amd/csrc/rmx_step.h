@@ -29,8 +29,8 @@ struct StepBatch {
     unsigned long long* stats;
     int32_t* bcount;
     BandCtl* band;
-    double lam;               // dt / h
-    double hl;                // dt / (2 h)
+    double lam[3];            // dt / Delta_a
+    double hl[3];             // dt / (2 Delta_a)
 };
 
 // Transverse face states and advecting velocities (zeroes the call's statistics and

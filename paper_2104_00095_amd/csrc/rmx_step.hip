@@ -123,7 +123,6 @@ __device__ __forceinline__ int64_t wave_segment() {
 // Transverse faces.  Block 0 also zeroes the call's statistics and brick counters.
 // ------------------------------------------------------------------------------------
 __device__ void trans_segment(const StepBatch& b, int64_t w) {
-    const double hl = b.hl;
     {
         const Seg g = segment(b, w);
         const DevSolid* d = b.solids + g.s;
@@ -143,6 +142,7 @@ __device__ void trans_segment(const StepBatch& b, int64_t w) {
             if (ct < 2 || ct > nt - 4) continue;
             const int64_t s = axis_stride(d, t);
             const int64_t x = g.c, y = g.c + s;
+            const double hl = b.hl[t];
             const double* v = sd->u + t * nc;
             const double vx = ld(v, x), vy = ld(v, y);
             const double vd = vx + (0.5 - hl * vx) * slope_at(v, x, s);
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_step_trans(StepBatch b) {
     if (w < b.total_words) trans_segment(b, w);
 }
 
-// Tangential term along axis t at cell m, component q, without the 1/h: (mean of the
+// Tangential term along axis t at cell m, component q, without the 1/Delta_t: (mean of the
 // transverse advecting velocities on the cell's two t-faces) x (difference of the chosen
 // states).
 __device__ __forceinline__ double tangential(const StepDev* sd, const DevSolid* d, int64_t m,
@@ -186,8 +186,8 @@ __device__ __forceinline__ double tangential(const StepDev* sd, const DevSolid* 
 }
 
 // Expansion of component q from cell x to its +a face (side = 0, the left state of that
-// face) or to its -a face (side = 1, the right state of that face), with the tangential
-// terms of the other two axes.
+// face) or to its -a face (side = 1, the right state of that face); hl = dt / (2 Delta_a),
+// tang = the tangential terms of the other two axes, each times its dt / (2 Delta_t).
 __device__ __forceinline__ double side_state(const StepDev* sd, const DevSolid* d, double hl,
                                              int64_t x, int a, int q, int side, double tang) {
     const int64_t nc = d->ncell;
@@ -195,8 +195,8 @@ __device__ __forceinline__ double side_state(const StepDev* sd, const DevSolid* 
     const double* ua = sd->u + a * nc;
     const double* p = sd->xi_n + q * nc;
     const double sl = slope_at(p, x, s);
-    if (side == 0) return (ld(p, x) + (0.5 - hl * ld(ua, x)) * sl) - hl * tang;
-    return (ld(p, x) - (0.5 + hl * ld(ua, x)) * sl) - hl * tang;
+    if (side == 0) return (ld(p, x) + (0.5 - hl * ld(ua, x)) * sl) - tang;
+    return (ld(p, x) - (0.5 + hl * ld(ua, x)) * sl) - tang;
 }
 
 // Face-normal velocity on the low face of cell (i, j, k) along axis a.
@@ -223,7 +223,6 @@ __device__ __forceinline__ bool predicted(const StepDev* sd, const DevSolid* d, 
 // faces[(a * 2 + side) * 3 + q][cell].
 // ------------------------------------------------------------------------------------
 __device__ void faces_segment(const StepBatch& b, int64_t w) {
-    const double hl = b.hl;
     const Seg g = segment(b, w);
     const DevSolid* d = b.solids + g.s;
     const StepDev* sd = b.steps + g.s;
@@ -243,9 +242,11 @@ __device__ void faces_segment(const StepBatch& b, int64_t w) {
         const bool lo = self || predicted(sd, d, g.i - (a == 0), g.j - (a == 1), g.k - (a == 2));
         if (!hi && !lo) continue;
         const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+        const double hl = b.hl[a], h1 = b.hl[t1], h2 = b.hl[t2];
 #pragma unroll 1
         for (int q = 0; q < 3; ++q) {
-            const double tang = tangential(sd, d, g.c, t1, q) + tangential(sd, d, g.c, t2, q);
+            const double tang =
+                h1 * tangential(sd, d, g.c, t1, q) + h2 * tangential(sd, d, g.c, t2, q);
             if (hi)
                 sd->faces[(int64_t)((a * 2 + 0) * 3 + q) * nc + g.c] =
                     side_state(sd, d, hl, g.c, a, q, 0, tang);
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(256) void k_step_faces(StepBatch b) {
 // Predictor and the interior mask of step n + 1.
 // ------------------------------------------------------------------------------------
 __device__ void predict_segment(const StepBatch& b, int64_t w) {
-    const double lam = b.lam;
+    const double l0 = b.lam[0], l1 = b.lam[1], l2 = b.lam[2];
     const int lane = threadIdx.x & 63;
     const Seg g = segment(b, w);
     const DevSolid* d = b.solids + g.s;
@@ -303,8 +304,8 @@ __device__ void predict_segment(const StepBatch& b, int64_t w) {
                     const double xp = upwind(up[a], ld(fl, g.c), ld(fr, g.c + s));
                     term[a] = (0.5 * (um[a] + up[a])) * (xp - xm);
                 }
-                const double acc = (term[0] + term[1]) + term[2];
-                nv[q] = ld(sd->xi_n, q * nc + g.c) - lam * acc;
+                const double acc = (l0 * term[0] + l1 * term[1]) + l2 * term[2];
+                nv[q] = ld(sd->xi_n, q * nc + g.c) - acc;
                 d->xi[q * nc + g.c] = nv[q];
             }
             inside = interior(load_shape(d), nv[0], nv[1], nv[2]);

@@ -34,7 +34,8 @@ class DeviceWorkload:
 
 def upload(w, device="cuda:0", decisions=False, keep_input=True, xi_normal=None):
     import torch
-    g = rmx.grid(w.grid_n, w.h, w.origin)
+    g = rmx.grid(w.grid_n, w.h, w.origin, spacing=getattr(w, "spacing", None),
+                 periodic=getattr(w, "periodic", None))
     solids, xis, labs, decs, ins = [], [], [], [], []
     for idx, s in enumerate(w.solids):
         xi = torch.from_numpy(np.ascontiguousarray(s.xi)).to(device)

@@ -39,7 +39,8 @@ EXPORTS = [
 
 class Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double),
-                ("origin", ctypes.c_double * 3)]
+                ("origin", ctypes.c_double * 3), ("spacing", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
 
 
 class Shape(ctypes.Structure):
@@ -160,11 +161,15 @@ def options(r_s=2, r_max=4, normal_layers=2, precision=FP64, flags=0) -> Options
     return o
 
 
-def grid(n, h, origin=(0.0, 0.0, 0.0)) -> Grid:
+def grid(n, h, origin=(0.0, 0.0, 0.0), spacing=None, periodic=None) -> Grid:
+    """spacing: per-axis cell sizes (0 or None: h); periodic: axes along which the grid
+    wraps."""
     g = Grid()
     g.n[:] = [int(v) for v in n]
     g.h = float(h)
     g.origin[:] = [float(v) for v in origin]
+    g.spacing[:] = [float(v) for v in (spacing or (0.0, 0.0, 0.0))]
+    g.periodic[:] = [1 if v else 0 for v in (periodic or (0, 0, 0))]
     return g
 
 
@@ -263,6 +268,15 @@ def step_solid(lo, ext, shp: Shape, n_layers, xi_n, labels_n, u, uf, xi_next, la
     s.decisions = _ptr(decisions)
     s._keep = (xi_n, labels_n, u, tuple(uf), xi_next, labels_next, xi_half, decisions)
     return s
+
+
+def _check_size(t, n, what):
+    """A float64 buffer of at least n elements (None passes: the entry point decides)."""
+    if t is None or not hasattr(t, "numel"):
+        return
+    if t.numel() < n or getattr(t, "element_size", lambda: 8)() != 8:
+        raise ValueError(f"{what}: need {n} float64 elements, got {t.numel()} of "
+                         f"{t.element_size()} bytes")
 
 
 def _stream_handle(stream):
@@ -364,6 +378,11 @@ class Context:
              stream=None):
         """Modified Heaviside on the grid (rmx_blur): H cuda float64 [n2, n1, n0] (cells
         inside some box are written), phis: per solid a cuda float64 [e2, e1, e0] or None."""
+        n0, n1, n2 = g.n
+        _check_size(H, n0 * n1 * n2, "H")
+        for i, p in enumerate(phis or []):
+            e = solids[i].ext
+            _check_size(p, e[0] * e[1] * e[2], f"phis[{i}]")
         arr = (Solid * len(solids))(*solids)
         pp = None
         if phis is not None:
@@ -376,8 +395,13 @@ class Context:
     def solid_stress(self, g: Grid, solids: Sequence[Solid], eps: float, G, taus,
                      stream=None):
         """Blended neo-Hookean solid stress on the faces (rmx_solid_stress): taus = three
-        cuda float64 arrays [6, n2 + (a==2), n1 + (a==1), n0 + (a==0)]; G: one shear
-        modulus per solid."""
+        cuda float64 arrays [6, n2 + (a==2), n1 + (a==1), n0 + (a==0)], without the extra
+        face along a periodic axis a; G: one shear modulus per solid."""
+        for a in range(3):
+            n = [int(v) for v in g.n]
+            if not g.periodic[a]:
+                n[a] += 1
+            _check_size(taus[a], 6 * n[0] * n[1] * n[2], f"taus[{a}]")
         arr = (Solid * len(solids))(*solids)
         Gs = (ctypes.c_double * len(solids))(*[float(v) for v in G])
         tp = (ctypes.c_void_p * 3)(*[_ptr(t) for t in taus])

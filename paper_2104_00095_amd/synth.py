@@ -26,6 +26,11 @@ Workloads (the paper's simulation states are not available; these stand in for t
                       U (sin pi x cos pi y, -cos pi x sin pi y) plus a uniform drift w0 along
                       z (divergence-free), sampled at cell centres and at face centres of
                       each solid's box; dt from a CFL number.
+* ``periodic_box`` -- the method variants at once: a 48 x 40 x 56 grid with spacings
+                      (1/48, 1/32, 1/64) (unequal), periodic along x and z (the paper's
+                      periodic test box), walled along y; six rotated ellipsoids with
+                      semi-axes U[0.07, 0.12], each with its own affine+sine field over
+                      its unwrapped box, boxes that cross the periodic ends; L=5.
 """
 from __future__ import annotations
 
@@ -63,6 +68,13 @@ class Workload:
     h: float
     origin: tuple
     solids: List[Solid] = field(default_factory=list)
+    spacing: tuple = (0.0, 0.0, 0.0)   # per-axis cell size; 0 means h
+    periodic: tuple = (0, 0, 0)        # 1: the grid wraps along the axis
+
+    @property
+    def deltas(self) -> tuple:
+        """The cell size along x, y, z."""
+        return tuple(float(d) if d > 0.0 else float(self.h) for d in self.spacing)
 
     @property
     def box_cells(self) -> int:
@@ -101,10 +113,12 @@ def _modes(rng, n_modes, kmax):
 
 
 def cell_centres(lo, ext, h, origin):
-    """Coordinates (x, y, z) broadcastable to [ext2, ext1, ext0]."""
-    x = origin[0] + (np.arange(lo[0], lo[0] + ext[0]) + 0.5) * h
-    y = origin[1] + (np.arange(lo[1], lo[1] + ext[1]) + 0.5) * h
-    z = origin[2] + (np.arange(lo[2], lo[2] + ext[2]) + 0.5) * h
+    """Coordinates (x, y, z) broadcastable to [ext2, ext1, ext0]; h: one spacing or one
+    per axis.  A box past the end of a periodic axis gets its unwrapped coordinates."""
+    d = np.broadcast_to(np.asarray(h, dtype=np.float64), (3,))
+    x = origin[0] + (np.arange(lo[0], lo[0] + ext[0]) + 0.5) * d[0]
+    y = origin[1] + (np.arange(lo[1], lo[1] + ext[1]) + 0.5) * d[1]
+    z = origin[2] + (np.arange(lo[2], lo[2] + ext[2]) + 0.5) * d[2]
     return x[None, None, :], y[None, :, None], z[:, None, None]
 
 
@@ -448,23 +462,23 @@ class StepVelocity:
 def step_velocity(w: "Workload", U=1.0, w0=0.3):
     """Per solid of `w`: the velocity at its cell centres and its face centres."""
     out = []
-    h, o = w.h, w.origin
+    (hx, hy, hz), o = w.deltas, w.origin
     for s in w.solids:
         lo, e = s.lo, s.ext
-        x, y, z = cell_centres(lo, e, h, o)
+        x, y, z = cell_centres(lo, e, (hx, hy, hz), o)
         u = flow_velocity(x, y, z, U, w0)
         k, j, i = np.meshgrid(np.arange(e[2]), np.arange(e[1]), np.arange(e[0] + 1),
                               indexing="ij")
-        ufx = flow_velocity(o[0] + (lo[0] + i) * h, o[1] + (lo[1] + j + 0.5) * h,
-                            o[2] + (lo[2] + k + 0.5) * h, U, w0)[0]
+        ufx = flow_velocity(o[0] + (lo[0] + i) * hx, o[1] + (lo[1] + j + 0.5) * hy,
+                            o[2] + (lo[2] + k + 0.5) * hz, U, w0)[0]
         k, j, i = np.meshgrid(np.arange(e[2]), np.arange(e[1] + 1), np.arange(e[0]),
                               indexing="ij")
-        ufy = flow_velocity(o[0] + (lo[0] + i + 0.5) * h, o[1] + (lo[1] + j) * h,
-                            o[2] + (lo[2] + k + 0.5) * h, U, w0)[1]
+        ufy = flow_velocity(o[0] + (lo[0] + i + 0.5) * hx, o[1] + (lo[1] + j) * hy,
+                            o[2] + (lo[2] + k + 0.5) * hz, U, w0)[1]
         k, j, i = np.meshgrid(np.arange(e[2] + 1), np.arange(e[1]), np.arange(e[0]),
                               indexing="ij")
-        ufz = flow_velocity(o[0] + (lo[0] + i + 0.5) * h, o[1] + (lo[1] + j + 0.5) * h,
-                            o[2] + (lo[2] + k) * h, U, w0)[2]
+        ufz = flow_velocity(o[0] + (lo[0] + i + 0.5) * hx, o[1] + (lo[1] + j + 0.5) * hy,
+                            o[2] + (lo[2] + k) * hz, U, w0)[2]
         out.append(StepVelocity(np.ascontiguousarray(u), (np.ascontiguousarray(ufx),
                                                           np.ascontiguousarray(ufy),
                                                           np.ascontiguousarray(ufz))))
@@ -472,5 +486,46 @@ def step_velocity(w: "Workload", U=1.0, w0=0.3):
 
 
 def step_dt(w: "Workload", cfl=0.4, U=1.0, w0=0.3) -> float:
-    """dt with max |u_a| dt / h = cfl (per axis)."""
-    return cfl * w.h / max(abs(U), abs(w0))
+    """dt with max |u_a| dt / Delta_a <= cfl on every axis."""
+    return cfl * min(w.deltas) / max(abs(U), abs(w0))
+
+
+# ------------------------------------------------------------------------------------------
+# periodic_box: unequal spacings, periodic axes, boxes across the periodic ends
+# ------------------------------------------------------------------------------------------
+def periodic_box(seed: int = 6, grid_n=(48, 40, 56), spacing=(1.0 / 48, 1.0 / 32, 1.0 / 64),
+                 periodic=(1, 0, 1), n_solids: int = 6, n_layers: int = 5,
+                 semi_lo: float = 0.07, semi_hi: float = 0.12) -> Workload:
+    """Ellipsoids placed at random (overlaps allowed: every solid is independent); along a
+    periodic axis the centre is anywhere and the box, lo taken mod n, may run past the
+    grid's end with the field on its unwrapped coordinates; along a walled axis the box
+    stays inside the grid."""
+    rng = np.random.default_rng(seed)
+    d = np.asarray(spacing, dtype=np.float64)
+    n = np.asarray(grid_n)
+    length = n * d
+    w = Workload("periodic_box", tuple(int(v) for v in grid_n), float(d.min()),
+                 (0.0, 0.0, 0.0), spacing=tuple(float(v) for v in d),
+                 periodic=tuple(int(v) for v in periodic))
+    for _ in range(n_solids):
+        semi = rng.uniform(semi_lo, semi_hi, 3)
+        rot = random_rotation(rng)
+        # cells from the centre to the box face: the semi-axis bound, the band and a margin
+        half = np.ceil(semi.max() * 1.05 / d).astype(int) + n_layers + 2
+        ext = 2 * half + 1
+        c = np.empty(3)
+        lo = np.empty(3, dtype=int)
+        for a in range(3):
+            if periodic[a]:
+                c[a] = rng.uniform(0.0, length[a])
+            else:
+                c[a] = rng.uniform((half[a] + 1) * d[a], length[a] - (half[a] + 1) * d[a])
+            lo[a] = int(math.floor(c[a] / d[a])) - half[a]
+        A = np.eye(3) + 0.04 * rng.standard_normal((3, 3))
+        modes = _modes(rng, 3, 2)
+        xi = affine_sine_field(tuple(int(v) for v in lo), tuple(int(v) for v in ext), d,
+                               (0.0, 0.0, 0.0), c, A, 0.006, modes)
+        lo_grid = tuple(int(lo[a] % n[a]) if periodic[a] else int(lo[a]) for a in range(3))
+        w.solids.append(Solid(lo_grid, tuple(int(v) for v in ext),
+                              ellipsoid_shape(c, semi, rot), n_layers, xi))
+    return w

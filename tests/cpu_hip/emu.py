@@ -34,13 +34,22 @@ def build(sanitize=True):
     return EXE
 
 
+def grid_line(w, n_solids):
+    """The grid line of a case file: solids, n, h, origin, spacing, periodic."""
+    sp = getattr(w, "spacing", (0.0, 0.0, 0.0))
+    per = getattr(w, "periodic", (0, 0, 0))
+    return (f"{n_solids} {w.grid_n[0]} {w.grid_n[1]} {w.grid_n[2]} {w.h!r} "
+            f"{w.origin[0]!r} {w.origin[1]!r} {w.origin[2]!r} "
+            + " ".join(repr(float(v)) for v in sp) + " "
+            + " ".join(str(int(bool(v))) for v in per))
+
+
 def run(w, tmpdir, r_s=2, r_max=4, normal_layers=2, precision=0, flags=0, reps=1,
         xi_normal=None, timeout=600, pre_flags=(), cus=None):
     """Write workload `w` to tmpdir, run the emulated library, return
     (status, [(xi_out, labels, decisions, stats_raw)])."""
     os.makedirs(tmpdir, exist_ok=True)
-    lines = [f"{len(w.solids)} {w.grid_n[0]} {w.grid_n[1]} {w.grid_n[2]} {w.h!r} "
-             f"{w.origin[0]!r} {w.origin[1]!r} {w.origin[2]!r}",
+    lines = [grid_line(w, len(w.solids)),
              f"{r_s} {r_max} {normal_layers} {precision} {flags} {reps}"]
     for i, s in enumerate(w.solids):
         sh = s.shape
@@ -91,7 +100,9 @@ def run_step(w, tmpdir, xi_n, labels_n, u, uf, dt, xi_next_init, xi_half_init, r
     for i, s in enumerate(w.solids):
         solids.append(types.SimpleNamespace(lo=s.lo, ext=s.ext, n_layers=s.n_layers,
                                             shape=s.shape, xi=xi_next_init[i]))
-    ww = types.SimpleNamespace(solids=solids, grid_n=w.grid_n, h=w.h, origin=w.origin)
+    ww = types.SimpleNamespace(solids=solids, grid_n=w.grid_n, h=w.h, origin=w.origin,
+                               spacing=getattr(w, "spacing", (0.0, 0.0, 0.0)),
+                               periodic=getattr(w, "periodic", (0, 0, 0)))
     os.makedirs(tmpdir, exist_ok=True)
     with open(os.path.join(tmpdir, "step.txt"), "w") as f:
         f.write(f"{float(dt)!r}\n")
@@ -124,7 +135,9 @@ def run_blur(w, tmpdir, xi, labels, eps, G, H_init, phi_init, tau_init, timeout=
     import types
     solids = [types.SimpleNamespace(lo=s.lo, ext=s.ext, n_layers=s.n_layers, shape=s.shape,
                                     xi=xi[i]) for i, s in enumerate(w.solids)]
-    ww = types.SimpleNamespace(solids=solids, grid_n=w.grid_n, h=w.h, origin=w.origin)
+    ww = types.SimpleNamespace(solids=solids, grid_n=w.grid_n, h=w.h, origin=w.origin,
+                               spacing=getattr(w, "spacing", (0.0, 0.0, 0.0)),
+                               periodic=getattr(w, "periodic", (0, 0, 0)))
     os.makedirs(tmpdir, exist_ok=True)
     with open(os.path.join(tmpdir, "blur.txt"), "w") as f:
         f.write(f"{float(eps)!r} " + " ".join(repr(float(v)) for v in G) + "\n")
@@ -141,8 +154,7 @@ def run_blur(w, tmpdir, xi, labels, eps, G, H_init, phi_init, tau_init, timeout=
         os.makedirs(tmpdir, exist_ok=True)
         for i, s in enumerate(solids):
             np.ascontiguousarray(s.xi, dtype=np.float64).tofile(os.path.join(tmpdir, f"xi{i}.bin"))
-        lines = [f"{len(solids)} {w.grid_n[0]} {w.grid_n[1]} {w.grid_n[2]} {w.h!r} "
-                 f"{w.origin[0]!r} {w.origin[1]!r} {w.origin[2]!r}", "2 4 2 0 0 1"]
+        lines = [grid_line(w, len(solids)), "2 4 2 0 0 1"]
         for s in solids:
             sh = s.shape
             vals = list(s.lo) + list(s.ext) + [s.n_layers, sh.kind]

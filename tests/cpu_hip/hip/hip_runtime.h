@@ -142,7 +142,11 @@ inline int __builtin_amdgcn_readfirstlane(int v) {
     rmx_emu::group_done(64);
     return r;
 }
-inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
+// A poll's pause.  The bounded waits of the persistent kernel count polls; emulated blocks
+// run thousands of host threads under the sanitizers, so a pause of 20 us (about 20 s over
+// the bound) keeps a slow but progressing wait from running out, and frees the CPU for the
+// blocks that do the work.
+inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __ffsll(long long x) { return __builtin_ffsll(x); }
 

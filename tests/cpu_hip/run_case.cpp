@@ -31,6 +31,8 @@ int main(int argc, char** argv) {
     int ns = 0, reps = 1;
     if (std::fscanf(h, "%d %d %d %d %lf %lf %lf %lf", &ns, &g.n[0], &g.n[1], &g.n[2], &g.h,
                     &g.origin[0], &g.origin[1], &g.origin[2]) != 8) return 2;
+    if (std::fscanf(h, "%lf %lf %lf %d %d %d", &g.spacing[0], &g.spacing[1], &g.spacing[2],
+                    &g.periodic[0], &g.periodic[1], &g.periodic[2]) != 6) return 2;
     unsigned flags = 0;
     if (std::fscanf(h, "%d %d %d %d %u %d", &o.r_s, &o.r_max, &o.normal_layers, &o.precision,
                     &flags, &reps) != 6) return 2;

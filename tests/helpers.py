@@ -5,18 +5,35 @@ import itertools
 import numpy as np
 
 import oracle
-from paper_2104_00095_amd import synth
+from paper_2104_00095_amd import rmx, synth
 
 
 def oracle_shape(shape):
     return oracle.make_shape(shape.kind, shape.centre, shape.semi, shape.rot)
 
 
+def spacing_of(w):
+    """The cell size along x, y, z of workload w."""
+    sp = getattr(w, "spacing", (0.0, 0.0, 0.0))
+    return tuple(float(d) if d > 0.0 else float(w.h) for d in sp)
+
+
+def periodic_of(w):
+    return tuple(int(v) for v in getattr(w, "periodic", (0, 0, 0)))
+
+
+def grid_of(w):
+    """The library's grid descriptor of workload w."""
+    return rmx.grid(w.grid_n, w.h, w.origin, spacing=getattr(w, "spacing", None),
+                    periodic=periodic_of(w))
+
+
 def oracle_problem(w, s, r_s=2, r_max=4, normal_layers=2, n_layers=None, adjacency=6):
     return oracle.make_problem(w.grid_n, s.lo, s.ext, oracle_shape(s.shape),
                                s.n_layers if n_layers is None else n_layers,
                                r_s=r_s, r_max=r_max, normal_layers=normal_layers,
-                               adjacency=adjacency)
+                               adjacency=adjacency, periodic=periodic_of(w),
+                               spacing=spacing_of(w))
 
 
 def run_oracle(w, s, **kw):
@@ -190,7 +207,7 @@ class StepCase:
             p = oracle_problem(self.w, s, **self.opts)
             v = self.vel[i]
             out.append(oracle.step(p, self.xi_n[i], self.labels_n[i], v.u, v.uf, self.dt,
-                                   self.w.h, self.next_init[i], self.half_init[i]))
+                                   spacing_of(self.w), self.next_init[i], self.half_init[i]))
         return out
 
 
@@ -290,10 +307,12 @@ class BlurCase:
         rng = np.random.default_rng(seed)
         self.G = list(rng.uniform(0.5, 3.0, size=len(w.solids)))
         n0, n1, n2 = w.grid_n
+        per = periodic_of(w)
         self.H_init = np.full((n2, n1, n0), 5.0)
         self.phi_init = [np.full(x.shape[1:], -6.0) for x in self.xi]
-        self.tau_init = [np.full((6, n2 + (a == 2), n1 + (a == 1), n0 + (a == 0)), 7.0)
-                         for a in range(3)]
+        # a periodic axis has n faces, a walled one n + 1
+        self.tau_init = [np.full((6, n2 + (a == 2 and not per[2]), n1 + (a == 1 and not per[1]),
+                                  n0 + (a == 0 and not per[0])), 7.0) for a in range(3)]
 
     def oracle_solids(self):
         return [(s.lo, s.ext, oracle_shape(s.shape), s.n_layers, self.xi[i], self.labels[i])
@@ -301,9 +320,11 @@ class BlurCase:
 
     def oracle(self):
         sols = self.oracle_solids()
-        H, phis = oracle.blur(self.w.grid_n, sols, self.eps, self.H_init, self.phi_init)
-        taus = oracle.solid_stress(self.w.grid_n, sols, self.eps, self.w.h, self.G,
-                                   self.tau_init)
+        per = periodic_of(self.w)
+        H, phis = oracle.blur(self.w.grid_n, sols, self.eps, self.H_init, self.phi_init,
+                              periodic=per)
+        taus = oracle.solid_stress(self.w.grid_n, sols, self.eps, spacing_of(self.w), self.G,
+                                   self.tau_init, periodic=per)
         return H, phis, taus
 
 

@@ -47,6 +47,7 @@ int main(void) {
          offsetof(rmx_step_solid, uf), offsetof(rmx_step_solid, xi_next),
          offsetof(rmx_step_solid, decisions));
   printf("%d %d\\n", RMX_N_PHASES, RMX_PHASE_STEP_TRANS);
+  printf("%zu %zu\\n", offsetof(rmx_grid, spacing), offsetof(rmx_grid, periodic));
   return 0;
 }
 """)
@@ -60,7 +61,8 @@ int main(void) {
             ctypes.sizeof(rmx.Tuning), rmx.Tuning.ms.offset,
             ctypes.sizeof(rmx.StepSolid), rmx.StepSolid.xi_n.offset, rmx.StepSolid.uf.offset,
             rmx.StepSolid.xi_next.offset, rmx.StepSolid.decisions.offset,
-            rmx.N_PHASES, rmx.PHASES.index("step_trans")]
+            rmx.N_PHASES, rmx.PHASES.index("step_trans"),
+            rmx.Grid.spacing.offset, rmx.Grid.periodic.offset]
     assert [int(v) for v in a] == want
     assert len(rmx.PHASES) == rmx.N_PHASES
 

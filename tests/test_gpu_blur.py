@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
-from tests.helpers import BlurCase, blur_pair_workload, compare_blur
+from tests.helpers import BlurCase, blur_pair_workload, compare_blur, grid_of
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def gpu_blur(ctx, case):
         keep += [xi, lab]
         shp = rmx.shape(s.shape.kind, s.shape.centre, s.shape.semi, s.shape.rot)
         sols.append(rmx.solid(s.lo, s.ext, shp, s.n_layers, xi, lab))
-    g = rmx.grid(case.w.grid_n, case.w.h, case.w.origin)
+    g = grid_of(case.w)
     H = T(case.H_init)
     phis = [T(p) for p in case.phi_init]
     taus = [T(t) for t in case.tau_init]

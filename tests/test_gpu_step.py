@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
-from tests.helpers import StepCase, compare_step, rel_err, wall_sphere
+from tests.helpers import StepCase, compare_step, grid_of, rel_err, wall_sphere
 
 pytestmark = pytest.mark.gpu
 
@@ -69,7 +69,7 @@ def gpu_step(ctx, case, precision=0, flags=0):
     import torch
     from paper_2104_00095_amd import rmx
     d = DevStep(case)
-    g = rmx.grid(case.w.grid_n, case.w.h, case.w.origin)
+    g = grid_of(case.w)
     opt = rmx.options(precision=precision, flags=flags, **case.opts)
     st, stats = ctx.step(g, d.solids(), case.dt, opt, check=False)
     torch.cuda.synchronize()
@@ -117,7 +117,7 @@ def test_step_loop_on_device(ctx):
     w = synth.sphere32(n=32, n_layers=6)
     case = StepCase(w)
     d = DevStep(case)
-    g = rmx.grid(w.grid_n, w.h, w.origin)
+    g = grid_of(w)
     opt = rmx.options(**case.opts)
     for _ in range(3):
         st, stats = ctx.step(g, d.solids(), case.dt, opt)
@@ -148,7 +148,7 @@ def test_step_refuses_unsupported_forms(ctx):
     w = synth.sphere32(n=32, n_layers=6)
     case = StepCase(w)
     d = DevStep(case)
-    g = rmx.grid(w.grid_n, w.h, w.origin)
+    g = grid_of(w)
     for fl in (rmx.FLAG_GRAPH, rmx.FLAG_PER_SOLID, rmx.FLAG_PERSISTENT):
         st, _ = ctx.step(g, d.solids(), case.dt, rmx.options(flags=fl), check=False)
         assert st == rmx.E_ARG
@@ -167,7 +167,7 @@ def test_step_profile_phases(ctx):
     w = synth.sphere32(n=32, n_layers=6)
     case = StepCase(w)
     d = DevStep(case)
-    g = rmx.grid(w.grid_n, w.h, w.origin)
+    g = grid_of(w)
     ctx.profile_read()
     st, _ = ctx.step(g, d.solids(), case.dt, rmx.options(flags=rmx.FLAG_PROFILE, **case.opts))
     torch.cuda.synchronize()
