@@ -23,6 +23,7 @@ struct BlurDev {
     const int8_t* labels;                // [e2][e1][e0]
     double* phi;                         // [e2][e1][e0] or null
     double G;                            // shear modulus
+    int64_t row0;                        // first row of the solid in the fill's rows
 };
 
 struct BlurBatch {
@@ -35,6 +36,9 @@ struct BlurBatch {
     const int32_t* tile_start;   // [tiles + 1]: candidate solids of each tile (CSR)
     const int32_t* tile_list;    // ascending solid indices (boxes dilated by one cell)
     const int32_t* active;       // tiles with a candidate
+    int32_t* n_covered;          // tiles of `active` with a covered cell (zeroed per call)
+    int32_t* covered;            // [n_active]: those tiles, in the order the scan found them
+    int64_t fill_rows;           // rows (along x) of the boxes' cells or faces, all solids
     double eps;
     double h[3];                 // spacing of each axis
     double* H;                   // [n2][n1][n0] or null

@@ -11,7 +11,12 @@
 //                     at the face's xi; the blend T (sum of weights S <= 1) or T / S.
 // A block takes one 8^3 tile of the grid; the solids that can touch it come from a list
 // built on the host (boxes dilated by one cell), visited in ascending order, so every sum
-// runs in the same order as in any other implementation.  Periodic axes (SI "Test
+// runs in the same order as in any other implementation.  Each consumer runs in three
+// launches: a fill writes, row by row along x, the result every cell or face of a box takes
+// when no solid covers its stencil (H = 1, zero stress); a scan over every tile with a
+// candidate lists the tiles where a candidate labels (0..L) a cell of the tile (dilated by
+// one cell for the faces' stencils); the full kernel, whose phi0 and 3x3 inverse hold many
+// registers, then computes those tiles only, over the fill's values.  Periodic axes (SI "Test
 // cases"): a box holds the solid's unwrapped map and may run past the grid's end; grid
 // cell g lies at box coordinate (g - lo) mod n there, and difference stencils are taken in
 // box coordinates, so they never join the two ends of a box that spans the axis.  Stencil gathers of FP64 fields
@@ -29,6 +34,40 @@ __device__ __forceinline__ double heaviside_eps(double phi, double eps) {
     if (phi <= -eps) return 0.0;
     if (phi >= eps) return 1.0;
     return 0.5 * ((1.0 + phi / eps) + sin(kPi * phi / eps) / kPi);
+}
+
+// 1 - H_eps(phi0(x)), the weight of a solid at x.  Where the distance from x to an
+// ellipsoid's surface is certainly at least eps, H_eps is exactly 0 or 1 whatever the exact
+// phi0, and the bisection of the exact distance is skipped.  Two certificates, in body
+// coordinates y with semi-axes a and r = eps (1 + 1e-9):
+//  - the cube |v_i| <= r around y lies inside the ellipsoid if
+//    sum_i ((|y_i| + r) / a_i)^2 < 1, and outside it if sum_i (max(|y_i| - r, 0) / a_i)^2 > 1
+//    (the quadratic form grows with every |y_i|), and the cube holds the ball of radius r;
+//  - with rho = |y / a|, the distance is at least (rho - 1) a_min outside (rho E contains the
+//    ellipsoid grown by a ball of that radius) and (1 - rho) a_min inside.
+// Each sum is compared with 1 -+ 1e-12 and each bound with r: margins far above the
+// rounding of these few operations and of any exact distance.
+__device__ __forceinline__ double weight_at(const ShapeR& s, double x0, double x1, double x2,
+                                           double eps) {
+#pragma clang fp contract(off)
+    if (s.kind == 2 && finite3(x0, x1, x2)) {
+        double y0, y1, y2;
+        body(s, x0, x1, x2, y0, y1, y2);
+        const double r = eps * (1.0 + 1e-9);
+        const double u0 = fabs(y0), u1 = fabs(y1), u2 = fabs(y2);
+        const double i0 = (u0 + r) / s.e0, i1 = (u1 + r) / s.e1, i2 = (u2 + r) / s.e2;
+        if ((i0 * i0 + i1 * i1) + i2 * i2 < 1.0 - 1e-12) return 1.0;   // phi0 <= -eps
+        const double o0 = fmax(u0 - r, 0.0) / s.e0, o1 = fmax(u1 - r, 0.0) / s.e1,
+                     o2 = fmax(u2 - r, 0.0) / s.e2;
+        if ((o0 * o0 + o1 * o1) + o2 * o2 > 1.0 + 1e-12) return 0.0;   // phi0 >= eps
+        const double q0 = y0 / s.e0, q1 = y1 / s.e1, q2 = y2 / s.e2;
+        const double rho = sqrt((q0 * q0 + q1 * q1) + q2 * q2);
+        const double amin = fmin(s.e0, fmin(s.e1, s.e2));
+        const double need = r + 1e-9 * amin * (rho + 1.0);
+        if ((1.0 - rho) * amin >= need) return 1.0;
+        if ((rho - 1.0) * amin >= need) return 0.0;
+    }
+    return 1.0 - heaviside_eps(phi0(s, x0, x1, x2), eps);
 }
 
 __device__ __forceinline__ ShapeR blur_shape(const BlurDev& s) {
@@ -84,10 +123,178 @@ __device__ __forceinline__ void tile_cell(const BlurBatch& b, int t, int q, int 
 }
 
 // ------------------------------------------------------------------------------------
+// The scan: does a candidate label any cell of the tile dilated by one cell?  (A face's
+// difference stencil reaches one cell beyond its owner's tile; a cell's phi only the cell.)
+// ------------------------------------------------------------------------------------
+__device__ bool tile_covered(const BlurBatch& b, int t, int e0, int e1, bool dilate) {
+    const int tx = t % b.tiles[0], ty = (t / b.tiles[0]) % b.tiles[1];
+    const int tz = t / (b.tiles[0] * b.tiles[1]);
+    const int h = dilate ? 1 : 0;
+    const int o0 = tx * kBlurTX - h, o1 = ty * kBlurTY - h, o2 = tz * kBlurTZ - h;
+    const int DX = kBlurTX + 2 * h, DY = kBlurTY + 2 * h, DZ = kBlurTZ + 2 * h;
+    int hit = 0;
+    for (int e = e0; e < e1; ++e) {
+        const BlurDev& s = b.solids[b.tile_list[e]];
+        for (int q = threadIdx.x; q < DX * DY * DZ; q += 256) {
+            int g[3] = {o0 + q % DX, o1 + (q / DX) % DY, o2 + q / (DX * DY)};
+            bool on = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (g[a] >= 0 && g[a] < b.grid[a]) continue;
+                if (b.periodic[a])
+                    g[a] = g[a] < 0 ? g[a] + b.grid[a] : g[a] - b.grid[a];
+                else
+                    on = false;
+            }
+            int l[3];
+            if (on && box_coords(b, s, g, l) && covered(s, box_cell(s, l[0], l[1], l[2])))
+                hit = 1;
+        }
+    }
+    return __syncthreads_or(hit) != 0;
+}
+
+template <bool STRESS>
+__global__ __launch_bounds__(256) void k_blur_scan(BlurBatch b) {
+    const int t = b.active[blockIdx.x];
+    const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
+    if (tile_covered(b, t, e0, e1, STRESS) && threadIdx.x == 0)
+        b.covered[atomicAdd(b.n_covered, 1)] = t;
+}
+
+// ------------------------------------------------------------------------------------
+// The fill: what a cell or face with no covered stencil takes (H = 1 on a cell inside some
+// box; zero stress on a face with a cell inside some box), over every box, one row along x
+// per wave (whole cache lines).  Box regions that overlap are written more than once, with
+// the same value.  Face rows of axis a span the box's ext_a + 1 faces along a (n on a
+// periodic axis that the box spans); rows are ordered per solid, then (for the stress)
+// axis, component, z, y.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int fill_extent(const BlurBatch& b, const BlurDev& s, int a, int ax) {
+    int e = s.ext[ax] + (ax == a ? 1 : 0);
+    if (b.periodic[ax] && e > b.grid[ax]) e = b.grid[ax];
+    return e;
+}
+
+__device__ __forceinline__ int find_solid_by_row(const BlurBatch& b, int64_t r) {
+    int lo = 0, hi = b.n_solids - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.solids[mid].row0 <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A fill row's place: solid m, axis a and component c (stress only), box row (y, z), and
+// the extents E0 x E1 x E2 of the rows' region.
+struct FillPos {
+    int m, a, c, y, z, E0, E1, E2;
+};
+
+template <bool STRESS>
+__device__ __forceinline__ void fill_extents(const BlurBatch& b, FillPos& p) {
+    const BlurDev& s = b.solids[p.m];
+    if (STRESS) {
+        p.E0 = fill_extent(b, s, p.a, 0);
+        p.E1 = fill_extent(b, s, p.a, 1);
+        p.E2 = fill_extent(b, s, p.a, 2);
+    } else {
+        p.E0 = s.ext[0];
+        p.E1 = s.ext[1];
+        p.E2 = s.ext[2];
+    }
+}
+
+// Place of row r (divisions; once per wave).
+template <bool STRESS>
+__device__ FillPos fill_pos(const BlurBatch& b, int64_t r) {
+    FillPos p;
+    p.m = uniform_int(find_solid_by_row(b, r));
+    int64_t q = r - b.solids[p.m].row0;
+    p.a = 0;
+    p.c = 0;
+    fill_extents<STRESS>(b, p);
+    if (STRESS) {
+        while (q >= 6 * (int64_t)p.E1 * p.E2) {
+            q -= 6 * (int64_t)p.E1 * p.E2;
+            ++p.a;
+            fill_extents<STRESS>(b, p);
+        }
+        const int64_t plane = (int64_t)p.E1 * p.E2;
+        p.c = (int)(q / plane);
+        q -= (int64_t)p.c * plane;
+    }
+    p.y = (int)(q % p.E1);
+    p.z = (int)(q / p.E1);
+    return p;
+}
+
+// The next row's place (y fastest, then z, component, axis, solid).
+template <bool STRESS>
+__device__ __forceinline__ void fill_next(const BlurBatch& b, FillPos& p) {
+    if (++p.y < p.E1) return;
+    p.y = 0;
+    if (++p.z < p.E2) return;
+    p.z = 0;
+    if (STRESS) {
+        if (++p.c < 6) return;
+        p.c = 0;
+        if (++p.a < 3) {
+            fill_extents<STRESS>(b, p);
+            return;
+        }
+        p.a = 0;
+    }
+    if (++p.m < b.n_solids) fill_extents<STRESS>(b, p);
+}
+
+// Each wave writes one contiguous run of rows.
+template <bool STRESS>
+__global__ __launch_bounds__(256) void k_blur_fill(BlurBatch b) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    const int64_t per = (b.fill_rows + waves - 1) / waves;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * per;
+    const int64_t r1 = r0 + per < b.fill_rows ? r0 + per : b.fill_rows;
+    if (r0 >= r1) return;
+    FillPos p = fill_pos<STRESS>(b, r0);
+    for (int64_t r = r0; r < r1; ++r, fill_next<STRESS>(b, p)) {
+        const BlurDev& s = b.solids[p.m];
+        int gy = s.lo[1] + p.y, gz = s.lo[2] + p.z;
+        if (b.periodic[1] && gy >= b.grid[1]) gy -= b.grid[1];
+        if (b.periodic[2] && gz >= b.grid[2]) gz -= b.grid[2];
+        double* out;
+        int64_t n0, n1;
+        double v;
+        if (STRESS) {
+            const int a = p.a;
+            n0 = b.grid[0] + (a == 0 && !b.periodic[0]);
+            n1 = b.grid[1] + (a == 1 && !b.periodic[1]);
+            const int64_t n2 = b.grid[2] + (a == 2 && !b.periodic[2]);
+            out = b.tau[a] + (int64_t)p.c * (n0 * n1 * n2);
+            v = 0.0;
+        } else {
+            n0 = b.grid[0];
+            n1 = b.grid[1];
+            out = b.H;
+            v = 1.0;
+        }
+        const int64_t base = ((int64_t)gz * n1 + gy) * n0;
+        for (int t = lane; t < p.E0; t += 64) {
+            int gx = s.lo[0] + t;
+            if (b.periodic[0] && gx >= b.grid[0]) gx -= b.grid[0];
+            out[base + gx] = v;
+        }
+    }
+}
+
+// Blocks of the full kernels: they stride over the covered tiles.
+constexpr int kBlurFullBlocks = 2048;
+
+// ------------------------------------------------------------------------------------
 // Modified Heaviside (and phi_m).
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
-    const int t = b.active[blockIdx.x];
+__device__ void heaviside_tile(const BlurBatch& b, int t) {
     const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
     for (int q = threadIdx.x; q < kBlurTileCells; q += 256) {
         int g[3];
@@ -104,14 +311,23 @@ __global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
             if (!covered(s, c)) continue;
             double v[3];
             xi_at(s, c, v);
-            const double p = phi0(blur_shape(s), v[0], v[1], v[2]);
-            if (s.phi) s.phi[c] = p;
-            acc += 1.0 - heaviside_eps(p, b.eps);
+            if (s.phi) {
+                const double p = phi0(blur_shape(s), v[0], v[1], v[2]);
+                s.phi[c] = p;
+                acc += 1.0 - heaviside_eps(p, b.eps);
+            } else {
+                acc += weight_at(blur_shape(s), v[0], v[1], v[2], b.eps);
+            }
         }
         if (!any || !b.H) continue;
         const double d = 1.0 - acc;
         b.H[((int64_t)g[2] * b.grid[1] + g[1]) * b.grid[0] + g[0]] = d > 0.0 ? d : 0.0;
     }
+}
+
+__global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
+    const int n = *b.n_covered;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) heaviside_tile(b, b.covered[i]);
 }
 
 // ------------------------------------------------------------------------------------
@@ -182,7 +398,7 @@ __device__ bool face_stress(const BlurDev& s, const int f[3], int a, const doubl
     tau[5] = G * B[1][2];
     const double x0 = (xp[0] + xq[0]) * 0.5, x1 = (xp[1] + xq[1]) * 0.5,
                  x2 = (xp[2] + xq[2]) * 0.5;
-    *w = 1.0 - heaviside_eps(phi0(blur_shape(s), x0, x1, x2), eps);
+    *w = weight_at(blur_shape(s), x0, x1, x2, eps);
     return true;
 }
 
@@ -223,8 +439,7 @@ __device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3], i
     for (int c = 0; c < 6; ++c) out[c * nf + fi] = S <= 1.0 ? T[c] : T[c] / S;
 }
 
-__global__ __launch_bounds__(256) void k_blur_stress(BlurBatch b) {
-    const int t = b.active[blockIdx.x];
+__device__ void stress_tile(const BlurBatch& b, int t) {
     const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
     for (int q = threadIdx.x; q < kBlurTileCells; q += 256) {
         int g[3];
@@ -244,17 +459,45 @@ __global__ __launch_bounds__(256) void k_blur_stress(BlurBatch b) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_blur_stress(BlurBatch b) {
+    const int n = *b.n_covered;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) stress_tile(b, b.covered[i]);
+}
+
 }  // namespace
+
+// Blocks of the fill: four rows per block at a time.
+static int fill_grid(const BlurBatch& b) {
+    int64_t blocks = (b.fill_rows + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    return (int)(blocks > 0 ? blocks : 1);
+}
 
 hipError_t launch_blur_heaviside(const BlurBatch& b, hipStream_t st) {
     if (b.n_active <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_blur_heaviside, dim3(b.n_active), dim3(256), 0, st, b);
+    hipError_t e;
+    if (b.H) {
+        hipLaunchKernelGGL(k_blur_fill<false>, dim3(fill_grid(b)), dim3(256), 0, st, b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_blur_scan<false>, dim3(b.n_active), dim3(256), 0, st, b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int g = b.n_active < kBlurFullBlocks ? b.n_active : kBlurFullBlocks;
+    hipLaunchKernelGGL(k_blur_heaviside, dim3(g), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 
 hipError_t launch_blur_stress(const BlurBatch& b, hipStream_t st) {
     if (b.n_active <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_blur_stress, dim3(b.n_active), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_blur_fill<true>, dim3(fill_grid(b)), dim3(256), 0, st, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_blur_scan<true>, dim3(b.n_active), dim3(256), 0, st, b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int g = b.n_active < kBlurFullBlocks ? b.n_active : kBlurFullBlocks;
+    hipLaunchKernelGGL(k_blur_stress, dim3(g), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

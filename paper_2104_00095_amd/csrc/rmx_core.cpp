@@ -178,7 +178,10 @@ static hipError_t step_chain(const Plan& p, const Batch& b, const StepBatch& sb,
         if (prof && (e = prof->end(rec, st)) != hipSuccess) return e;
         return hipSuccess;
     };
-    if ((e = timed(RMX_PHASE_STEP_TRANS, [&] { return launch_step_trans(sb, st); })) != hipSuccess)
+    if ((e = timed(RMX_PHASE_STEP_TRANS, [&] {
+             const hipError_t r = launch_step_scan(sb, 0, st);
+             return r != hipSuccess ? r : launch_step_trans(sb, st);
+         })) != hipSuccess)
         return e;
     if ((e = timed(RMX_PHASE_STEP_FACES, [&] { return launch_step_faces(sb, st); })) !=
         hipSuccess)
@@ -187,7 +190,10 @@ static hipError_t step_chain(const Plan& p, const Batch& b, const StepBatch& sb,
         hipSuccess)
         return e;
     if ((e = enqueue(p, b, precision, st, prof, false)) != hipSuccess) return e;
-    return timed(RMX_PHASE_STEP_CORRECT, [&] { return launch_step_correct(sb, st); });
+    return timed(RMX_PHASE_STEP_CORRECT, [&] {
+        const hipError_t r = launch_step_scan(sb, 1, st);
+        return r != hipSuccess ? r : launch_step_correct(sb, st);
+    });
 }
 
 int launch_planned(rmx_ctx* c, Plan& p, int n, const rmx_options* opt, hipStream_t st,
@@ -502,11 +508,17 @@ int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t
         RMX_OK)
         return rc;
     if ((rc = ensure_ws(c, p.ws_bytes)) != RMX_OK) return rc;
-    // Step workspace: the step descriptors, then 30 doubles per box cell: per axis the
-    // transverse advecting velocity and the three chosen transverse xi states (12), and the
-    // expansions of the three xi components to the cell's +a and -a faces (18).
-    const size_t desc = (sizeof(StepDev) * n_solids + 255) & ~size_t(255);
-    const size_t need = desc + sizeof(double) * 30 * (size_t)p.total_cells;
+    // Step workspace: the step descriptors and the two list lengths (uploaded, the lengths
+    // as 0), then 30 doubles per box cell: per axis the transverse advecting velocity and
+    // the three chosen transverse xi states (12), and the expansions of the three xi
+    // components to the cell's +a and -a faces (18); then the two row-segment lists.
+    if (p.total_words >= (int64_t)0x7fffffff) return RMX_E_BOX;
+    const size_t ncount = 2 * kStepLists;
+    const size_t up = sizeof(StepDev) * n_solids + ncount * sizeof(int32_t);
+    const size_t desc = (up + 255) & ~size_t(255);
+    const size_t fields = sizeof(double) * 30 * (size_t)p.total_cells;
+    const int64_t cap = step_list_cap(p.total_words);
+    const size_t need = desc + fields + ncount * sizeof(int32_t) * (size_t)cap;
     if (need > c->step_ws_size) {
         if (c->fixed) return RMX_E_WORKSPACE;
         if (c->step_ws) {
@@ -535,15 +547,20 @@ int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t
         trans += 30 * p.solids[i].ncell;
     }
     Staging* sg = nullptr;
-    if ((rc = get_stage(c, sizeof(StepDev) * n_solids, &sg)) != RMX_OK) return rc;
+    if ((rc = get_stage(c, up, &sg)) != RMX_OK) return rc;
     std::memcpy(sg->host, sd.data(), sizeof(StepDev) * n_solids);
-    if (hipMemcpyAsync(c->step_ws, sg->host, sizeof(StepDev) * n_solids,
-                       hipMemcpyHostToDevice, st) != hipSuccess ||
+    std::memset(static_cast<char*>(sg->host) + sizeof(StepDev) * n_solids, 0,
+                ncount * sizeof(int32_t));
+    if (hipMemcpyAsync(c->step_ws, sg->host, up, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipEventRecord(sg->ev, st) != hipSuccess)
         return RMX_E_HIP;
     sg->pending = true;
+    char* wsb = static_cast<char*>(c->step_ws);
     StepBatch sb{};
-    sb.steps = static_cast<const StepDev*>(c->step_ws);
+    sb.steps = reinterpret_cast<const StepDev*>(wsb);
+    sb.counts = reinterpret_cast<int32_t*>(wsb + sizeof(StepDev) * n_solids);
+    sb.lists = reinterpret_cast<int32_t*>(wsb + desc + fields);
+    sb.list_cap = cap;
     for (int a = 0; a < 3; ++a) {
         sb.lam[a] = dt / (grid->spacing[a] > 0.0 ? grid->spacing[a] : grid->h);
         sb.hl[a] = 0.5 * sb.lam[a];
@@ -558,8 +575,8 @@ int rmx_step(rmx_ctx* c, const rmx_grid* grid, const rmx_step_solid* ss, int32_t
 // one cell, so that a face sees the solids of its low cell), uploaded to the context's
 // blur workspace on `st`.
 static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int32_t n,
-                      double eps, const double* G, double* const* phi, hipStream_t st,
-                      BlurBatch* b) {
+                      double eps, const double* G, double* const* phi, bool stress,
+                      hipStream_t st, BlurBatch* b) {
     if (!c || !grid || !solids || n < 1) return RMX_E_ARG;
     if (!(eps > 0.0) || !std::isfinite(eps)) return RMX_E_ARG;
     int rc;
@@ -633,11 +650,34 @@ static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
         d.phi = phi ? phi[m] : nullptr;
         d.G = G ? G[m] : 0.0;
     }
+    // the fill's rows along x: per solid its box's cells (H), or per axis a and component
+    // the box's faces along a (ext_a + 1 of them, at most n on a periodic axis)
+    int64_t rows = 0;
+    for (int m = 0; m < n; ++m) {
+        sd[m].row0 = rows;
+        const rmx_solid& s = solids[m];
+        if (!stress) {
+            rows += (int64_t)s.ext[1] * s.ext[2];
+            continue;
+        }
+        for (int a = 0; a < 3; ++a) {
+            int64_t e[3];
+            for (int x = 0; x < 3; ++x) {
+                e[x] = s.ext[x] + (x == a ? 1 : 0);
+                if (grid->periodic[x] && e[x] > grid->n[x]) e[x] = grid->n[x];
+            }
+            rows += 6 * e[1] * e[2];
+        }
+    }
     auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
     const size_t o_start = al(sizeof(BlurDev) * n);
     const size_t o_list = o_start + al(sizeof(int32_t) * (nt + 1));
     const size_t o_active = o_list + al(sizeof(int32_t) * std::max<size_t>(list.size(), 1));
-    const size_t bytes = o_active + sizeof(int32_t) * std::max<size_t>(active.size(), 1);
+    // the scan's count of covered tiles (uploaded as 0) and their list
+    const size_t o_ncov = o_active + al(sizeof(int32_t) * std::max<size_t>(active.size(), 1));
+    const size_t o_cov = o_ncov + 256;
+    const size_t up = o_ncov + sizeof(int32_t);   // bytes uploaded
+    const size_t bytes = o_cov + sizeof(int32_t) * std::max<size_t>(active.size(), 1);
     if (hipSetDevice(c->device) != hipSuccess) return RMX_E_HIP;
     if (bytes > c->blur_ws_size) {
         if (c->fixed) return RMX_E_WORKSPACE;
@@ -654,13 +694,15 @@ static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
         c->blur_ws_size = bytes;
     }
     Staging* sg = nullptr;
-    if ((rc = get_stage(c, bytes, &sg)) != RMX_OK) return rc;
+    if ((rc = get_stage(c, up, &sg)) != RMX_OK) return rc;
     char* h = static_cast<char*>(sg->host);
     std::memcpy(h, sd.data(), sizeof(BlurDev) * n);
     std::memcpy(h + o_start, count.data(), sizeof(int32_t) * (nt + 1));
     if (!list.empty()) std::memcpy(h + o_list, list.data(), sizeof(int32_t) * list.size());
     if (!active.empty()) std::memcpy(h + o_active, active.data(), sizeof(int32_t) * active.size());
-    if (hipMemcpyAsync(c->blur_ws, h, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+    const int32_t zero = 0;
+    std::memcpy(h + o_ncov, &zero, sizeof(zero));
+    if (hipMemcpyAsync(c->blur_ws, h, up, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipEventRecord(sg->ev, st) != hipSuccess)
         return RMX_E_HIP;
     sg->pending = true;
@@ -678,7 +720,10 @@ static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     b->tile_start = reinterpret_cast<const int32_t*>(base + o_start);
     b->tile_list = reinterpret_cast<const int32_t*>(base + o_list);
     b->active = reinterpret_cast<const int32_t*>(base + o_active);
+    b->n_covered = reinterpret_cast<int32_t*>(base + o_ncov);
+    b->covered = reinterpret_cast<int32_t*>(base + o_cov);
     b->eps = eps;
+    b->fill_rows = rows;
     return RMX_OK;
 }
 
@@ -687,7 +732,7 @@ int rmx_blur(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids, int32_t 
     if (!H && !phi) return RMX_E_ARG;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     BlurBatch b;
-    int rc = blur_setup(c, grid, solids, n_solids, eps, nullptr, phi, st, &b);
+    int rc = blur_setup(c, grid, solids, n_solids, eps, nullptr, phi, false, st, &b);
     if (rc != RMX_OK) return rc;
     b.H = H;
     return launch_blur_heaviside(b, st) == hipSuccess ? RMX_OK : RMX_E_HIP;
@@ -699,7 +744,7 @@ int rmx_solid_stress(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     if (!G || !tau || !tau[0] || !tau[1] || !tau[2]) return RMX_E_ARG;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     BlurBatch b;
-    int rc = blur_setup(c, grid, solids, n_solids, eps, G, nullptr, st, &b);
+    int rc = blur_setup(c, grid, solids, n_solids, eps, G, nullptr, true, st, &b);
     if (rc != RMX_OK) return rc;
     for (int a = 0; a < 3; ++a) b.tau[a] = tau[a];
     return launch_blur_stress(b, st) == hipSuccess ? RMX_OK : RMX_E_HIP;

@@ -31,10 +31,29 @@ struct StepBatch {
     BandCtl* band;
     double lam[3];            // dt / Delta_a
     double hl[3];             // dt / (2 Delta_a)
+    int32_t* lists;           // [2][kStepLists][list_cap]: row segments with a cell
+                              // labelled 0..L at step n (0) and at n + 1 (1), in
+                              // kStepLists sub-lists (the scan's blocks b % kStepLists)
+    int32_t* counts;          // [2][kStepLists]: their lengths (zero when the call starts)
+    int64_t list_cap;         // entries per sub-list
 };
 
-// Transverse face states and advecting velocities (zeroes the call's statistics and
-// counters first, as the classification does in an extrapolation call).
+// Sub-lists per list: a scan block appends its segments to sub-list (block % kStepLists)
+// with one atomic, so the appends spread over that many counters.
+constexpr int kStepLists = 8;
+// Row segments per scan block (16 per wave).
+constexpr int kStepScanWords = 64;
+// Entries per sub-list for a batch of `words` row segments.
+inline int64_t step_list_cap(int64_t words) {
+    const int64_t blocks = (words + kStepScanWords - 1) / kStepScanWords;
+    return (blocks + kStepLists - 1) / kStepLists * kStepScanWords;
+}
+
+// Lists the row segments labelled at step n (which = 0: also zeroes the call's statistics,
+// counters and interior masks, as the classification does in an extrapolation call) or
+// at n + 1 (which = 1).
+hipError_t launch_step_scan(const StepBatch& b, int which, hipStream_t st);
+// Transverse face states and advecting velocities.
 hipError_t launch_step_trans(const StepBatch& b, hipStream_t st);
 // Expansions of xi from the cells next to predicted cells to their faces.
 hipError_t launch_step_faces(const StepBatch& b, hipStream_t st);

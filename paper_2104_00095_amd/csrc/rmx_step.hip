@@ -20,7 +20,9 @@
 //   k_step_correct  per cell labelled at n + 1 (unless the solid failed): xi^{n+1/2} =
 //                   (xi^n + xi^{n+1}) / 2 where the cell was labelled at n too, else
 //                   xi^{n+1}.
-// Every kernel takes one 64-cell row segment per wave (the mask word of the segment).
+// A scan lists the 64-cell row segments (mask words) with a labelled cell, at step n
+// before the predictor and at n + 1 before the corrector; every other kernel then takes
+// one listed segment per wave, so a launch spans the thin band, not the box.
 // The arithmetic is evaluated per value in one fixed order without contraction (this
 // file is compiled with -ffp-contract=off), so the predicted values, and with them the
 // interior decisions, are those of any implementation of the same expressions.
@@ -64,6 +66,18 @@ __device__ __forceinline__ T ld(const T* p, int64_t i) {
 // Slope of field p at cell x along a stride s.
 __device__ __forceinline__ double slope_at(const double* p, int64_t x, int64_t s) {
     return slope4(ld(p, x - 2 * s), ld(p, x - s), ld(p, x), ld(p, x + s), ld(p, x + 2 * s));
+}
+
+// Field p at cells x and x + s, and its slopes there: the six values x - 2s .. x + 3s are
+// loaded once.
+struct Pair {
+    double vx, vy, sx, sy;
+};
+
+__device__ __forceinline__ Pair pair_at(const double* p, int64_t x, int64_t s) {
+    const double m2 = ld(p, x - 2 * s), m1 = ld(p, x - s), c0 = ld(p, x), p1 = ld(p, x + s),
+                 p2 = ld(p, x + 2 * s), p3 = ld(p, x + 3 * s);
+    return {c0, p1, slope4(m2, m1, c0, p1, p2), slope4(m1, c0, p1, p2, p3)};
 }
 
 // Godunov choice of a transverse advecting velocity from its down and up expansions.
@@ -120,7 +134,110 @@ __device__ __forceinline__ int64_t wave_segment() {
 }
 
 // ------------------------------------------------------------------------------------
-// Transverse faces.  Block 0 also zeroes the call's statistics and brick counters.
+// The scan: 16 row segments per wave, their labels loaded together; a segment with a cell
+// labelled 0..L joins the list.  A block appends its segments with one atomic to its
+// sub-list, in segment order.  At step n (which = 0) block 0 also zeroes the call's
+// statistics and brick counters, and every segment's interior mask word is zeroed (the
+// predictor writes the listed ones).
+// ------------------------------------------------------------------------------------
+constexpr int kScanWords = kStepScanWords / 4;
+
+__global__ __launch_bounds__(256) void k_step_scan(StepBatch b, int which) {
+    __shared__ int s_cnt[4];
+    __shared__ int s_base;
+    if (which == 0 && blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 256) b.stats[i] = 0ull;
+        for (int i = threadIdx.x; i < kMaxLayers * kBuckets; i += 256) b.bcount[i] = 0;
+        const int nctl = (int)(sizeof(BandCtl) / sizeof(int));
+        for (int i = threadIdx.x; i < nctl; i += 256) reinterpret_cast<int*>(b.band)[i] = 0;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t w0 = wave_segment() * kScanWords;
+    int lab[kScanWords];
+    // the wave's segments are consecutive: the first one's place is computed, the rest
+    // follow by steps (a new solid is located again)
+    // (the solid's fields are held in registers: the mask stores could alias them)
+    const int8_t* lp = nullptr;
+    unsigned long long* mask = nullptr;
+    int64_t end_w = 0, lw = 0;
+    int wx = 0, j = 0, k = 0, n0 = 0, n1 = 0, W = 1, L = 0;
+#pragma unroll
+    for (int u = 0; u < kScanWords; ++u) {
+        lab[u] = -1;
+        const int64_t w = w0 + u;
+        if (w >= b.total_words) continue;   // uniform
+        if (w >= end_w) {
+            const int s = uniform_int(find_solid_by_word(b.solids, b.n_solids, w));
+            const DevSolid* d = b.solids + s;
+            lp = which == 0 ? b.steps[s].labels_n : d->labels;
+            mask = d->mask;
+            n0 = d->n0;
+            n1 = d->n1;
+            W = d->W;
+            L = d->L;
+            end_w = d->word_base + (int64_t)W * n1 * d->n2;
+            lw = w - d->word_base;
+            const int row = (int)(lw / W);
+            wx = (int)(lw - (int64_t)row * W);
+            k = row / n1;
+            j = row - k * n1;
+        }
+        const int i = wx * 64 + lane;
+        if (i < n0) {
+            const int l = ld(lp, ((int64_t)k * n1 + j) * n0 + i);
+            lab[u] = l <= L ? l : -1;
+        }
+        if (which == 0 && lane == 0) mask[lw] = 0ull;
+        ++lw;
+        if (++wx == W) {
+            wx = 0;
+            if (++j == n1) {
+                j = 0;
+                ++k;
+            }
+        }
+    }
+    unsigned act = 0u;   // bit u: segment w0 + u is listed (the same in every lane)
+#pragma unroll
+    for (int u = 0; u < kScanWords; ++u) {
+        if (w0 + u >= b.total_words) break;   // uniform
+        if (__ballot(lab[u] >= 0)) act |= 1u << u;
+    }
+    if (lane == 0) s_cnt[wid] = __builtin_popcount(act);
+    __syncthreads();
+    const int x = blockIdx.x % kStepLists;
+    if (threadIdx.x == 0) {
+        const int tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        s_base = tot ? atomicAdd(&b.counts[which * kStepLists + x], tot) : 0;
+    }
+    __syncthreads();
+    if (lane == 0 && act) {
+        int pos = s_base;
+        for (int v = 0; v < wid; ++v) pos += s_cnt[v];
+        int32_t* list = b.lists + (int64_t)(which * kStepLists + x) * b.list_cap;
+        for (int u = 0; u < kScanWords; ++u)
+            if ((act >> u) & 1u) list[pos++] = (int32_t)(w0 + u);
+    }
+}
+
+// A listed kernel: wave i of the launch takes entries i, i + waves, ... of the
+// concatenated sub-lists.
+#define STEP_LIST_LOOP(which, body)                                                     \
+    do {                                                                                \
+        int pre_[kStepLists + 1];                                                       \
+        pre_[0] = 0;                                                                    \
+        for (int x_ = 0; x_ < kStepLists; ++x_)                                         \
+            pre_[x_ + 1] = pre_[x_] + b.counts[(which) * kStepLists + x_];               \
+        for (int i_ = (int)wave_segment(); i_ < pre_[kStepLists]; i_ += gridDim.x * 4) { \
+            int x_ = 0;                                                                 \
+            while (i_ >= pre_[x_ + 1]) ++x_;                                            \
+            const int32_t* list_ = b.lists + (int64_t)((which) * kStepLists + x_) * b.list_cap; \
+            body(b, (int64_t)list_[i_ - pre_[x_]]);                                     \
+        }                                                                               \
+    } while (0)
+
+// ------------------------------------------------------------------------------------
+// Transverse faces.
 // ------------------------------------------------------------------------------------
 __device__ void trans_segment(const StepBatch& b, int64_t w) {
     {
@@ -141,20 +258,20 @@ __device__ void trans_segment(const StepBatch& b, int64_t w) {
             const int nt = t == 0 ? d->n0 : (t == 1 ? d->n1 : d->n2);
             if (ct < 2 || ct > nt - 4) continue;
             const int64_t s = axis_stride(d, t);
-            const int64_t x = g.c, y = g.c + s;
+            const int64_t x = g.c;
             const double hl = b.hl[t];
-            const double* v = sd->u + t * nc;
-            const double vx = ld(v, x), vy = ld(v, y);
-            const double vd = vx + (0.5 - hl * vx) * slope_at(v, x, s);
-            const double vu = vy - (0.5 + hl * vy) * slope_at(v, y, s);
+            const Pair v = pair_at(sd->u + t * nc, x, s);
+            const double vx = v.vx, vy = v.vy;
+            const double vd = vx + (0.5 - hl * vx) * v.sx;
+            const double vu = vy - (0.5 + hl * vy) * v.sy;
             const double wv = godunov_vel(vd, vu);
             double* tr = sd->trans + (int64_t)t * 4 * nc;
             tr[x] = wv;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                const double* p = sd->xi_n + q * nc;
-                const double qd = ld(p, x) + (0.5 - hl * vx) * slope_at(p, x, s);
-                const double qu = ld(p, y) - (0.5 + hl * vy) * slope_at(p, y, s);
+                const Pair pq = pair_at(sd->xi_n + q * nc, x, s);
+                const double qd = pq.vx + (0.5 - hl * vx) * pq.sx;
+                const double qu = pq.vy - (0.5 + hl * vy) * pq.sy;
                 tr[(1 + q) * nc + x] = upwind(wv, qd, qu);
             }
         }
@@ -162,14 +279,7 @@ __device__ void trans_segment(const StepBatch& b, int64_t w) {
 }
 
 __global__ __launch_bounds__(256) void k_step_trans(StepBatch b) {
-    if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 256) b.stats[i] = 0ull;
-        for (int i = threadIdx.x; i < kMaxLayers * kBuckets; i += 256) b.bcount[i] = 0;
-        const int nctl = (int)(sizeof(BandCtl) / sizeof(int));
-        for (int i = threadIdx.x; i < nctl; i += 256) reinterpret_cast<int*>(b.band)[i] = 0;
-    }
-    const int64_t w = wave_segment();
-    if (w < b.total_words) trans_segment(b, w);
+    STEP_LIST_LOOP(0, trans_segment);
 }
 
 // Tangential term along axis t at cell m, component q, without the 1/Delta_t: (mean of the
@@ -183,20 +293,6 @@ __device__ __forceinline__ double tangential(const StepDev* sd, const DevSolid* 
     const double wm = ld(tr, m - s), wp = ld(tr, m);
     const double qm = ld(tr, (1 + q) * nc + m - s), qp = ld(tr, (1 + q) * nc + m);
     return (0.5 * (wm + wp)) * (qp - qm);
-}
-
-// Expansion of component q from cell x to its +a face (side = 0, the left state of that
-// face) or to its -a face (side = 1, the right state of that face); hl = dt / (2 Delta_a),
-// tang = the tangential terms of the other two axes, each times its dt / (2 Delta_t).
-__device__ __forceinline__ double side_state(const StepDev* sd, const DevSolid* d, double hl,
-                                             int64_t x, int a, int q, int side, double tang) {
-    const int64_t nc = d->ncell;
-    const int64_t s = axis_stride(d, a);
-    const double* ua = sd->u + a * nc;
-    const double* p = sd->xi_n + q * nc;
-    const double sl = slope_at(p, x, s);
-    if (side == 0) return (ld(p, x) + (0.5 - hl * ld(ua, x)) * sl) - tang;
-    return (ld(p, x) - (0.5 + hl * ld(ua, x)) * sl) - tang;
 }
 
 // Face-normal velocity on the low face of cell (i, j, k) along axis a.
@@ -243,23 +339,27 @@ __device__ void faces_segment(const StepBatch& b, int64_t w) {
         if (!hi && !lo) continue;
         const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
         const double hl = b.hl[a], h1 = b.hl[t1], h2 = b.hl[t2];
-#pragma unroll 1
+        const int64_t s = axis_stride(d, a);
+        const double ux = ld(sd->u + a * nc, g.c);
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
             const double tang =
                 h1 * tangential(sd, d, g.c, t1, q) + h2 * tangential(sd, d, g.c, t2, q);
+            // both sides share the cell's value, slope and tangential terms
+            const double* p = sd->xi_n + q * nc;
+            const double sl = slope_at(p, g.c, s), px = ld(p, g.c);
             if (hi)
                 sd->faces[(int64_t)((a * 2 + 0) * 3 + q) * nc + g.c] =
-                    side_state(sd, d, hl, g.c, a, q, 0, tang);
+                    (px + (0.5 - hl * ux) * sl) - tang;
             if (lo)
                 sd->faces[(int64_t)((a * 2 + 1) * 3 + q) * nc + g.c] =
-                    side_state(sd, d, hl, g.c, a, q, 1, tang);
+                    (px - (0.5 + hl * ux) * sl) - tang;
         }
     }
 }
 
 __global__ __launch_bounds__(256) void k_step_faces(StepBatch b) {
-    const int64_t w = wave_segment();
-    if (w < b.total_words) faces_segment(b, w);
+    STEP_LIST_LOOP(0, faces_segment);
 }
 
 // ------------------------------------------------------------------------------------
@@ -323,8 +423,7 @@ __device__ void predict_segment(const StepBatch& b, int64_t w) {
 }
 
 __global__ __launch_bounds__(256) void k_step_predict(StepBatch b) {
-    const int64_t w = wave_segment();
-    if (w < b.total_words) predict_segment(b, w);
+    STEP_LIST_LOOP(0, predict_segment);
 }
 
 // ------------------------------------------------------------------------------------
@@ -353,19 +452,29 @@ __device__ void correct_segment(const StepBatch& b, int64_t w) {
 }
 
 __global__ __launch_bounds__(256) void k_step_correct(StepBatch b) {
-    const int64_t w = wave_segment();
-    if (w < b.total_words) correct_segment(b, w);
+    STEP_LIST_LOOP(1, correct_segment);
 }
 
-// One row segment per wave, four waves per block.  (Eight segments per wave, scanned with
-// one round of label loads, measured slower: a wave then works through the active
-// segments of the dense interior one after another.)
+// Listed kernels: four waves per block, one listed segment per wave at a time, at most
+// kStepBlocks blocks (a list never exceeds the box's segments).  (Eight segments per
+// wave, one after another, measured slower: a wave then works through the active segments
+// of the dense interior in turn.)
+constexpr int64_t kStepBlocks = 4096;
+
 int step_grid(const StepBatch& b) {
-    const int64_t blocks = (b.total_words + 3) / 4;
+    int64_t blocks = (b.total_words + 3) / 4;
+    if (blocks > kStepBlocks) blocks = kStepBlocks;
     return (int)(blocks > 0 ? blocks : 1);
 }
 
 }  // namespace
+
+hipError_t launch_step_scan(const StepBatch& b, int which, hipStream_t st) {
+    const int64_t blocks = (b.total_words + kStepScanWords - 1) / kStepScanWords;
+    hipLaunchKernelGGL(k_step_scan, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
+                       st, b, which);
+    return hipGetLastError();
+}
 
 hipError_t launch_step_trans(const StepBatch& b, hipStream_t st) {
     hipLaunchKernelGGL(k_step_trans, dim3(step_grid(b)), dim3(256), 0, st, b);

@@ -392,6 +392,19 @@ class Context:
         if st != OK:
             raise RmxError(st, "rmx_blur")
 
+    def blur_raw(self, g: Grid, arr, n: int, eps: float, H_ptr, phi_ptrs, stream_handle):
+        """rmx_blur on a prebuilt Solid array and raw device pointers, no checks (timing
+        loops); returns the status."""
+        return lib().rmx_blur(self.h, ctypes.byref(g), arr, n, float(eps), H_ptr, phi_ptrs,
+                              stream_handle)
+
+    def solid_stress_raw(self, g: Grid, arr, n: int, eps: float, G_arr, tau_ptrs,
+                         stream_handle):
+        """rmx_solid_stress on prebuilt arrays, no checks (timing loops); returns the
+        status."""
+        return lib().rmx_solid_stress(self.h, ctypes.byref(g), arr, n, float(eps), G_arr,
+                                      tau_ptrs, stream_handle)
+
     def solid_stress(self, g: Grid, solids: Sequence[Solid], eps: float, G, taus,
                      stream=None):
         """Blended neo-Hookean solid stress on the faces (rmx_solid_stress): taus = three

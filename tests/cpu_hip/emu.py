@@ -176,3 +176,9 @@ def run_blur(w, tmpdir, xi, labels, eps, G, H_init, phi_init, tau_init, timeout=
     phis = [get(f"phiout{i}", phi_init[i]) for i in range(len(solids))]
     taus = [get(f"tauout{a}", tau_init[a]) for a in range(3)]
     return st, H, phis, taus
+
+
+def read_h_without_phi(tmpdir, like):
+    """H of the run_blur case's second rmx_blur call, made without phi outputs."""
+    return np.fromfile(os.path.join(tmpdir, "hout_nophi.bin"), dtype=np.float64).reshape(
+        like.shape)

@@ -159,6 +159,11 @@ int main(int argc, char** argv) {
                       nullptr);
         if (st == RMX_OK)
             st = rmx_solid_stress(ctx, &g, sol.data(), ns, eps, G.data(), tau, nullptr);
+        // H once more without phi (the kernel then takes the weights' certified bounds)
+        auto H2 = load("hinit");
+        if (st == RMX_OK)
+            st = rmx_blur(ctx, &g, sol.data(), ns, eps, static_cast<double*>(H2.first), nullptr,
+                          nullptr);
         hipDeviceSynchronize();
         auto put = [&](const std::string& name, const void* p, size_t n) {
             FILE* f = std::fopen((dir + "/" + name + ".bin").c_str(), "wb");
@@ -166,6 +171,7 @@ int main(int argc, char** argv) {
             std::fclose(f);
         };
         put("hout", H.first, H.second);
+        put("hout_nophi", H2.first, H2.second);
         for (int a = 0; a < 3; ++a) put("tauout" + std::to_string(a), tau[a], taun[a]);
         for (int i = 0; i < ns; ++i) put("phiout" + std::to_string(i), phi[i], phin[i]);
         FILE* out = std::fopen((dir + "/status.txt").c_str(), "w");

@@ -6,6 +6,7 @@ import os
 import tempfile
 from concurrent.futures import ThreadPoolExecutor
 
+import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
@@ -31,9 +32,10 @@ def blurred():
 
     def one(item):
         name, c = item
-        st, H, phis, taus = emu.run_blur(c.w, os.path.join(root, name), c.xi, c.labels, c.eps,
-                                         c.G, c.H_init, c.phi_init, c.tau_init)
-        return name, (c, st, (H, phis, taus))
+        d = os.path.join(root, name)
+        st, H, phis, taus = emu.run_blur(c.w, d, c.xi, c.labels, c.eps, c.G, c.H_init,
+                                         c.phi_init, c.tau_init)
+        return name, (c, st, (H, phis, taus), emu.read_h_without_phi(d, H))
 
     with ThreadPoolExecutor(max_workers=3) as ex:
         return dict(ex.map(one, _cases().items()))
@@ -41,6 +43,14 @@ def blurred():
 
 @pytest.mark.parametrize("name", ["sphere24", "pair", "suspension3"])
 def test_emulated_blur_matches_oracle(blurred, name):
-    c, st, got = blurred[name]
+    c, st, got, _ = blurred[name]
     assert st == 0
     compare_blur(c, got, c.oracle(), tag=name)
+
+
+@pytest.mark.parametrize("name", ["sphere24", "pair", "suspension3"])
+def test_emulated_heaviside_without_phi_is_the_same(blurred, name):
+    """Without phi outputs the kernel weighs ellipsoids through the certified distance
+    bounds where they decide H_eps: H must not change by a bit."""
+    c, st, got, h2 = blurred[name]
+    assert np.array_equal(h2.view(np.uint64), got[0].view(np.uint64))

@@ -78,3 +78,25 @@ def test_blur_refuses_bad_arguments(ctx):
     case = BlurCase(synth.sphere32(n=32, n_layers=6))
     with pytest.raises(rmx.RmxError):
         ctx.blur(rmx.grid(case.w.grid_n, case.w.h), [], case.eps, None)
+
+
+@pytest.mark.parametrize("name", ["ellipsoid64", "suspension8"])
+def test_heaviside_without_phi_is_the_same(ctx, name):
+    """Without phi outputs, ellipsoids are weighed through certified distance bounds where
+    those decide H_eps; H must equal the one computed with phi, bit for bit."""
+    import torch
+    from paper_2104_00095_amd import rmx
+    case = CASES[name]()
+    H1, _, _ = gpu_blur(ctx, case)
+    T = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    sols, keep = [], []
+    for i, s in enumerate(case.w.solids):
+        xi, lab = T(case.xi[i]), T(case.labels[i], torch.int8)
+        keep += [xi, lab]
+        sols.append(rmx.solid(s.lo, s.ext, rmx.shape(s.shape.kind, s.shape.centre,
+                                                     s.shape.semi, s.shape.rot),
+                              s.n_layers, xi, lab))
+    H2 = T(case.H_init)
+    ctx.blur(grid_of(case.w), sols, case.eps, H2, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(H2.cpu().numpy().view(np.uint64), H1.view(np.uint64))
