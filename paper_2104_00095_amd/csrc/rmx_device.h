@@ -485,6 +485,12 @@ static __constant__ double c_rlen[49] = {
     0.15430334996209191, 0.15249857033260467, 0.15075567228888181, 0.14907119849998598,
     0.14744195615489714, 0.14586499149789456, 0.14433756729740644};
 
+// 1 / |(fx rho_0, fy rho_1, fz rho_2)| (out of line: the rare path of unequal spacings
+// keeps its registers to itself).
+static __device__ __noinline__ double rlen_scaled(const double* rho, double fx, double fy, double fz) {
+    return 1.0 / norm3(fx * rho[0], fy * rho[1], fz * rho[2]);
+}
+
 struct CellCtx {
     int i, j, k, n0, n1, n2, le;
     int64_t ncell;
@@ -493,8 +499,7 @@ struct CellCtx {
     int32_t anchor;               // linear index of the anchor datum
     double a0, a1, a2;            // its xi
     double g0, g1, g2, rgn;       // normal (unnormalised) and 1/|g / rho|
-    double r0, r1, r2;            // spacing ratios (rho) when aniso
-    int aniso;
+    const double* rho;            // the solid's spacing ratios; null when they are equal
 };
 
 // Accumulate, from global memory, the moments of the eligible data within Chebyshev
@@ -524,9 +529,8 @@ __device__ __forceinline__ void gather_any(const CellCtx& cx, int r, bool use_no
                 const double fx = (double)dx, fy = (double)dy, fz = (double)dz;
                 const double dot = (fx * cx.g0 + fy * cx.g1) + fz * cx.g2;
                 if (!(dot < 0.0)) continue;
-                const double rl =
-                    cx.aniso ? 1.0 / norm3(fx * cx.r0, fy * cx.r1, fz * cx.r2)
-                             : c_rlen[dx * dx + dy * dy + dz * dz];
+                const double rl = cx.rho ? rlen_scaled(cx.rho, fx, fy, fz)
+                                         : c_rlen[dx * dx + dy * dy + dz * dz];
                 ww = (-dot * rl * cx.rgn) * ww;
             }
             const T tw = (T)ww;

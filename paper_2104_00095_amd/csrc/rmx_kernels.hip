@@ -658,6 +658,7 @@ __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
     const double* __restrict__ xi = d->xi;
     const int8_t* __restrict__ labels = d->labels;
     const int grp = threadIdx.x / NL, lq = threadIdx.x % NL;
+    const double* rho = d->aniso ? d->rho : nullptr;
     for (int ci = grp; ci < total; ci += 256 / NL) {
         const int idx = cells[ci];
         const int x = idx % kBrickSpan, y = (idx / kBrickSpan) % kBrickSpan,
@@ -686,14 +687,11 @@ __device__ __forceinline__ void fit_cells(const Batch& b, const DevSolid* d,
         cx.g1 = gn1;
         cx.g2 = gn2;
         cx.rgn = 0.0;
-        cx.r0 = d->rho[0];
-        cx.r1 = d->rho[1];
-        cx.r2 = d->rho[2];
-        cx.aniso = d->aniso;
+        cx.rho = rho;
         const bool has_normal = nrm && (gn0 != 0.0 || gn1 != 0.0 || gn2 != 0.0);
         // the physical gradient is g / rho up to a common factor (1 / h)
         if (has_normal)
-            cx.rgn = 1.0 / norm3(gn0 * d->irho[0], gn1 * d->irho[1], gn2 * d->irho[2]);
+            cx.rgn = rho ? rlen_scaled(d->irho, gn0, gn1, gn2) : 1.0 / norm3(gn0, gn1, gn2);
         const bool no_normal = nrm && !has_normal;
 
         // Passes: radii r_s..r_max with eq. (weight), then F1 (normal factor dropped) at
@@ -758,6 +756,8 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, int s, unsigned lon
                                              unsigned char* lds, int* s_wave,
                                              double* s_anchor, double* s_rlen, int& tab) {
     const DevSolid* d = b.solids + s;
+    // the table this brick needs (read before the staging, off the barriers' path)
+    const int want = d->aniso ? s : -1;
     T* sx = reinterpret_cast<T*>(lds);
     uint8_t* ss = reinterpret_cast<uint8_t*>(lds + kBrickCells * 3 * sizeof(T));
     uint16_t* cells = reinterpret_cast<uint16_t*>(lds + kBrickCells * (3 * sizeof(T) + 1));
@@ -822,7 +822,6 @@ __device__ __forceinline__ void extrap_brick(const Batch& b, int s, unsigned lon
     __syncthreads();
     // the reciprocal-length table of the solid's spacings, when another one is loaded
     // (uniform: the table's owner is the same in every thread)
-    const int want = d->aniso ? s : -1;
     if (want != tab) {
         if (tid < kRlen) s_rlen[tid] = rlen_entry(d, tid);
         tab = want;
