@@ -320,6 +320,17 @@ int rmx_solid_stress(rmx_ctx* ctx, const rmx_grid* grid, const rmx_solid* solids
 int rmx_layers_for_blur(double eps, double h, double stretch, int32_t reach, uint32_t flags,
                         int32_t* L);
 
+/* The same count on a grid with unequal spacings (rmx_grid.spacing; equal spacings give
+ * rmx_layers_for_blur's count with h).  Host only.  With Delta_a the spacings, a resolved
+ * solid holds a ball of radius |Delta| / 2 beneath every surface point, so a cell with
+ * 0 < phi < eps lies within D = stretch * eps + |Delta| of an interior cell centre; that
+ * is at most ceil(D / min_a Delta_a) cube layers (RMX_FLAG_ADJ26) or
+ * ceil(D * sqrt(sum_a Delta_a^-2)) face layers (the L1 cell distance of a displacement v
+ * is sum_a |v_a| / Delta_a <= |v| sqrt(sum_a Delta_a^-2)), plus `reach`.  Errors as
+ * rmx_layers_for_blur's, and RMX_E_ARG for a null or invalid grid. */
+int rmx_layers_for_blur_grid(const rmx_grid* grid, double eps, double stretch, int32_t reach,
+                             uint32_t flags, int32_t* L);
+
 const char* rmx_status_string(int status);
 
 /* Autotuner.  Launch shapes that change no result: the label tile width (1, 2 or 4 words

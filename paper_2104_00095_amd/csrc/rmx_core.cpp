@@ -763,6 +763,27 @@ int rmx_layers_for_blur(double eps, double h, double stretch, int32_t reach, uin
     return RMX_OK;
 }
 
+int rmx_layers_for_blur_grid(const rmx_grid* grid, double eps, double stretch, int32_t reach,
+                             uint32_t flags, int32_t* L) {
+    if (!grid || !L || !(grid->h > 0.0) || !std::isfinite(grid->h) || !(eps > 0.0) ||
+        !std::isfinite(eps) || !(stretch >= 1.0) || !std::isfinite(stretch) || reach < 0)
+        return RMX_E_ARG;
+    double d2 = 0.0, inv2 = 0.0, dmin = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (!(grid->spacing[a] >= 0.0) || !std::isfinite(grid->spacing[a])) return RMX_E_ARG;
+        const double d = grid->spacing[a] > 0.0 ? grid->spacing[a] : grid->h;
+        d2 += d * d;
+        inv2 += 1.0 / (d * d);
+        dmin = a == 0 ? d : std::min(dmin, d);
+    }
+    const double D = stretch * eps + std::sqrt(d2);
+    const double cells = (flags & RMX_FLAG_ADJ26) ? D / dmin : D * std::sqrt(inv2);
+    const double l = std::ceil(cells) + (double)reach;
+    if (!(l <= RMX_MAX_LAYERS)) return RMX_E_LAYERS;
+    *L = (int32_t)l;
+    return RMX_OK;
+}
+
 int rmx_extrapolate_noalloc(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
                             int32_t n_solids, const rmx_options* opt, void* hip_stream,
                             rmx_solid_stats* stats) {

@@ -34,6 +34,7 @@ EXPORTS = [
     "rmx_server_usage", "rmx_server_destroy", "rmx_profile_read", "rmx_autotune",
     "rmx_set_tuning", "rmx_extrapolate_noalloc", "rmx_step", "rmx_blur", "rmx_solid_stress",
     "rmx_layers_for_blur",
+    "rmx_layers_for_blur_grid",
 ]
 
 
@@ -136,6 +137,9 @@ def lib():
                                ctypes.c_double, vp, P(SolidStats)]
         L.rmx_blur.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, ctypes.c_double, vp, vp,
                                vp]
+        L.rmx_layers_for_blur_grid.argtypes = [P(Grid), ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_int32, ctypes.c_uint32,
+                                               P(ctypes.c_int32)]
         L.rmx_layers_for_blur.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int32, ctypes.c_uint32, P(ctypes.c_int32)]
         L.rmx_solid_stress.argtypes = [vp, P(Grid), P(Solid), ctypes.c_int32, ctypes.c_double,
@@ -240,6 +244,18 @@ def layers_for_blur(eps: float, h: float, stretch: float = 1.0, reach: int = 0,
                                    int(flags), ctypes.byref(out))
     if st != OK:
         raise RmxError(st, "rmx_layers_for_blur")
+    return int(out.value)
+
+
+def layers_for_blur_grid(g: Grid, eps: float, stretch: float = 1.0, reach: int = 0,
+                         flags: int = 0) -> int:
+    """Layer count whose band covers the blur zone on a grid with unequal spacings
+    (rmx_layers_for_blur_grid)."""
+    out = ctypes.c_int32(0)
+    st = lib().rmx_layers_for_blur_grid(ctypes.byref(g), float(eps), float(stretch),
+                                        int(reach), int(flags), ctypes.byref(out))
+    if st != OK:
+        raise RmxError(st, "rmx_layers_for_blur_grid")
     return int(out.value)
 
 

@@ -53,3 +53,51 @@ def test_band_covers_the_blur_zone(seed, adj):
     phi = np.vectorize(lambda x, y, z: oracle.phi0(shape, (x, y, z)))(X[0], X[1], X[2])
     blur = phi < eps
     assert np.all(lab[blur] >= 0), int((lab[blur] < 0).sum())
+
+
+def test_grid_form_with_equal_spacings_is_the_plain_form():
+    h = 0.02
+    for eps, stretch, reach, flags in ((0.03, 1.0, 0, 0), (0.05, 1.5, 2, rmx.FLAG_ADJ26),
+                                      (0.01, 1.0, 1, 0)):
+        want = rmx.layers_for_blur(eps, h, stretch, reach, flags)
+        assert rmx.layers_for_blur_grid(rmx.grid((10, 10, 10), h), eps, stretch, reach,
+                                        flags) == want
+        assert rmx.layers_for_blur_grid(rmx.grid((10, 10, 10), 1.0, spacing=(h, h, h)), eps,
+                                        stretch, reach, flags) == want
+    for bad in ((rmx.grid((10, 10, 10), h, spacing=(h, -h, h)), 0.03),
+                (rmx.grid((10, 10, 10), h, spacing=(h, float("inf"), h)), 0.03),
+                (rmx.grid((10, 10, 10), 0.0), 0.03), (rmx.grid((10, 10, 10), h), 0.0)):
+        with pytest.raises(rmx.RmxError):
+            rmx.layers_for_blur_grid(*bad)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("adj", [6, 26])
+def test_band_covers_the_blur_zone_with_unequal_spacings(seed, adj):
+    """Random spacings per axis (0.7..1.5 of h), random resolved spheres and rotated
+    ellipsoids in physical coordinates (xi = x): every cell with phi0 < eps is labelled."""
+    rng = np.random.default_rng(700 + seed)
+    h = 1.0 / 40
+    sp = tuple(float(v) for v in rng.uniform(0.7, 1.5, 3) * h)
+    n = tuple(int(math.ceil(1.0 / d)) for d in sp)
+    eps = float(rng.uniform(1.0, 2.5)) * max(sp)
+    flags = rmx.FLAG_ADJ26 if adj == 26 else 0
+    L = rmx.layers_for_blur_grid(rmx.grid(n, h, spacing=sp), eps, flags=flags)
+    c = rng.uniform(0.42, 0.58, 3)
+    if seed % 2:
+        shape = oracle.make_shape(1, c, (float(rng.uniform(0.1, 0.2)),))
+    else:
+        th = rng.uniform(0, 2 * math.pi, 2)
+        Rz = np.array([[math.cos(th[0]), -math.sin(th[0]), 0],
+                       [math.sin(th[0]), math.cos(th[0]), 0], [0, 0, 1]])
+        Rx = np.array([[1, 0, 0], [0, math.cos(th[1]), -math.sin(th[1])],
+                       [0, math.sin(th[1]), math.cos(th[1])]])
+        shape = oracle.make_shape(2, c, tuple(rng.uniform(0.1, 0.2, 3)), Rz @ Rx)
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    X = np.stack([(i + 0.5) * sp[0], (j + 0.5) * sp[1], (k + 0.5) * sp[2]])
+    prob = oracle.make_problem(n, (0, 0, 0), n, shape, L, adjacency=adj, spacing=sp)
+    nint, lab, trunc = oracle.label(prob, X)
+    assert nint > 0 and not trunc
+    phi = np.vectorize(lambda x, y, z: oracle.phi0(shape, (x, y, z)))(X[0], X[1], X[2])
+    blur = phi < eps
+    assert np.all(lab[blur] >= 0), int((lab[blur] < 0).sum())
