@@ -142,9 +142,10 @@ __device__ __forceinline__ int64_t wave_segment() {
 // ------------------------------------------------------------------------------------
 constexpr int kScanWords = kStepScanWords / 4;
 
+__device__ void scan_append(const StepBatch& b, int which, unsigned act, int lane, int wid,
+                            int64_t w0);
+
 __global__ __launch_bounds__(256) void k_step_scan(StepBatch b, int which) {
-    __shared__ int s_cnt[4];
-    __shared__ int s_base;
     if (which == 0 && blockIdx.x == 0) {
         for (int i = threadIdx.x; i < b.n_solids * kStatWords; i += 256) b.stats[i] = 0ull;
         for (int i = threadIdx.x; i < kMaxLayers * kBuckets; i += 256) b.bcount[i] = 0;
@@ -153,6 +154,31 @@ __global__ __launch_bounds__(256) void k_step_scan(StepBatch b, int which) {
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t w0 = wave_segment() * kScanWords;
+    unsigned act = 0u;   // bit u: segment w0 + u is listed (the same in every lane)
+    // Whole rows of whole segments (n0 a multiple of 64, 16-byte aligned labels): the
+    // wave's 16 segments are 1 KB of consecutive labels, 16 bytes per lane, tested four at
+    // a time for a byte below L + 1 (unsigned: -1 is 255).
+    if (w0 < b.total_words) {
+        const int s = uniform_int(find_solid_by_word(b.solids, b.n_solids, w0));
+        const DevSolid* d = b.solids + s;
+        const int8_t* lp = which == 0 ? b.steps[s].labels_n : d->labels;
+        const int64_t lw0 = w0 - d->word_base;
+        const int64_t nw = (int64_t)d->W * d->n1 * d->n2;
+        if (d->n0 == 64 * d->W && lw0 + kScanWords <= nw &&
+            (reinterpret_cast<uintptr_t>(lp) & 15) == 0) {
+            const uint4 v = reinterpret_cast<const uint4*>(lp + lw0 * 64)[lane];
+            const unsigned n = 0x01010101u * (unsigned)(d->L + 1);
+            const auto below = [n](unsigned x) { return ((x - n) & ~x & 0x80808080u) != 0u; };
+            const bool f = below(v.x) || below(v.y) || below(v.z) || below(v.w);
+            const unsigned long long m = __ballot(f);
+#pragma unroll
+            for (int u = 0; u < kScanWords; ++u)
+                if ((m >> (4 * u)) & 0xFull) act |= 1u << u;
+            if (which == 0 && lane < kScanWords) d->mask[lw0 + lane] = 0ull;
+            scan_append(b, which, act, lane, wid, w0);
+            return;
+        }
+    }
     int lab[kScanWords];
     // the wave's segments are consecutive: the first one's place is computed, the rest
     // follow by steps (a new solid is located again)
@@ -197,12 +223,20 @@ __global__ __launch_bounds__(256) void k_step_scan(StepBatch b, int which) {
             }
         }
     }
-    unsigned act = 0u;   // bit u: segment w0 + u is listed (the same in every lane)
 #pragma unroll
     for (int u = 0; u < kScanWords; ++u) {
         if (w0 + u >= b.total_words) break;   // uniform
         if (__ballot(lab[u] >= 0)) act |= 1u << u;
     }
+    scan_append(b, which, act, lane, wid, w0);
+}
+
+// A block's listed segments (bits of each wave's act) appended to its sub-list with one
+// atomic, in segment order.
+__device__ void scan_append(const StepBatch& b, int which, unsigned act, int lane, int wid,
+                            int64_t w0) {
+    __shared__ int s_cnt[4];
+    __shared__ int s_base;
     if (lane == 0) s_cnt[wid] = __builtin_popcount(act);
     __syncthreads();
     const int x = blockIdx.x % kStepLists;

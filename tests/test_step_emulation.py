@@ -26,6 +26,8 @@ def _workloads():
                                         n_layers=6),
         "sphere24_L5": synth.sphere32(n=24, n_layers=5),
         "wall_sphere24": wall_sphere(24),
+        # rows of whole 64-cell segments: the scan's 16-byte-per-lane path
+        "sphere64": synth.sphere32(n=64, n_layers=5),
     }
 
 
@@ -50,7 +52,8 @@ def stepped():
         return dict(ex.map(one, _workloads().items()))
 
 
-@pytest.mark.parametrize("name", ["sphere24", "ellipsoid36", "suspension3", "sphere24_L5"])
+@pytest.mark.parametrize("name", ["sphere24", "ellipsoid36", "suspension3", "sphere24_L5",
+                                  "sphere64"])
 def test_emulated_step_matches_oracle(stepped, name):
     case, st, got = stepped[name]
     expect = [(o[0], o[1], o[2], o[3], o[5]) for o in case.oracle()]
