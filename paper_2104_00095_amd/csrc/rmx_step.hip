@@ -94,6 +94,14 @@ __device__ __forceinline__ double upwind(double w, double lo, double hi) {
     return 0.5 * (lo + hi);
 }
 
+// upwind() on stored states, loading only the state(s) the sign of w selects.
+__device__ __forceinline__ double upwind_ld(double w, const double* plo, int64_t ilo,
+                                            const double* phi, int64_t ihi) {
+    if (w > 0.0) return load_global(plo + ilo);
+    if (w < 0.0) return load_global(phi + ihi);
+    return 0.5 * (load_global(plo + ilo) + load_global(phi + ihi));
+}
+
 __device__ __forceinline__ int find_solid_by_word(const DevSolid* s, int n, int64_t w) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -303,10 +311,20 @@ __device__ void trans_segment(const StepBatch& b, int64_t w) {
             tr[x] = wv;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                const Pair pq = pair_at(sd->xi_n + q * nc, x, s);
-                const double qd = pq.vx + (0.5 - hl * vx) * pq.sx;
-                const double qu = pq.vy - (0.5 + hl * vy) * pq.sy;
-                tr[(1 + q) * nc + x] = upwind(wv, qd, qu);
+                // only the expansion the sign of wv selects (both where it is 0)
+                const double* p = sd->xi_n + q * nc;
+                double v;
+                if (wv > 0.0) {
+                    v = ld(p, x) + (0.5 - hl * vx) * slope_at(p, x, s);
+                } else if (wv < 0.0) {
+                    v = ld(p, x + s) - (0.5 + hl * vy) * slope_at(p, x + s, s);
+                } else {
+                    const Pair pq = pair_at(p, x, s);
+                    const double qd = pq.vx + (0.5 - hl * vx) * pq.sx;
+                    const double qu = pq.vy - (0.5 + hl * vy) * pq.sy;
+                    v = upwind(wv, qd, qu);
+                }
+                tr[(1 + q) * nc + x] = v;
             }
         }
     }
@@ -314,19 +332,6 @@ __device__ void trans_segment(const StepBatch& b, int64_t w) {
 
 __global__ __launch_bounds__(256) void k_step_trans(StepBatch b) {
     STEP_LIST_LOOP(0, trans_segment);
-}
-
-// Tangential term along axis t at cell m, component q, without the 1/Delta_t: (mean of the
-// transverse advecting velocities on the cell's two t-faces) x (difference of the chosen
-// states).
-__device__ __forceinline__ double tangential(const StepDev* sd, const DevSolid* d, int64_t m,
-                                             int t, int q) {
-    const int64_t nc = d->ncell;
-    const int64_t s = axis_stride(d, t);
-    const double* tr = sd->trans + (int64_t)t * 4 * nc;
-    const double wm = ld(tr, m - s), wp = ld(tr, m);
-    const double qm = ld(tr, (1 + q) * nc + m - s), qp = ld(tr, (1 + q) * nc + m);
-    return (0.5 * (wm + wp)) * (qp - qm);
 }
 
 // Face-normal velocity on the low face of cell (i, j, k) along axis a.
@@ -368,17 +373,32 @@ __device__ void faces_segment(const StepBatch& b, int64_t w) {
     for (int a = 0; a < 3; ++a) {
         // +a face: read by this cell or by its +a neighbour; -a face: by this cell or by its
         // -a neighbour
-        const bool hi = self || predicted(sd, d, g.i + (a == 0), g.j + (a == 1), g.k + (a == 2));
-        const bool lo = self || predicted(sd, d, g.i - (a == 0), g.j - (a == 1), g.k - (a == 2));
+        // ... and only the side the face velocity's sign selects there (both where it is 0)
+        const bool hi =
+            (self || predicted(sd, d, g.i + (a == 0), g.j + (a == 1), g.k + (a == 2))) &&
+            !(face_vel(sd, d, a, g.i + (a == 0), g.j + (a == 1), g.k + (a == 2)) < 0.0);
+        const bool lo =
+            (self || predicted(sd, d, g.i - (a == 0), g.j - (a == 1), g.k - (a == 2))) &&
+            !(face_vel(sd, d, a, g.i, g.j, g.k) > 0.0);
         if (!hi && !lo) continue;
         const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
         const double hl = b.hl[a], h1 = b.hl[t1], h2 = b.hl[t2];
         const int64_t s = axis_stride(d, a);
         const double ux = ld(sd->u + a * nc, g.c);
+        // Tangential terms along t1 and t2, each without its 1/Delta_t: (mean of the
+        // transverse advecting velocities on the cell's two t-faces, shared by the three
+        // components) x (difference of the chosen states)
+        const int64_t s1 = axis_stride(d, t1), s2 = axis_stride(d, t2);
+        const double* tr1 = sd->trans + (int64_t)t1 * 4 * nc;
+        const double* tr2 = sd->trans + (int64_t)t2 * 4 * nc;
+        const double w1 = 0.5 * (ld(tr1, g.c - s1) + ld(tr1, g.c));
+        const double w2 = 0.5 * (ld(tr2, g.c - s2) + ld(tr2, g.c));
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const double tang =
-                h1 * tangential(sd, d, g.c, t1, q) + h2 * tangential(sd, d, g.c, t2, q);
+            const double* q1 = tr1 + (1 + q) * nc;
+            const double* q2 = tr2 + (1 + q) * nc;
+            const double tang = h1 * (w1 * (ld(q1, g.c) - ld(q1, g.c - s1))) +
+                                h2 * (w2 * (ld(q2, g.c) - ld(q2, g.c - s2)));
             // both sides share the cell's value, slope and tangential terms
             const double* p = sd->xi_n + q * nc;
             const double sl = slope_at(p, g.c, s), px = ld(p, g.c);
@@ -433,9 +453,9 @@ __device__ void predict_segment(const StepBatch& b, int64_t w) {
                     const double* fl = sd->faces + (int64_t)((a * 2 + 0) * 3 + q) * nc;
                     const double* fr = sd->faces + (int64_t)((a * 2 + 1) * 3 + q) * nc;
                     // -a face: left state from cell c - e_a, right state from c
-                    const double xm = upwind(um[a], ld(fl, g.c - s), ld(fr, g.c));
+                    const double xm = upwind_ld(um[a], fl, g.c - s, fr, g.c);
                     // +a face: left state from c, right state from c + e_a
-                    const double xp = upwind(up[a], ld(fl, g.c), ld(fr, g.c + s));
+                    const double xp = upwind_ld(up[a], fl, g.c, fr, g.c + s);
                     term[a] = (0.5 * (um[a] + up[a])) * (xp - xm);
                 }
                 const double acc = (l0 * term[0] + l1 * term[1]) + l2 * term[2];
