@@ -344,17 +344,6 @@ __device__ __forceinline__ int opaque_lane_value(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0xE4, 0xf, 0xf, false);   // quad_perm [0,1,2,3]
 }
 
-// Spread the low 4 bits of x to the low bit of 4 bytes (bit q -> byte q).  The partial
-// products of x * (1 + 2^7 + 2^14 + 2^21) land on distinct bit positions, so no carries.
-__device__ __forceinline__ uint32_t spread4(uint32_t x) {
-    return (x * 0x00204081u) & 0x01010101u;
-}
-
-__device__ __forceinline__ unsigned long long spread8(uint32_t x) {
-    return (unsigned long long)spread4(x & 15u) |
-           ((unsigned long long)spread4((x >> 4) & 15u) << 32);
-}
-
 // ------------------------------------------------------------------------------------
 // Extrapolation of one layer.  A group of NL = 4, 8 or 16 aligned lanes per band cell.
 // ------------------------------------------------------------------------------------

@@ -159,16 +159,60 @@ __global__ __launch_bounds__(256) void k_classify(Batch b) {
 }
 
 // ------------------------------------------------------------------------------------
-// Labels of one tile of 16 (y) x 16 (z) rows x tile_w 64-cell words (x); thread (tj, tk)
-// owns one row of the tile.  The region in LDS carries a halo of L rows in y and z and
+// Labels of one tile of 16 (y) x 16 (z) rows x tile_w 64-cell words (x), by a block of
+// 512 threads: threads i and i + 256 own row (tj, tk) = (i % 16, i / 16) of the tile, the
+// first the low half of its words, the second the high half (with one word, the first
+// all of it).  The region in LDS carries a halo of L rows in y and z and
 // one word on each side in x where the box continues (L <= 16 < 64), so after L dilations
 // through face neighbours (64-bit shifts and ORs) the tile is exact; dilation l is formed
 // only on the rows within L - l of the tile, the only ones later dilations read.  Counts
 // go to LDS by atomics, one wave appends the tile's bricks with one round of global
-// atomics for all layers, and full-width tiles write their labels through an LDS
-// transpose, whole 128-byte rows per store instruction.
+// atomics for all layers, and the labels go through an LDS transpose: whole 128-byte rows
+// per store instruction in full-width tiles, aligned 4-byte words elsewhere.
 // ------------------------------------------------------------------------------------
-constexpr int kRowsPerThread = 9;   // ceil((16 + 2 * 16)^2 / 256)
+constexpr int kLabelThreads = 512;
+constexpr int kRowsPerThread =      // region rows per thread at most: (16 + 2 * 16)^2 rows
+    ((kTileJ + 2 * kMaxLayers) * (kTileK + 2 * kMaxLayers) + kLabelThreads - 1) / kLabelThreads;
+
+// Label bytes of the 8 cells at bits 8g..8g+7 of a row word: the layer (bit planes
+// p0..p4 hold its bits) where the cell was reached, 0xFF where not.  Bit q of a plane's
+// nibble goes to bit 8q + k of a 32-bit half by one product (the partial products of
+// nibble * (1 + 2^7 + 2^14 + 2^21) never overlap, and the shift by the plane k is folded
+// into the constants); a cell not reached has no plane bit.  NP planes are read: layers
+// below 2^NP.
+template <int NP>
+__device__ __forceinline__ unsigned long long label_word(
+    unsigned long long p0, unsigned long long p1, unsigned long long p2, unsigned long long p3,
+    unsigned long long p4, unsigned long long reached, int sh8) {
+    const unsigned long long pl[5] = {p0, p1, p2, p3, p4};
+    uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const uint32_t b = (uint32_t)(pl[k] >> sh8) & 255u;
+        lo |= ((b & 15u) * (0x00204081u << k)) & (0x01010101u << k);
+        hi |= ((b >> 4) * (0x00204081u << k)) & (0x01010101u << k);
+    }
+    const uint32_t u = (uint32_t)(~reached >> sh8) & 255u;
+    lo |= (((u & 15u) * 0x00204081u) & 0x01010101u) * 0xFFu;
+    hi |= (((u >> 4) * 0x00204081u) & 0x01010101u) * 0xFFu;
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// The sum over the wave (every lane active): DPP sums within each row of 16 lanes (every
+// lane of a row ends with the row's sum), then the four rows' sums read out.
+__device__ __forceinline__ int wave_sum(int v) {
+    v += dpp_i<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_i<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_i<0x141>(v);   // row_half_mirror
+    v += dpp_i<0x140>(v);   // row_mirror
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
+
+template <int N>
+struct IntC {
+    static constexpr int value = N;
+};
 
 // Brick r of a tile's layer-l flags (r = brick row pair * 8 * MAXTW + 8 w + g).
 template <int MAXTW>
@@ -176,9 +220,47 @@ __device__ __forceinline__ bool brick_flag(const unsigned int* s_bmask, int l, i
     return (s_bmask[(l - 1) * 4 + r / (8 * MAXTW)] >> (r % (8 * MAXTW))) & 1u;
 }
 
+// Bytes value(r, x) of the cells of a tile (row r = tk * kTileJ + tj, column x of the nx
+// from the tile's first column xs) into dst, a box array, by the whole block; quad(r, x)
+// gives the four bytes x..x+3 of row r at once.  The tile's bytes form runs: one per plane
+// when it spans whole box rows (its rows of a plane are contiguous), else one per row.
+// Thread i takes aligned 4-byte slot i of the runs' slots: one word store where the slot
+// lies inside one row of its run, byte stores at a run's ends and across two rows.
+template <typename F, typename Q>
+__device__ __forceinline__ void store_tile_bytes(int8_t* dst, const DevSolid* d, int xs, int nx,
+                                                 int j0, int k0, F value, Q quad) {
+    const int n0 = d->n0, n1 = d->n1, n2 = d->n2;
+    const int nj = min(kTileJ, n1 - j0), nk = min(kTileK, n2 - k0);
+    const bool whole = xs == 0 && nx == n0;
+    const int len = whole ? nj * n0 : nx;   // bytes per run
+    const int nrun = whole ? nk : nk * nj;
+    const int U = (len + 3) / 4 + 1;        // aligned slots a run touches, at most
+    for (int i = threadIdx.x; i < nrun * U; i += blockDim.x) {
+        const int u = i / U, slot = i - u * U;
+        const int tk = whole ? u : u / nj, tj0 = whole ? 0 : u - (u / nj) * nj;
+        int8_t* run = dst + ((int64_t)(k0 + tk) * n1 + (j0 + tj0)) * n0 + xs;
+        const int q0 = 4 * slot - (int)(reinterpret_cast<uintptr_t>(run) & 3u);
+        if (q0 >= len) continue;
+        const int qs = q0 < 0 ? 0 : q0;
+        const int tj = whole ? qs / n0 : 0;   // row within the run, and column
+        int r = tk * kTileJ + tj0 + tj, x = qs - tj * (whole ? n0 : 0);
+        if (q0 >= 0 && q0 + 4 <= len && x + 4 <= nx) {
+            *reinterpret_cast<uint32_t*>(run + q0) = quad(r, x);
+            continue;
+        }
+        for (int q = qs; q < q0 + 4 && q < len; ++q) {
+            run[q] = (int8_t)value(r, x);
+            if (++x == nx) {
+                x = 0;
+                ++r;
+            }
+        }
+    }
+}
+
 // Labels of a tile with no layer cell: -1 everywhere (and decision 0).  Whole-width tiles
 // with 16-byte aligned rows store 16-byte chunks, consecutive threads on consecutive
-// chunks of a row; other tiles store their rows byte by byte.
+// chunks of a row; other tiles go through the block's word stores.
 template <int MAXTW>
 __device__ __forceinline__ void label_tile_empty(const DevSolid* d, int wx0, int tw, int j0,
                                                  int k0) {
@@ -192,8 +274,8 @@ __device__ __forceinline__ void label_tile_empty(const DevSolid* d, int wx0, int
         constexpr int CPR = 4 * MAXTW;   // 16-byte chunks per row
         const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u), zero = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-        for (int h = 0; h < CPR; ++h) {
-            const int c = tid + 256 * h;
+        for (int h = 0; h < 256 * CPR / kLabelThreads; ++h) {
+            const int c = tid + kLabelThreads * h;
             const int row = c / CPR, off = c % CPR;
             const int jj = j0 + row % kTileJ, kk = k0 + row / kTileJ;
             if (jj < n1 && kk < n2) {
@@ -204,19 +286,18 @@ __device__ __forceinline__ void label_tile_empty(const DevSolid* d, int wx0, int
         }
         return;
     }
-    const int jj = j0 + tid % kTileJ, kk = k0 + tid / kTileJ;
-    if (jj >= n1 || kk >= n2) return;
-    const int64_t o = ((int64_t)kk * n1 + jj) * n0 + xs;
-    for (int i = 0; i < nx; ++i) {
-        d->labels[o + i] = (int8_t)-1;
-        if (d->decisions) d->decisions[o + i] = 0;
-    }
+    store_tile_bytes(d->labels, d, xs, nx, j0, k0, [](int, int) { return 0xFFu; },
+                     [](int, int) { return 0xFFFFFFFFu; });
+    if (d->decisions)
+        store_tile_bytes(d->decisions, d, xs, nx, j0, k0, [](int, int) { return 0u; },
+                         [](int, int) { return 0u; });
 }
 
 template <int MAXTW>
-__global__ __launch_bounds__(256) void k_label(Batch b) {
+__global__ __launch_bounds__(kLabelThreads) void k_label(Batch b) {
     constexpr int FPL = 4 * 8 * MAXTW;   // brick flags per layer: 2 (y) x 2 (z) x 8 per word
     constexpr int MW = MAXTW + 2;        // region words per row at most
+    constexpr int WPH = MAXTW > 1 ? MAXTW / 2 : 1;   // row words per owning thread
     HIP_DYNAMIC_SHARED(double, lds_d)
     unsigned long long* lds = reinterpret_cast<unsigned long long*>(lds_d);
     __shared__ int s_cnt[kLT];
@@ -246,7 +327,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     const unsigned long long tail = (n0 & 63) ? ((1ull << (n0 & 63)) - 1ull) : ~0ull;
     const unsigned long long* __restrict__ mask = d->mask;
 
-    for (int q = tid; q < L * 4; q += 256) s_bmask[q] = 0u;
+    for (int q = tid; q < L * 4; q += kLabelThreads) s_bmask[q] = 0u;
     if (tid < kLT) s_cnt[tid] = 0;
     if (tid == 0) s_trunc = 0;
     // The mask rows of the region (rows outside the box: empty).  Every load of the
@@ -256,7 +337,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     unsigned long long any = 0ull;
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
-        const int rr = tid + 256 * q;
+        const int rr = tid + kLabelThreads * q;
         const int rj = rr % RJ, rk = rr / RJ;
         const int jj = j0 - L + rj, kk = k0 - L + rk;
         const bool ok = rr < R && jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
@@ -276,7 +357,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     }
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
-        const int rr = tid + 256 * q;
+        const int rr = tid + kLabelThreads * q;
         if (rr < R) {
 #pragma unroll
             for (int w = 0; w < MW; ++w)
@@ -285,22 +366,24 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     }
     __syncthreads();
 
-    const int tj = tid % kTileJ, tk = tid / kTileJ;
+    const int row = tid & 255, wb = (tid >> 8) * WPH;   // the row; its first owned word
+    const int tj = row % kTileJ, tk = row / kTileJ;
     const int jrow = j0 + tj, krow = k0 + tk;
     const bool row_ok = jrow < n1 && krow < n2;
-    const int my = ((tk + L) * RJ + (tj + L)) * RS + (wx0 - xr0);
-    unsigned long long prev[MAXTW], p0[MAXTW], p1[MAXTW], p2[MAXTW], p3[MAXTW], p4[MAXTW];
+    const int my = ((tk + L) * RJ + (tj + L)) * RS + (wx0 - xr0) + wb;
+    // owned words wb + w, w < WPH (none past the tile)
+    unsigned long long prev[WPH], p0[WPH], p1[WPH], p2[WPH], p3[WPH], p4[WPH];
     int cnt0 = 0;
     bool trunc = false;
 #pragma unroll
-    for (int w = 0; w < MAXTW; ++w) {
-        prev[w] = (row_ok && w < tw) ? A[my + w] : 0ull;
+    for (int w = 0; w < WPH; ++w) {
+        prev[w] = (row_ok && wb + w < tw) ? A[my + w] : 0ull;
         p0[w] = p1[w] = p2[w] = p3[w] = p4[w] = 0ull;
         cnt0 += __popcll(prev[w]);
         // An interior cell closer than L to a box face that is no grid wall: the band
         // would leave the box (reported; the solid's band is then not fitted).
         if (prev[w]) {
-            const int x0 = (wx0 + w) * 64;
+            const int x0 = (wx0 + wb + w) * 64;
             if (!d->wall_lo[0] && x0 < L) {
                 const int nb = min(64, L - x0);
                 trunc |= (prev[w] & (nb == 64 ? ~0ull : ((1ull << nb) - 1ull))) != 0ull;
@@ -315,8 +398,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
     }
     // counts: wave sums, then one LDS atomic per wave
     const int lane = tid & 63;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cnt0 += __shfl_xor(cnt0, o, 64);
+    cnt0 = wave_sum(cnt0);
     if (lane == 0 && cnt0) atomicAdd(&s_cnt[0], cnt0);
     if (trunc) s_trunc = 1;
 
@@ -330,7 +412,7 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
         const unsigned long long* __restrict__ Ar = A;
         unsigned long long* __restrict__ Br = B;
         const int SJ = RJ - 2 * l, S = SJ * (RK - 2 * l);
-        for (int i = tid; i < S; i += 256) {
+        for (int i = tid; i < S; i += kLabelThreads) {
             const int rk = l + i / SJ, rj = l + i % SJ;
             const int jj = j0 - L + rj, kk = k0 - L + rk;
             const bool rok = jj >= 0 && jj < n1 && kk >= 0 && kk < n2;
@@ -373,8 +455,8 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
         int cnt = 0;
         unsigned int fl = 0u;   // bricks of this row holding a layer-l cell: bit 8w + g
 #pragma unroll
-        for (int w = 0; w < MAXTW; ++w) {
-            const unsigned long long dl = (row_ok && w < tw) ? A[my + w] : 0ull;
+        for (int w = 0; w < WPH; ++w) {
+            const unsigned long long dl = (row_ok && wb + w < tw) ? A[my + w] : 0ull;
             const unsigned long long nw = dl & ~prev[w];
             prev[w] = dl;
             if (l & 1) p0[w] |= nw;
@@ -385,19 +467,27 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
             cnt += __popcll(nw);
 #pragma unroll
             for (int g = 0; g < 8; ++g)
-                if ((nw >> (8 * g)) & 255ull) fl |= 1u << (w * 8 + g);
+                if ((nw >> (8 * g)) & 255ull) fl |= 1u << ((wb + w) * 8 + g);
         }
-        // Wave sums of the counts; the flags ORed over the lanes of one brick row pair (a
-        // wave's lanes share tk >> 3; lane bit 3 is tj >> 3): then a few LDS atomics.
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-        if (lane == 0 && cnt) atomicAdd(&s_cnt[l], cnt);
-        fl |= __shfl_xor(fl, 1, 64);
-        fl |= __shfl_xor(fl, 2, 64);
-        fl |= __shfl_xor(fl, 4, 64);
-        fl |= __shfl_xor(fl, 16, 64);
-        fl |= __shfl_xor(fl, 32, 64);
-        if ((lane & 0x37) == 0 && fl) atomicOr(&s_bmask[(l - 1) * 4 + by2], fl);
+        // Wave sums of the counts; the flags ORed over the lanes of each brick row pair (a
+        // wave's lanes share tk >> 3, lane bit 3 is tj >> 3): then lane 0's LDS atomics.
+        cnt = wave_sum(cnt);
+        fl |= dpp_i<0xB1>((int)fl);    // quad_perm [1,0,3,2]
+        fl |= dpp_i<0x4E>((int)fl);    // quad_perm [2,3,0,1]
+        fl |= dpp_i<0x141>((int)fl);   // row_half_mirror: the OR over each 8 lanes
+        const unsigned int f0 = (unsigned)(__builtin_amdgcn_readlane((int)fl, 0) |
+                                           __builtin_amdgcn_readlane((int)fl, 16) |
+                                           __builtin_amdgcn_readlane((int)fl, 32) |
+                                           __builtin_amdgcn_readlane((int)fl, 48));
+        const unsigned int f1 = (unsigned)(__builtin_amdgcn_readlane((int)fl, 8) |
+                                           __builtin_amdgcn_readlane((int)fl, 24) |
+                                           __builtin_amdgcn_readlane((int)fl, 40) |
+                                           __builtin_amdgcn_readlane((int)fl, 56));
+        if (lane == 0) {
+            if (cnt) atomicAdd(&s_cnt[l], cnt);
+            if (f0) atomicOr(&s_bmask[(l - 1) * 4 + (by2 & ~1)], f0);
+            if (f1) atomicOr(&s_bmask[(l - 1) * 4 + (by2 | 1)], f1);
+        }
     }
     __syncthreads();   // counts, flags and the last step complete; A/B free
     if (tid <= L) b.tile_cnt[(int64_t)t * kLT + tid] = s_cnt[tid];
@@ -443,38 +533,38 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
         }
     }
 
-    // Labels: byte = layer where the cell was reached, 0xFF where not.  Full-width tiles
-    // with aligned rows are transposed through LDS so that each store instruction writes
-    // whole 128-byte rows; other tiles write their rows thread by thread.
-    int8_t* lab0 = d->labels + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64;
-    int8_t* dec0 = d->decisions ? d->decisions + ((int64_t)krow * n1 + jrow) * n0 + wx0 * 64
-                                : nullptr;
+    // Labels: byte = layer where the cell was reached, 0xFF where not.  Each thread forms
+    // its row's label words in LDS; full-width tiles with aligned rows then store whole
+    // 128-byte rows per store instruction, other tiles go through the block's word stores.
+    constexpr int TS = 8 * MAXTW + 1;   // padded row stride: rows on distinct banks
+    unsigned long long* T = lds;         // [256 rows][TS] label words
+    {
+        // the planes the layers 1..L use (L uniform: one branch per tile)
+        auto fill = [&](auto np) {
+            constexpr int NP = decltype(np)::value;
+#pragma unroll
+            for (int w = 0; w < WPH; ++w) {
+                if (wb + w >= MAXTW) break;   // (the second thread of a one-word row)
+#pragma unroll
+                for (int g = 0; g < 8; ++g)
+                    T[row * TS + (wb + w) * 8 + g] =
+                        label_word<NP>(p0[w], p1[w], p2[w], p3[w], p4[w], prev[w], 8 * g);
+            }
+        };
+        if (L < 8)
+            fill(IntC<3>{});
+        else
+            fill(IntC<5>{});
+    }
+    __syncthreads();
     const bool full = tw == MAXTW && (wx0 + MAXTW) * 64 <= n0 && (n0 & 7) == 0 &&
                       (reinterpret_cast<uintptr_t>(d->labels) & 7) == 0 &&
                       (!d->decisions || (reinterpret_cast<uintptr_t>(d->decisions) & 7) == 0);
     if (full) {   // uniform
-        constexpr int TS = 8 * MAXTW + 1;   // padded row stride: rows on distinct banks
-        unsigned long long* T = lds;         // [256 rows][TS] label words
-#pragma unroll
-        for (int w = 0; w < MAXTW; ++w) {
-#pragma unroll
-            for (int g = 0; g < 8; ++g) {
-                const int sh8 = 8 * g;
-                unsigned long long word =
-                    spread8((uint32_t)(p0[w] >> sh8) & 255u) |
-                    (spread8((uint32_t)(p1[w] >> sh8) & 255u) << 1) |
-                    (spread8((uint32_t)(p2[w] >> sh8) & 255u) << 2) |
-                    (spread8((uint32_t)(p3[w] >> sh8) & 255u) << 3) |
-                    (spread8((uint32_t)(p4[w] >> sh8) & 255u) << 4);
-                word |= spread8((uint32_t)(~prev[w] >> sh8) & 255u) * 0xFFull;
-                T[tid * TS + w * 8 + g] = word;
-            }
-        }
-        __syncthreads();
         constexpr int CPR = 8 * MAXTW;   // 8-byte chunks per tile row
 #pragma unroll
-        for (int h = 0; h < CPR; ++h) {
-            const int ch = tid + 256 * h;
+        for (int h = 0; h < 256 * CPR / kLabelThreads; ++h) {
+            const int ch = tid + kLabelThreads * h;
             const int row = ch / CPR, off = ch % CPR;   // row = tk * 16 + tj
             const int rj = j0 + row % kTileJ, rk = k0 + row / kTileJ;
             if (rj < n1 && rk < n2) {
@@ -483,45 +573,23 @@ __global__ __launch_bounds__(256) void k_label(Batch b) {
                 if (d->decisions) reinterpret_cast<unsigned long long*>(d->decisions + o)[0] = 0ull;
             }
         }
-    } else if (row_ok) {
-#pragma unroll
-        for (int w = 0; w < MAXTW; ++w) {
-            if (w >= tw) break;
-            int8_t* lab = lab0 + 64 * w;
-            int8_t* dec = dec0 ? dec0 + 64 * w : nullptr;
-            const int nx = min(64, n0 - (wx0 + w) * 64);
-            const bool vec = ((n0 & 7) == 0) && nx == 64 &&
-                             ((reinterpret_cast<uintptr_t>(lab) & 7) == 0) &&
-                             (!dec || (reinterpret_cast<uintptr_t>(dec) & 7) == 0);
-            if (vec) {
-#pragma unroll
-                for (int g = 0; g < 8; ++g) {
-                    const int sh8 = 8 * g;
-                    unsigned long long word =
-                        spread8((uint32_t)(p0[w] >> sh8) & 255u) |
-                        (spread8((uint32_t)(p1[w] >> sh8) & 255u) << 1) |
-                        (spread8((uint32_t)(p2[w] >> sh8) & 255u) << 2) |
-                        (spread8((uint32_t)(p3[w] >> sh8) & 255u) << 3) |
-                        (spread8((uint32_t)(p4[w] >> sh8) & 255u) << 4);
-                    word |= spread8((uint32_t)(~prev[w] >> sh8) & 255u) * 0xFFull;
-                    reinterpret_cast<unsigned long long*>(lab)[g] = word;
-                    if (dec) reinterpret_cast<unsigned long long*>(dec)[g] = 0ull;
-                }
-                continue;
-            }
-            for (int i = 0; i < nx; ++i) {
-                int v;
-                if ((prev[w] >> i) & 1ull) {
-                    v = (int)(((p0[w] >> i) & 1ull) | (((p1[w] >> i) & 1ull) << 1) |
-                              (((p2[w] >> i) & 1ull) << 2) | (((p3[w] >> i) & 1ull) << 3) |
-                              (((p4[w] >> i) & 1ull) << 4));
-                } else {
-                    v = -1;
-                }
-                lab[i] = (int8_t)v;
-                if (dec) dec[i] = 0;
-            }
-        }
+    } else {
+        const int xs = wx0 * 64, nx = min(64 * tw, n0 - xs);
+        const uint8_t* Tb = reinterpret_cast<const uint8_t*>(T);
+        const uint32_t* Tw = reinterpret_cast<const uint32_t*>(T);
+        // four bytes of a row from the two aligned words holding them (a row's padding word
+        // lies past its last byte)
+        auto quad = [&](int r, int x) {
+            const int o = r * TS * 8 + x;
+            const unsigned long long two =
+                ((unsigned long long)Tw[(o >> 2) + 1] << 32) | Tw[o >> 2];
+            return (uint32_t)(two >> (8 * (o & 3)));
+        };
+        store_tile_bytes(d->labels, d, xs, nx, j0, k0,
+                         [&](int r, int x) { return (uint32_t)Tb[r * TS * 8 + x]; }, quad);
+        if (d->decisions)
+            store_tile_bytes(d->decisions, d, xs, nx, j0, k0, [](int, int) { return 0u; },
+                             [](int, int) { return 0u; });
     }
 }
 
@@ -1403,11 +1471,11 @@ size_t label_lds_bytes(int Lmax, int tile_w, int Wmax) {
 
 hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st) {
     if (b.tile_w == 1)
-        hipLaunchKernelGGL(k_label<1>, dim3(b.n_tiles), dim3(256), lds, st, b);
+        hipLaunchKernelGGL(k_label<1>, dim3(b.n_tiles), dim3(kLabelThreads), lds, st, b);
     else if (b.tile_w == 2)
-        hipLaunchKernelGGL(k_label<2>, dim3(b.n_tiles), dim3(256), lds, st, b);
+        hipLaunchKernelGGL(k_label<2>, dim3(b.n_tiles), dim3(kLabelThreads), lds, st, b);
     else if (b.tile_w == 4)
-        hipLaunchKernelGGL(k_label<4>, dim3(b.n_tiles), dim3(256), lds, st, b);
+        hipLaunchKernelGGL(k_label<4>, dim3(b.n_tiles), dim3(kLabelThreads), lds, st, b);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

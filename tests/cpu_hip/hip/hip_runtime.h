@@ -136,6 +136,14 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int, int, boo
 // correctly rounded one, so an exact reciprocal serves.
 inline double __builtin_amdgcn_rcp(double x) { return 1.0 / x; }
 inline double __builtin_amdgcn_rsq(double x) { return 1.0 / std::sqrt(x); }
+// The value of lane `src` of the wave (every lane active; a 64-lane collective here).
+inline int __builtin_amdgcn_readlane(int v, int src) {
+    if (src < 0 || src > 63) std::abort();
+    uint64_t* s = rmx_emu::group_exchange((uint64_t)(uint32_t)v, 64);
+    const int r = (int)(uint32_t)s[src];
+    rmx_emu::group_done(64);
+    return r;
+}
 inline int __builtin_amdgcn_readfirstlane(int v) {
     uint64_t* s = rmx_emu::group_exchange((uint64_t)(uint32_t)v, 64);
     const int r = (int)(uint32_t)s[0];

@@ -192,6 +192,13 @@ int main(int argc, char** argv) {
                     return 4;
                 continue;
             }
+            if (pf > 8192u && pf <= 8196u) {   // a given label tile width (8192 + width)
+                rmx_tuning t{};
+                t.tile_w = (int32_t)(pf - 8192u);
+                t.extrap_blocks = 64;
+                if (rmx_set_tuning(ctx, &g, sol.data(), ns, &o, &t) != RMX_OK) return 4;
+                continue;
+            }
             std::vector<rmx_solid> tmp = sol;
             for (int i = 0; i < ns; ++i) {
                 double* x = nullptr;

@@ -270,6 +270,22 @@ def wall_sphere(n=24, n_layers=6):
     return w
 
 
+def wide_box_sphere(n0=130, n=40, n_layers=16, seed=5):
+    """A sphere in a grid (= its box) 130 cells wide: rows of 2 words and a ragged third
+    that no 8-byte store aligns to, so the label tiles narrower than the box (a tuned width,
+    or the width the LDS allows with many layers) write their rows in runs of one row."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    c = np.array([0.5 * n0 * h, 0.5, 0.5])
+    A = np.eye(3) + 0.05 * rng.standard_normal((3, 3))
+    modes = synth._modes(rng, 3, 2)
+    lo, ext = (0, 0, 0), (n0, n, n)
+    xi = synth.affine_sine_field(lo, ext, h, (0.0, 0.0, 0.0), c, A, 0.01, modes)
+    w = synth.Workload("wide_box_sphere", (n0, n, n), h, (0.0, 0.0, 0.0))
+    w.solids.append(synth.Solid(lo, ext, synth.sphere_shape(c, 0.25), n_layers, xi))
+    return w
+
+
 # ---- blur-zone consumers ------------------------------------------------------------------
 def blur_pair_workload(n=40, n_layers=6):
     """Two spheres whose blur zones overlap (gap under one cell), each with its own

@@ -16,7 +16,7 @@ import pytest
 
 from paper_2104_00095_amd import synth
 from tests.helpers import (axis_plane_workload, edge_workloads, plates_workload, rel_err,
-                           run_oracle)
+                           run_oracle, wide_box_sphere)
 
 emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
@@ -24,6 +24,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host c
 TOL = {0: 1e-12, 1: 1e-5}
 BATCHED, PER_SOLID, GRAPH, PERSISTENT, ADJ26 = 0, 4, 2, 16, 32
 AUTOTUNE = 1024   # (run_case: run the autotuner on the fields first)
+TILE_W = 8192     # (run_case: TILE_W + w fixes the label tile width w first)
 NOALLOC = 4096    # (run_case: make the call through the allocation-free entry point)
 
 
@@ -71,6 +72,11 @@ def _runs():
         "statuses_batched": (trunc, 0, BATCHED, ()),
         "statuses_per_solid": (trunc, 0, PER_SOLID, ()),
         "sphere64": (synth.sphere32(n=64, n_layers=3), 0, BATCHED, ()),
+        # 16 layers: the label tiles' five bit planes all in use
+        "sphere40_L16": (synth.sphere32(n=40, n_layers=16), 0, BATCHED, ()),
+        # label tiles narrower than a 130-cell box: rows written in runs of one row
+        "wide_box_L16_tw1": (wide_box_sphere(n_layers=16), 0, BATCHED, (TILE_W + 1,)),
+        "wide_box_L4_tw2": (wide_box_sphere(n_layers=4), 0, BATCHED, (TILE_W + 2,)),
         # 64 CUs: 125 fit blocks for a few dozen bricks per layer (most blocks find no
         # brick of their own)
         "ellipsoid40_cus64": (synth.ellipsoid128(n=40, n_layers=4), 0, BATCHED, (),
@@ -124,8 +130,9 @@ def _check(w, outs, precision, xi_normal=None, adjacency=6):
 
 @pytest.mark.parametrize("name", ["sphere16", "ellipsoid24", "suspension3",
                                   "suspension3_per_solid", "suspension3_fp32_graph",
-                                  "suspension3_cus5", "sphere64", "ellipsoid40_cus64",
-                                  "ellipsoid40_cus64_fp32"])
+                                  "suspension3_cus5", "sphere64", "sphere40_L16",
+                                  "wide_box_L16_tw1", "wide_box_L4_tw2",
+                                  "ellipsoid40_cus64", "ellipsoid40_cus64_fp32"])
 def test_emulated_kernels_match_oracle(emulated, name):
     w, prec, st, outs, xn = emulated[name]
     assert st == 0

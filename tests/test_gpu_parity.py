@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_2104_00095_amd import synth
 from tests.helpers import (axis_plane_workload, edge_workloads, oracle_problem, rel_err,
-                           run_oracle)
+                           run_oracle, wide_box_sphere)
 
 pytestmark = pytest.mark.gpu
 
@@ -115,6 +115,34 @@ def test_suspension_batched_full(ctx, precision, mode):
     st, gpu = run_gpu(ctx, w, precision, flags=MODES[mode])
     assert st == 0
     print("suspension rel err", compare(w, gpu, precision, tag="susp"))
+
+
+@pytest.mark.parametrize("n,L,tile_w", [(40, 16, 0), (48, 11, 0), (48, 11, 1), (40, 16, 2)])
+def test_many_layers(ctx, n, L, tile_w):
+    """Layer numbers up to 16 need all five bit planes of the label tiles (layers 8..16
+    use the upper two); every label tile width that fits the LDS."""
+    from paper_2104_00095_amd import fields, rmx
+    w = synth.sphere32(n=n, n_layers=L)
+    if tile_w:
+        dw = fields.upload(w)
+        ctx.set_tuning(dw.grid, dw.solids, tile_w, 256)
+    st, gpu = run_gpu(ctx, w)
+    assert st == 0 and int(gpu[0][1].max()) == L
+    compare(w, gpu, 0, tag=f"sphere{n}_L{L}_tw{tile_w}")
+
+
+@pytest.mark.parametrize("L,tile_w", [(16, 0), (16, 1), (4, 1), (4, 2)])
+def test_label_tiles_narrower_than_the_box(ctx, L, tile_w):
+    """A box 130 cells wide (two words and a ragged third per row, no row 8-byte
+    aligned): tiles narrower than the box write their rows in runs of one row."""
+    from paper_2104_00095_amd import fields
+    w = wide_box_sphere(n_layers=L)
+    if tile_w:
+        dw = fields.upload(w)
+        ctx.set_tuning(dw.grid, dw.solids, tile_w, 256)
+    st, gpu = run_gpu(ctx, w)
+    assert st == 0 and int(gpu[0][1].max()) == L
+    compare(w, gpu, 0, tag=f"wide_box_L{L}_tw{tile_w}")
 
 
 @pytest.mark.parametrize("seed", range(31, 39))

@@ -27,3 +27,21 @@ def test_phi0_bitwise_equal_to_oracle(tmp_path):
     out = subprocess.run([exe, "400000"], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "400000 points, 0 mismatches" in out.stdout
+
+
+def test_blur_weight_certificates_match_the_exact_distance(tmp_path):
+    """The blur weight 1 - H_eps(phi0) skips the ellipsoid's bisection where certified
+    bounds put the distance at eps or more; on points crowded within 3 eps of the surface
+    (eps from 1e-3 to 0.5 of the shortest semi-axis) the weight must equal the one from the
+    oracle's exact distance bit for bit."""
+    import oracle
+    lib = oracle.build(force=False)
+    exe = str(tmp_path / "weight_check")
+    subprocess.check_call([emu.CLANG, "-std=c++20", "-O2", "-ffp-contract=off",
+                           "-Wno-unknown-attributes", "-I", HERE,
+                           "-I", os.path.join(emu.ROOT, "include"), "-I", emu.CSRC,
+                           "-x", "c++", os.path.join(HERE, "weight_check.cpp"), "-x", "none",
+                           lib, "-Wl,-rpath," + os.path.dirname(lib), "-o", exe])
+    out = subprocess.run([exe, "400000"], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "400000 points, 0 mismatches" in out.stdout
