@@ -295,9 +295,12 @@ __global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
 // ------------------------------------------------------------------------------------
 // Neo-Hookean stress of solid s at the face between the cells at box coordinates
 // P = f - e_a and Q = f, and its weight; false (no contribution) unless every stencil
-// cell lies in the box and is labelled.  h: the spacings.
-__device__ bool face_stress(const BlurDev& s, const int f[3], int a, const double* h,
-                            double eps, double tau[6], double* w) {
+// cell lies in the box and is labelled.  h: the spacings.  The axis a is a template
+// argument: the Jacobian's columns and the stencil offsets are then fixed at compile time
+// and stay in registers.
+template <int a>
+__device__ bool face_stress(const BlurDev& s, const int f[3], const double* h, double eps,
+                            double tau[6], double* w) {
     int P[3] = {f[0], f[1], f[2]};
     P[a] -= 1;
     const int64_t cp = box_cell(s, P[0], P[1], P[2]), cq = box_cell(s, f[0], f[1], f[2]);
@@ -364,7 +367,8 @@ __device__ bool face_stress(const BlurDev& s, const int f[3], int a, const doubl
 
 // The face f along a (between grid cells f - e_a and f; f[a] in [0, n), or n on a walled
 // axis).
-__device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3], int a) {
+template <int a>
+__device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3]) {
     int P[3] = {f[0], f[1], f[2]};
     P[a] -= 1;   // the face's low cell (wrapped on a periodic axis)
     if (b.periodic[a] && P[a] < 0) P[a] += b.grid[a];
@@ -383,7 +387,7 @@ __device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3], i
 #pragma unroll
         for (int c = 0; c < 3; ++c) q[c] = inq ? lq[c] : lp[c] + (c == a && !inq);
         double t6[6], w;
-        if (!face_stress(s, q, a, b.h, b.eps, t6, &w)) continue;
+        if (!face_stress<a>(s, q, b.h, b.eps, t6, &w)) continue;
         S += w;
 #pragma unroll
         for (int c = 0; c < 6; ++c) T[c] += w * t6[c];
@@ -399,27 +403,33 @@ __device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3], i
     for (int c = 0; c < 6; ++c) out[c * nf + fi] = S <= 1.0 ? T[c] : T[c] / S;
 }
 
+// A cell's faces along a: its low face, and on a walled axis the last cell's face beyond.
+template <int a>
+__device__ __forceinline__ void cell_faces(const BlurBatch& b, int e0, int e1, const int g[3]) {
+    const int nf = (g[a] == b.grid[a] - 1 && !b.periodic[a]) ? 2 : 1;
+#pragma unroll 1
+    for (int k = 0; k < nf; ++k) {
+        int f[3] = {g[0], g[1], g[2]};
+        f[a] += k;
+        blend_face<a>(b, e0, e1, f);
+    }
+}
+
 __device__ void stress_tile(const BlurBatch& b, int t) {
     const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
     for (int q = threadIdx.x; q < kBlurTileCells; q += 256) {
         int g[3];
         tile_cell(b, t, q, g);
         if (g[0] >= b.grid[0] || g[1] >= b.grid[1] || g[2] >= b.grid[2]) continue;
-#pragma unroll 1
-        for (int a = 0; a < 3; ++a) {
-            // a cell owns its low face along a; on a walled axis the last cell also the
-            // face beyond it
-            blend_face(b, e0, e1, g, a);
-            if (g[a] == b.grid[a] - 1 && !b.periodic[a]) {
-                int f[3] = {g[0], g[1], g[2]};
-                f[a] += 1;
-                blend_face(b, e0, e1, f, a);
-            }
-        }
+        cell_faces<0>(b, e0, e1, g);
+        cell_faces<1>(b, e0, e1, g);
+        cell_faces<2>(b, e0, e1, g);
     }
 }
 
-__global__ __launch_bounds__(256) void k_blur_stress(BlurBatch b) {
+// Three waves per SIMD: the face code holds about 190 registers; at 168 a few spill, which
+// costs less than the third of the waves it gains on many-body boxes.
+__global__ __launch_bounds__(256, 3) void k_blur_stress(BlurBatch b) {
     const int n = *b.n_covered;
     for (int i = blockIdx.x; i < n; i += gridDim.x) stress_tile(b, b.covered[i]);
 }

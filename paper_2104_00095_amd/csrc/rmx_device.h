@@ -140,8 +140,8 @@ __device__ __forceinline__ double rcp_refined(double x) {
 // and moves s0 without an evaluation; likewise sm >= b once f(b) < 0.  The midpoints, and
 // so the final bracket, are those of evaluating every step.  a and b lie 2^-44 (relative)
 // either side of a few Newton steps on g(s) = F(s)^(-1/2) - 1 (F = f + 1, close to
-// linear in s), taken in approximate arithmetic; each is used only once its own f has
-// the needed sign.
+// linear in s), taken in approximate arithmetic, or 2^-24 out where the first probe
+// missed; each is used only once its own f has the needed sign.
 struct Bracket {
     double s0, s1;
 };
@@ -162,10 +162,24 @@ __device__ __forceinline__ Bracket ellipsoid_bisect(double c0, double c1, double
         s = fmin(fmax(s - step, s0), s1);                      // (a NaN step leaves s0 or s1)
     }
     const double pa = fmax(s * (1.0 - 0x1p-44), s0), pb = fmin(s * (1.0 + 0x1p-44), s1);
-    const double a = ell_f<kMid>(pa, c0, c1, c2, d0, d1, d2, w0, w1, w2) > 0.0
-                         ? pa : -__builtin_huge_val();
-    const double b = ell_f<kMid>(pb, c0, c1, c2, d0, d1, d2, w0, w1, w2) < 0.0
-                         ? pb : __builtin_huge_val();
+    const double fa = ell_f<kMid>(pa, c0, c1, c2, d0, d1, d2, w0, w1, w2);
+    const double fb = ell_f<kMid>(pb, c0, c1, c2, d0, d1, d2, w0, w1, w2);
+    // Any point whose f is positive bounds the root from below, any with f negative from
+    // above: a probe that landed on the other side of the root is a bound of the other
+    // kind, and one probe 2^-24 out then looks for the missing one.  Without it such a
+    // lane would evaluate every step on that side (and hold its wave there).
+    double a = fa > 0.0 ? pa : -__builtin_huge_val();
+    double b = fb < 0.0 ? pb : __builtin_huge_val();
+    if (b == __builtin_huge_val()) {
+        if (fb > 0.0) a = fmax(a, pb);
+        const double pw = fmin(s * (1.0 + 0x1p-24), s1);
+        if (ell_f<kMid>(pw, c0, c1, c2, d0, d1, d2, w0, w1, w2) < 0.0) b = pw;
+    }
+    if (a == -__builtin_huge_val()) {
+        if (fa < 0.0) b = fmin(b, pa);
+        const double pw = fmax(s * (1.0 - 0x1p-24), s0);
+        if (ell_f<kMid>(pw, c0, c1, c2, d0, d1, d2, w0, w1, w2) > 0.0) a = pw;
+    }
     for (int it = 0; it < 4096; ++it) {
         const double sm = 0.5 * (s0 + s1);
         if (sm <= s0 || sm >= s1) break;

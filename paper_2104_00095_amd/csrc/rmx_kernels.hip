@@ -1172,7 +1172,9 @@ __device__ __forceinline__ void solid_counts(const Batch& b, unsigned long long*
     }
 }
 
-__global__ __launch_bounds__(256) void k_normal(Batch b) {
+// Four waves per SIMD (at most 128 registers, none spilled): the blocks go through their
+// bricks' bisections one at a time, so resident waves hide the divide chains.
+__global__ __launch_bounds__(256, 4) void k_normal(Batch b) {
     __shared__ int s_wave[4];
     __shared__ int s_pref[kMaxLayers * kBuckets + 1];
     __shared__ unsigned long long s_acc[kLT];
