@@ -460,6 +460,9 @@ def step_variant(ctx, steps=100, warmup=10, n_layers=6, precision=0):
     dw = fields.upload(w)
     st, stats = ctx.extrapolate(dw.grid, dw.solids, rmx.options())
     assert st == 0
+    # launch shapes (label tile width, fit blocks) tuned on this machine's extrapolation; the
+    # step's chain plans the same boxes and layers, so it takes them too
+    tuned = ctx.autotune(dw.grid, dw.solids, rmx.options(precision=precision), reps=5)
     vel = synth.step_velocity(w)
     dt = synth.step_dt(w, 0.4)
     s = w.solids[0]
@@ -521,7 +524,7 @@ def step_variant(ctx, steps=100, warmup=10, n_layers=6, precision=0):
            "predicted_cells": n_pred, "transverse_cells": n_trans, "band_cells": nb,
            "box_cells": box,
            "predicted_cells_per_s": n_pred / (ms * 1e-3), "band_cells_per_s": nb / (ms * 1e-3),
-           "dt": dt, "precision": precision, "kernels": kern,
+           "dt": dt, "precision": precision, "launch_shapes": tuned, "kernels": kern,
            "step_roofline": {"bound": "hbm", "kernels": list(own), "dominant": f"k_{dom}",
                              "algorithmic_bytes": own_bytes, "ms": own_ms,
                              "achieved": own_bytes / (own_ms * 1e-3) / 1e9,
