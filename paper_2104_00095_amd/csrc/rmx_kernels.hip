@@ -1143,9 +1143,10 @@ __device__ __forceinline__ void solid_counts(const Batch& b, unsigned long long*
         const DevSolid* d = b.solids + s;
         if (tid < kLT) s_acc[tid] = 0ull;
         __syncthreads();
-        unsigned long long acc[kLT];
+        // (a count is at most the box's cells, below 2^31: 32-bit sums)
+        int acc[kLT];
 #pragma unroll
-        for (int l = 0; l < kLT; ++l) acc[l] = 0ull;
+        for (int l = 0; l < kLT; ++l) acc[l] = 0;
         const int L = d->L;
         for (int t = d->tile_base + tid; t < d->tile_base + d->n_tiles; t += 256) {
             // every count of the tile loaded at once (entries past L hold no count of
@@ -1154,16 +1155,15 @@ __device__ __forceinline__ void solid_counts(const Batch& b, unsigned long long*
 #pragma unroll
             for (int l = 0; l < kLT; ++l) v[l] = b.tile_cnt[(int64_t)t * kLT + l];
 #pragma unroll
-            for (int l = 0; l < kLT; ++l) acc[l] += l <= L ? (unsigned)v[l] : 0u;
+            for (int l = 0; l < kLT; ++l) acc[l] += l <= L ? v[l] : 0;
         }
-        // wave sums first: one LDS atomic per wave and count
+        // wave sums first (DPP row sums and four lane reads): one LDS atomic per wave and
+        // count
 #pragma unroll
         for (int l = 0; l < kLT; ++l) {
             if (l <= L) {   // uniform
-                unsigned long long v = acc[l];
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-                if ((tid & 63) == 0 && v) atomicAdd(&s_acc[l], v);
+                const int v = wave_sum(acc[l]);
+                if ((tid & 63) == 0 && v) atomicAdd(&s_acc[l], (unsigned long long)(unsigned)v);
             }
         }
         __syncthreads();
