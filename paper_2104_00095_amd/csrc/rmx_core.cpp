@@ -152,7 +152,8 @@ uint64_t tune_key(const Plan& p) {
 int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids, int n,
               const rmx_options* opt, const Tuning* force, Plan* p) {
     const int bpc = c->band_per_cu[opt->precision == RMX_FP32_ACCUM ? 1 : 0];
-    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, p, c->normal_per_cu, bpc);
+    int rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, Tuning{}, p, c->normal_per_cu, bpc,
+                  c->normal_sphere_per_cu);
     if (rc != RMX_OK) return rc;
     Tuning tn{};
     if (force) {
@@ -162,7 +163,8 @@ int plan_call(rmx_ctx* c, const rmx_grid* const* grids, const rmx_solid* solids,
         if (it != c->tuned.end()) tn = it->second;
     }
     if (tn.tile_w || tn.extrap_blocks)
-        rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, p, c->normal_per_cu, bpc);
+        rc = plan(grids, solids, n, opt, c->lds_limit, c->cus, tn, p, c->normal_per_cu, bpc,
+                  c->normal_sphere_per_cu);
     return rc;
 }
 
@@ -344,7 +346,8 @@ int rmx_create(int device, size_t workspace_bytes, rmx_ctx** out) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) ==
             hipSuccess && v > 0)
         c->cus = v;
-    c->normal_per_cu = normal_blocks_per_cu();
+    c->normal_per_cu = normal_blocks_per_cu(false);
+    c->normal_sphere_per_cu = normal_blocks_per_cu(true);
     c->band_per_cu[0] = band_blocks_per_cu(RMX_FP64);
     c->band_per_cu[1] = band_blocks_per_cu(RMX_FP32_ACCUM);
     for (auto& s : c->stage)

@@ -29,6 +29,7 @@ struct Plan {
     int tile_w = 1;
     int extrap_blocks = 1;
     int normal_blocks = 1;
+    bool spheres = false;      // every solid is a sphere: the normal kernel's sphere-only form
     bool persistent = false;   // the band work in one persistent launch
     int band_blocks = 1;
     size_t lds_bytes = 0;
@@ -74,10 +75,11 @@ int validate_options(const rmx_options* opt);
 int validate_solid(const rmx_grid* grid, const rmx_solid* s, bool need_fields = true);
 
 // Plan a batch: solid i lives on grid grids[i].  `cu` = compute units of the device,
-// `normal_per_cu` = blocks of the normal kernel resident per compute unit.
+// `normal_per_cu` = blocks of the normal kernel resident per compute unit, in its general
+// and in its sphere-only form.
 int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,
          const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p,
-         int normal_per_cu = 4, int band_per_cu = 2);
+         int normal_per_cu = 4, int band_per_cu = 2, int normal_sphere_per_cu = 0);
 void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b);
 void pack_desc(const Plan& p, void* host);
 // The launch chain of a planned call.  classify = false: the interior mask is already in

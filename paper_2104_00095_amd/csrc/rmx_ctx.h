@@ -31,6 +31,7 @@ struct rmx_ctx {
     size_t lds_limit = 65536;
     int cus = 256;
     int normal_per_cu = 4;   // resident blocks of the normal kernel per compute unit
+    int normal_sphere_per_cu = 4;   // the same, in its sphere-only form
     int band_per_cu[2] = {2, 2};   // ... of the band kernel, FP64 and FP32-accumulate
     bool fixed = false;
     bool exact_ws = false;   // grow the workspace to exactly what a call needs (server)

@@ -281,6 +281,16 @@ __device__ inline double ellipsoid_distance(double e0, double e1, double e2, dou
     return sqrt(D);
 }
 
+// phi0 of a sphere: the operations of phi0's sphere branch below, without the ellipsoid
+// code (whose registers a sphere-only kernel then does not hold).
+__device__ __forceinline__ double phi0_sphere(const ShapeR& s, double v0, double v1, double v2) {
+#pragma clang fp contract(off)
+    const double dx = v0 - s.c0, dy = v1 - s.c1, dz = v2 - s.c2;
+    const double dist = fabs(sqrt((dx * dx + dy * dy) + dz * dz) - s.e0);
+    const bool in = finite3(v0, v1, v2) && ((dx * dx + dy * dy) + dz * dz) < s.e0 * s.e0;
+    return in ? -dist : dist;
+}
+
 // Signed distance phi0(v), negative inside; the sign is the interior predicate's.
 __device__ inline double phi0(const ShapeR& s, double v0, double v1, double v2) {
 #pragma clang fp contract(off)

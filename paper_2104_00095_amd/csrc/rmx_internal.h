@@ -95,7 +95,8 @@ struct Batch {
     int32_t tile_w;          // 64-cell words per label tile along x (1..kMaxTileW)
     int32_t n_chunks;        // classification chunks (kChunkWords mask words each)
     int32_t adj26;           // layers by the 26-neighbour adjacency (else face neighbours)
-    int32_t pad_adj;
+    int32_t spheres;         // every solid of the call is a sphere (the normal kernel's
+                             // sphere-only form)
     int64_t total_words;
     int64_t blist_cap;       // brick-list entries per layer: n_tiles * 32 * tile_w
     const int32_t* tile_solid;  // [n_tiles]
@@ -122,7 +123,7 @@ size_t label_lds_bytes(int Lmax, int tile_w, int Wmax);
 hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st);
 hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st);
 // Blocks of the normal kernel resident per compute unit (occupancy, queried once).
-int normal_blocks_per_cu();
+int normal_blocks_per_cu(bool spheres);
 hipError_t launch_extrap(const Batch& b, int layer, int precision, int blocks,
                          hipStream_t st);
 // The persistent band launch (normals and every layer's fits in one launch).

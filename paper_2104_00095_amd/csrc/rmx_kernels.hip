@@ -1019,6 +1019,7 @@ __device__ __forceinline__ unsigned long long list_entry(const Batch& b, int l0,
 constexpr int kNSpan = kBrick + 2;                        // brick with a halo of 1
 constexpr int kNCells = kNSpan * kNSpan * kNSpan;         // 1000
 
+template <bool kSpheres>
 __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long long* st, int l,
                                              int bx, int by, int bz, double* s_phi,
                                              unsigned char* s_flag, int8_t* s_lab,
@@ -1101,7 +1102,14 @@ __device__ __forceinline__ void normal_brick(const DevSolid* d, unsigned long lo
         const double x0 = load_global(f + c), x1 = load_global(f + nc + c),
                      x2 = load_global(f + 2 * nc + c);
         const bool def = in && finite3(x0, x1, x2);
-        s_phi[r] = def ? phi0(sh, x0, x1, x2) : 0.0;
+        double ph = 0.0;
+        if (def) {
+            if constexpr (kSpheres)
+                ph = phi0_sphere(sh, x0, x1, x2);
+            else
+                ph = phi0(sh, x0, x1, x2);
+        }
+        s_phi[r] = ph;
         s_flag[r] = def ? 3 : 1;
     }
     __syncthreads();
@@ -1173,8 +1181,11 @@ __device__ __forceinline__ void solid_counts(const Batch& b, unsigned long long*
 }
 
 // Four waves per SIMD (at most 128 registers, none spilled): the blocks go through their
-// bricks' bisections one at a time, so resident waves hide the divide chains.
-__global__ __launch_bounds__(256, 4) void k_normal(Batch b) {
+// bricks' bisections one at a time, so resident waves hide the divide chains.  A call
+// whose solids are all spheres takes the sphere-only form (kSpheres), which holds no
+// bisection and keeps more blocks resident.
+template <bool kSpheres>
+__global__ __launch_bounds__(256, kSpheres ? 8 : 4) void k_normal(Batch b) {
     __shared__ int s_wave[4];
     __shared__ int s_pref[kMaxLayers * kBuckets + 1];
     __shared__ unsigned long long s_acc[kLT];
@@ -1210,7 +1221,8 @@ __global__ __launch_bounds__(256, 4) void k_normal(Batch b) {
         l = uniform_int(l);
         unsigned long long* st = b.stats + (int64_t)s * kStatWords;
         if (st[ST_FLAGS] & FLAG_TRUNCATED) continue;   // uniform: no fit follows
-        normal_brick(b.solids + s, st, l, bx, by, bz, s_phi, s_flag, s_lab, s_list, s_wave);
+        normal_brick<kSpheres>(b.solids + s, st, l, bx, by, bz, s_phi, s_flag, s_lab, s_list,
+                               s_wave);
         __syncthreads();   // the LDS is reused by the next brick
     }
 }
@@ -1436,7 +1448,7 @@ __global__ __launch_bounds__(256, 3) void k_band(Batch b, int work_bytes) {
             unsigned long long* st = b.stats + (int64_t)s * kStatWords;
             if (!(st[ST_FLAGS] & FLAG_TRUNCATED)) {   // uniform: no fit follows a truncation
                 if (p == 0)
-                    normal_brick(b.solids + s, st, layer, bx, by, bz, L.s_phi, L.s_flag, L.s_lab,
+                    normal_brick<false>(b.solids + s, st, layer, bx, by, bz, L.s_phi, L.s_flag, L.s_lab,
                                  L.s_list, L.s_wave);
                 else
                     extrap_brick<T>(b, s, st, p, bx, by, bz, L.work, L.s_wave, L.s_anchor,
@@ -1483,19 +1495,29 @@ hipError_t launch_label(const Batch& b, size_t lds, hipStream_t st) {
     return hipGetLastError();
 }
 
-int normal_blocks_per_cu() {
-    static const int n = [] {
-        int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_normal, 256, 0) != hipSuccess ||
-            v < 1)
-            v = 4;
-        return v;
-    }();
-    return n;
+int normal_blocks_per_cu(bool spheres) {
+    static const int n[2] = {[] {
+                                 int v = 0;
+                                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                         &v, k_normal<false>, 256, 0) != hipSuccess || v < 1)
+                                     v = 4;
+                                 return v;
+                             }(),
+                             [] {
+                                 int v = 0;
+                                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                         &v, k_normal<true>, 256, 0) != hipSuccess || v < 1)
+                                     v = 4;
+                                 return v;
+                             }()};
+    return n[spheres ? 1 : 0];
 }
 
 hipError_t launch_normal(const Batch& b, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_normal, dim3(blocks), dim3(256), 0, st, b);
+    if (b.spheres)
+        hipLaunchKernelGGL(k_normal<true>, dim3(blocks), dim3(256), 0, st, b);
+    else
+        hipLaunchKernelGGL(k_normal<false>, dim3(blocks), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

@@ -98,7 +98,7 @@ int validate_solid(const rmx_grid* grid, const rmx_solid* sp, bool need_fields) 
 
 int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids,
          const rmx_options* opt, size_t lds_limit, int cu, const Tuning& tune, Plan* p,
-         int normal_per_cu, int band_per_cu) {
+         int normal_per_cu, int band_per_cu, int normal_sphere_per_cu) {
     p->n_solids = n_solids;
     p->solids.assign(n_solids, DevSolid{});
     p->tile_solid.clear();
@@ -191,8 +191,11 @@ int plan(const rmx_grid* const* grids, const rmx_solid* solids, int32_t n_solids
     p->dlist_cap = std::max<int64_t>(bricks, 1);
     // normal: as many blocks as are resident at once (each block scans the brick lists
     // once, then strides over its bricks), no more than the bricks of its layers
+    p->spheres = true;
+    for (const DevSolid& d : p->solids) p->spheres = p->spheres && d.kind == 1;
+    const int npc = p->spheres && normal_sphere_per_cu > 0 ? normal_sphere_per_cu : normal_per_cu;
     p->normal_blocks = (int)std::max<int64_t>(
-        std::min<int64_t>((int64_t)std::max(normal_per_cu, 1) * std::max(cu, 1),
+        std::min<int64_t>((int64_t)std::max(npc, 1) * std::max(cu, 1),
                           bricks * std::max(p->normal_layers, 1)),
         1);
     // persistent band launch: the resident blocks (at least one per queue)
@@ -253,6 +256,7 @@ void bind(Plan* p, void* ws, const rmx_options* opt, Batch* b) {
     b->r_max = opt->r_max;
     b->tile_w = p->tile_w;
     b->adj26 = (opt->flags & RMX_FLAG_ADJ26) != 0;
+    b->spheres = p->spheres ? 1 : 0;
     b->n_chunks = p->n_chunks;
     b->total_words = p->total_words;
     b->blist_cap = p->blist_cap;
