@@ -33,6 +33,7 @@ struct BlurBatch {
     int32_t periodic[3];         // 1: the grid wraps along the axis (n faces, not n + 1)
     int32_t tiles[3];            // tiles along x, y, z
     int32_t n_active;
+    int32_t spheres;             // every solid is a sphere: the full kernels' sphere-only form
     const int32_t* tile_start;   // [tiles + 1]: candidate solids of each tile (CSR)
     const int32_t* tile_list;    // ascending solid indices (boxes dilated by one cell)
     const int32_t* active;       // tiles with a candidate

@@ -251,9 +251,29 @@ __global__ __launch_bounds__(256) void k_blur_fill(BlurBatch b) {
 // Blocks of the full kernels: they stride over the covered tiles.
 constexpr int kBlurFullBlocks = 2048;
 
+// phi0 and the weight 1 - H_eps(phi0), in the sphere-only form (kSpheres: calls whose
+// solids are all spheres; the same operations as the general functions' sphere branch,
+// without the ellipsoid code and its registers) or the general one.
+template <bool kSpheres>
+__device__ __forceinline__ double phi0_of(const ShapeR& s, double x0, double x1, double x2) {
+    if constexpr (kSpheres)
+        return phi0_sphere(s, x0, x1, x2);
+    else
+        return phi0(s, x0, x1, x2);
+}
+template <bool kSpheres>
+__device__ __forceinline__ double weight_of(const ShapeR& s, double x0, double x1, double x2,
+                                            double eps) {
+    if constexpr (kSpheres)
+        return 1.0 - heaviside_eps(phi0_sphere(s, x0, x1, x2), eps);
+    else
+        return weight_at(s, x0, x1, x2, eps);
+}
+
 // ------------------------------------------------------------------------------------
 // Modified Heaviside (and phi_m).
 // ------------------------------------------------------------------------------------
+template <bool kSpheres>
 __device__ void heaviside_tile(const BlurBatch& b, int t) {
     const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
     for (int q = threadIdx.x; q < kBlurTileCells; q += 256) {
@@ -272,11 +292,11 @@ __device__ void heaviside_tile(const BlurBatch& b, int t) {
             double v[3];
             xi_at(s, c, v);
             if (s.phi) {
-                const double p = phi0(blur_shape(s), v[0], v[1], v[2]);
+                const double p = phi0_of<kSpheres>(blur_shape(s), v[0], v[1], v[2]);
                 s.phi[c] = p;
                 acc += 1.0 - heaviside_eps(p, b.eps);
             } else {
-                acc += weight_at(blur_shape(s), v[0], v[1], v[2], b.eps);
+                acc += weight_of<kSpheres>(blur_shape(s), v[0], v[1], v[2], b.eps);
             }
         }
         if (!any || !b.H) continue;
@@ -285,9 +305,10 @@ __device__ void heaviside_tile(const BlurBatch& b, int t) {
     }
 }
 
+template <bool kSpheres>
 __global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
     const int n = *b.n_covered;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) heaviside_tile(b, b.covered[i]);
+    for (int i = blockIdx.x; i < n; i += gridDim.x) heaviside_tile<kSpheres>(b, b.covered[i]);
 }
 
 // ------------------------------------------------------------------------------------
@@ -298,7 +319,7 @@ __global__ __launch_bounds__(256) void k_blur_heaviside(BlurBatch b) {
 // cell lies in the box and is labelled.  h: the spacings.  The axis a is a template
 // argument: the Jacobian's columns and the stencil offsets are then fixed at compile time
 // and stay in registers.
-template <int a>
+template <int a, bool kSpheres>
 __device__ bool face_stress(const BlurDev& s, const int f[3], const double* h, double eps,
                             double tau[6], double* w) {
     int P[3] = {f[0], f[1], f[2]};
@@ -361,13 +382,13 @@ __device__ bool face_stress(const BlurDev& s, const int f[3], const double* h, d
     tau[5] = G * B[1][2];
     const double x0 = (xp[0] + xq[0]) * 0.5, x1 = (xp[1] + xq[1]) * 0.5,
                  x2 = (xp[2] + xq[2]) * 0.5;
-    *w = weight_at(blur_shape(s), x0, x1, x2, eps);
+    *w = weight_of<kSpheres>(blur_shape(s), x0, x1, x2, eps);
     return true;
 }
 
 // The face f along a (between grid cells f - e_a and f; f[a] in [0, n), or n on a walled
 // axis).
-template <int a>
+template <int a, bool kSpheres>
 __device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3]) {
     int P[3] = {f[0], f[1], f[2]};
     P[a] -= 1;   // the face's low cell (wrapped on a periodic axis)
@@ -387,7 +408,7 @@ __device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) q[c] = inq ? lq[c] : lp[c] + (c == a && !inq);
         double t6[6], w;
-        if (!face_stress<a>(s, q, b.h, b.eps, t6, &w)) continue;
+        if (!face_stress<a, kSpheres>(s, q, b.h, b.eps, t6, &w)) continue;
         S += w;
 #pragma unroll
         for (int c = 0; c < 6; ++c) T[c] += w * t6[c];
@@ -404,34 +425,36 @@ __device__ void blend_face(const BlurBatch& b, int e0, int e1, const int f[3]) {
 }
 
 // A cell's faces along a: its low face, and on a walled axis the last cell's face beyond.
-template <int a>
+template <int a, bool kSpheres>
 __device__ __forceinline__ void cell_faces(const BlurBatch& b, int e0, int e1, const int g[3]) {
     const int nf = (g[a] == b.grid[a] - 1 && !b.periodic[a]) ? 2 : 1;
 #pragma unroll 1
     for (int k = 0; k < nf; ++k) {
         int f[3] = {g[0], g[1], g[2]};
         f[a] += k;
-        blend_face<a>(b, e0, e1, f);
+        blend_face<a, kSpheres>(b, e0, e1, f);
     }
 }
 
+template <bool kSpheres>
 __device__ void stress_tile(const BlurBatch& b, int t) {
     const int e0 = b.tile_start[t], e1 = b.tile_start[t + 1];
     for (int q = threadIdx.x; q < kBlurTileCells; q += 256) {
         int g[3];
         tile_cell(b, t, q, g);
         if (g[0] >= b.grid[0] || g[1] >= b.grid[1] || g[2] >= b.grid[2]) continue;
-        cell_faces<0>(b, e0, e1, g);
-        cell_faces<1>(b, e0, e1, g);
-        cell_faces<2>(b, e0, e1, g);
+        cell_faces<0, kSpheres>(b, e0, e1, g);
+        cell_faces<1, kSpheres>(b, e0, e1, g);
+        cell_faces<2, kSpheres>(b, e0, e1, g);
     }
 }
 
 // Three waves per SIMD: the face code holds about 190 registers; at 168 a few spill, which
 // costs less than the third of the waves it gains on many-body boxes.
+template <bool kSpheres>
 __global__ __launch_bounds__(256, 3) void k_blur_stress(BlurBatch b) {
     const int n = *b.n_covered;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) stress_tile(b, b.covered[i]);
+    for (int i = blockIdx.x; i < n; i += gridDim.x) stress_tile<kSpheres>(b, b.covered[i]);
 }
 
 }  // namespace
@@ -454,7 +477,10 @@ hipError_t launch_blur_heaviside(const BlurBatch& b, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int g = b.n_active < kBlurFullBlocks ? b.n_active : kBlurFullBlocks;
-    hipLaunchKernelGGL(k_blur_heaviside, dim3(g), dim3(256), 0, st, b);
+    if (b.spheres)
+        hipLaunchKernelGGL(k_blur_heaviside<true>, dim3(g), dim3(256), 0, st, b);
+    else
+        hipLaunchKernelGGL(k_blur_heaviside<false>, dim3(g), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 
@@ -467,7 +493,10 @@ hipError_t launch_blur_stress(const BlurBatch& b, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int g = b.n_active < kBlurFullBlocks ? b.n_active : kBlurFullBlocks;
-    hipLaunchKernelGGL(k_blur_stress, dim3(g), dim3(256), 0, st, b);
+    if (b.spheres)
+        hipLaunchKernelGGL(k_blur_stress<true>, dim3(g), dim3(256), 0, st, b);
+    else
+        hipLaunchKernelGGL(k_blur_stress<false>, dim3(g), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

@@ -713,6 +713,8 @@ static int blur_setup(rmx_ctx* c, const rmx_grid* grid, const rmx_solid* solids,
     *b = BlurBatch{};
     b->solids = reinterpret_cast<const BlurDev*>(base);
     b->n_solids = n;
+    b->spheres = 1;
+    for (int i = 0; i < n; ++i) b->spheres &= solids[i].phi0.kind == RMX_SPHERE ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
         b->grid[a] = grid->n[a];
         b->periodic[a] = grid->periodic[a] ? 1 : 0;
