@@ -127,6 +127,17 @@ def edge_workloads(seed=11, n=16, n_layers=3):
     return out
 
 
+def mixed_kinds_workload(n=32, n_layers=6):
+    """A sphere and an ellipsoid (the sphere32 and ellipsoid128 recipes on one n^3 grid)
+    in one batch: a call with both kinds takes the kernels' general forms (calls of spheres
+    alone take sphere-only forms)."""
+    sph = synth.sphere32(n=n, n_layers=n_layers)
+    ell = synth.ellipsoid128(n=n, n_layers=n_layers)
+    w = synth.Workload("mixed_kinds", sph.grid_n, sph.h, sph.origin)
+    w.solids = [sph.solids[0], ell.solids[0]]
+    return w
+
+
 def axis_plane_workload(n=24, n_layers=3):
     """An axis-aligned ellipsoid centred at the origin with xi = (index - n/2) h: body
     coordinates are exactly 0 on the three centre planes, and +-1e-230 on half of two of

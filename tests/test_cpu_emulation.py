@@ -16,7 +16,7 @@ import pytest
 
 from paper_2104_00095_amd import synth
 from tests.helpers import (axis_plane_workload, edge_workloads, plates_workload, rel_err,
-                           run_oracle, wide_box_sphere)
+                           run_oracle, wide_box_sphere, mixed_kinds_workload)
 
 emu = pytest.importorskip("tests.cpu_hip.emu")
 pytestmark = pytest.mark.skipif(not os.path.exists(emu.CLANG), reason="no host clang++")
@@ -74,6 +74,8 @@ def _runs():
         "sphere64": (synth.sphere32(n=64, n_layers=3), 0, BATCHED, ()),
         # 16 layers: the label tiles' five bit planes all in use
         "sphere40_L16": (synth.sphere32(n=40, n_layers=16), 0, BATCHED, ()),
+        # a sphere and an ellipsoid in one call: the general forms
+        "mixed_kinds": (mixed_kinds_workload(n=24, n_layers=4), 0, BATCHED, ()),
         # label tiles narrower than a 130-cell box: rows written in runs of one row
         "wide_box_L16_tw1": (wide_box_sphere(n_layers=16), 0, BATCHED, (TILE_W + 1,)),
         "wide_box_L4_tw2": (wide_box_sphere(n_layers=4), 0, BATCHED, (TILE_W + 2,)),
@@ -131,7 +133,7 @@ def _check(w, outs, precision, xi_normal=None, adjacency=6):
 @pytest.mark.parametrize("name", ["sphere16", "ellipsoid24", "suspension3",
                                   "suspension3_per_solid", "suspension3_fp32_graph",
                                   "suspension3_cus5", "sphere64", "sphere40_L16",
-                                  "wide_box_L16_tw1", "wide_box_L4_tw2",
+                                  "wide_box_L16_tw1", "wide_box_L4_tw2", "mixed_kinds",
                                   "ellipsoid40_cus64", "ellipsoid40_cus64_fp32"])
 def test_emulated_kernels_match_oracle(emulated, name):
     w, prec, st, outs, xn = emulated[name]

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2104_00095_amd import synth
-from tests.helpers import BlurCase, blur_pair_workload, compare_blur, grid_of
+from tests.helpers import BlurCase, blur_pair_workload, compare_blur, grid_of, mixed_kinds_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -50,6 +50,8 @@ CASES = {
     "ellipsoid64": lambda: BlurCase(synth.ellipsoid128(n=64, n_layers=6), eps_cells=3.0),
     "suspension8": lambda: BlurCase(synth.suspension(n_solids=8, grid_n=(64, 64, 96),
                                                      h=1.0 / 64, n_layers=6)),
+    # both kinds in one call: the general forms of the full kernels
+    "mixed_kinds": lambda: BlurCase(mixed_kinds_workload()),
 }
 
 

@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_2104_00095_amd import synth
 from tests.helpers import (axis_plane_workload, edge_workloads, oracle_problem, rel_err,
-                           run_oracle, wide_box_sphere)
+                           run_oracle, wide_box_sphere, mixed_kinds_workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -129,6 +129,15 @@ def test_many_layers(ctx, n, L, tile_w):
     st, gpu = run_gpu(ctx, w)
     assert st == 0 and int(gpu[0][1].max()) == L
     compare(w, gpu, 0, tag=f"sphere{n}_L{L}_tw{tile_w}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sphere_and_ellipsoid_in_one_batch(ctx, precision):
+    """A batch with both kinds runs the normal kernel's general form; each solid equals
+    the oracle as when it is alone."""
+    w = mixed_kinds_workload()
+    st, gpu = run_gpu(ctx, w, precision)
+    compare(w, gpu, precision, tag="mixed_kinds")
 
 
 @pytest.mark.parametrize("L,tile_w", [(16, 0), (16, 1), (4, 1), (4, 2)])
